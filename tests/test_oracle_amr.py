@@ -1,0 +1,279 @@
+"""Pins for the oracle's patch-based AMR (Sec. 3): transfers, ghost fill,
+subcycling with the conservative fix, regrid and 2:1 balance."""
+import numpy as np
+import pytest
+
+import afsynth
+import oracle
+
+
+def _biquadratic(seed, ncomp=1):
+    rng = np.random.default_rng(seed)
+    coeffs = []
+    for _ in range(ncomp):
+        c = rng.standard_normal((3, 3))
+        coeffs.append({(m, n): c[m, n] for m in range(3) for n in range(3)})
+    return afsynth.polynomial(coeffs, ncomp)
+
+
+def _leaf_block_exact(h, leaf, data):
+    l, ix, iy = h.leaves()[leaf]
+    dx, dy = h.dx(l), h.dy(l)
+    return afsynth.dofs_block(data, h.m, 2, h.x0 + ix * h.m * dx, h.y0 + iy * h.m * dy, dx, dy, nq=6)
+
+
+
+def _valid_masks(m):
+    S1 = m + 5
+    loc = np.arange(S1) - 2
+    I, J = np.meshgrid(loc, loc)
+    return {"avg": (I < m + 2) & (J < m + 2), "corner": np.ones_like(I, bool),
+            "xedge": J < m + 2, "yedge": I < m + 2}
+
+
+@pytest.mark.parametrize("eq", [0, 1])
+def test_uniform_patches_equal_single_grid(eq):
+    """A single level cut into patches with same-level periodic ghost fill
+    reproduces the single-grid run (Sec. 3.1: same-level ghost copy).  The
+    level-1 hierarchy takes two subcycled steps of dt0/2 per coarse step,
+    exercising the layer-1 advance and the intermediate fill."""
+    m, n0 = 8, 2
+    N = n0 * m * 2
+    data = afsynth.fourier_modes(5) if eq == 0 else afsynth.gaussian_pulse(5)
+    h = oracle.Hier(eq, m, n0, n0, 1, a=1.0, b=0.5, c=1.0)
+    h.set_leaves(afsynth.uniform_leaves(n0, n0, 1))
+    h.init_from(data)
+    dt0 = 0.8 / (n0 * m)  # level-1 CFL 0.4
+    h.run(dt0, 3)
+    d0 = afsynth.dofs_periodic(data, N, N)
+    d1 = oracle.run_periodic(eq, d0, 0.5 * dt0, 6, a=1.0, b=0.5, c=1.0)
+    for k, (l, ix, iy) in enumerate(h.leaves()):
+        blk = h.get_block(k)
+        for kind in oracle.KINDS:
+            a = blk[kind][:, 2:2 + m, 2:2 + m]
+            b = d1[kind][:, iy * m:(iy + 1) * m, ix * m:(ix + 1) * m]
+            np.testing.assert_allclose(a, b, atol=1e-13, err_msg=kind)
+
+
+def test_refine_and_coarsen_exact_on_biquadratics():
+    """Coarse->fine: the reconstruction is exact for a biquadratic, so the
+    fine points are exact and Simpson gives the exact fine averages; fine->
+    coarse: the mean of the four exact fine averages is the exact coarse
+    average and fine vertices carry the exact coarse points (Sec. 3.1)."""
+    m = 8
+    data = _biquadratic(11, 3)
+    h = oracle.Hier(1, m, 1, 1, 1)
+    h.set_leaves([(0, 0, 0)])
+    h.set_block(0, _leaf_block_exact(h, 0, data))
+    hf = oracle.Hier(1, m, 1, 1, 1)
+    hf.set_leaves([(1, q & 1, q >> 1) for q in range(4)])
+    interior = {"avg": (slice(2, 2 + m), slice(2, 2 + m)), "corner": (slice(2, 3 + m), slice(2, 3 + m)),
+                "xedge": (slice(2, 2 + m), slice(2, 3 + m)), "yedge": (slice(2, 3 + m), slice(2, 2 + m))}
+    for q in range(4):
+        fine = h.refine_block(0, q & 1, q >> 1)
+        ref = _leaf_block_exact(hf, q, data)
+        for kind, sl in interior.items():
+            np.testing.assert_allclose(fine[kind][(slice(None),) + sl], ref[kind][(slice(None),) + sl],
+                                       atol=1e-12, err_msg=kind)
+        hf.set_block(q, ref)
+    coarse = hf.coarsen_block([0, 1, 2, 3])
+    ref = _leaf_block_exact(h, 0, data)
+    for kind, sl in interior.items():
+        np.testing.assert_allclose(coarse[kind][(slice(None),) + sl], ref[kind][(slice(None),) + sl],
+                                   atol=1e-12, err_msg=kind)
+
+
+def test_refine_conserves_and_coarsen_inverts():
+    """Simpson is exact on the reconstruction, so the four fine averages of a
+    refined cell sum to four times its average (Sec. 3.1); coarsening the
+    refined data returns the original DOFs."""
+    m = 8
+    h = oracle.Hier(0, m, 1, 1, 1)
+    h.set_leaves([(0, 0, 0)])
+    rng = np.random.default_rng(2)
+    blk = {k: rng.standard_normal((1, m + 5, m + 5)) for k in oracle.KINDS}
+    h.set_block(0, blk)
+    kids = [h.refine_block(0, q & 1, q >> 1) for q in range(4)]
+    fine = np.zeros((2 * m, 2 * m))
+    for q in range(4):
+        fine[(q >> 1) * m:(q >> 1) * m + m, (q & 1) * m:(q & 1) * m + m] = kids[q]["avg"][0, 2:2 + m, 2:2 + m]
+    coarse_from_fine = 0.25 * (fine[0::2, 0::2] + fine[1::2, 0::2] + fine[0::2, 1::2] + fine[1::2, 1::2])
+    np.testing.assert_allclose(coarse_from_fine, blk["avg"][0, 2:2 + m, 2:2 + m], atol=1e-13)
+    h2 = oracle.Hier(0, m, 1, 1, 1)
+    h2.set_leaves([(1, q & 1, q >> 1) for q in range(4)])
+    for q in range(4):
+        h2.set_block(q, kids[q])
+    back = h2.coarsen_block([0, 1, 2, 3])
+    np.testing.assert_allclose(back["avg"][0, 2:2 + m, 2:2 + m], blk["avg"][0, 2:2 + m, 2:2 + m], atol=1e-13)
+    for kind, (r, c) in {"corner": (m + 1, m + 1), "xedge": (m, m + 1), "yedge": (m + 1, m)}.items():
+        np.testing.assert_allclose(back[kind][0, 2:2 + r, 2:2 + c], blk[kind][0, 2:2 + r, 2:2 + c], atol=1e-14)
+
+
+@pytest.mark.parametrize("layout", ["diagonal", "corner"])
+def test_fill_exact_on_biquadratic_data(layout):
+    """After a synchronised fill, every ghost DOF of every patch whose block
+    does not wrap around the periodic boundary equals the exact value of a
+    global biquadratic: same-level copies, fine->coarse means and
+    coarse->fine interpolation are all exact for it (Sec. 3.1)."""
+    m, n0 = 8, 4
+    if layout == "diagonal":
+        leaves = afsynth.diagonal_leaves(n0, 0)
+    else:
+        leaves = [(0, ix, iy) for iy in range(n0) for ix in range(n0) if (ix, iy) != (1, 1)]
+        leaves += [(1, 2 + (q & 1), 2 + (q >> 1)) for q in range(4)]
+        leaves = afsynth.sort_leaves(leaves)
+    data = _biquadratic(21, 1)
+    h = oracle.Hier(0, m, n0, n0, 1)
+    h.set_leaves(leaves)
+    exact = [_leaf_block_exact(h, k, data) for k in range(len(leaves))]
+    for k in range(len(leaves)):
+        blk = {kind: exact[k][kind].copy() for kind in oracle.KINDS}
+        # poison everything outside the patch's own closed square: interior
+        # averages and the nodes of the closed square (which a step writes)
+        # survive; all ghost DOFs must come back from the fill
+        for kind in oracle.KINDS:
+            mask = np.ones_like(blk[kind][0], bool)
+            if kind == "avg":
+                mask[2:2 + m, 2:2 + m] = False
+            elif kind == "corner":
+                mask[2:3 + m, 2:3 + m] = False
+            elif kind == "xedge":
+                mask[2:2 + m, 2:3 + m] = False
+            else:
+                mask[2:3 + m, 2:2 + m] = False
+            blk[kind][0][mask] = 1e6
+        h.set_block(k, blk)
+    h.fill()
+    valid = _valid_masks(m)
+    checked = 0
+    for k, (l, ix, iy) in enumerate(h.leaves()):
+        npl = n0 << l
+        if ix in (0, npl - 1) or iy in (0, npl - 1):
+            continue
+        got = h.get_block(k)
+        for kind in oracle.KINDS:
+            v = valid[kind]
+            np.testing.assert_allclose(got[kind][0][v], exact[k][kind][0][v], atol=1e-11,
+                                       err_msg=f"{kind} leaf {(l, ix, iy)}")
+        checked += 1
+    assert checked >= 3
+
+
+@pytest.mark.parametrize("eq", [0, 1])
+def test_amr_subcycling_conserves(eq):
+    """Periodic domain, diagonal refinement (levels 1-2 on 2x2 base patches),
+    subcycling and the Berger-Colella fix: the sum of leaf averages times
+    cell area is constant to round-off (Sec. 3.2, global conservation)."""
+    data = afsynth.fourier_modes(3) if eq == 0 else afsynth.gaussian_pulse(3)
+    h = oracle.Hier(eq, 8, 2, 2, 2, a=1.0, b=0.5, c=1.0)
+    h.set_leaves(afsynth.diagonal_leaves(2, 1))
+    h.init_from(data)
+    s0 = h.total()
+    h.run(0.4 * h.dx(0), 4)
+    s1 = h.total()
+    scale = max(1.0, float(np.abs(s0).max()))
+    assert np.abs(s1 - s0).max() < 1e-14 * scale * 10, (s0, s1)
+
+
+@pytest.mark.parametrize("eq", [0, 1])
+def test_amr_constant_state_exact(eq):
+    """With constant coefficients every flux is the same constant, so a
+    constant state survives AMR with subcycling exactly (Sec. 4.2 argument,
+    trivial for constant a, b, c)."""
+    h = oracle.Hier(eq, 8, 2, 2, 2, a=1.0, b=-0.5, c=1.0)
+    h.set_leaves(afsynth.diagonal_leaves(2, 1))
+    nc = 3 if eq else 1
+    h.init_from(afsynth.InitialData(nc, lambda x, y: np.stack([np.full_like(x, 1.5 + q) for q in range(nc)])))
+    h.run(0.4 * h.dx(0), 3)
+    for k in range(len(h.leaves())):
+        blk = h.get_block(k)
+        for q in range(nc):
+            np.testing.assert_allclose(blk["avg"][q, 2:10, 2:10], 1.5 + q, atol=1e-13)
+            np.testing.assert_allclose(blk["corner"][q, 2:11, 2:11], 1.5 + q, atol=1e-13)
+
+
+def test_amr_advection_third_order():
+    """Static diagonal refinement with 16x16 patches on a 1x1 base (Sec. 4.1
+    refines along the diagonal): levels (3,4) vs (4,5), smooth periodic data
+    advected to t = 0.25; the L1 error of the averages decays at third order
+    (measured EOC 2.98; coarser pairs are still pre-asymptotic: 2.56, 2.83)."""
+    def q0(x, y):
+        return (np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y) + 0.5 * np.cos(2 * np.pi * (x + 2 * y)))[None]
+
+    data = afsynth.InitialData(1, q0)
+    T = 0.25
+    moved = afsynth.InitialData(1, lambda x, y: q0(x - T, y - 0.5 * T))
+    errs = []
+    for lc in (3, 4):
+        h = oracle.Hier(0, 16, 1, 1, lc + 1, a=1.0, b=0.5)
+        h.set_leaves(afsynth.diagonal_leaves(1, lc))
+        h.init_from(data)
+        n = int(np.ceil(T / (0.4 * h.dx(0))))
+        h.run(T / n, n)
+        err = 0.0
+        for k, (l, ix, iy) in enumerate(h.leaves()):
+            ex = _leaf_block_exact(h, k, moved)
+            got = h.get_block(k)
+            err += np.abs(got["avg"][0, 2:18, 2:18] - ex["avg"][0, 2:18, 2:18]).sum() * h.dx(l) * h.dy(l)
+        errs.append(err)
+    eoc = np.log2(errs[0] / errs[1])
+    assert 2.85 <= eoc <= 3.15, (errs, eoc)
+
+
+def test_regrid_balance_and_conservation():
+    """Random tag sequences: after each regrid the hierarchy is 2:1 balanced
+    with corner adjacency (Sec. 3: well-balanced mesh) and refinement /
+    coarsening conserve the total (Sec. 3.1)."""
+    rng = np.random.default_rng(5)
+    h = oracle.Hier(1, 8, 2, 2, 3, c=1.0)
+    h.set_leaves(afsynth.uniform_leaves(2, 2, 0))
+    h.init_from(afsynth.gaussian_pulse(7))
+    s0 = h.total()
+    for it in range(6):
+        n = len(h.leaves())
+        tags = rng.integers(-1, 2, n).astype(np.int8)
+        h.regrid(tags)
+        assert h.balanced()
+        np.testing.assert_allclose(h.total(), s0, atol=1e-14)
+    assert len(set(l for l, _, _ in h.leaves())) >= 2
+
+
+def test_regrid_refines_and_coarsens_families():
+    """A family of four tagged -1 becomes its parent; a leaf tagged +1 becomes
+    four children; a family whose parent would touch a leaf two levels finer
+    (here through the periodic wrap) is kept."""
+    h = oracle.Hier(0, 8, 4, 4, 2)
+    h.set_leaves(afsynth.uniform_leaves(4, 4, 1))
+    h.init_from(afsynth.fourier_modes(0))
+    lv = h.leaves()
+    tags = np.zeros(len(lv), np.int8)
+    for k, (l, ix, iy) in enumerate(lv):
+        if ix >> 1 == 2 and iy >> 1 == 2:
+            tags[k] = -1          # family under level-0 patch (2,2)
+        if ix >> 1 == 3 and iy >> 1 == 0:
+            tags[k] = -1          # family under (3,0): touches (0,0) via the wrap
+        if (ix, iy) == (0, 0):
+            tags[k] = 1
+    h.regrid(tags)
+    got = set(h.leaves())
+    assert (0, 2, 2) in got
+    assert all((2, x, y) in got for x in (0, 1) for y in (0, 1))
+    assert (0, 3, 0) not in got and (1, 7, 0) in got
+    assert h.balanced()
+
+
+def test_tagging_gradient_of_linear_field():
+    """A linear field has centred gradient equal to its slope everywhere."""
+    h = oracle.Hier(1, 8, 2, 2, 1, c=1.0)
+    h.set_leaves(afsynth.uniform_leaves(2, 2, 1))
+    slope = 3.0
+    h.init_from(afsynth.InitialData(3, lambda x, y: np.stack([slope * x + 0.5 * y, 0 * x, 0 * x])))
+    tags, vals = h.tag(0, 0, 2.9, 1.0)
+    # interior patches see the exact slope; patches at the periodic seam see the jump
+    lv = h.leaves()
+    for k, (l, ix, iy) in enumerate(lv):
+        if 0 < ix < 3:
+            assert abs(vals[k] - slope) < 1e-10
+            assert tags[k] == 0  # at lmax: refine is not possible
+    tags2, _ = h.tag(0, 0, 10.0, 3.5)
+    assert all(t == -1 for k, t in enumerate(tags2) if 0 < lv[k][1] < 3)

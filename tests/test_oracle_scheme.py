@@ -1,0 +1,221 @@
+"""Pins for the oracle's single-grid AF step (Sec. 2): exactness on data the
+scheme must reproduce, special cases, conservation, third-order convergence,
+and the paper's own error tables."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import afsynth
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")
+M = 8
+G = 2
+
+
+def _block(data, dx, dy, x0p=0.3, y0p=-0.2):
+    return afsynth.dofs_block(data, M, G, x0p, y0p, dx, dy, nq=6)
+
+
+def _interior(blk, kind, region=0):
+    lo = G - region
+    hi = G + M + region
+    if kind == "avg":
+        return blk[kind][:, lo:hi, lo:hi]
+    if kind == "corner":
+        return blk[kind][:, lo:hi + 1, lo:hi + 1]
+    if kind == "xedge":
+        return blk[kind][:, lo:hi, lo:hi + 1]
+    return blk[kind][:, lo:hi + 1, lo:hi]
+
+
+# ---------------------------------------------------------------- advection
+
+@pytest.mark.parametrize("a,b,cfl,region", [(1.0, 0.5, 0.4, 0), (-0.7, 0.9, 0.9, 1),
+                                            (0.3, -1.0, 0.75, 0), (-1.0, -1.0, 1.0, 1),
+                                            (1.0, 0.0, 0.55, 0)])
+def test_advection_exact_on_quadratics(a, b, cfl, region):
+    """For total-degree-2 data the exact solution q0(x-at, y-bt) is quadratic
+    in (x, y, t): the reconstruction and the upwind-foot evaluation are exact
+    and Simpson's rule is exact along every face, so one step reproduces the
+    exact averages and point values (eq. advection-update, eq. Simpson-2d)."""
+    coeffs = {(0, 0): 0.3, (1, 0): -1.2, (0, 1): 0.7, (2, 0): 0.9, (1, 1): -0.4, (0, 2): 1.3}
+    data = afsynth.polynomial([coeffs])
+    dx, dy = 0.05, 0.04
+    dt = cfl * min(dx / max(abs(a), 1e-30), dy / max(abs(b), 1e-30))
+    blk = _block(data, dx, dy)
+    out = oracle.patch_step(0, M, blk, dx, dy, dt, region=region, a=a, b=b)
+    exact = afsynth.polynomial([coeffs])
+    moved = afsynth.InitialData(1, lambda x, y: exact.f(x - a * dt, y - b * dt))
+    ref = _block(moved, dx, dy)
+    for kind in oracle.KINDS:
+        np.testing.assert_allclose(_interior(out, kind, region), _interior(ref, kind, region),
+                                   atol=2e-13, err_msg=kind)
+
+
+def test_advection_one_cell_shift():
+    """b = 0 and a dt = dx on x-dependent data: every DOF moves exactly one
+    cell (the point values are exact translates and the flux integrand is
+    quadratic in t)."""
+    N = 16
+    data = afsynth.InitialData(1, lambda x, y: (np.sin(2 * np.pi * x) + 0.3 * np.cos(6 * np.pi * x) + 0 * y)[None])
+    d0 = afsynth.dofs_periodic(data, N, N)
+    d1 = oracle.run_periodic(0, d0, d0["dx"], 1, a=1.0, b=0.0)
+    for kind in oracle.KINDS:
+        np.testing.assert_allclose(d1[kind], np.roll(d0[kind], 1, axis=2), atol=1e-13, err_msg=kind)
+
+
+def test_advection_zero_velocity_is_identity_and_constant_preserved():
+    N = 12
+    rng = np.random.default_rng(3)
+    d0 = {k: rng.standard_normal((1, N, N)) for k in oracle.KINDS}
+    d0["dx"] = d0["dy"] = 1.0 / N
+    d1 = oracle.run_periodic(0, d0, 0.01, 3, a=0.0, b=0.0)
+    for kind in oracle.KINDS:
+        np.testing.assert_allclose(d1[kind], d0[kind], atol=1e-14)
+    c0 = {k: np.full((1, N, N), 2.5) for k in oracle.KINDS}
+    c0["dx"] = c0["dy"] = 1.0 / N
+    c1 = oracle.run_periodic(0, c0, 0.5 / N, 5, a=0.8, b=-0.6)
+    for kind in oracle.KINDS:
+        np.testing.assert_allclose(c1[kind], 2.5, atol=1e-13)
+
+
+def test_advection_conserves_sum():
+    N = 24
+    d0 = afsynth.dofs_periodic(afsynth.fourier_modes(1), N, N)
+    d1 = oracle.run_periodic(0, d0, 0.4 / N, 20, a=1.0, b=0.5)
+    assert abs(d1["avg"].sum() - d0["avg"].sum()) < 1e-12 * N * N
+
+
+def test_advection_periodic_return_third_order():
+    """Periodic advection with (a,b) = (1,0.5) returns to q0 at T = 2; the
+    error against the exact averages decays at third order (Sec. 4: the
+    method is third order)."""
+    errs = []
+    for N in (32, 64, 128):
+        data = afsynth.sinsin_bump()
+        d0 = afsynth.dofs_periodic(data, N, N)
+        d1 = oracle.run_periodic(0, d0, 0.4 / N, 5 * N, a=1.0, b=0.5)
+        errs.append(np.abs(d1["avg"] - d0["avg"]).mean())
+    eoc = np.log2(errs[1] / errs[2])
+    assert 2.8 <= eoc <= 3.2, (errs, eoc)
+
+
+def test_advection_table1_uniform_level4():
+    """Table 1 (left), uniform level 4: tanh disc, a=1, b=0.5, CFL 0.6, t=1,
+    L1 error of the averages.  Level 4 is read as 256^2 cells (16x16-cell
+    patches, level l = 2^l patches per side)."""
+    gold = json.load(open(GOLDEN))["table1_advection"]["uniform"]["4"]
+    N, cfl = 256, 0.6
+    data = afsynth.tanh_disc()
+    d0 = afsynth.dofs_periodic(data, N, N, nq=10)
+    nst = int(np.ceil(1.0 / (cfl / N)))
+    d1 = oracle.run_periodic(0, d0, 1.0 / nst, nst, a=1.0, b=0.5)
+    ex = afsynth.dofs_periodic(afsynth.InitialData(1, lambda x, y: data.exact(x, y, 1.0)), N, N, nq=10)
+    err = np.abs(d1["avg"] - ex["avg"]).mean()
+    assert abs(err / gold - 1.0) < 0.01, (err, gold)
+
+
+# ---------------------------------------------------------------- acoustics
+
+def _wave_series_quadratic(alpha, beta, gamma, delta, eps, zeta, ulin, vlin, c):
+    """Exact acoustic solution for quadratic p0 and linear (u0, v0) with
+    constant vorticity: p = p0 - c t div u0 + c^2 t^2 (delta + zeta),
+    u = u0 - c t p0_x, v = v0 - c t p0_y (terminating series of Sec. 2.3's
+    second-order form)."""
+    u0a, u0b, u0c = ulin  # u0 = u0a + u0b x + u0c y
+    v0a, v0b, v0c = vlin
+    div = u0b + v0c
+
+    def sol(x, y, t):
+        p0 = alpha + beta * x + gamma * y + delta * x * x + eps * x * y + zeta * y * y
+        p = p0 - c * t * div + c * c * t * t * (delta + zeta)
+        u = u0a + u0b * x + u0c * y - c * t * (beta + 2 * delta * x + eps * y)
+        v = v0a + v0b * x + v0c * y - c * t * (gamma + eps * x + 2 * zeta * y)
+        return np.stack([p, u, v])
+
+    return sol
+
+
+@pytest.mark.parametrize("cfl,region", [(0.4, 0), (0.5, 1), (0.25, 0)])
+def test_acoustics_exact_on_quadratic_constant_vorticity(cfl, region):
+    c = 1.3
+    sol = _wave_series_quadratic(0.2, -0.5, 0.8, 1.1, -0.7, 0.6, (0.1, 0.4, -0.9), (-0.3, 0.5, -1.2), c)
+    dx, dy = 0.05, 0.05
+    dt = cfl * dx / c
+    blk = _block(afsynth.InitialData(3, lambda x, y: sol(x, y, 0.0)), dx, dy)
+    out = oracle.patch_step(1, M, blk, dx, dy, dt, region=region, c=c)
+    ref = _block(afsynth.InitialData(3, lambda x, y: sol(x, y, dt)), dx, dy)
+    for kind in oracle.KINDS:
+        np.testing.assert_allclose(_interior(out, kind, region), _interior(ref, kind, region),
+                                   atol=5e-13, err_msg=kind)
+
+
+def test_acoustics_point_values_biquartic_pressure():
+    """p0 = x^2 y^2, u = v = 0 (zero vorticity): the ER formula on the exact
+    biquadratic reconstruction gives the exact wave solution at the nodes,
+    p = x^2 y^2 + (ct)^2 (x^2 + y^2) + (ct)^4 / 3 (series sum_k (ct)^{2k}
+    Delta^k p0 / (2k)!)."""
+    c = 0.8
+    dx = dy = 0.05
+    dt = 0.5 * dx / c
+    data = afsynth.InitialData(3, lambda x, y: np.stack([x * x * y * y, 0 * x, 0 * x]))
+    blk = _block(data, dx, dy, x0p=-0.2, y0p=-0.25)
+    out = oracle.patch_step(1, M, blk, dx, dy, dt, region=0, c=c)
+    R = c * dt
+    pos = afsynth.block_positions(M, G, -0.2, -0.25, dx, dy)
+    for kind in ("corner", "xedge", "yedge"):
+        x, y, _ = pos[kind]
+        exact_p = x * x * y * y + R * R * (x * x + y * y) + R ** 4 / 3.0
+        exact_u = -2 * c * dt * x * y * y - 2 * c ** 3 * dt ** 3 * x / 3.0
+        lo, hi = G, G + M
+        sl = (slice(lo, hi + 1), slice(lo, hi + 1))
+        if kind == "xedge":
+            sl = (slice(lo, hi), slice(lo, hi + 1))
+        if kind == "yedge":
+            sl = (slice(lo, hi + 1), slice(lo, hi))
+        np.testing.assert_allclose(out[kind][0][sl], exact_p[sl], atol=1e-14, err_msg=kind)
+        np.testing.assert_allclose(out[kind][1][sl], exact_u[sl], atol=1e-14, err_msg=kind)
+
+
+def test_acoustics_stationary_states_preserved():
+    """Constant pressure with a rigid rotation u = w(-y, x) is a stationary
+    state that the piecewise biquadratic represents exactly; M_R of linear data
+    is its point value and d/dR vanishes, and the fluxes cancel, so one step
+    leaves every DOF unchanged to round-off."""
+    w = 2.3
+    data = afsynth.InitialData(3, lambda x, y: np.stack([1.7 + 0 * x, -w * y, w * x]))
+    dx = dy = 0.05
+    blk = _block(data, dx, dy)
+    out = oracle.patch_step(1, M, blk, dx, dy, 0.4 * dx, region=1, c=1.0)
+    for kind in oracle.KINDS:
+        np.testing.assert_allclose(_interior(out, kind, 1), _interior(blk, kind, 1), atol=1e-14)
+
+
+def test_acoustics_conserves_sums():
+    N = 16
+    d0 = afsynth.dofs_periodic(afsynth.gaussian_pulse(2), N, N)
+    d1 = oracle.run_periodic(1, d0, 0.4 / N, 6, c=1.0)
+    for k in range(3):
+        assert abs(d1["avg"][k].sum() - d0["avg"][k].sum()) < 1e-13
+
+
+def test_acoustics_lukacova_third_order():
+    """Sec. 4.5.1 test on [-1,1]^2, c = 1, CFL 0.4, t = 1; pressure error
+    decays at third order."""
+    errs = []
+    for N in (32, 64):
+        data = afsynth.lukacova()
+        d0 = afsynth.dofs_periodic(data, N, N, x0=-1, y0=-1, lx=2, ly=2)
+        nst = int(np.ceil(1.0 / (0.4 * 2.0 / N)))
+        d1 = oracle.run_periodic(1, d0, 1.0 / nst, nst, c=1.0)
+        ex = afsynth.dofs_periodic(afsynth.InitialData(3, lambda x, y: data.exact(x, y, 1.0)), N, N,
+                                   x0=-1, y0=-1, lx=2, ly=2)
+        errs.append(np.abs(d1["avg"][0] - ex["avg"][0]).mean())
+    gold = json.load(open(GOLDEN))["table4_acoustics"]["uniform"]
+    eoc = np.log2(errs[0] / errs[1])
+    assert 2.8 <= eoc <= 3.2, (errs, eoc)
+    # soft pin against Table 4, level 2 (64^2), pressure: mean-normalised L1
+    assert 0.8 <= errs[1] / gold["2"]["p"] <= 1.25, (errs[1], gold["2"]["p"])
