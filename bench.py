@@ -1,0 +1,186 @@
+"""Benchmark: batched Active Flux patch step on one MI355X.
+
+Workload (the metric's configuration): 2D linear advection, a=1, b=0.5, on
+the periodic unit square as one level of 16x16 patches of 32x32 cells
+(512^2 cells, two ghost layers), seeded 8-mode Fourier initial data, T=1
+(1280 steps at CFL 0.4).  One "step" is one pass of the whole path: ghost
+fill between patches plus the patch step of every patch, replayed as a
+hipGraph.  FP32 is the headline (FP32 state and arithmetic, FP64 sums); the
+FP64 path is timed beside it.
+
+Prints one JSON line.  --gpus N with N > 1 is not supported (single GPU).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+M, N0 = 32, 16
+NCELL = (M * N0) ** 2
+T_FINAL = 1.0
+NSTEPS_T = 1280
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=NSTEPS_T)
+    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-steps", type=int, default=48)
+    return p.parse_args()
+
+
+def setup(prec, data):
+    import torch
+    import afsynth
+    import paper_2205_07572_amd as af
+    prob = af.Problem(eq=af.ADVECTION, prec=prec, m=M, n0x=N0, n0y=N0, lmax=0, a=1.0, b=0.5)
+    ctx = af.Context(prob)
+    leaves = afsynth.uniform_leaves(N0, N0, 0)
+    blocks = []
+    for (l, ix, iy) in leaves:
+        dx = prob.dx(0)
+        blocks.append(afsynth.dofs_block(data, M, 2, ix * M * dx, iy * M * dx, dx, dx, 4))
+    h = af.Hierarchy(ctx, leaves)
+    b0 = af.blocks_to_state(ctx, blocks)
+    bufs = [b0, torch.zeros_like(b0)]
+    reg = torch.zeros((len(leaves), 4, M, 1), dtype=torch.float64, device="cuda")
+    return ctx, h, bufs, reg, blocks
+
+
+def run_steps(ctx, h, bufs, reg, mask, nsteps, dt):
+    for _ in range(nsteps):
+        mask = ctx.amr_coarse_step(h, bufs, mask, dt, reg, use_graph=True)
+    return mask
+
+
+def time_path(prec, data, steps, warmup, dt):
+    import torch
+    ctx, h, bufs, reg, blocks = setup(prec, data)
+    mask = 0
+    mask = run_steps(ctx, h, bufs, reg, mask, warmup, dt)
+    torch.cuda.synchronize()
+    # restart from the initial state so the timed run covers steps 0..K-1
+    import paper_2205_07572_amd as af
+    bufs[0].copy_(af.blocks_to_state(ctx, blocks))
+    mask = 0
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    mask = run_steps(ctx, h, bufs, reg, mask, steps, dt)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    # dominant kernel: the patch step, timed alone with HIP events on the
+    # stream it runs on (same launch configuration as inside the graph)
+    nk = max(50, min(steps, 400))
+    cur = mask & 1
+    ctx.patch_step(bufs[cur], bufs[cur ^ 1], 0, N0 * N0, 0, dt, 0)
+    torch.cuda.synchronize()
+    k0 = torch.cuda.Event(enable_timing=True)
+    k1 = torch.cuda.Event(enable_timing=True)
+    k0.record()
+    for _ in range(nk):
+        ctx.patch_step(bufs[cur], bufs[cur ^ 1], 0, N0 * N0, 0, dt, 0)
+    k1.record()
+    torch.cuda.synchronize()
+    k_ms = k0.elapsed_time(k1) / nk
+    out = af.state_to_blocks(ctx, bufs[mask & 1])
+    return ms, k_ms, out, ctx.tile
+
+
+def cpu_baseline(data, nsteps, dt):
+    import afsynth
+    import oracle
+    d0 = afsynth.dofs_periodic(data, M * N0, M * N0, nq=4)
+    t0 = time.perf_counter()
+    oracle.run_periodic(0, d0, dt, nsteps, a=1.0, b=0.5)
+    el = time.perf_counter() - t0
+    return NCELL * nsteps / el, el
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "single-GPU build: --gpus must be 1 (multi-GPU sharding is design-only)"}))
+        sys.exit(2)
+    import torch
+    import afsynth
+    import paper_2205_07572_amd as af
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    data = afsynth.fourier_modes(0)
+    dt = T_FINAL / NSTEPS_T
+    res = {}
+    for name, prec in (("fp32", af.FP32), ("fp64", af.FP64)):
+        ms, k_ms, out, tile = time_path(prec, data, args.steps, args.warmup, dt)
+        res[name] = dict(ms=ms, k_ms=k_ms, out=out, tile=tile)
+        print(f"[bench] {name}: {args.steps} steps in {ms:.3f} ms, patch-step kernel {k_ms * 1e3:.2f} us "
+              f"(tile {tile})", file=sys.stderr, flush=True)
+    # accuracy: FP32 vs FP64 (FP64 is parity-tested against the oracle) and
+    # both against the exact solution when the run reaches T = 1
+    def interior(blocks):
+        return np.stack([np.stack([b[k][0, 2:2 + M, 2:2 + M] for k in af.KINDS]) for b in blocks])
+    a32, a64 = interior(res["fp32"]["out"]), interior(res["fp64"]["out"])
+    linf_32_64 = float(np.abs(a32 - a64).max() / np.abs(a64).max())
+    err_exact = None
+    if args.steps == NSTEPS_T:
+        t = args.steps * dt
+        ex = []
+        for (l, ix, iy) in afsynth.uniform_leaves(N0, N0, 0):
+            dx = 1.0 / (M * N0)
+            b = afsynth.dofs_block(afsynth.InitialData(1, lambda x, y: data.exact(x, y, t)), M, 2, ix * M * dx,
+                                   iy * M * dx, dx, dx, 4)
+            ex.append(b)
+        ae = interior(ex)
+        err_exact = {"fp32": float(np.abs(a32 - ae).max()), "fp64": float(np.abs(a64 - ae).max())}
+    ms32, k32 = res["fp32"]["ms"], res["fp32"]["k_ms"]
+    ms64, k64 = res["fp64"]["ms"], res["fp64"]["k_ms"]
+    ups32 = NCELL * args.steps / (ms32 * 1e-3)
+    ups64 = NCELL * args.steps / (ms64 * 1e-3)
+    bytes32 = 8 * 4 * NCELL  # algorithmic: read 4 DOFs and write 4 DOFs per cell-update
+    achieved = bytes32 / (k32 * 1e-3) / 1e9
+    line = {
+        "metric": "cell-updates/s (FP32 vs FP64) of batched AMR AF step; % HBM roofline; L∞ err",
+        "value": ups32,
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "advection a=1 b=0.5, periodic unit square, one level of 16x16 patches of "
+                               "32x32 cells (512^2), 2 ghost layers, seeded 8-mode Fourier data, T=1 "
+                               "(1280 steps, CFL 0.4); step = ghost fill + patch step, hipGraph replay",
+                   "patches": N0 * N0, "patch_cells": M, "tile_rows": res["fp32"]["tile"]},
+        "fp64": {"value": ups64, "ms_per_step": ms64 / args.steps, "kernel_us": k64 * 1e3,
+                 "speedup_fp32_over_fp64": ups32 / ups64},
+        "linf_fp32_vs_fp64_rel": linf_32_64,
+        "linf_vs_exact_T1": err_exact,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_patch_step<float,adv,32,8>", "kernel_us": k32 * 1e3,
+                     "algorithmic_bytes_per_launch": bytes32},
+    }
+    if not args.no_cpu:
+        v, el = cpu_baseline(data, args.cpu_steps, dt)
+        line["cpu_baseline"] = {"value": v, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
+                                "sample": f"{args.cpu_steps} of the 1280 steps on the 512^2 grid "
+                                          f"(single-threaded FP64 oracle, {el:.1f} s)"}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,243 @@
+/*
+ * af.h -- C ABI of the MI355X Active Flux patch-step library (libaf.so).
+ *
+ * The library advances the Cartesian-grid Active Flux (AF) method of
+ * Calhoun, Chudzik & Helzel (arXiv 2205.07572) on a quadtree of equal-size
+ * patches on one AMD Instinct MI355X (gfx950) GPU.
+ *
+ * Method (Sec. 2): each cell carries its average and the point values at its
+ * corners and edge midpoints; cell (i,j) owns the average Q_ij, the left-edge
+ * midpoint Q_{i-1/2,j}, the bottom-left corner Q_{i-1/2,j-1/2} and the
+ * bottom-edge midpoint Q_{i,j-1/2}.  A step reconstructs the continuous
+ * biquadratic in every cell, evolves the point values to t+dt/2 and t+dt
+ * with the exact operators of linear advection (Sec. 2.1) or acoustics
+ * (Sec. 2.3, Eymann-Roe formula), forms Simpson space-time fluxes
+ * (eq. Simpson-2d) and updates the averages conservatively (eq. 2dfv).
+ * Patches exchange data through two ghost layers (Sec. 3.1, 3.2), finer
+ * levels subcycle (Sec. 3.2) and the coarse-fine flux mismatch is repaired
+ * by the Berger-Colella fix (Sec. 3.2, global conservation).
+ *
+ * Conventions common to every call
+ *  - All state, flux-register, tag and value buffers are caller-owned DEVICE
+ *    memory; the library never frees them.  Library-owned objects (af_ctx,
+ *    af_hier) hold only small tables.
+ *  - Every launching call takes a hipStream_t (0 = the null stream) and is
+ *    asynchronous.  Arguments are validated on the host before anything is
+ *    launched; on error nothing is launched.
+ *  - Every call returns af_status (AF_OK = 0, negative on error);
+ *    af_last_error() returns a thread-local message for the last failure.
+ *  - Periodic boundaries on the rectangle [x0,x0+lx] x [y0,y0+ly].
+ *
+ * State layout (af_state)
+ *  Four arrays dof[k], k = AF_AVG, AF_CORNER, AF_XEDGE, AF_YEDGE, each of
+ *  shape [ncomp][npatch][m+5][pitch] of the problem precision (double for
+ *  AF_FP64, float for AF_FP32), ncomp = 1 (advection, q) or 3 (acoustics,
+ *  p,u,v).  Row r, column c of a patch plane hold the DOF of local index
+ *  (i,j) = (c-2, r-2): cells of the interior are i,j in [0,m), the two ghost
+ *  layers extend to [-2, m+2).  Valid entries: avg i,j in [-2,m+2); corner
+ *  i,j in [-2,m+2]; xedge (point (x_{i-1/2}, y_j)) i in [-2,m+2], j in
+ *  [-2,m+2); yedge (point (x_i, y_{j-1/2})) i in [-2,m+2), j in [-2,m+2].
+ *  Other entries are padding.  pitch >= m+5.
+ */
+#ifndef AF_H
+#define AF_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  AF_OK = 0,
+  AF_ERR_ARG = -1,      /* bad argument value or combination */
+  AF_ERR_CFL = -2,      /* time step violates eq. cfl-adv or eq. cfl-acoustics */
+  AF_ERR_LAYOUT = -3,   /* bad pitch / patch count / alignment */
+  AF_ERR_BALANCE = -4,  /* leaf set is not a 2:1 corner-balanced cover */
+  AF_ERR_DEVICE = -5,   /* HIP runtime error */
+  AF_ERR_STATE = -6     /* call not valid in the object's current state */
+} af_status;
+
+typedef enum { AF_ADVECTION = 0, AF_ACOUSTICS = 1 } af_equation;
+typedef enum { AF_FP64 = 0, AF_FP32 = 1 } af_precision;
+enum { AF_AVG = 0, AF_CORNER = 1, AF_XEDGE = 2, AF_YEDGE = 3 };
+enum { AF_SIDE_W = 0, AF_SIDE_E = 1, AF_SIDE_S = 2, AF_SIDE_N = 3 };
+/* step regions (Sec. 3.2: "the first layer of ghost cells is updated along
+ * with all interior cells") */
+enum { AF_REGION_INTERIOR = 0, AF_REGION_LAYER1 = 1 };
+/* tagging criteria (Sec. 4.1: q_max - q_min per patch; Sec. 4.4: centred
+ * gradient) */
+enum { AF_TAG_GRADIENT = 0, AF_TAG_MAXMIN = 1 };
+
+typedef struct {
+  int32_t eq;          /* af_equation */
+  int32_t prec;        /* af_precision: AF_FP32 = FP32 state and arithmetic,
+                          FP64 flux registers and sums */
+  int32_t m;           /* interior cells per patch side: even, 4..128 */
+  int32_t n0x, n0y;    /* level-0 patches per side */
+  int32_t lmax;        /* finest level a hierarchy may hold (<= 12) */
+  double x0, y0, lx, ly; /* periodic domain */
+  double a, b;         /* advection velocity (eq. advection2d) */
+  double c;            /* speed of sound (eq. acoustics) */
+} af_problem;
+
+typedef struct {
+  void* dof[4];        /* device pointers, see "State layout" */
+  int32_t npatch;      /* patches the arrays hold (>= leaves addressed) */
+  int32_t pitch;       /* row pitch in elements, >= m+5 */
+} af_state;
+
+typedef struct af_ctx af_ctx;
+typedef struct af_hier af_hier;
+
+const char* af_last_error(void);
+
+/* Context: validates the problem and keeps its constants.  Owns nothing on
+ * the device except a small reduction workspace. */
+af_status af_ctx_create(const af_problem* prob, af_ctx** out);
+af_status af_ctx_destroy(af_ctx* ctx);
+/* Patch-step tile height (cell rows of one patch per 256-thread block);
+ * supported: m=8: 8; m=16: 8,16; m=32: 4,8; m=64: 2,4; m=128: 2.  The
+ * autotuner picks it; results do not depend on it. */
+af_status af_ctx_set_tile(af_ctx* ctx, int32_t ty);
+int32_t af_ctx_get_tile(const af_ctx* ctx);
+
+/* ---------------------------------------------------------------------
+ * Hierarchy (Sec. 3): a leaf set of the quadtree.  Leaf k is patch k of
+ * every af_state used with it.  Leaves must be sorted by level (patches of
+ * one level are a contiguous range); af_hier_regrid returns them sorted by
+ * (level, iy, ix).  Creation checks that the leaves tile the domain exactly
+ * and are 2:1 balanced across edges AND corners (periodic), else
+ * AF_ERR_BALANCE.  The object holds host and device tables (per-level
+ * patch lookup, side relations, coarse-fine face list); it is immutable.
+ * --------------------------------------------------------------------- */
+af_status af_hier_create(af_ctx* ctx, int32_t nleaves, const int32_t* level,
+                         const int32_t* ix, const int32_t* iy, af_hier** out);
+af_status af_hier_destroy(af_hier* h);
+int32_t af_hier_num_leaves(const af_hier* h);
+/* host arrays of length af_hier_num_leaves() */
+af_status af_hier_get_leaves(const af_hier* h, int32_t* level, int32_t* ix, int32_t* iy);
+/* leaves of `level` are [*first, *first + *count) */
+af_status af_hier_level_range(const af_hier* h, int32_t level, int32_t* first, int32_t* count);
+int32_t af_hier_finest_level(const af_hier* h);
+/* side relation of each leaf, host int8 [n][4] (W,E,S,N): 0 same level,
+ * -1 coarser neighbour, +1 finer neighbours */
+af_status af_hier_side_relations(const af_hier* h, int8_t* rel);
+
+/* ---------------------------------------------------------------------
+ * af_patch_step -- one AF time step of `count` patches of one level
+ * (Sec. 2: eq. poly, eq. advection-update / eq. ERFormula,
+ * eq. Simpson-2d, eq. 2dfv).
+ *   in, out    states (distinct buffers of equal layout); the patches
+ *              [first, first+count) are read from `in` (interior and ghost
+ *              layers must be current) and written to `out`.
+ *   level      the patches' level; dx = lx/(n0x m 2^level), likewise dy.
+ *   dt         time step; AF_ERR_CFL if max(|a| dt/dx, |b| dt/dy) > 1
+ *              (advection, eq. cfl-adv) or c dt / min(dx,dy) > 1/2
+ *              (acoustics, eq. cfl-acoustics).
+ *   region     AF_REGION_INTERIOR: averages of cells [0,m)^2 and all nodes
+ *              of the closed square [0,m]^2 are written;
+ *              AF_REGION_LAYER1: cells [-1,m+1)^2 and nodes [-1,m+1]^2.
+ *              Other entries of `out` are left untouched.
+ *   flux_reg   NULL, or FP64 registers [npatch][4][m][ncomp] (side-major
+ *              W,E,S,N; index along the side); for every patch side whose
+ *              bit is set in side_mask[patch] the step ADDS F*dy*dt (x-faces)
+ *              or G*dx*dt (y-faces) of the m boundary faces of the interior.
+ *   side_mask  device uint8 [npatch]; NULL = no recording.
+ * --------------------------------------------------------------------- */
+af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t first,
+                        int32_t count, int32_t level, double dt, int32_t region,
+                        double* flux_reg, const uint8_t* side_mask, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * af_ghost_fill -- ghost data exchange between patches (Sec. 3.1 and
+ * Sec. 3.2).  Each level's data lives in bufs[(level_buf_mask >> level) & 1]
+ * (pass the same state twice and mask 0 for a single buffer).  For every
+ * leaf of level >= tmin, every DOF outside its interior cells and strictly
+ * inside-nodes is set from the leaves of level >= smin:
+ *   averages: same level copy; finer: mean of the four fine averages
+ *   (fine->coarse transfer); coarser: Simpson 3x3 of the coarse
+ *   reconstruction over the fine cell (coarse->fine transfer);
+ *   nodes: the finest leaf whose closed square contains the node
+ *   (fine values win on coarse-fine lines); same/finer: copy the vertex,
+ *   coarser: evaluate the coarse reconstruction.  Candidates of one level
+ *   are tried in the order (hi,hi),(lo,hi),(hi,lo),(lo,lo).
+ * DOFs without an admissible source keep their values (at non-synchronised
+ * times the patch's own layer-1 values serve over coarser neighbours).
+ * Two launches: same-level/fine->coarse, then coarse->fine.
+ * --------------------------------------------------------------------- */
+af_status af_ghost_fill(af_ctx* ctx, const af_hier* h, af_state* bufs, uint32_t level_buf_mask,
+                        int32_t tmin, int32_t smin, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * af_flux_correct -- Berger-Colella conservative fix (Sec. 3.2) for all
+ * coarse cells of `level` adjacent to leaves of level+1:
+ *   Q_c += s (R_c - sum R_f) / (dx_c dy_c),  s = +1 (E,N sides), -1 (W,S),
+ * with R_c the coarse register entry of the face and R_f the two fine
+ * entries facing it (accumulated over the two fine substeps).  The
+ * registers used are then zeroed.  flux_reg as in af_patch_step.
+ * --------------------------------------------------------------------- */
+af_status af_flux_correct(af_ctx* ctx, const af_hier* h, af_state* bufs,
+                          uint32_t level_buf_mask, int32_t level, double* flux_reg,
+                          hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * af_regrid_tag -- per-patch refinement flag (Sec. 3; criteria of Sec. 4.1
+ * and 4.4).  mode AF_TAG_GRADIENT: value = max over interior cells of
+ * max(|Q_{i+1,j}-Q_{i-1,j}|/(2dx), |Q_{i,j+1}-Q_{i,j-1}|/(2dy)) of component
+ * `comp` (uses ghost layer 1); AF_TAG_MAXMIN: max - min of interior
+ * averages.  tag = +1 if value >= theta_r and level < lmax; -1 if value <
+ * theta_c and level > 0; else 0.  tags: device int8 [nleaves]; values:
+ * device double [nleaves] or NULL.
+ * --------------------------------------------------------------------- */
+af_status af_regrid_tag(af_ctx* ctx, const af_hier* h, const af_state* bufs,
+                        uint32_t level_buf_mask, int32_t mode, int32_t comp, double theta_r,
+                        double theta_c, int8_t* tags, double* values, hipStream_t stream);
+
+/* af_hier_regrid -- host only: the leaf set after applying tags (host int8
+ * [nleaves]): (a) refine leaves tagged +1 below lmax; (b) refine any leaf
+ * touching (edge or corner, periodic) a leaf two or more levels finer,
+ * until none does; (c) a family of four sibling leaves all tagged -1
+ * coarsens if its parent would touch no leaf finer than the siblings (all
+ * families judged on the set after (b)); sorted by (level, iy, ix). */
+af_status af_hier_regrid(af_ctx* ctx, const af_hier* old, const int8_t* tags, af_hier** out);
+
+/* af_regrid_apply -- device DOF transfer from `old` to `new_h` (Sec. 3.1):
+ * unchanged leaves copy their interior and closed-square nodes; refined
+ * leaves interpolate from the parent (reconstruction at fine nodes, Simpson
+ * for fine averages); coarsened leaves average four children and copy fine
+ * vertices.  Writes every leaf of new_h into `dst` (ghosts are not filled:
+ * call af_ghost_fill(tmin=0, smin=0) after). */
+af_status af_regrid_apply(af_ctx* ctx, const af_hier* old, const af_state* old_bufs,
+                          uint32_t old_mask, const af_hier* new_h, af_state* dst,
+                          hipStream_t stream);
+
+/* af_reduce_sum -- FP64 sum over leaves of interior averages times cell
+ * area, per component (global conservation, Sec. 3.2).  out: device double
+ * [ncomp]. */
+af_status af_reduce_sum(af_ctx* ctx, const af_hier* h, const af_state* bufs,
+                        uint32_t level_buf_mask, double* out, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
+ * af_amr_coarse_step -- one coarse time step dt0 of the whole hierarchy
+ * with subcycling (Sec. 3.2): full fill; then advance(0): step level l with
+ * dt0/2^l (layer-1 region for the first of each pair of fine substeps),
+ * recursively advance level l+1 twice with a same-or-finer fill between,
+ * then the conservative fix of level l.  Levels ping-pong between bufs[0]
+ * and bufs[1]; *level_buf_mask is updated.  flux_reg: FP64
+ * [npatch][4][m][ncomp], zero on entry (left zero on exit).  side_mask:
+ * device uint8 [npatch] from af_hier_side_mask.  use_graph != 0 replays a
+ * hipGraph captured on first use for this (hierarchy, mask, dt0).
+ * --------------------------------------------------------------------- */
+af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* level_buf_mask,
+                             double dt0, double* flux_reg, int32_t use_graph,
+                             hipStream_t stream);
+
+/* device uint8 [nleaves]: bit s set when side s borders another level */
+const uint8_t* af_hier_side_mask(const af_hier* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AF_H */

@@ -766,7 +766,10 @@ void fill(Hier& h, int tmin, int smin) {
               const Source s = node_source(h, lt, HX, HY, smin);
               if (s.leaf < 0) continue;
               if ((phase == 0) != (s.rel >= 0)) continue;
-              if (s.leaf == t) continue;  // the target itself is the finest: keep
+              // the target itself at the same position is the finest: keep;
+              // a periodic image of the node inside the target is a source
+              if (s.leaf == t && s.rel == 0 && s.X == HX - 2LL * m * T.ix && s.Y == HY - 2LL * m * T.iy)
+                continue;
               const Leaf& Sx = h.leaves[s.leaf];
               for (int c = 0; c < h.ncomp; ++c) {
                 const double val = (s.rel >= 0) ? node_value(h, Sx, c, s.X, s.Y)

@@ -1,0 +1,223 @@
+"""MI355X Active Flux patch-step library (Python side).
+
+A thin layer over libaf.so (include/af.h): it allocates state buffers as
+torch tensors on the GPU, marshals arguments, and passes torch's current
+stream.  All arithmetic of the method runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _lib
+from ._lib import AFError, check
+
+ADVECTION, ACOUSTICS = 0, 1
+FP64, FP32 = 0, 1
+KINDS = ("avg", "corner", "xedge", "yedge")
+REGION_INTERIOR, REGION_LAYER1 = 0, 1
+TAG_GRADIENT, TAG_MAXMIN = 0, 1
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+@dataclass
+class Problem:
+    eq: int = ADVECTION
+    prec: int = FP64
+    m: int = 16
+    n0x: int = 1
+    n0y: int = 1
+    lmax: int = 0
+    x0: float = 0.0
+    y0: float = 0.0
+    lx: float = 1.0
+    ly: float = 1.0
+    a: float = 1.0
+    b: float = 0.5
+    c: float = 1.0
+
+    @property
+    def ncomp(self):
+        return 3 if self.eq == ACOUSTICS else 1
+
+    def dx(self, level):
+        return self.lx / (self.n0x * self.m) / 2 ** level
+
+    def dy(self, level):
+        return self.ly / (self.n0y * self.m) / 2 ** level
+
+
+class Context:
+    def __init__(self, prob: Problem):
+        self.prob = prob
+        L = _lib.load()
+        cp = _lib.af_problem(prob.eq, prob.prec, prob.m, prob.n0x, prob.n0y, prob.lmax, prob.x0, prob.y0,
+                             prob.lx, prob.ly, prob.a, prob.b, prob.c)
+        h = ctypes.c_void_p()
+        check(L.af_ctx_create(ctypes.byref(cp), ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.load().af_ctx_destroy(self.h)
+            self.h = None
+
+    @property
+    def tile(self):
+        return _lib.load().af_ctx_get_tile(self.h)
+
+    @tile.setter
+    def tile(self, ty):
+        check(_lib.load().af_ctx_set_tile(self.h, int(ty)))
+
+    # ----------------------------------------------------------------- state
+    def new_state(self, npatch, pitch=None):
+        """Zeroed state tensor [4][ncomp][npatch][m+5][pitch] on the GPU."""
+        torch = _torch()
+        pitch = pitch or (self.prob.m + 5)
+        dt = torch.float32 if self.prob.prec == FP32 else torch.float64
+        return torch.zeros((4, self.prob.ncomp, npatch, self.prob.m + 5, pitch), dtype=dt, device="cuda")
+
+    @staticmethod
+    def cstate(t):
+        s = _lib.af_state()
+        for k in range(4):
+            s.dof[k] = t[k].data_ptr()
+        s.npatch = t.shape[2]
+        s.pitch = t.shape[4]
+        return s
+
+    # ----------------------------------------------------------------- calls
+    def patch_step(self, tin, tout, first, count, level, dt, region=REGION_INTERIOR, flux_reg=None,
+                   side_mask=None):
+        sin, sout = self.cstate(tin), self.cstate(tout)
+        sm = ctypes.c_void_p(side_mask) if isinstance(side_mask, int) else _ptr(side_mask)
+        check(_lib.load().af_patch_step(self.h, ctypes.byref(sin), ctypes.byref(sout), int(first), int(count),
+                                        int(level), float(dt), int(region), _ptr(flux_reg), sm, _stream()))
+
+    def _pair(self, bufs):
+        arr = (_lib.af_state * 2)()
+        arr[0] = self.cstate(bufs[0])
+        arr[1] = self.cstate(bufs[1] if len(bufs) > 1 else bufs[0])
+        return arr
+
+    def ghost_fill(self, hier, bufs, mask=0, tmin=0, smin=0):
+        check(_lib.load().af_ghost_fill(self.h, hier.h, self._pair(bufs), int(mask), int(tmin), int(smin),
+                                        _stream()))
+
+    def flux_correct(self, hier, bufs, mask, level, flux_reg):
+        check(_lib.load().af_flux_correct(self.h, hier.h, self._pair(bufs), int(mask), int(level),
+                                          _ptr(flux_reg), _stream()))
+
+    def regrid_tag(self, hier, bufs, mask, mode, comp, theta_r, theta_c, tags, values=None):
+        check(_lib.load().af_regrid_tag(self.h, hier.h, self._pair(bufs), int(mask), int(mode), int(comp),
+                                        float(theta_r), float(theta_c), _ptr(tags), _ptr(values), _stream()))
+
+    def regrid_apply(self, old, bufs, mask, new, dst):
+        d = self.cstate(dst)
+        check(_lib.load().af_regrid_apply(self.h, old.h, self._pair(bufs), int(mask), new.h, ctypes.byref(d),
+                                          _stream()))
+
+    def reduce_sum(self, hier, bufs, mask, out):
+        check(_lib.load().af_reduce_sum(self.h, hier.h, self._pair(bufs), int(mask), _ptr(out), _stream()))
+
+    def amr_coarse_step(self, hier, bufs, mask, dt0, flux_reg, use_graph=False):
+        mk = ctypes.c_uint32(mask)
+        check(_lib.load().af_amr_coarse_step(self.h, hier.h, self._pair(bufs), ctypes.byref(mk), float(dt0),
+                                             _ptr(flux_reg), int(bool(use_graph)), _stream()))
+        return mk.value
+
+
+class Hierarchy:
+    def __init__(self, ctx: Context, leaves=None, _handle=None):
+        self.ctx = ctx
+        L = _lib.load()
+        if _handle is not None:
+            self.h = _handle
+        else:
+            lv = np.ascontiguousarray([l[0] for l in leaves], dtype=np.int32)
+            ix = np.ascontiguousarray([l[1] for l in leaves], dtype=np.int32)
+            iy = np.ascontiguousarray([l[2] for l in leaves], dtype=np.int32)
+            h = ctypes.c_void_p()
+            check(L.af_hier_create(ctx.h, len(lv), lv.ctypes.data_as(ctypes.c_void_p),
+                                   ix.ctypes.data_as(ctypes.c_void_p), iy.ctypes.data_as(ctypes.c_void_p),
+                                   ctypes.byref(h)))
+            self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            _lib.load().af_hier_destroy(self.h)
+            self.h = None
+
+    def __len__(self):
+        return _lib.load().af_hier_num_leaves(self.h)
+
+    def leaves(self):
+        n = len(self)
+        lv, ix, iy = (np.zeros(n, np.int32) for _ in range(3))
+        check(_lib.load().af_hier_get_leaves(self.h, lv.ctypes.data_as(ctypes.c_void_p),
+                                             ix.ctypes.data_as(ctypes.c_void_p), iy.ctypes.data_as(ctypes.c_void_p)))
+        return [(int(a), int(b), int(c)) for a, b, c in zip(lv, ix, iy)]
+
+    def level_range(self, level):
+        f, c = ctypes.c_int32(), ctypes.c_int32()
+        check(_lib.load().af_hier_level_range(self.h, int(level), ctypes.byref(f), ctypes.byref(c)))
+        return f.value, c.value
+
+    def finest(self):
+        return _lib.load().af_hier_finest_level(self.h)
+
+    def side_relations(self):
+        rel = np.zeros((len(self), 4), np.int8)
+        check(_lib.load().af_hier_side_relations(self.h, rel.ctypes.data_as(ctypes.c_void_p)))
+        return rel
+
+    def side_mask_ptr(self):
+        return _lib.load().af_hier_side_mask(self.h)
+
+    def regrid(self, tags):
+        t = np.ascontiguousarray(tags, dtype=np.int8)
+        assert len(t) == len(self)
+        h = ctypes.c_void_p()
+        check(_lib.load().af_hier_regrid(self.ctx.h, self.h, t.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)))
+        return Hierarchy(self.ctx, _handle=h)
+
+
+# ---------------------------------------------------------------------------
+# host <-> state marshalling (layout conversion only)
+# ---------------------------------------------------------------------------
+
+def blocks_to_state(ctx: Context, blocks, npatch=None, pitch=None):
+    """blocks: list over patches of dict kind -> [ncomp][m+5][m+5] arrays."""
+    torch = _torch()
+    npatch = npatch or len(blocks)
+    t = ctx.new_state(npatch, pitch)
+    S1 = ctx.prob.m + 5
+    host = np.zeros((4, ctx.prob.ncomp, npatch, S1, t.shape[4]))
+    for p, blk in enumerate(blocks):
+        for k, kind in enumerate(KINDS):
+            host[k, :, p, :, :S1] = blk[kind]
+    t.copy_(torch.from_numpy(host).to(t.dtype))
+    return t
+
+
+def state_to_blocks(ctx: Context, t, npatch=None):
+    S1 = ctx.prob.m + 5
+    host = t.detach().double().cpu().numpy()
+    n = npatch or t.shape[2]
+    return [{kind: host[k, :, p, :, :S1].copy() for k, kind in enumerate(KINDS)} for p in range(n)]

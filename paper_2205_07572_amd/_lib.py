@@ -1,0 +1,94 @@
+"""ctypes binding of libaf.so (include/af.h).  Argument marshalling only:
+every step of the method runs in the library's HIP kernels.  There is no
+fallback: if the library is missing, loading raises."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libaf.so")
+
+AF_OK, AF_ERR_ARG, AF_ERR_CFL, AF_ERR_LAYOUT, AF_ERR_BALANCE, AF_ERR_DEVICE, AF_ERR_STATE = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "AF_OK", -1: "AF_ERR_ARG", -2: "AF_ERR_CFL", -3: "AF_ERR_LAYOUT", -4: "AF_ERR_BALANCE",
+                -5: "AF_ERR_DEVICE", -6: "AF_ERR_STATE"}
+
+# Every symbol include/af.h declares.
+EXPORTS = [
+    "af_last_error", "af_ctx_create", "af_ctx_destroy", "af_ctx_set_tile", "af_ctx_get_tile",
+    "af_hier_create", "af_hier_destroy", "af_hier_num_leaves", "af_hier_get_leaves",
+    "af_hier_level_range", "af_hier_finest_level", "af_hier_side_relations", "af_hier_side_mask",
+    "af_patch_step", "af_ghost_fill", "af_flux_correct", "af_regrid_tag", "af_hier_regrid",
+    "af_regrid_apply", "af_reduce_sum", "af_amr_coarse_step",
+]
+
+
+class af_problem(ctypes.Structure):
+    _fields_ = [("eq", ctypes.c_int32), ("prec", ctypes.c_int32), ("m", ctypes.c_int32),
+                ("n0x", ctypes.c_int32), ("n0y", ctypes.c_int32), ("lmax", ctypes.c_int32),
+                ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("lx", ctypes.c_double),
+                ("ly", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double),
+                ("c", ctypes.c_double)]
+
+
+class af_state(ctypes.Structure):
+    _fields_ = [("dof", ctypes.c_void_p * 4), ("npatch", ctypes.c_int32), ("pitch", ctypes.c_int32)]
+
+
+class AFError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2205_07572_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    D = ctypes.c_double
+    S = ctypes.POINTER(af_state)
+    L.af_last_error.restype = ctypes.c_char_p
+    L.af_ctx_create.argtypes = [ctypes.POINTER(af_problem), ctypes.POINTER(P)]
+    L.af_ctx_destroy.argtypes = [P]
+    L.af_ctx_set_tile.argtypes = [P, i32]
+    L.af_ctx_get_tile.argtypes = [P]
+    L.af_ctx_get_tile.restype = i32
+    L.af_hier_create.argtypes = [P, i32, P, P, P, ctypes.POINTER(P)]
+    L.af_hier_destroy.argtypes = [P]
+    L.af_hier_num_leaves.argtypes = [P]
+    L.af_hier_num_leaves.restype = i32
+    L.af_hier_get_leaves.argtypes = [P, P, P, P]
+    L.af_hier_level_range.argtypes = [P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.af_hier_finest_level.argtypes = [P]
+    L.af_hier_finest_level.restype = i32
+    L.af_hier_side_relations.argtypes = [P, P]
+    L.af_hier_side_mask.argtypes = [P]
+    L.af_hier_side_mask.restype = P
+    L.af_patch_step.argtypes = [P, S, S, i32, i32, i32, D, i32, P, P, P]
+    L.af_ghost_fill.argtypes = [P, P, S, ctypes.c_uint32, i32, i32, P]
+    L.af_flux_correct.argtypes = [P, P, S, ctypes.c_uint32, i32, P, P]
+    L.af_regrid_tag.argtypes = [P, P, S, ctypes.c_uint32, i32, i32, D, D, P, P, P]
+    L.af_hier_regrid.argtypes = [P, P, P, ctypes.POINTER(P)]
+    L.af_regrid_apply.argtypes = [P, P, S, ctypes.c_uint32, P, S, P]
+    L.af_reduce_sum.argtypes = [P, P, S, ctypes.c_uint32, P, P]
+    L.af_amr_coarse_step.argtypes = [P, P, S, ctypes.POINTER(ctypes.c_uint32), D, P, i32, P]
+    for name in EXPORTS:
+        if name not in ("af_last_error", "af_hier_num_leaves", "af_ctx_get_tile", "af_hier_finest_level",
+                        "af_hier_side_mask"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def check(status):
+    if status != AF_OK:
+        msg = load().af_last_error()
+        raise AFError(status, msg.decode() if msg else "")

@@ -1,0 +1,639 @@
+// af_api.cpp -- C ABI of libaf.so (declared in include/af.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "af.h"
+#include "af_hier.h"
+#include "af_internal.h"
+#include "af_launch.h"
+#include "af_weights.h"
+
+using namespace af;
+
+namespace {
+
+thread_local std::string g_err;
+
+af_status fail(af_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define AF_HIP(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess) return fail(AF_ERR_DEVICE, std::string(#call ": ") + hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+struct af_ctx {
+  af_problem P;
+  int ncomp;
+  int ty = 0;  // step tile height (rows per block)
+  // fill-set entries of one patch block (device)
+  std::vector<int32_t> h_entries;
+  int32_t* d_entries = nullptr;  // uploaded on first device use
+  int nentries = 0;
+  // reduction workspace
+  double* d_part = nullptr;
+  int part_cap = 0;
+  // weights cache keyed by (dt/dx, dt/dy)
+  std::map<std::pair<double, double>, std::vector<unsigned char>> wcache;
+
+  double dx(int l) const { return P.lx / double(P.n0x * P.m) / double(1 << l); }
+  double dy(int l) const { return P.ly / double(P.n0y * P.m) / double(1 << l); }
+  bool fp32() const { return P.prec == AF_FP32; }
+  size_t elem() const { return fp32() ? 4 : 8; }
+};
+
+struct GraphKey {
+  uint32_t mask;
+  double dt0;
+  const void* b0;
+  const void* b1;
+  const double* reg;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(mask, dt0, b0, b1, reg) < std::tie(o.mask, o.dt0, o.b0, o.b1, o.reg);
+  }
+};
+
+struct af_hier {
+  af_ctx* ctx = nullptr;
+  Hier H;
+  int32_t* d_lut = nullptr;
+  int32_t* d_level = nullptr;
+  int32_t* d_ix = nullptr;
+  int32_t* d_iy = nullptr;
+  uint8_t* d_side_mask = nullptr;
+  CFFace* d_faces = nullptr;
+  std::vector<int> face_off;  // per coarse level offset into d_faces
+  std::vector<CFFace> all_faces;
+  bool on_device = false;     // tables are uploaded on first device use
+  HierDev dev{};
+  std::map<GraphKey, hipGraphExec_t> graphs;
+};
+
+namespace {
+
+template <typename T>
+T* dev_upload(const std::vector<T>& v, hipError_t* err) {
+  T* p = nullptr;
+  const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
+  *err = hipMalloc(&p, bytes);
+  if (*err != hipSuccess) return nullptr;
+  if (!v.empty()) *err = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return p;
+}
+
+af_status check_state(const af_ctx* c, const af_state* s, int need_patches, const char* what) {
+  if (!s) return fail(AF_ERR_ARG, std::string(what) + ": null state");
+  for (int k = 0; k < 4; ++k)
+    if (!s->dof[k]) return fail(AF_ERR_ARG, std::string(what) + ": null DOF array");
+  if (s->pitch < c->P.m + 5) return fail(AF_ERR_LAYOUT, std::string(what) + ": pitch < m+5");
+  if (s->npatch < need_patches) return fail(AF_ERR_LAYOUT, std::string(what) + ": state holds too few patches");
+  for (int k = 0; k < 4; ++k)
+    if (reinterpret_cast<uintptr_t>(s->dof[k]) % c->elem() != 0)
+      return fail(AF_ERR_LAYOUT, std::string(what) + ": misaligned DOF array");
+  return AF_OK;
+}
+
+af_status check_cfl(const af_ctx* c, int level, double dt) {
+  if (!(dt >= 0.0) || !std::isfinite(dt)) return fail(AF_ERR_ARG, "dt must be finite and >= 0");
+  const double dx = c->dx(level), dy = c->dy(level);
+  if (c->P.eq == AF_ADVECTION) {
+    const double cfl = std::max(std::fabs(c->P.a) * dt / dx, std::fabs(c->P.b) * dt / dy);
+    if (cfl > 1.0 + 1e-12) return fail(AF_ERR_CFL, "advection CFL > 1 (eq. cfl-adv)");
+  } else {
+    const double cfl = c->P.c * dt / std::min(dx, dy);
+    if (cfl > 0.5 + 1e-12) return fail(AF_ERR_CFL, "acoustic CFL > 1/2 (eq. cfl-acoustics)");
+  }
+  return AF_OK;
+}
+
+const void* weights_for(af_ctx* c, double dtdx, double dtdy) {
+  auto key = std::make_pair(dtdx, dtdy);
+  auto it = c->wcache.find(key);
+  if (it != c->wcache.end()) return it->second.data();
+  std::vector<unsigned char> buf;
+  if (c->P.eq == AF_ADVECTION) {
+    if (c->fp32()) {
+      buf.resize(sizeof(AdvWeights<float>));
+      make_adv_weights<float>(c->P.a * dtdx, c->P.b * dtdy, reinterpret_cast<AdvWeights<float>*>(buf.data()));
+    } else {
+      buf.resize(sizeof(AdvWeights<double>));
+      make_adv_weights<double>(c->P.a * dtdx, c->P.b * dtdy, reinterpret_cast<AdvWeights<double>*>(buf.data()));
+    }
+  } else {
+    if (c->fp32()) {
+      buf.resize(sizeof(AcWeights<float>));
+      make_ac_weights<float>(c->P.c * dtdx, c->P.c * dtdy, reinterpret_cast<AcWeights<float>*>(buf.data()));
+    } else {
+      buf.resize(sizeof(AcWeights<double>));
+      make_ac_weights<double>(c->P.c * dtdx, c->P.c * dtdy, reinterpret_cast<AcWeights<double>*>(buf.data()));
+    }
+  }
+  auto res = c->wcache.emplace(key, std::move(buf));
+  return res.first->second.data();
+}
+
+BufLaunch make_buf(const af_ctx* c, const af_state* b0, const af_state* b1, uint32_t mask) {
+  BufLaunch B;
+  for (int k = 0; k < 4; ++k) {
+    B.p[0][k] = b0->dof[k];
+    B.p[1][k] = b1->dof[k];
+  }
+  B.npatch = b0->npatch;
+  B.pitch = b0->pitch;
+  B.m = c->P.m;
+  B.ncomp = c->ncomp;
+  B.mask = mask;
+  return B;
+}
+
+af_status ctx_device(af_ctx* c) {
+  if (c->d_entries) return AF_OK;
+  hipError_t err;
+  c->d_entries = dev_upload(c->h_entries, &err);
+  if (err != hipSuccess) return fail(AF_ERR_DEVICE, std::string("fill table upload: ") + hipGetErrorString(err));
+  return AF_OK;
+}
+
+af_status hier_device(af_hier* h) {
+  if (h->on_device) return AF_OK;
+  const int n = int(h->H.leaves.size());
+  std::vector<int32_t> lv(n), vx(n), vy(n);
+  for (int k = 0; k < n; ++k) {
+    lv[k] = h->H.leaves[k].level;
+    vx[k] = h->H.leaves[k].ix;
+    vy[k] = h->H.leaves[k].iy;
+  }
+  hipError_t err;
+  h->d_lut = dev_upload(h->H.lut, &err);
+  if (err == hipSuccess) h->d_level = dev_upload(lv, &err);
+  if (err == hipSuccess) h->d_ix = dev_upload(vx, &err);
+  if (err == hipSuccess) h->d_iy = dev_upload(vy, &err);
+  if (err == hipSuccess) h->d_side_mask = dev_upload(h->H.side_mask, &err);
+  if (err == hipSuccess) h->d_faces = dev_upload(h->all_faces, &err);
+  if (err != hipSuccess) return fail(AF_ERR_DEVICE, std::string("hierarchy upload: ") + hipGetErrorString(err));
+  HierDev& D = h->dev;
+  D.lut = h->d_lut;
+  D.plevel = h->d_level;
+  D.pix = h->d_ix;
+  D.piy = h->d_iy;
+  for (int l = 0; l < kMaxLevels; ++l) D.lut_off[l] = (l <= h->H.lmax) ? h->H.lut_off[l] : 0;
+  D.npx0 = h->H.n0x;
+  D.npy0 = h->H.n0y;
+  D.lmax = h->H.lmax;
+  D.nleaves = n;
+  h->on_device = true;
+  return AF_OK;
+}
+
+af_status check_pair(const af_ctx* c, const af_hier* h, const af_state* bufs, const char* what) {
+  if (!bufs) return fail(AF_ERR_ARG, std::string(what) + ": null buffers");
+  const int n = int(h->H.leaves.size());
+  af_status s = check_state(c, &bufs[0], n, what);
+  if (s != AF_OK) return s;
+  s = check_state(c, &bufs[1], n, what);
+  if (s != AF_OK) return s;
+  if (bufs[0].npatch != bufs[1].npatch || bufs[0].pitch != bufs[1].pitch)
+    return fail(AF_ERR_LAYOUT, std::string(what) + ": the two buffers differ in layout");
+  return AF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* af_last_error(void) { return g_err.c_str(); }
+
+af_status af_ctx_create(const af_problem* prob, af_ctx** out) {
+  if (!prob || !out) return fail(AF_ERR_ARG, "null argument");
+  const af_problem& P = *prob;
+  if (P.eq != AF_ADVECTION && P.eq != AF_ACOUSTICS) return fail(AF_ERR_ARG, "unknown equation");
+  if (P.prec != AF_FP64 && P.prec != AF_FP32) return fail(AF_ERR_ARG, "unknown precision");
+  if (!(P.m == 8 || P.m == 16 || P.m == 32 || P.m == 64 || P.m == 128))
+    return fail(AF_ERR_ARG, "m must be 8, 16, 32, 64 or 128");
+  if (P.n0x < 1 || P.n0y < 1 || P.lmax < 0 || P.lmax >= kMaxLevels) return fail(AF_ERR_ARG, "bad patch counts or lmax");
+  if (!(P.lx > 0 && P.ly > 0)) return fail(AF_ERR_ARG, "domain extents must be positive");
+  if (P.eq == AF_ACOUSTICS && !(P.c > 0)) return fail(AF_ERR_ARG, "speed of sound must be positive");
+  auto c = std::make_unique<af_ctx>();
+  c->P = P;
+  c->ncomp = P.eq == AF_ACOUSTICS ? 3 : 1;
+  // default tile heights: about 256 cells per block, smaller for FP64 acoustics (LDS)
+  const bool big = (P.eq == AF_ACOUSTICS && P.prec == AF_FP64);
+  switch (P.m) {
+    case 8: c->ty = 8; break;
+    case 16: c->ty = big ? 8 : 16; break;
+    case 32: c->ty = big ? 4 : 8; break;
+    case 64: c->ty = big ? 2 : 4; break;
+    default: c->ty = 2; break;
+  }
+  // fill-set entries: every block DOF except interior averages and nodes
+  // strictly inside the interior square
+  std::vector<int32_t> ent;
+  const int m = P.m;
+  for (int kind = 0; kind < 4; ++kind) {
+    const int ihi = (kind == 0 || kind == 3) ? m + 1 : m + 2;
+    const int jhi = (kind == 0 || kind == 2) ? m + 1 : m + 2;
+    for (int j = -2; j <= jhi; ++j)
+      for (int i = -2; i <= ihi; ++i) {
+        bool inside;
+        if (kind == 0) inside = i >= 0 && i < m && j >= 0 && j < m;
+        else if (kind == 1) inside = i >= 1 && i <= m - 1 && j >= 1 && j <= m - 1;
+        else if (kind == 2) inside = i >= 1 && i <= m - 1 && j >= 0 && j <= m - 1;
+        else inside = i >= 0 && i <= m - 1 && j >= 1 && j <= m - 1;
+        if (!inside) ent.push_back((kind << 24) | ((i + 2) << 12) | (j + 2));
+      }
+  }
+  c->h_entries = std::move(ent);
+  c->nentries = int(c->h_entries.size());
+  *out = c.release();
+  return AF_OK;
+}
+
+af_status af_ctx_destroy(af_ctx* ctx) {
+  if (!ctx) return AF_OK;
+  (void)hipFree(ctx->d_entries);
+  (void)hipFree(ctx->d_part);
+  delete ctx;
+  return AF_OK;
+}
+
+af_status af_ctx_set_tile(af_ctx* ctx, int32_t ty) {
+  if (!ctx) return fail(AF_ERR_ARG, "null ctx");
+  if (!step_shape_supported(ctx->P.m, ty)) return fail(AF_ERR_ARG, "unsupported tile height for this m");
+  ctx->ty = ty;
+  return AF_OK;
+}
+
+int32_t af_ctx_get_tile(const af_ctx* ctx) { return ctx ? ctx->ty : -1; }
+
+// ----------------------------------------------------------------- hierarchy
+
+af_status af_hier_create(af_ctx* ctx, int32_t n, const int32_t* level, const int32_t* ix, const int32_t* iy,
+                         af_hier** out) {
+  if (!ctx || !out || n <= 0 || !level || !ix || !iy) return fail(AF_ERR_ARG, "bad hierarchy arguments");
+  auto h = std::make_unique<af_hier>();
+  h->ctx = ctx;
+  h->H.m = ctx->P.m;
+  h->H.n0x = ctx->P.n0x;
+  h->H.n0y = ctx->P.n0y;
+  h->H.lmax = ctx->P.lmax;
+  std::vector<Leaf> leaves(n);
+  for (int k = 0; k < n; ++k) leaves[k] = {level[k], ix[k], iy[k]};
+  const std::string msg = h->H.build(leaves);
+  if (!msg.empty()) {
+    const bool bal = msg.find("balanced") != std::string::npos || msg.find("cover") != std::string::npos ||
+                     msg.find("overlap") != std::string::npos || msg.find("duplicate") != std::string::npos;
+    return fail(bal ? AF_ERR_BALANCE : AF_ERR_ARG, "af_hier_create: " + msg);
+  }
+  h->face_off.assign(h->H.lmax + 2, 0);
+  for (int l = 0; l <= h->H.lmax; ++l) {
+    h->face_off[l] = int(h->all_faces.size());
+    h->all_faces.insert(h->all_faces.end(), h->H.faces[l].begin(), h->H.faces[l].end());
+  }
+  h->face_off[h->H.lmax + 1] = int(h->all_faces.size());
+  *out = h.release();
+  return AF_OK;
+}
+
+af_status af_hier_destroy(af_hier* h) {
+  if (!h) return AF_OK;
+  for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
+  (void)hipFree(h->d_lut);
+  (void)hipFree(h->d_level);
+  (void)hipFree(h->d_ix);
+  (void)hipFree(h->d_iy);
+  (void)hipFree(h->d_side_mask);
+  (void)hipFree(h->d_faces);
+  delete h;
+  return AF_OK;
+}
+
+int32_t af_hier_num_leaves(const af_hier* h) { return h ? int32_t(h->H.leaves.size()) : -1; }
+
+af_status af_hier_get_leaves(const af_hier* h, int32_t* level, int32_t* ix, int32_t* iy) {
+  if (!h || !level || !ix || !iy) return fail(AF_ERR_ARG, "null argument");
+  for (size_t k = 0; k < h->H.leaves.size(); ++k) {
+    level[k] = h->H.leaves[k].level;
+    ix[k] = h->H.leaves[k].ix;
+    iy[k] = h->H.leaves[k].iy;
+  }
+  return AF_OK;
+}
+
+af_status af_hier_level_range(const af_hier* h, int32_t level, int32_t* first, int32_t* count) {
+  if (!h || !first || !count) return fail(AF_ERR_ARG, "null argument");
+  if (level < 0 || level > h->H.lmax) {
+    *first = 0;
+    *count = 0;
+    return AF_OK;
+  }
+  *count = h->H.level_count[level];
+  *first = h->H.level_count[level] ? h->H.level_first[level] : 0;
+  return AF_OK;
+}
+
+int32_t af_hier_finest_level(const af_hier* h) { return h ? h->H.finest : -1; }
+
+af_status af_hier_side_relations(const af_hier* h, int8_t* rel) {
+  if (!h || !rel) return fail(AF_ERR_ARG, "null argument");
+  std::memcpy(rel, h->H.rel.data(), h->H.rel.size());
+  return AF_OK;
+}
+
+const uint8_t* af_hier_side_mask(const af_hier* h) {
+  if (!h || hier_device(const_cast<af_hier*>(h)) != AF_OK) return nullptr;
+  return h->d_side_mask;
+}
+
+// ----------------------------------------------------------------- step
+
+af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t first, int32_t count,
+                        int32_t level, double dt, int32_t region, double* flux_reg, const uint8_t* side_mask,
+                        hipStream_t stream) {
+  if (!ctx) return fail(AF_ERR_ARG, "null ctx");
+  if (count < 0 || first < 0) return fail(AF_ERR_ARG, "negative patch range");
+  if (region != AF_REGION_INTERIOR && region != AF_REGION_LAYER1) return fail(AF_ERR_ARG, "bad region");
+  if (level < 0 || level > ctx->P.lmax) return fail(AF_ERR_ARG, "level out of range");
+  af_status s = check_state(ctx, in, first + count, "af_patch_step(in)");
+  if (s != AF_OK) return s;
+  s = check_state(ctx, out, first + count, "af_patch_step(out)");
+  if (s != AF_OK) return s;
+  if (in->pitch != out->pitch || in->npatch != out->npatch)
+    return fail(AF_ERR_LAYOUT, "af_patch_step: in and out differ in layout");
+  for (int k = 0; k < 4; ++k)
+    if (in->dof[k] == out->dof[k]) return fail(AF_ERR_ARG, "af_patch_step: in and out must be distinct");
+  s = check_cfl(ctx, level, dt);
+  if (s != AF_OK) return s;
+  if (count == 0) return AF_OK;
+  const double dx = ctx->dx(level), dy = ctx->dy(level);
+  StepLaunch L;
+  L.fp32 = ctx->fp32();
+  L.eq = ctx->P.eq;
+  L.m = ctx->P.m;
+  L.ty = ctx->ty;
+  for (int k = 0; k < 4; ++k) {
+    L.in[k] = in->dof[k];
+    L.out[k] = out->dof[k];
+  }
+  L.npatch = in->npatch;
+  L.pitch = in->pitch;
+  L.first = first;
+  L.count = count;
+  L.region = region;
+  L.dtdx = dt / dx;
+  L.dtdy = dt / dy;
+  L.a = ctx->P.a;
+  L.b = ctx->P.b;
+  L.c = ctx->P.c;
+  L.len_dt_x = dy * dt;
+  L.len_dt_y = dx * dt;
+  L.reg = flux_reg;
+  L.side_mask = flux_reg ? side_mask : nullptr;
+  L.weights = weights_for(ctx, dt / dx, dt / dy);
+  AF_HIP(launch_patch_step(L, stream));
+  return AF_OK;
+}
+
+// ----------------------------------------------------------------- fill etc.
+
+af_status af_ghost_fill(af_ctx* ctx, const af_hier* h, af_state* bufs, uint32_t mask, int32_t tmin, int32_t smin,
+                        hipStream_t stream) {
+  if (!ctx || !h) return fail(AF_ERR_ARG, "null argument");
+  af_status s = check_pair(ctx, h, bufs, "af_ghost_fill");
+  if (s != AF_OK) return s;
+  if (tmin < 0 || smin < 0) return fail(AF_ERR_ARG, "negative level bound");
+  int first = -1;
+  for (int l = tmin; l <= h->H.lmax && first < 0; ++l)
+    if (h->H.level_count[l]) first = h->H.level_first[l];
+  if (first < 0) return AF_OK;
+  if ((s = ctx_device(ctx)) != AF_OK || (s = hier_device(const_cast<af_hier*>(h))) != AF_OK) return s;
+  // the coarse->fine phase is needed only if some target level has leaves
+  // one level down that may serve as sources
+  bool need_b = false;
+  for (int l = std::max(tmin, 1); l <= h->H.lmax; ++l)
+    if (h->H.level_count[l] && h->H.level_count[l - 1] && l - 1 >= smin) need_b = true;
+  const int n = int(h->H.leaves.size()) - first;
+  AF_HIP(launch_ghost_fill(ctx->fp32(), make_buf(ctx, &bufs[0], &bufs[1], mask), h->dev, ctx->d_entries,
+                           ctx->nentries, first, n, tmin, smin, need_b, stream));
+  return AF_OK;
+}
+
+af_status af_flux_correct(af_ctx* ctx, const af_hier* h, af_state* bufs, uint32_t mask, int32_t level,
+                          double* flux_reg, hipStream_t stream) {
+  if (!ctx || !h || !flux_reg) return fail(AF_ERR_ARG, "null argument");
+  af_status s = check_pair(ctx, h, bufs, "af_flux_correct");
+  if (s != AF_OK) return s;
+  if (level < 0 || level > h->H.lmax) return fail(AF_ERR_ARG, "level out of range");
+  if ((s = hier_device(const_cast<af_hier*>(h))) != AF_OK) return s;
+  const int off = h->face_off[level], nf = h->face_off[level + 1] - off;
+  const double inv_area = 1.0 / (ctx->dx(level) * ctx->dy(level));
+  AF_HIP(launch_flux_correct(ctx->fp32(), make_buf(ctx, &bufs[0], &bufs[1], mask), h->d_faces + off, nf, flux_reg,
+                             level, inv_area, stream));
+  return AF_OK;
+}
+
+af_status af_regrid_tag(af_ctx* ctx, const af_hier* h, const af_state* bufs, uint32_t mask, int32_t mode,
+                        int32_t comp, double theta_r, double theta_c, int8_t* tags, double* values,
+                        hipStream_t stream) {
+  if (!ctx || !h || !tags) return fail(AF_ERR_ARG, "null argument");
+  af_status s = check_pair(ctx, h, bufs, "af_regrid_tag");
+  if (s != AF_OK) return s;
+  if (mode != AF_TAG_GRADIENT && mode != AF_TAG_MAXMIN) return fail(AF_ERR_ARG, "bad tag mode");
+  if (comp < 0 || comp >= ctx->ncomp) return fail(AF_ERR_ARG, "component out of range");
+  if ((s = hier_device(const_cast<af_hier*>(h))) != AF_OK) return s;
+  AF_HIP(launch_tag(ctx->fp32(), make_buf(ctx, &bufs[0], &bufs[1], mask), h->dev, mode, comp,
+                    1.0 / (2.0 * ctx->dx(0)), 1.0 / (2.0 * ctx->dy(0)), theta_r, theta_c, tags, values, stream));
+  return AF_OK;
+}
+
+af_status af_hier_regrid(af_ctx* ctx, const af_hier* old, const int8_t* tags, af_hier** out) {
+  if (!ctx || !old || !tags || !out) return fail(AF_ERR_ARG, "null argument");
+  const std::vector<Leaf> nl = old->H.regrid(tags);
+  std::vector<int32_t> lv(nl.size()), vx(nl.size()), vy(nl.size());
+  for (size_t k = 0; k < nl.size(); ++k) {
+    lv[k] = nl[k].level;
+    vx[k] = nl[k].ix;
+    vy[k] = nl[k].iy;
+  }
+  return af_hier_create(ctx, int32_t(nl.size()), lv.data(), vx.data(), vy.data(), out);
+}
+
+af_status af_regrid_apply(af_ctx* ctx, const af_hier* old, const af_state* old_bufs, uint32_t old_mask,
+                          const af_hier* nh, af_state* dst, hipStream_t stream) {
+  if (!ctx || !old || !nh || !dst) return fail(AF_ERR_ARG, "null argument");
+  af_status s = check_pair(ctx, old, old_bufs, "af_regrid_apply(old)");
+  if (s != AF_OK) return s;
+  s = check_state(ctx, dst, int(nh->H.leaves.size()), "af_regrid_apply(dst)");
+  if (s != AF_OK) return s;
+  if (dst->pitch != old_bufs[0].pitch) return fail(AF_ERR_LAYOUT, "af_regrid_apply: pitch differs");
+  for (int k = 0; k < 4; ++k)
+    if (dst->dof[k] == old_bufs[0].dof[k] || dst->dof[k] == old_bufs[1].dof[k])
+      return fail(AF_ERR_ARG, "af_regrid_apply: dst must differ from the old buffers");
+  std::vector<Transfer> tr(nh->H.leaves.size());
+  for (size_t k = 0; k < nh->H.leaves.size(); ++k) {
+    const Leaf& L = nh->H.leaves[k];
+    Transfer& X = tr[k];
+    X.qx = X.qy = 0;
+    for (int q = 0; q < 4; ++q) X.src[q] = -1;
+    const int same = old->H.find(L.level, L.ix, L.iy);
+    if (same >= 0) {
+      X.mode = 0;
+      X.src[0] = same;
+      continue;
+    }
+    const int par = L.level > 0 ? old->H.find(L.level - 1, L.ix >> 1, L.iy >> 1) : -1;
+    if (par >= 0) {
+      X.mode = 1;
+      X.src[0] = par;
+      X.qx = L.ix & 1;
+      X.qy = L.iy & 1;
+      continue;
+    }
+    X.mode = 2;
+    for (int q = 0; q < 4; ++q) {
+      X.src[q] = old->H.find(L.level + 1, 2 * L.ix + (q & 1), 2 * L.iy + (q >> 1));
+      if (X.src[q] < 0) return fail(AF_ERR_STATE, "af_regrid_apply: new leaf is not a copy, child or parent of old leaves");
+    }
+  }
+  if ((s = hier_device(const_cast<af_hier*>(old))) != AF_OK) return s;
+  hipError_t err;
+  Transfer* d_tr = dev_upload(tr, &err);
+  if (err != hipSuccess) return fail(AF_ERR_DEVICE, "transfer table upload");
+  HierDev HO = old->dev;
+  BufLaunch ob = make_buf(ctx, &old_bufs[0], &old_bufs[1], old_mask);
+  BufLaunch nb = make_buf(ctx, dst, dst, 0);
+  err = launch_transfer(ctx->fp32(), ob, HO, nb, d_tr, int(tr.size()), stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(stream);
+  (void)hipFree(d_tr);
+  if (err != hipSuccess) return fail(AF_ERR_DEVICE, std::string("transfer: ") + hipGetErrorString(err));
+  return AF_OK;
+}
+
+af_status af_reduce_sum(af_ctx* ctx, const af_hier* h, const af_state* bufs, uint32_t mask, double* out,
+                        hipStream_t stream) {
+  if (!ctx || !h || !out) return fail(AF_ERR_ARG, "null argument");
+  af_status s = check_pair(ctx, h, bufs, "af_reduce_sum");
+  if (s != AF_OK) return s;
+  if ((s = hier_device(const_cast<af_hier*>(h))) != AF_OK) return s;
+  const int n = int(h->H.leaves.size());
+  if (ctx->part_cap < n * ctx->ncomp) {
+    (void)hipFree(ctx->d_part);
+    ctx->d_part = nullptr;
+    AF_HIP(hipMalloc(&ctx->d_part, size_t(n) * ctx->ncomp * sizeof(double)));
+    ctx->part_cap = n * ctx->ncomp;
+  }
+  AF_HIP(launch_sum(ctx->fp32(), make_buf(ctx, &bufs[0], &bufs[1], mask), h->dev, ctx->dx(0) * ctx->dy(0),
+                    ctx->d_part, out, stream));
+  return AF_OK;
+}
+
+// ----------------------------------------------------------------- AMR driver
+
+namespace {
+
+struct Driver {
+  af_ctx* ctx;
+  af_hier* h;
+  af_state* bufs;
+  uint32_t mask;
+  double* reg;
+  hipStream_t st;
+
+  af_status step_level(int l, double dt, int region) {
+    int first, count;
+    af_hier_level_range(h, l, &first, &count);
+    const int cur = (mask >> l) & 1;
+    // an empty level still flips, so that the mask after a coarse step is
+    // always "bit 0 flipped"
+    mask ^= (1u << l);
+    if (count == 0) return AF_OK;
+    return af_patch_step(ctx, &bufs[cur], &bufs[cur ^ 1], first, count, l, dt, region, reg,
+                         h->d_side_mask, st);
+  }
+
+  af_status advance(int l, double dt, bool first_of_pair, int finest) {
+    af_status s = step_level(l, dt, (l > 0 && first_of_pair) ? AF_REGION_LAYER1 : AF_REGION_INTERIOR);
+    if (s != AF_OK) return s;
+    if (l + 1 <= finest) {
+      if ((s = advance(l + 1, 0.5 * dt, true, finest)) != AF_OK) return s;
+      if ((s = af_ghost_fill(ctx, h, bufs, mask, l + 1, l + 1, st)) != AF_OK) return s;
+      if ((s = advance(l + 1, 0.5 * dt, false, finest)) != AF_OK) return s;
+      int first, count;
+      af_hier_level_range(h, l, &first, &count);
+      if (count) {
+        if ((s = af_flux_correct(ctx, h, bufs, mask, l, reg, st)) != AF_OK) return s;
+      }
+    }
+    return AF_OK;
+  }
+
+  af_status coarse_step(double dt0) {
+    af_status s = af_ghost_fill(ctx, h, bufs, mask, 0, 0, st);
+    if (s != AF_OK) return s;
+    return advance(0, dt0, true, h->H.finest);
+  }
+};
+
+}  // namespace
+
+af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* mask, double dt0, double* flux_reg,
+                             int32_t use_graph, hipStream_t stream) {
+  if (!ctx || !h || !mask || !flux_reg) return fail(AF_ERR_ARG, "null argument");
+  af_status s = check_pair(ctx, h, bufs, "af_amr_coarse_step");
+  if (s != AF_OK) return s;
+  // every level's CFL is that of level 0 (dt_l / dx_l fixed)
+  s = check_cfl(ctx, 0, dt0);
+  if (s != AF_OK) return s;
+  if ((s = ctx_device(ctx)) != AF_OK || (s = hier_device(h)) != AF_OK) return s;
+  Driver D{ctx, h, bufs, *mask, flux_reg, stream};
+  if (!use_graph) {
+    s = D.coarse_step(dt0);
+    if (s == AF_OK) *mask = D.mask;
+    return s;
+  }
+  const GraphKey key{*mask, dt0, bufs[0].dof[0], bufs[1].dof[0], flux_reg};
+  auto it = h->graphs.find(key);
+  if (it == h->graphs.end()) {
+    // weights are computed on the host outside the capture
+    for (int l = 0; l <= h->H.finest; ++l) weights_for(ctx, dt0 / (1 << l) / ctx->dx(l), dt0 / (1 << l) / ctx->dy(l));
+    hipStream_t cs;
+    AF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      return fail(AF_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(e));
+    }
+    Driver G{ctx, h, bufs, *mask, flux_reg, cs};
+    s = G.coarse_step(dt0);
+    e = hipStreamEndCapture(cs, &g);
+    (void)hipStreamDestroy(cs);
+    if (s != AF_OK) return s;
+    if (e != hipSuccess) return fail(AF_ERR_DEVICE, std::string("end capture: ") + hipGetErrorString(e));
+    hipGraphExec_t ex;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(AF_ERR_DEVICE, std::string("instantiate: ") + hipGetErrorString(e));
+    it = h->graphs.emplace(key, ex).first;
+  }
+  AF_HIP(hipGraphLaunch(it->second, stream));
+  // the mask after a coarse step: level 0 flips, finer levels take an even
+  // number of steps
+  *mask ^= 1u;
+  return AF_OK;
+}
+
+}  // extern "C"

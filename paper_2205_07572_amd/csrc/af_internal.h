@@ -1,0 +1,94 @@
+// af_internal.h -- definitions shared by the library's host code and its
+// HIP kernels (never by anything outside libaf.so).
+#pragma once
+
+#include <cstdint>
+#include <cstddef>
+
+namespace af {
+
+constexpr int kGhost = 2;          // two ghost layers (Sec. 3.2)
+constexpr int kMaxLevels = 13;     // levels 0..12
+constexpr int kThreads = 256;      // block size of every kernel (4 wave64)
+
+// Raw DOFs of one cell in the order used by every stencil table:
+// 0 avg, 1 corner(i,j), 2 corner(i+1,j), 3 corner(i,j+1), 4 corner(i+1,j+1),
+// 5 xedge(i,j), 6 xedge(i+1,j), 7 yedge(i,j), 8 yedge(i,j+1).
+constexpr int kCellDofs = 9;
+
+// Node kinds (also the af.h AF_CORNER/AF_XEDGE/AF_YEDGE indices minus one).
+enum NodeKind { NK_CORNER = 0, NK_XEDGE = 1, NK_YEDGE = 2 };
+
+// Neighbourhood of raw DOFs entering the acoustic evolution of a node owned
+// by cell (i,j): the union of the raw DOFs of the cells adjacent to the node
+// (four for a corner, two for an edge midpoint).  Each entry is
+// (state kind 0..3, di, dj) relative to (i,j).
+struct NbEntry {
+  int8_t kind, di, dj;
+};
+constexpr int kNbCorner = 25;
+constexpr int kNbEdge = 15;
+
+// corner (i,j): cells (i-1..i, j-1..j)
+constexpr NbEntry kNbCornerTab[kNbCorner] = {
+    {0, -1, -1}, {0, 0, -1}, {0, -1, 0}, {0, 0, 0},
+    {1, -1, -1}, {1, 0, -1}, {1, 1, -1}, {1, -1, 0}, {1, 0, 0}, {1, 1, 0},
+    {1, -1, 1}, {1, 0, 1}, {1, 1, 1},
+    {2, -1, -1}, {2, 0, -1}, {2, 1, -1}, {2, -1, 0}, {2, 0, 0}, {2, 1, 0},
+    {3, -1, -1}, {3, 0, -1}, {3, -1, 0}, {3, 0, 0}, {3, -1, 1}, {3, 0, 1}};
+// xedge (i,j): cells (i-1,j), (i,j)
+constexpr NbEntry kNbXedgeTab[kNbEdge] = {
+    {0, -1, 0}, {0, 0, 0},
+    {1, -1, 0}, {1, 0, 0}, {1, 1, 0}, {1, -1, 1}, {1, 0, 1}, {1, 1, 1},
+    {2, -1, 0}, {2, 0, 0}, {2, 1, 0},
+    {3, -1, 0}, {3, 0, 0}, {3, -1, 1}, {3, 0, 1}};
+// yedge (i,j): cells (i,j-1), (i,j)
+constexpr NbEntry kNbYedgeTab[kNbEdge] = {
+    {0, 0, -1}, {0, 0, 0},
+    {1, 0, -1}, {1, 1, -1}, {1, 0, 0}, {1, 1, 0}, {1, 0, 1}, {1, 1, 1},
+    {2, 0, -1}, {2, 1, -1}, {2, 0, 0}, {2, 1, 0},
+    {3, 0, -1}, {3, 0, 0}, {3, 0, 1}};
+
+// Stencil weights of one level's step (same on every level under 2:1
+// subcycling, since dt/dx is fixed).  Index [kind][tau] with tau 0 = dt/2,
+// 1 = dt.
+template <typename T>
+struct AdvWeights {
+  T w[3][2][kCellDofs];     // weights of the source cell's raw DOFs
+  int32_t off[3][2][2];     // source cell offset (di, dj) from the owner cell
+};
+
+// Acoustics: p = K.p - Dx.u - Dy.v ; u = K.u - Dx.p ; v = K.v - Dy.p
+// (eq. ERFormula: K is M_R + R d/dR M_R, Dx and Dy are R M_R of the x- and
+// y-derivative), each a vector over the node's neighbourhood.
+template <typename T>
+struct AcWeights {
+  T corner[2][3][kNbCorner];  // [tau][K,Dx,Dy][entry]
+  T xedge[2][3][kNbEdge];
+  T yedge[2][3][kNbEdge];
+};
+
+// Device tables of a hierarchy.
+struct HierDev {
+  const int32_t* lut;        // per-level dense patch lookup: leaf id or -1
+  const int32_t* plevel;     // [nleaves]
+  const int32_t* pix;
+  const int32_t* piy;
+  int32_t lut_off[kMaxLevels];
+  int32_t npx0, npy0, lmax, nleaves;
+};
+
+// Coarse-fine face for the conservative fix, grouped by coarse cell.
+struct CFFace {
+  int32_t coarse, side, k;   // coarse leaf, side (W,E,S,N), cell index along the side
+  int32_t fine, fk;          // fine leaf facing it, index of the first of two fine faces
+};
+
+// Regrid transfer descriptor for one new leaf.
+struct Transfer {
+  int32_t mode;       // 0 copy, 1 refine from parent, 2 coarsen from children
+  int32_t src[4];     // old leaf ids (copy/refine: src[0]; coarsen: child (qy*2+qx))
+  int32_t qx, qy;     // refine: quadrant of the parent
+};
+
+}  // namespace af

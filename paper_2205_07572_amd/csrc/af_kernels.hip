@@ -1,0 +1,788 @@
+// af_kernels.hip -- gfx950 kernels of the Active Flux patch-step library.
+//
+// Every kernel uses 256-thread blocks (four 64-wide wavefronts).  State
+// arrays are structure-of-arrays: four DOF kinds, each [ncomp][npatch]
+// [m+5][pitch] (see include/af.h).
+#include <hip/hip_runtime.h>
+
+#include "af_internal.h"
+#include "af_launch.h"
+
+namespace af {
+
+// ---------------------------------------------------------------------------
+// Patch step (Sec. 2): reconstruction + point-value evolution + Simpson flux
+// + conservative update, for a tile of TY rows of one patch.
+//
+// A block stages rows [jlo-1, jhi+1] x cols [ilo-1, ihi+1] of all four DOF
+// kinds in LDS, evaluates the owned point values of the "extended" cells
+// [ilo,ihi] x [jlo,jhi] at t+dt/2 and t+dt, keeps their Simpson time sums
+// (n + 4 (n+1/2) + (n+1)) in LDS, and updates the averages of cells
+// [ilo,ihi) x [jlo,jhi) from the face fluxes.  Face fluxes are formed by one
+// helper from the same LDS operands on both sides of a face, so neighbouring
+// cells (and neighbouring patches) see bitwise-identical fluxes.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct StepArgs {
+  const T* in[4];
+  T* out[4];
+  int32_t npatch, pitch, first, region;
+  T dtdx, dtdy;            // dt/dx, dt/dy
+  T a, b, c;               // physics
+  double len_dt_x;         // dy * dt (x-faces)
+  double len_dt_y;         // dx * dt (y-faces)
+  double* reg;             // [npatch][4][M][ncomp] or null
+  const uint8_t* side_mask;
+};
+
+template <typename T, int NCOMP, int NR, int NC>
+struct StepLds {
+  T in[4][NCOMP][NR][NC];
+  T tsum[3][NCOMP][NR - 2][NC - 2];
+};
+
+// Simpson space-time sum of one face from the time sums of its three nodes
+// (eq. Simpson-2d without the 1/36 and the flux function).
+template <typename T>
+__device__ __forceinline__ T face_sum(T lo, T mid, T hi) {
+  return (lo + T(4) * mid) + hi;
+}
+
+template <typename T, int NR, int NC>
+__device__ __forceinline__ T adv_eval(const T (&s)[4][1][NR][NC], int r, int c, const T* w) {
+  // raw-DOF order of af_internal.h: avg, corners ll, rl, lu, ru, xedges l, r, yedges b, t
+  T v = w[0] * s[0][0][r][c];
+  v += w[1] * s[1][0][r][c];
+  v += w[2] * s[1][0][r][c + 1];
+  v += w[3] * s[1][0][r + 1][c];
+  v += w[4] * s[1][0][r + 1][c + 1];
+  v += w[5] * s[2][0][r][c];
+  v += w[6] * s[2][0][r][c + 1];
+  v += w[7] * s[3][0][r][c];
+  v += w[8] * s[3][0][r + 1][c];
+  return v;
+}
+
+// Acoustic node evaluation over a fixed neighbourhood table.
+template <typename T, int NR, int NC, int NB>
+__device__ __forceinline__ void ac_eval(const T (&s)[4][3][NR][NC], int r, int c,
+                                        const NbEntry (&tab)[NB], const T (&w)[2][3][NB],
+                                        T out[2][3]) {
+  T p[NB], u[NB], v[NB];
+#pragma unroll
+  for (int e = 0; e < NB; ++e) {
+    const int k = tab[e].kind, rr = r + tab[e].dj, cc = c + tab[e].di;
+    p[e] = s[k][0][rr][cc];
+    u[e] = s[k][1][rr][cc];
+    v[e] = s[k][2][rr][cc];
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    T kp = 0, ku = 0, kv = 0, dxu = 0, dyv = 0, dxp = 0, dyp = 0;
+#pragma unroll
+    for (int e = 0; e < NB; ++e) {
+      kp += w[t][0][e] * p[e];
+      ku += w[t][0][e] * u[e];
+      kv += w[t][0][e] * v[e];
+      dxu += w[t][1][e] * u[e];
+      dyv += w[t][2][e] * v[e];
+      dxp += w[t][1][e] * p[e];
+      dyp += w[t][2][e] * p[e];
+    }
+    out[t][0] = kp - dxu - dyv;
+    out[t][1] = ku - dxp;
+    out[t][2] = kv - dyp;
+  }
+}
+
+template <typename T, int EQ>
+struct WSel;
+template <typename T>
+struct WSel<T, 0> { using type = AdvWeights<T>; };
+template <typename T>
+struct WSel<T, 1> { using type = AcWeights<T>; };
+
+template <typename T, int EQ, int M, int TY>
+__global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
+                                                         const typename WSel<T, EQ>::type W) {
+  constexpr int NCOMP = EQ ? 3 : 1;
+  constexpr int NR = TY + 3;
+  constexpr int NC = M + 5;
+  __shared__ StepLds<T, NCOMP, NR, NC> L;
+
+  const int region = A.region;
+  const int ilo = -region, ihi = M + region;
+  const int span = ihi - ilo;
+  const int tiles = (span + TY - 1) / TY;
+  const int pl = blockIdx.x / tiles;
+  const int patch = A.first + pl;
+  const int tile = blockIdx.x - pl * tiles;
+  const int jlo = ilo + tile * TY;
+  const int jhi = min(jlo + TY, ihi);
+  const int nrow = jhi - jlo;
+  const int SR = nrow + 3, SC = span + 3;
+  const size_t plane = size_t(M + 5) * A.pitch;
+
+  // ---- stage rows j in [jlo-1, jhi+1], cols i in [ilo-1, ihi+1]
+  for (int e = threadIdx.x; e < 4 * NCOMP * SR * SC; e += kThreads) {
+    const int cc = e % SC;
+    int t = e / SC;
+    const int rr = t % SR;
+    t /= SR;
+    const int comp = t % NCOMP, kind = t / NCOMP;
+    const int i = ilo - 1 + cc, j = jlo - 1 + rr;
+    L.in[kind][comp][rr][cc] =
+        A.in[kind][(size_t(comp) * A.npatch + patch) * plane + size_t(j + kGhost) * A.pitch + (i + kGhost)];
+  }
+  __syncthreads();
+
+  // ---- point values of the extended cells [ilo, ihi] x [jlo, jhi]
+  const int EC = span + 1, ER = nrow + 1;
+  const bool last_tile = (jhi == ihi);
+  for (int e = threadIdx.x; e < EC * ER; e += kThreads) {
+    const int ii = e % EC, jj = e / EC;
+    const int i = ilo + ii, j = jlo + jj;
+    const int r = jj + 1, c = ii + 1;  // staged position of cell (i,j)
+    const bool wrow = (jj < nrow) || last_tile;
+    const bool has_x = jj < nrow;      // xedge (i,j) belongs to rows [jlo, jhi)
+    const bool has_y = ii < span;      // yedge (i,j) belongs to cols [ilo, ihi)
+    const size_t obase = size_t(j + kGhost) * A.pitch + (i + kGhost);
+    if constexpr (EQ == 0) {
+#pragma unroll
+      for (int kind = 0; kind < 3; ++kind) {
+        if (kind == NK_XEDGE && !has_x) continue;
+        if (kind == NK_YEDGE && !has_y) continue;
+        const T h = adv_eval<T, NR, NC>(L.in, r + W.off[kind][0][1], c + W.off[kind][0][0], W.w[kind][0]);
+        const T f = adv_eval<T, NR, NC>(L.in, r + W.off[kind][1][1], c + W.off[kind][1][0], W.w[kind][1]);
+        const T cur = L.in[kind + 1][0][r][c];
+        L.tsum[kind][0][jj][ii] = (cur + T(4) * h) + f;
+        if (wrow) A.out[kind + 1][size_t(patch) * plane + obase] = f;
+      }
+    } else {
+      T res[2][3];
+      ac_eval<T, NR, NC, kNbCorner>(L.in, r, c, kNbCornerTab, W.corner, res);
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        L.tsum[NK_CORNER][q][jj][ii] = (L.in[1][q][r][c] + T(4) * res[0][q]) + res[1][q];
+        if (wrow) A.out[1][(size_t(q) * A.npatch + patch) * plane + obase] = res[1][q];
+      }
+      if (has_x) {
+        ac_eval<T, NR, NC, kNbEdge>(L.in, r, c, kNbXedgeTab, W.xedge, res);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          L.tsum[NK_XEDGE][q][jj][ii] = (L.in[2][q][r][c] + T(4) * res[0][q]) + res[1][q];
+          A.out[2][(size_t(q) * A.npatch + patch) * plane + obase] = res[1][q];
+        }
+      }
+      if (has_y) {
+        ac_eval<T, NR, NC, kNbEdge>(L.in, r, c, kNbYedgeTab, W.yedge, res);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          L.tsum[NK_YEDGE][q][jj][ii] = (L.in[3][q][r][c] + T(4) * res[0][q]) + res[1][q];
+          if (wrow) A.out[3][(size_t(q) * A.npatch + patch) * plane + obase] = res[1][q];
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- fluxes and conservative update (eq. 2dfv) of cells [ilo,ihi) x [jlo,jhi)
+  const uint8_t smask = (A.reg && A.side_mask) ? A.side_mask[patch] : uint8_t(0);
+  const T inv36 = T(1) / T(36);
+  for (int e = threadIdx.x; e < span * nrow; e += kThreads) {
+    const int ii = e % span, jj = e / span;
+    const int i = ilo + ii, j = jlo + jj;
+    const size_t obase = size_t(j + kGhost) * A.pitch + (i + kGhost);
+    T FL[NCOMP], FR[NCOMP], GB[NCOMP], GT[NCOMP];
+#pragma unroll
+    for (int q = 0; q < NCOMP; ++q) {
+      FL[q] = face_sum(L.tsum[NK_CORNER][q][jj][ii], L.tsum[NK_XEDGE][q][jj][ii], L.tsum[NK_CORNER][q][jj + 1][ii]);
+      FR[q] = face_sum(L.tsum[NK_CORNER][q][jj][ii + 1], L.tsum[NK_XEDGE][q][jj][ii + 1],
+                       L.tsum[NK_CORNER][q][jj + 1][ii + 1]);
+      GB[q] = face_sum(L.tsum[NK_CORNER][q][jj][ii], L.tsum[NK_YEDGE][q][jj][ii], L.tsum[NK_CORNER][q][jj][ii + 1]);
+      GT[q] = face_sum(L.tsum[NK_CORNER][q][jj + 1][ii], L.tsum[NK_YEDGE][q][jj + 1][ii],
+                       L.tsum[NK_CORNER][q][jj + 1][ii + 1]);
+    }
+    // physical fluxes of the Simpson sums: advection f = a q, g = b q;
+    // acoustics f = c (u, p, 0), g = c (v, 0, p)  (Sec. 2.3)
+    T fL[NCOMP], fR[NCOMP], gB[NCOMP], gT[NCOMP];
+    if constexpr (EQ == 0) {
+      fL[0] = A.a * FL[0] * inv36; fR[0] = A.a * FR[0] * inv36;
+      gB[0] = A.b * GB[0] * inv36; gT[0] = A.b * GT[0] * inv36;
+    } else {
+      fL[0] = A.c * FL[1] * inv36; fL[1] = A.c * FL[0] * inv36; fL[2] = T(0);
+      fR[0] = A.c * FR[1] * inv36; fR[1] = A.c * FR[0] * inv36; fR[2] = T(0);
+      gB[0] = A.c * GB[2] * inv36; gB[1] = T(0); gB[2] = A.c * GB[0] * inv36;
+      gT[0] = A.c * GT[2] * inv36; gT[1] = T(0); gT[2] = A.c * GT[0] * inv36;
+    }
+#pragma unroll
+    for (int q = 0; q < NCOMP; ++q) {
+      const T Q = L.in[0][q][jj + 1][ii + 1];
+      const T Qn = Q - A.dtdx * (fR[q] - fL[q]) - A.dtdy * (gT[q] - gB[q]);
+      A.out[0][(size_t(q) * A.npatch + patch) * plane + obase] = Qn;
+    }
+    if (smask) {
+      // boundary faces of the interior block -> FP64 registers (Sec. 3.2)
+      double* R = A.reg + size_t(patch) * 4 * M * NCOMP;
+      const bool interior = (i >= 0 && i < M && j >= 0 && j < M);
+      if (interior) {
+#pragma unroll
+        for (int q = 0; q < NCOMP; ++q) {
+          if (i == 0 && (smask & 1)) R[(0 * M + j) * NCOMP + q] += double(fL[q]) * A.len_dt_x;
+          if (i == M - 1 && (smask & 2)) R[(1 * M + j) * NCOMP + q] += double(fR[q]) * A.len_dt_x;
+          if (j == 0 && (smask & 4)) R[(2 * M + i) * NCOMP + q] += double(gB[q]) * A.len_dt_y;
+          if (j == M - 1 && (smask & 8)) R[(3 * M + i) * NCOMP + q] += double(gT[q]) * A.len_dt_y;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Common helpers for ghost fill and transfers.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct Bufs {
+  T* p[2][4];
+  int32_t npatch, pitch, m, ncomp;
+  uint32_t mask;  // bit l: buffer of level l
+};
+
+template <typename T>
+__device__ __forceinline__ T* buf_of(const Bufs<T>& B, int level, int kind) {
+  return B.p[(B.mask >> level) & 1u][kind];
+}
+
+template <typename T>
+__device__ __forceinline__ size_t at(const Bufs<T>& B, int comp, int patch, int i, int j) {
+  return ((size_t(comp) * B.npatch + patch) * (B.m + 5) + size_t(j + kGhost)) * B.pitch + (i + kGhost);
+}
+
+__device__ __forceinline__ long long fdiv(long long a, long long b) {
+  long long q = a / b;
+  if ((a % b != 0) && ((a < 0) != (b < 0))) --q;
+  return q;
+}
+
+__device__ __forceinline__ int lut_find(const HierDev& H, int l, long long px, long long py) {
+  if (l < 0 || l > H.lmax) return -1;
+  const long long nx = (long long)H.npx0 << l, ny = (long long)H.npy0 << l;
+  px = ((px % nx) + nx) % nx;
+  py = ((py % ny) + ny) % ny;
+  return H.lut[H.lut_off[l] + py * nx + px];
+}
+
+__device__ __forceinline__ double lagr(int a, double s) {
+  return a < 0 ? 0.5 * s * (s - 1.0) : (a == 0 ? 1.0 - s * s : 0.5 * s * (s + 1.0));
+}
+
+// Reconstruction of cell (ci,cj) of leaf `patch` evaluated at reference
+// point (xi, eta) (Sec. 2, eq. poly), in double precision.
+template <typename T>
+__device__ double eval_cell(const Bufs<T>& B, int level, int comp, int patch, int ci, int cj, double xi,
+                            double eta) {
+  const T* av = buf_of(B, level, 0);
+  const T* co = buf_of(B, level, 1);
+  const T* xe = buf_of(B, level, 2);
+  const T* ye = buf_of(B, level, 3);
+  double q[3][3];
+  q[0][0] = co[at(B, comp, patch, ci, cj)];
+  q[2][0] = co[at(B, comp, patch, ci + 1, cj)];
+  q[0][2] = co[at(B, comp, patch, ci, cj + 1)];
+  q[2][2] = co[at(B, comp, patch, ci + 1, cj + 1)];
+  q[0][1] = xe[at(B, comp, patch, ci, cj)];
+  q[2][1] = xe[at(B, comp, patch, ci + 1, cj)];
+  q[1][0] = ye[at(B, comp, patch, ci, cj)];
+  q[1][2] = ye[at(B, comp, patch, ci, cj + 1)];
+  const double avg = av[at(B, comp, patch, ci, cj)];
+  q[1][1] = (36.0 * avg - (q[0][0] + q[2][0] + q[0][2] + q[2][2]) - 4.0 * (q[0][1] + q[2][1] + q[1][0] + q[1][2])) / 16.0;
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const double la = lagr(a - 1, xi);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) s += q[a][b] * la * lagr(b - 1, eta);
+  }
+  return s;
+}
+
+// Simpson 3x3 average over the sub-square [xa, xa+1] x [ya, ya+1] of a cell's
+// reference square (exact for the biquadratic reconstruction, Sec. 3.1).
+template <typename T>
+__device__ double quarter_avg(const Bufs<T>& B, int level, int comp, int patch, int ci, int cj, double xa,
+                              double ya) {
+  const double w[3] = {1.0, 4.0, 1.0};
+  double s = 0.0;
+#pragma unroll
+  for (int p = 0; p < 3; ++p)
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      s += w[p] * w[q] * eval_cell(B, level, comp, patch, ci, cj, xa + 0.5 * p, ya + 0.5 * q);
+  return s / 36.0;
+}
+
+// ---------------------------------------------------------------------------
+// Ghost fill (Sec. 3.1, 3.2).  entries: packed (kind << 24) | ((i+2) << 12) |
+// (j+2) for every DOF of the fill set.  Phase 0: same-level and finer
+// sources; phase 1: coarser sources.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct FillArgs {
+  Bufs<T> B;
+  HierDev H;
+  const int32_t* entries;
+  int32_t nentries, chunks, first_target, tmin, smin, phase;
+};
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_ghost_fill(const FillArgs<T> A) {
+  const int tl = blockIdx.x / A.chunks;
+  const int chunk = blockIdx.x - tl * A.chunks;
+  const int t = A.first_target + tl;
+  const HierDev& H = A.H;
+  const int m = A.B.m, nc = A.B.ncomp;
+  const int lt = H.plevel[t];
+  const long long tx = H.pix[t], ty = H.piy[t];
+  for (int e = chunk * kThreads + threadIdx.x; e < A.nentries; e += A.chunks * kThreads) {
+    const int32_t code = A.entries[e];
+    const int kind = code >> 24, i = ((code >> 12) & 0xfff) - kGhost, j = (code & 0xfff) - kGhost;
+    const long long I = tx * m + i, J = ty * m + j;
+    if (kind == 0) {
+      int src = -1, rel = 0;
+      if (lt >= A.smin) {
+        src = lut_find(H, lt, fdiv(I, m), fdiv(J, m));
+        rel = 0;
+      }
+      if (src < 0 && lt + 1 <= H.lmax && lt + 1 >= A.smin) {
+        src = lut_find(H, lt + 1, fdiv(2 * I, m), fdiv(2 * J, m));
+        rel = 1;
+      }
+      if (src < 0 && lt - 1 >= 0 && lt - 1 >= A.smin) {
+        src = lut_find(H, lt - 1, fdiv(I, 2 * m), fdiv(J, 2 * m));
+        rel = -1;
+      }
+      if (src < 0) continue;
+      if ((A.phase == 0) != (rel >= 0)) continue;
+      const int ls = lt + rel;
+      T* dst = buf_of(A.B, lt, 0);
+      const T* sav = buf_of(A.B, ls, 0);
+      for (int q = 0; q < nc; ++q) {
+        double val;
+        if (rel == 0) {
+          const int li = int(I - fdiv(I, m) * m), lj = int(J - fdiv(J, m) * m);
+          val = sav[at(A.B, q, src, li, lj)];
+        } else if (rel == 1) {
+          const int fi = int(2 * I - fdiv(2 * I, m) * m), fj = int(2 * J - fdiv(2 * J, m) * m);
+          // mean of the four fine averages (fine -> coarse transfer)
+          val = 0.25 * ((double(sav[at(A.B, q, src, fi, fj)]) + double(sav[at(A.B, q, src, fi + 1, fj)])) +
+                        (double(sav[at(A.B, q, src, fi, fj + 1)]) + double(sav[at(A.B, q, src, fi + 1, fj + 1)])));
+        } else {
+          const long long CI = fdiv(I, 2), CJ = fdiv(J, 2);
+          const int ci = int(CI - fdiv(CI, m) * m), cj = int(CJ - fdiv(CJ, m) * m);
+          val = quarter_avg(A.B, ls, q, src, ci, cj, (I - 2 * CI == 0) ? -1.0 : 0.0, (J - 2 * CJ == 0) ? -1.0 : 0.0);
+        }
+        dst[at(A.B, q, t, i, j)] = T(val);
+      }
+    } else {
+      // node position in level-(lt+1) half-cell units
+      const long long FX = 4 * I + (kind == 3 ? 2 : 0);
+      const long long FY = 4 * J + (kind == 2 ? 2 : 0);
+      int src = -1, rel = 0;
+      long long sx = 0, sy = 0;  // source-local position in fine units
+      int sh = 0;
+      for (int k = lt + 1; k >= lt - 1 && src < 0; --k) {
+        if (k < 0 || k > H.lmax || k < A.smin) continue;
+        sh = lt + 1 - k;
+        const long long unit = 1LL << sh, P = 2LL * m * unit;
+        const long long hx = fdiv(FX, P), hy = fdiv(FY, P);
+        const bool bx = (FX - hx * P) == 0, by = (FY - hy * P) == 0;
+        const int ox[4] = {0, 1, 0, 1}, oy[4] = {0, 0, 1, 1};
+        for (int o = 0; o < 4; ++o) {
+          if (ox[o] && !bx) continue;
+          if (oy[o] && !by) continue;
+          const int id = lut_find(H, k, hx - ox[o], hy - oy[o]);
+          if (id < 0) continue;
+          src = id;
+          rel = k - lt;
+          sx = FX - (hx - ox[o]) * P;
+          sy = FY - (hy - oy[o]) * P;
+          break;
+        }
+      }
+      if (src < 0) continue;
+      if ((A.phase == 0) != (rel >= 0)) continue;
+      const long long unit = 1LL << sh;
+      if (rel == 0 && src == t) {
+        // the target itself: skip unless the match is a periodic image
+        const long long X = sx / unit, Y = sy / unit;
+        const long long Xt = 2 * i + (kind == 3 ? 1 : 0), Yt = 2 * j + (kind == 2 ? 1 : 0);
+        if (X == Xt && Y == Yt) continue;
+      }
+      const int ls = lt + rel;
+      T* dst = buf_of(A.B, lt, kind);
+      for (int q = 0; q < nc; ++q) {
+        double val;
+        if (rel >= 0) {
+          const long long X = sx / unit, Y = sy / unit;  // source half-cell units
+          const bool ex = (X % 2) == 0, ey = (Y % 2) == 0;
+          if (ex && ey) val = buf_of(A.B, ls, 1)[at(A.B, q, src, int(X / 2), int(Y / 2))];
+          else if (ex) val = buf_of(A.B, ls, 2)[at(A.B, q, src, int(X / 2), int((Y - 1) / 2))];
+          else val = buf_of(A.B, ls, 3)[at(A.B, q, src, int((X - 1) / 2), int(Y / 2))];
+        } else {
+          const double xs = double(sx) / 4.0, ys = double(sy) / 4.0;  // coarse half-cell units
+          int ci = int(floor(xs / 2.0)), cj = int(floor(ys / 2.0));
+          ci = min(max(ci, 0), m - 1);
+          cj = min(max(cj, 0), m - 1);
+          val = eval_cell(A.B, ls, q, src, ci, cj, xs - (2.0 * ci + 1.0), ys - (2.0 * cj + 1.0));
+        }
+        dst[at(A.B, q, t, i, j)] = T(val);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Conservative fix (Sec. 3.2).  faces are grouped by coarse cell; the first
+// thread of a group applies all of its faces, so no two threads touch one
+// cell.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_flux_correct(Bufs<T> B, const CFFace* faces, int nfaces,
+                                                           double* reg, int level, double inv_area) {
+  const int f = blockIdx.x * kThreads + threadIdx.x;
+  if (f >= nfaces) return;
+  const int m = B.m, nc = B.ncomp;
+  auto cell_of = [&](const CFFace& F, int* ci, int* cj) {
+    *ci = F.side == 0 ? 0 : (F.side == 1 ? m - 1 : F.k);
+    *cj = F.side == 2 ? 0 : (F.side == 3 ? m - 1 : F.k);
+  };
+  int ci, cj;
+  cell_of(faces[f], &ci, &cj);
+  if (f > 0) {
+    int pi, pj;
+    cell_of(faces[f - 1], &pi, &pj);
+    if (faces[f - 1].coarse == faces[f].coarse && pi == ci && pj == cj) return;
+  }
+  T* av = buf_of(B, level, 0);
+  for (int g = f; g < nfaces; ++g) {
+    const CFFace F = faces[g];
+    int gi, gj;
+    cell_of(F, &gi, &gj);
+    if (F.coarse != faces[f].coarse || gi != ci || gj != cj) break;
+    const double sgn = (F.side == 1 || F.side == 3) ? 1.0 : -1.0;
+    const int opp = F.side ^ 1;
+    double* Rc = reg + (size_t(F.coarse) * 4 + F.side) * m * nc + size_t(F.k) * nc;
+    double* Rf = reg + (size_t(F.fine) * 4 + opp) * m * nc + size_t(F.fk) * nc;
+    for (int q = 0; q < nc; ++q) {
+      const double rf = Rf[q] + Rf[nc + q];
+      const size_t idx = at(B, q, F.coarse, ci, cj);
+      av[idx] = T(double(av[idx]) + sgn * (Rc[q] - rf) * inv_area);
+      Rc[q] = 0.0;
+      Rf[q] = 0.0;
+      Rf[nc + q] = 0.0;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tagging (Sec. 3; criteria of Sec. 4.1, 4.4): one block per leaf.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_tag(Bufs<T> B, HierDev H, int mode, int comp, double inv2dx0,
+                                                  double inv2dy0, double tr, double tc, int8_t* tags,
+                                                  double* values) {
+  const int p = blockIdx.x;
+  const int l = H.plevel[p];
+  const int m = B.m;
+  const T* av = buf_of(B, l, 0);
+  const double s2x = inv2dx0 * double(1 << l), s2y = inv2dy0 * double(1 << l);
+  double vmax = -1e300, vmin = 1e300;
+  for (int e = threadIdx.x; e < m * m; e += kThreads) {
+    const int i = e % m, j = e / m;
+    if (mode == 0) {
+      const double gx = fabs(double(av[at(B, comp, p, i + 1, j)]) - double(av[at(B, comp, p, i - 1, j)])) * s2x;
+      const double gy = fabs(double(av[at(B, comp, p, i, j + 1)]) - double(av[at(B, comp, p, i, j - 1)])) * s2y;
+      vmax = fmax(vmax, fmax(gx, gy));
+    } else {
+      const double v = av[at(B, comp, p, i, j)];
+      vmax = fmax(vmax, v);
+      vmin = fmin(vmin, v);
+    }
+  }
+  __shared__ double smax[kThreads], smin[kThreads];
+  smax[threadIdx.x] = vmax;
+  smin[threadIdx.x] = vmin;
+  __syncthreads();
+  for (int s = kThreads / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+      smin[threadIdx.x] = fmin(smin[threadIdx.x], smin[threadIdx.x + s]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double v = mode == 0 ? smax[0] : smax[0] - smin[0];
+    int8_t tg = 0;
+    if (v >= tr && l < H.lmax) tg = 1;
+    else if (v < tc && l > 0) tg = -1;
+    tags[p] = tg;
+    if (values) values[p] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Regrid transfer (Sec. 3.1): one block per new leaf.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_transfer(Bufs<T> OLD, HierDev HO, Bufs<T> NEW, const Transfer* tr) {
+  const int p = blockIdx.x;
+  const Transfer X = tr[p];
+  const int m = NEW.m, nc = NEW.ncomp;
+  const int n_avg = m * m, n_c = (m + 1) * (m + 1), n_x = m * (m + 1), n_y = (m + 1) * m;
+  const int total = n_avg + n_c + n_x + n_y;
+  for (int e = threadIdx.x; e < total; e += kThreads) {
+    int kind, i, j;
+    if (e < n_avg) { kind = 0; i = e % m; j = e / m; }
+    else if (e < n_avg + n_c) { const int f = e - n_avg; kind = 1; i = f % (m + 1); j = f / (m + 1); }
+    else if (e < n_avg + n_c + n_x) { const int f = e - n_avg - n_c; kind = 2; i = f % (m + 1); j = f / (m + 1); }
+    else { const int f = e - n_avg - n_c - n_x; kind = 3; i = f % m; j = f / m; }
+    for (int q = 0; q < nc; ++q) {
+      double val;
+      if (X.mode == 0) {
+        const int s = X.src[0];
+        val = buf_of(OLD, HO.plevel[s], kind)[at(OLD, q, s, i, j)];
+      } else if (X.mode == 1) {
+        const int s = X.src[0];
+        const int ls = HO.plevel[s];
+        if (kind == 0) {
+          const int fi = X.qx * m + i, fj = X.qy * m + j;
+          val = quarter_avg(OLD, ls, q, s, fi >> 1, fj >> 1, (fi & 1) ? 0.0 : -1.0, (fj & 1) ? 0.0 : -1.0);
+        } else {
+          // node position in parent half-cell units
+          double xs = double(X.qx * m + i), ys = double(X.qy * m + j);
+          if (kind == 2) ys += 0.5;
+          if (kind == 3) xs += 0.5;
+          int ci = min(max(int(floor(xs / 2.0)), 0), m - 1), cj = min(max(int(floor(ys / 2.0)), 0), m - 1);
+          val = eval_cell(OLD, ls, q, s, ci, cj, xs - (2.0 * ci + 1.0), ys - (2.0 * cj + 1.0));
+        }
+      } else {
+        if (kind == 0) {
+          const int fi = 2 * i, fj = 2 * j;
+          const int qx = fi / m, qy = fj / m;
+          const int s = X.src[qy * 2 + qx];
+          const T* av = buf_of(OLD, HO.plevel[s], 0);
+          const int li = fi - qx * m, lj = fj - qy * m;
+          val = 0.25 * ((double(av[at(OLD, q, s, li, lj)]) + double(av[at(OLD, q, s, li + 1, lj)])) +
+                        (double(av[at(OLD, q, s, li, lj + 1)]) + double(av[at(OLD, q, s, li + 1, lj + 1)])));
+        } else {
+          int FX = 2 * i, FY = 2 * j;
+          if (kind == 2) FY += 1;
+          if (kind == 3) FX += 1;
+          const int qx = min(FX / m, 1), qy = min(FY / m, 1);
+          const int s = X.src[qy * 2 + qx];
+          val = buf_of(OLD, HO.plevel[s], 1)[at(OLD, q, s, FX - qx * m, FY - qy * m)];
+        }
+      }
+      NEW.p[0][kind][at(NEW, q, p, i, j)] = T(val);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 sums (global conservation): per-leaf partials, then one block.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_sum_partial(Bufs<T> B, HierDev H, double area0, double* part) {
+  const int p = blockIdx.x;
+  const int l = H.plevel[p];
+  const int m = B.m, nc = B.ncomp;
+  const T* av = buf_of(B, l, 0);
+  __shared__ double red[kThreads];
+  for (int q = 0; q < nc; ++q) {
+    double s = 0.0;
+    for (int e = threadIdx.x; e < m * m; e += kThreads) s += double(av[at(B, q, p, e % m, e / m)]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) part[size_t(p) * nc + q] = red[0] * area0 / double(1LL << (2 * l));
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sum_final(const double* part, int n, int nc, double* out) {
+  __shared__ double red[kThreads];
+  for (int q = 0; q < nc; ++q) {
+    double s = 0.0;
+    for (int p = threadIdx.x; p < n; p += kThreads) s += part[size_t(p) * nc + q];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+      if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[q] = red[0];
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+template <typename T, int EQ, int M, int TY>
+static hipError_t launch_step_t(const StepLaunch& s, hipStream_t st) {
+  StepArgs<T> A;
+  for (int k = 0; k < 4; ++k) {
+    A.in[k] = static_cast<const T*>(s.in[k]);
+    A.out[k] = static_cast<T*>(s.out[k]);
+  }
+  A.npatch = s.npatch; A.pitch = s.pitch; A.first = s.first; A.region = s.region;
+  A.dtdx = T(s.dtdx); A.dtdy = T(s.dtdy);
+  A.a = T(s.a); A.b = T(s.b); A.c = T(s.c);
+  A.len_dt_x = s.len_dt_x; A.len_dt_y = s.len_dt_y;
+  A.reg = s.reg; A.side_mask = s.side_mask;
+  const int span = M + 2 * s.region;
+  const int tiles = (span + TY - 1) / TY;
+  const dim3 grid(unsigned(s.count * tiles));
+  if constexpr (EQ == 0) {
+    hipLaunchKernelGGL((k_patch_step<T, 0, M, TY>), grid, dim3(kThreads), 0, st, A,
+                       *static_cast<const AdvWeights<T>*>(s.weights));
+  } else {
+    hipLaunchKernelGGL((k_patch_step<T, 1, M, TY>), grid, dim3(kThreads), 0, st, A,
+                       *static_cast<const AcWeights<T>*>(s.weights));
+  }
+  return hipGetLastError();
+}
+
+template <typename T, int EQ>
+static hipError_t launch_step_m(const StepLaunch& s, hipStream_t st) {
+  // tile heights chosen so that a tile holds about 256 cells
+  switch (s.m) {
+    case 8: return launch_step_t<T, EQ, 8, 8>(s, st);
+    case 16: return s.ty == 8 ? launch_step_t<T, EQ, 16, 8>(s, st) : launch_step_t<T, EQ, 16, 16>(s, st);
+    case 32: return s.ty == 4 ? launch_step_t<T, EQ, 32, 4>(s, st) : launch_step_t<T, EQ, 32, 8>(s, st);
+    case 64: return s.ty == 2 ? launch_step_t<T, EQ, 64, 2>(s, st) : launch_step_t<T, EQ, 64, 4>(s, st);
+    case 128: return launch_step_t<T, EQ, 128, 2>(s, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_patch_step(const StepLaunch& s, hipStream_t st) {
+  if (s.count <= 0) return hipSuccess;
+  if (s.fp32) return s.eq ? launch_step_m<float, 1>(s, st) : launch_step_m<float, 0>(s, st);
+  return s.eq ? launch_step_m<double, 1>(s, st) : launch_step_m<double, 0>(s, st);
+}
+
+bool step_shape_supported(int m, int ty) {
+  switch (m) {
+    case 8: return ty == 8;
+    case 16: return ty == 8 || ty == 16;
+    case 32: return ty == 4 || ty == 8;
+    case 64: return ty == 2 || ty == 4;
+    case 128: return ty == 2;
+    default: return false;
+  }
+}
+
+template <typename T>
+static Bufs<T> make_bufs(const BufLaunch& b) {
+  Bufs<T> B;
+  for (int s = 0; s < 2; ++s)
+    for (int k = 0; k < 4; ++k) B.p[s][k] = static_cast<T*>(b.p[s][k]);
+  B.npatch = b.npatch; B.pitch = b.pitch; B.m = b.m; B.ncomp = b.ncomp; B.mask = b.mask;
+  return B;
+}
+
+template <typename T>
+static hipError_t ghost_fill_t(const BufLaunch& b, const HierDev& H, const int32_t* entries, int nentries,
+                               int first_target, int ntargets, int tmin, int smin, bool phase_b,
+                               hipStream_t st) {
+  FillArgs<T> A;
+  A.B = make_bufs<T>(b);
+  A.H = H;
+  A.entries = entries;
+  A.nentries = nentries;
+  A.chunks = (nentries + kThreads - 1) / kThreads;
+  A.first_target = first_target;
+  A.tmin = tmin;
+  A.smin = smin;
+  for (int phase = 0; phase < (phase_b ? 2 : 1); ++phase) {
+    A.phase = phase;
+    hipLaunchKernelGGL(k_ghost_fill<T>, dim3(unsigned(ntargets * A.chunks)), dim3(kThreads), 0, st, A);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t launch_ghost_fill(bool fp32, const BufLaunch& b, const HierDev& H, const int32_t* entries,
+                             int nentries, int first_target, int ntargets, int tmin, int smin, bool phase_b,
+                             hipStream_t st) {
+  if (ntargets <= 0) return hipSuccess;
+  return fp32 ? ghost_fill_t<float>(b, H, entries, nentries, first_target, ntargets, tmin, smin, phase_b, st)
+              : ghost_fill_t<double>(b, H, entries, nentries, first_target, ntargets, tmin, smin, phase_b, st);
+}
+
+hipError_t launch_flux_correct(bool fp32, const BufLaunch& b, const CFFace* faces, int nfaces, double* reg,
+                               int level, double inv_area, hipStream_t st) {
+  if (nfaces <= 0) return hipSuccess;
+  const dim3 grid(unsigned((nfaces + kThreads - 1) / kThreads));
+  if (fp32)
+    hipLaunchKernelGGL(k_flux_correct<float>, grid, dim3(kThreads), 0, st, make_bufs<float>(b), faces, nfaces,
+                       reg, level, inv_area);
+  else
+    hipLaunchKernelGGL(k_flux_correct<double>, grid, dim3(kThreads), 0, st, make_bufs<double>(b), faces, nfaces,
+                       reg, level, inv_area);
+  return hipGetLastError();
+}
+
+hipError_t launch_tag(bool fp32, const BufLaunch& b, const HierDev& H, int mode, int comp, double inv2dx0,
+                      double inv2dy0, double tr, double tc, int8_t* tags, double* values, hipStream_t st) {
+  if (H.nleaves <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(k_tag<float>, dim3(unsigned(H.nleaves)), dim3(kThreads), 0, st, make_bufs<float>(b), H,
+                       mode, comp, inv2dx0, inv2dy0, tr, tc, tags, values);
+  else
+    hipLaunchKernelGGL(k_tag<double>, dim3(unsigned(H.nleaves)), dim3(kThreads), 0, st, make_bufs<double>(b), H,
+                       mode, comp, inv2dx0, inv2dy0, tr, tc, tags, values);
+  return hipGetLastError();
+}
+
+hipError_t launch_transfer(bool fp32, const BufLaunch& old_b, const HierDev& HO, const BufLaunch& new_b,
+                           const Transfer* tr, int nnew, hipStream_t st) {
+  if (nnew <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(k_transfer<float>, dim3(unsigned(nnew)), dim3(kThreads), 0, st, make_bufs<float>(old_b),
+                       HO, make_bufs<float>(new_b), tr);
+  else
+    hipLaunchKernelGGL(k_transfer<double>, dim3(unsigned(nnew)), dim3(kThreads), 0, st, make_bufs<double>(old_b),
+                       HO, make_bufs<double>(new_b), tr);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum(bool fp32, const BufLaunch& b, const HierDev& H, double area0, double* part, double* out,
+                      hipStream_t st) {
+  if (H.nleaves <= 0) return hipSuccess;
+  if (fp32)
+    hipLaunchKernelGGL(k_sum_partial<float>, dim3(unsigned(H.nleaves)), dim3(kThreads), 0, st,
+                       make_bufs<float>(b), H, area0, part);
+  else
+    hipLaunchKernelGGL(k_sum_partial<double>, dim3(unsigned(H.nleaves)), dim3(kThreads), 0, st,
+                       make_bufs<double>(b), H, area0, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_sum_final, dim3(1), dim3(kThreads), 0, st, part, H.nleaves, b.ncomp, out);
+  return hipGetLastError();
+}
+
+}  // namespace af

@@ -1,0 +1,43 @@
+// af_launch.h -- host-side launch descriptors of the library's kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "af_internal.h"
+
+namespace af {
+
+struct StepLaunch {
+  bool fp32;
+  int eq, m, ty;
+  const void* in[4];
+  void* out[4];
+  int npatch, pitch, first, count, region;
+  double dtdx, dtdy, a, b, c;
+  double len_dt_x, len_dt_y;
+  double* reg;
+  const uint8_t* side_mask;
+  const void* weights;  // AdvWeights<T> or AcWeights<T> matching fp32/eq
+};
+
+struct BufLaunch {
+  void* p[2][4];
+  int npatch, pitch, m, ncomp;
+  uint32_t mask;
+};
+
+hipError_t launch_patch_step(const StepLaunch& s, hipStream_t st);
+bool step_shape_supported(int m, int ty);
+hipError_t launch_ghost_fill(bool fp32, const BufLaunch& b, const HierDev& H, const int32_t* entries,
+                             int nentries, int first_target, int ntargets, int tmin, int smin, bool phase_b,
+                             hipStream_t st);
+hipError_t launch_flux_correct(bool fp32, const BufLaunch& b, const CFFace* faces, int nfaces, double* reg,
+                               int level, double inv_area, hipStream_t st);
+hipError_t launch_tag(bool fp32, const BufLaunch& b, const HierDev& H, int mode, int comp, double inv2dx0,
+                      double inv2dy0, double tr, double tc, int8_t* tags, double* values, hipStream_t st);
+hipError_t launch_transfer(bool fp32, const BufLaunch& old_b, const HierDev& HO, const BufLaunch& new_b,
+                           const Transfer* tr, int nnew, hipStream_t st);
+hipError_t launch_sum(bool fp32, const BufLaunch& b, const HierDev& H, double area0, double* part, double* out,
+                      hipStream_t st);
+
+}  // namespace af

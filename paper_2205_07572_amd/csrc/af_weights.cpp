@@ -1,0 +1,226 @@
+// af_weights.cpp -- host-side derivation of the fixed linear stencils of the
+// AF point-value evolution.
+//
+// With constant coefficients and a fixed ratio dt/dx, the value of a node at
+// t+tau is the same linear combination of the raw DOFs of the cells around
+// it for every node of a kind (Sec. 2.1, Sec. 2.3).  Under 2:1 subcycling
+// dt_l/dx_l is the same on every level, so one table serves all levels.
+// This file computes those combinations once, in FP64, from:
+//   * the biquadratic reconstruction (Sec. 2, eq. poly) in tensor Lagrange
+//     form, whose centre value follows from "cell average = tensor Simpson
+//     sum of the nodal values";
+//   * advection (eq. advection-update): evaluation at the upwind foot;
+//   * acoustics (eq. ERFormula, eq. sphe-mean): the spherical mean of each
+//     cell polynomial over the disc sectors lying in that cell, integrated
+//     in closed form monomial by monomial.
+#include <cmath>
+#include <cstring>
+
+#include "af_internal.h"
+#include "af_weights.h"
+
+namespace af {
+namespace {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// A biquadratic in reference coordinates: c[m][n] multiplies xi^m eta^n.
+struct Poly2 {
+  double c[3][3];
+};
+
+// 1D Lagrange basis on nodes -1, 0, 1 as monomial coefficients (power 0,1,2).
+void lagrange_coeffs(int node, double out[3]) {
+  if (node == -1) { out[0] = 0.0; out[1] = -0.5; out[2] = 0.5; }
+  else if (node == 0) { out[0] = 1.0; out[1] = 0.0; out[2] = -1.0; }
+  else { out[0] = 0.0; out[1] = 0.5; out[2] = 0.5; }
+}
+
+// Basis polynomial of raw DOF d (af_internal.h order) of one cell: the
+// reconstruction equals sum_d dof_d * basis_d.  Nodal functions phi_ab =
+// L_a(xi) L_b(eta); the centre value q00 = (36 avg - sum corners - 4 sum
+// edges)/16 distributes phi_00 onto the raw DOFs.
+Poly2 dof_basis(int d) {
+  static const int node_of[9][2] = {{0, 0},  {-1, -1}, {1, -1}, {-1, 1}, {1, 1},
+                                    {-1, 0}, {1, 0},   {0, -1}, {0, 1}};
+  double lx[3], ly[3], cx[3], cy[3];
+  lagrange_coeffs(0, cx);
+  lagrange_coeffs(0, cy);
+  Poly2 p;
+  double centre_w;
+  if (d == 0) {
+    std::memset(p.c, 0, sizeof p.c);
+    centre_w = 36.0 / 16.0;
+  } else {
+    lagrange_coeffs(node_of[d][0], lx);
+    lagrange_coeffs(node_of[d][1], ly);
+    for (int m = 0; m < 3; ++m)
+      for (int n = 0; n < 3; ++n) p.c[m][n] = lx[m] * ly[n];
+    centre_w = (d <= 4) ? -1.0 / 16.0 : -4.0 / 16.0;
+  }
+  for (int m = 0; m < 3; ++m)
+    for (int n = 0; n < 3; ++n) p.c[m][n] += centre_w * cx[m] * cy[n];
+  return p;
+}
+
+double poly_eval(const Poly2& p, double x, double y) {
+  double s = 0.0, xm = 1.0;
+  for (int m = 0; m < 3; ++m) {
+    double yn = 1.0;
+    for (int n = 0; n < 3; ++n) {
+      s += p.c[m][n] * xm * yn;
+      yn *= y;
+    }
+    xm *= x;
+  }
+  return s;
+}
+
+// Coefficients of p(x0 + s, y0 + t) in powers of (s, t).
+Poly2 poly_shift(const Poly2& p, double x0, double y0) {
+  static const double binom[3][3] = {{1, 0, 0}, {1, 1, 0}, {1, 2, 1}};
+  Poly2 r;
+  std::memset(r.c, 0, sizeof r.c);
+  for (int m = 0; m < 3; ++m)
+    for (int n = 0; n < 3; ++n)
+      for (int a = m; a < 3; ++a)
+        for (int b = n; b < 3; ++b)
+          r.c[m][n] += p.c[a][b] * binom[a][m] * binom[b][n] * std::pow(x0, a - m) * std::pow(y0, b - n);
+  return r;
+}
+
+// I(m,n) = int_0^{pi/2} cos^m(phi) sin^n(phi) dphi by the reduction
+// I(m,n) = (m-1)/(m+n) I(m-2,n), I(m,n) = (n-1)/(m+n) I(m,n-2).
+double trig_moment(int m, int n) {
+  if (m >= 2) return double(m - 1) / double(m + n) * trig_moment(m - 2, n);
+  if (n >= 2) return double(n - 1) / double(m + n) * trig_moment(m, n - 2);
+  if (m == 0 && n == 0) return kPi / 2.0;
+  if (m + n == 1) return 1.0;
+  return 0.5;  // m = n = 1
+}
+
+// Angular moment over quadrant q (phi in [q pi/2, (q+1) pi/2]).
+double quadrant_moment(int q, int m, int n) {
+  double s = trig_moment(m, n);
+  if ((q == 1 || q == 2) && (m & 1)) s = -s;  // cos < 0
+  if ((q == 2 || q == 3) && (n & 1)) s = -s;  // sin < 0
+  return s;
+}
+
+// Spherical mean, restricted to the quadrants in qmask, of a polynomial
+// given in powers of the scaled displacement (zx/hx, zy/hy) about the disc
+// centre: monomial (zx/hx)^m (zy/hy)^n contributes
+//   (R/hx)^m (R/hy)^n I_{0,m+n+1} A_mn / (2 pi)
+// (radial integral with s = R sin(theta)).  Returns M and R dM/dR.
+void sector_mean(const double c[4][4], int qmask, double rx, double ry, double* M, double* RdM) {
+  double sm = 0.0, sd = 0.0;
+  for (int m = 0; m < 4; ++m)
+    for (int n = 0; m + n < 6 && n < 4; ++n) {
+      if (c[m][n] == 0.0) continue;
+      double ang = 0.0;
+      for (int q = 0; q < 4; ++q)
+        if (qmask & (1 << q)) ang += quadrant_moment(q, m, n);
+      const double rad = trig_moment(0, m + n + 1);
+      const double mono = std::pow(rx, m) * std::pow(ry, n) * rad * ang / (2.0 * kPi);
+      sm += c[m][n] * mono;
+      sd += double(m + n) * c[m][n] * mono;
+    }
+  *M = sm;
+  *RdM = sd;
+}
+
+// Advection: foot of the node in cell units relative to the owner cell's
+// centre, then cell offset and reference coordinates.  A foot exactly on a
+// face is put in the cell between it and the node.
+void adv_locate(double node, double disp, int* off, double* ref) {
+  const double s = node + disp;
+  double k = std::floor(s + 0.5);
+  if (disp > 0.0 && s + 0.5 == k) k -= 1.0;
+  *off = int(k);
+  *ref = 2.0 * (s - k);
+}
+
+}  // namespace
+
+template <typename T>
+void make_adv_weights(double a_dtdx, double b_dtdy, AdvWeights<T>* W) {
+  static const double node_pos[3][2] = {{-0.5, -0.5}, {-0.5, 0.0}, {0.0, -0.5}};
+  for (int kind = 0; kind < 3; ++kind)
+    for (int t = 0; t < 2; ++t) {
+      const double frac = t == 0 ? 0.5 : 1.0;
+      int ox, oy;
+      double xi, eta;
+      adv_locate(node_pos[kind][0], -a_dtdx * frac, &ox, &xi);
+      adv_locate(node_pos[kind][1], -b_dtdy * frac, &oy, &eta);
+      W->off[kind][t][0] = ox;
+      W->off[kind][t][1] = oy;
+      for (int d = 0; d < kCellDofs; ++d) W->w[kind][t][d] = T(poly_eval(dof_basis(d), xi, eta));
+    }
+}
+
+template <typename T>
+void make_ac_weights(double c_dtdx, double c_dtdy, AcWeights<T>* W) {
+  // node kind -> sectors: (quadrant mask, cell offset, node position in the
+  // cell's reference coordinates)
+  struct Sector { int qmask, di, dj; double xi, eta; };
+  static const Sector corner_s[4] = {{1, 0, 0, -1, -1}, {2, -1, 0, 1, -1}, {4, -1, -1, 1, 1}, {8, 0, -1, -1, 1}};
+  static const Sector xedge_s[2] = {{1 | 8, 0, 0, -1, 0}, {2 | 4, -1, 0, 1, 0}};
+  static const Sector yedge_s[2] = {{1 | 2, 0, 0, 0, -1}, {4 | 8, 0, -1, 0, 1}};
+  // raw DOF d of cell (di,dj) as (state kind, offset) relative to the owner
+  static const int dof_kind[9] = {0, 1, 1, 1, 1, 2, 2, 3, 3};
+  static const int dof_off[9][2] = {{0, 0}, {0, 0}, {1, 0}, {0, 1}, {1, 1}, {0, 0}, {1, 0}, {0, 0}, {0, 1}};
+
+  for (int t = 0; t < 2; ++t) {
+    const double frac = t == 0 ? 0.5 : 1.0;
+    // scaled radii: R / (dx/2), R / (dy/2)
+    const double rx = 2.0 * c_dtdx * frac, ry = 2.0 * c_dtdy * frac;
+    for (int nk = 0; nk < 3; ++nk) {
+      const Sector* secs = nk == 0 ? corner_s : (nk == 1 ? xedge_s : yedge_s);
+      const int nsec = nk == 0 ? 4 : 2;
+      const NbEntry* tab = nk == 0 ? kNbCornerTab : (nk == 1 ? kNbXedgeTab : kNbYedgeTab);
+      const int nb = nk == 0 ? kNbCorner : kNbEdge;
+      double acc[3][kNbCorner] = {};
+      for (int s = 0; s < nsec; ++s) {
+        const Sector& S = secs[s];
+        for (int d = 0; d < kCellDofs; ++d) {
+          const Poly2 sh = poly_shift(dof_basis(d), S.xi, S.eta);
+          // value, x-derivative and y-derivative (reference units, powers of
+          // the scaled displacement) embedded in 4x4 coefficient grids
+          double cv[4][4] = {}, cdx[4][4] = {}, cdy[4][4] = {};
+          for (int m = 0; m < 3; ++m)
+            for (int n = 0; n < 3; ++n) {
+              cv[m][n] = sh.c[m][n];
+              if (m > 0) cdx[m - 1][n] += double(m) * sh.c[m][n];
+              if (n > 0) cdy[m][n - 1] += double(n) * sh.c[m][n];
+            }
+          double M, RdM, Mx, Rx, My, Ry;
+          sector_mean(cv, S.qmask, rx, ry, &M, &RdM);
+          sector_mean(cdx, S.qmask, rx, ry, &Mx, &Rx);
+          sector_mean(cdy, S.qmask, rx, ry, &My, &Ry);
+          // R d/dx = (R / (dx/2)) d/dxi = rx d/dxi
+          const double K = M + RdM, Dx = rx * Mx, Dy = ry * My;
+          const int kind = dof_kind[d];
+          const int di = S.di + dof_off[d][0], dj = S.dj + dof_off[d][1];
+          int e = 0;
+          while (e < nb && !(tab[e].kind == kind && tab[e].di == di && tab[e].dj == dj)) ++e;
+          acc[0][e] += K;
+          acc[1][e] += Dx;
+          acc[2][e] += Dy;
+        }
+      }
+      for (int w = 0; w < 3; ++w)
+        for (int e = 0; e < nb; ++e) {
+          if (nk == 0) W->corner[t][w][e] = T(acc[w][e]);
+          else if (nk == 1) W->xedge[t][w][e] = T(acc[w][e]);
+          else W->yedge[t][w][e] = T(acc[w][e]);
+        }
+    }
+  }
+}
+
+template void make_adv_weights<float>(double, double, AdvWeights<float>*);
+template void make_adv_weights<double>(double, double, AdvWeights<double>*);
+template void make_ac_weights<float>(double, double, AcWeights<float>*);
+template void make_ac_weights<double>(double, double, AcWeights<double>*);
+
+}  // namespace af

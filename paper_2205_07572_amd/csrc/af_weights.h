@@ -1,0 +1,16 @@
+// af_weights.h -- fixed evolution stencils (host side).
+#pragma once
+
+#include "af_internal.h"
+
+namespace af {
+
+// a_dtdx = a dt / dx, b_dtdy = b dt / dy.
+template <typename T>
+void make_adv_weights(double a_dtdx, double b_dtdy, AdvWeights<T>* W);
+
+// c_dtdx = c dt / dx, c_dtdy = c dt / dy.
+template <typename T>
+void make_ac_weights(double c_dtdx, double c_dtdy, AcWeights<T>* W);
+
+}  // namespace af

@@ -1,0 +1,103 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol that
+include/af.h declares, validates arguments on the host, and its host
+quadtree logic (balance check, side relations, regrid) agrees with the
+oracle's.  No kernel is launched here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import afsynth
+import oracle
+import paper_2205_07572_amd as af
+from paper_2205_07572_amd import _lib
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "af.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(af_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.load()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(_lib.EXPORTS) == names
+
+
+@pytest.mark.parametrize("field,value,status", [("m", 12, _lib.AF_ERR_ARG), ("eq", 5, _lib.AF_ERR_ARG),
+                                                ("prec", 3, _lib.AF_ERR_ARG), ("lmax", 40, _lib.AF_ERR_ARG),
+                                                ("lx", -1.0, _lib.AF_ERR_ARG), ("c", 0.0, _lib.AF_ERR_ARG)])
+def test_ctx_rejects_bad_problems(field, value, status):
+    p = af.Problem(eq=1, prec=0, m=16)
+    setattr(p, field, value)
+    with pytest.raises(af.AFError) as e:
+        af.Context(p)
+    assert e.value.status == status
+
+
+def test_tile_heights_validated():
+    ctx = af.Context(af.Problem(eq=0, prec=1, m=32))
+    assert ctx.tile in (4, 8)
+    ctx.tile = 4
+    assert ctx.tile == 4
+    with pytest.raises(af.AFError):
+        ctx.tile = 3
+
+
+@pytest.mark.parametrize("leaves,msg", [
+    ([(0, 0, 0), (0, 1, 0), (0, 0, 1)], "cover"),                       # hole
+    ([(0, 0, 0), (0, 1, 0), (0, 0, 1), (0, 1, 1), (1, 0, 0)], "overlap"),  # overlap
+    ([(1, 0, 0), (0, 1, 0), (0, 0, 1), (0, 1, 1), (1, 1, 0), (1, 0, 1), (1, 1, 1)], "sorted"),
+])
+def test_hierarchy_rejects_bad_leaf_sets(leaves, msg):
+    ctx = af.Context(af.Problem(eq=0, prec=0, m=8, n0x=2, n0y=2, lmax=3))
+    with pytest.raises(af.AFError) as e:
+        af.Hierarchy(ctx, leaves)
+    assert msg in str(e.value)
+
+
+def test_hierarchy_rejects_unbalanced():
+    ctx = af.Context(af.Problem(eq=0, prec=0, m=8, n0x=4, n0y=4, lmax=3))
+    leaves = [(0, ix, iy) for iy in range(4) for ix in range(4) if (ix, iy) != (1, 1)]
+    leaves += [(1, 2 + (q & 1), 2 + (q >> 1)) for q in range(4) if q != 3]
+    leaves += [(2, 6 + (q & 1), 6 + (q >> 1)) for q in range(4)]
+    with pytest.raises(af.AFError) as e:
+        af.Hierarchy(ctx, afsynth.sort_leaves(leaves))
+    assert e.value.status == _lib.AF_ERR_BALANCE
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_regrid_and_side_relations_match_oracle(seed):
+    rng = np.random.default_rng(seed)
+    n0 = 2 + seed % 2
+    ctx = af.Context(af.Problem(eq=1, prec=0, m=8, n0x=n0, n0y=n0, lmax=4))
+    o = oracle.Hier(1, 8, n0, n0, 4)
+    leaves = afsynth.uniform_leaves(n0, n0, 1)
+    o.set_leaves(leaves)
+    h = af.Hierarchy(ctx, leaves)
+    for _ in range(6):
+        tags = rng.integers(-1, 2, len(leaves)).astype(np.int8)
+        o.regrid(tags)
+        h = h.regrid(tags)
+        assert h.leaves() == o.leaves()
+        np.testing.assert_array_equal(h.side_relations(), o.side_relations())
+        leaves = h.leaves()
+    assert len(set(l for l, _, _ in leaves)) >= 2
+
+
+def test_level_ranges_cover_sorted_leaves():
+    ctx = af.Context(af.Problem(eq=0, prec=0, m=8, n0x=2, n0y=2, lmax=2))
+    h = af.Hierarchy(ctx, afsynth.diagonal_leaves(2, 1))
+    total = 0
+    for l in range(3):
+        f, c = h.level_range(l)
+        assert all(lv == l for lv, _, _ in h.leaves()[f:f + c])
+        total += c
+    assert total == len(h) and h.finest() == 2

@@ -32,6 +32,23 @@ def _valid_masks(m):
 
 
 @pytest.mark.parametrize("eq", [0, 1])
+def test_single_periodic_patch_equals_single_grid(eq):
+    """One patch covering the periodic domain fills its ghosts from its own
+    periodic images (Sec. 3.1 same-level copy with wrap)."""
+    m = 16
+    data = afsynth.fourier_modes(2) if eq == 0 else afsynth.gaussian_pulse(2)
+    h = oracle.Hier(eq, m, 1, 1, 0, a=1.0, b=0.5, c=1.0)
+    h.set_leaves([(0, 0, 0)])
+    h.init_from(data)
+    dt = 0.4 / m
+    h.run(dt, 4)
+    d1 = oracle.run_periodic(eq, afsynth.dofs_periodic(data, m, m), dt, 4, a=1.0, b=0.5, c=1.0)
+    blk = h.get_block(0)
+    for kind in oracle.KINDS:
+        np.testing.assert_allclose(blk[kind][:, 2:2 + m, 2:2 + m], d1[kind], atol=1e-13, err_msg=kind)
+
+
+@pytest.mark.parametrize("eq", [0, 1])
 def test_uniform_patches_equal_single_grid(eq):
     """A single level cut into patches with same-level periodic ghost fill
     reproduces the single-grid run (Sec. 3.1: same-level ghost copy).  The
