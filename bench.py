@@ -35,7 +35,22 @@ def parse():
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=48)
+    p.add_argument("--copy-probe", action="store_true",
+                   help="only run a plain 64 MiB device copy 20 times (HBM counter calibration)")
     return p.parse_args()
+
+
+def copy_probe():
+    """A plain device-to-device copy of known size: FETCH_SIZE / WRITE_SIZE
+    of this kernel calibrate the counters against bytes actually moved."""
+    import torch
+    n = 64 * 1024 * 1024 // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(20):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 20}), flush=True)
 
 
 def setup(prec, data):
@@ -110,6 +125,9 @@ def cpu_baseline(data, nsteps, dt):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: --gpus must be 1 (multi-GPU sharding is design-only)"}))
         sys.exit(2)

@@ -240,6 +240,7 @@ def _amr_run(eq, prec, leaves, n0, lmax, m, nsteps, data, use_graph):
     scale = np.zeros(prob.ncomp)
     for (l, _, _), b in zip(leaves, blocks):
         scale += np.abs(b["avg"][:, 2:2 + m, 2:2 + m]).sum(axis=(1, 2)) * prob.dx(l) * prob.dy(l)
+    scale = np.full(prob.ncomp, scale.max())  # components starting at zero share the overall scale
     g0, g1 = af.state_to_blocks(ctx, bufs[0]), af.state_to_blocks(ctx, bufs[1])
     got = [g1[k] if (mask >> leaves[k][0]) & 1 else g0[k] for k in range(len(leaves))]
     assert float(reg.abs().max()) == 0.0  # registers are consumed each coarse step
