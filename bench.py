@@ -35,6 +35,7 @@ def parse():
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=48)
+    p.add_argument("--general-steps", type=int, default=128)
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 64 MiB device copy 20 times (HBM counter calibration)")
     return p.parse_args()
@@ -77,40 +78,54 @@ def run_steps(ctx, h, bufs, reg, mask, nsteps, dt):
     return mask
 
 
-def time_path(prec, data, steps, warmup, dt):
+def _event_ms(fn):
     import torch
-    ctx, h, bufs, reg, blocks = setup(prec, data)
-    mask = 0
-    mask = run_steps(ctx, h, bufs, reg, mask, warmup, dt)
-    torch.cuda.synchronize()
-    # restart from the initial state so the timed run covers steps 0..K-1
-    import paper_2205_07572_amd as af
-    bufs[0].copy_(af.blocks_to_state(ctx, blocks))
-    mask = 0
-    torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
-    mask = run_steps(ctx, h, bufs, reg, mask, steps, dt)
+    out = fn()
     e1.record()
     torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    # dominant kernel: the patch step, timed alone with HIP events on the
-    # stream it runs on (same launch configuration as inside the graph)
-    nk = max(50, min(steps, 400))
-    cur = mask & 1
-    ctx.patch_step(bufs[cur], bufs[cur ^ 1], 0, N0 * N0, 0, dt, 0)
+    return e0.elapsed_time(e1), out
+
+
+def time_path(prec, data, steps, warmup, dt, general_steps):
+    """Autotune, then time `steps` steps of the level advance (the path this
+    workload takes: ghost exchange by gathering from same-level neighbours,
+    K steps per launch) and, for reference, `general_steps` coarse steps of
+    the general path (af_ghost_fill + af_patch_step replayed as a hipGraph)."""
+    import torch
+    import paper_2205_07572_amd as af
+    ctx, h, bufs, reg, blocks = setup(prec, data)
+    init = af.blocks_to_state(ctx, blocks)
+
+    def reset():
+        bufs[0].copy_(init)
+        bufs[1].zero_()
+        torch.cuda.synchronize()
+
+    step_us, adv_us = ctx.autotune(h, bufs, 0, dt, reps=10)
+    K, NT = ctx.advance_shape
+    reset()
+    ctx.level_advance(h, bufs, 0, 0, dt, warmup)
     torch.cuda.synchronize()
-    k0 = torch.cuda.Event(enable_timing=True)
-    k1 = torch.cuda.Event(enable_timing=True)
-    k0.record()
-    for _ in range(nk):
-        ctx.patch_step(bufs[cur], bufs[cur ^ 1], 0, N0 * N0, 0, dt, 0)
-    k1.record()
-    torch.cuda.synchronize()
-    k_ms = k0.elapsed_time(k1) / nk
+    reset()
+    ms, mask = _event_ms(lambda: ctx.level_advance(h, bufs, 0, 0, dt, steps))
     out = af.state_to_blocks(ctx, bufs[mask & 1])
-    return ms, k_ms, out, ctx.tile
+    # dominant kernel: one level-advance launch (K steps; a call with
+    # nsteps = K issues exactly one launch), timed with HIP events on the
+    # stream it runs on, in the benchmark's launch configuration
+    nl = 200
+    k_ms, _ = _event_ms(lambda: [ctx.level_advance(h, bufs, 0, 0, dt, K) for _ in range(nl)])
+    k_ms /= nl
+    # general path for reference
+    reset()
+    run_steps(ctx, h, bufs, reg, 0, 4, dt)
+    torch.cuda.synchronize()
+    reset()
+    g_ms, _ = _event_ms(lambda: run_steps(ctx, h, bufs, reg, 0, general_steps, dt))
+    return dict(ms=ms, k_ms=k_ms, K=K, NT=NT, out=out, tile=ctx.tile, step_us=step_us, adv_us=adv_us,
+                general_ms_per_step=g_ms / general_steps)
 
 
 def cpu_baseline(data, nsteps, dt):
@@ -139,10 +154,12 @@ def main():
     dt = T_FINAL / NSTEPS_T
     res = {}
     for name, prec in (("fp32", af.FP32), ("fp64", af.FP64)):
-        ms, k_ms, out, tile = time_path(prec, data, args.steps, args.warmup, dt)
-        res[name] = dict(ms=ms, k_ms=k_ms, out=out, tile=tile)
-        print(f"[bench] {name}: {args.steps} steps in {ms:.3f} ms, patch-step kernel {k_ms * 1e3:.2f} us "
-              f"(tile {tile})", file=sys.stderr, flush=True)
+        r = time_path(prec, data, args.steps, args.warmup, dt, args.general_steps)
+        res[name] = r
+        print(f"[bench] {name}: {args.steps} steps in {r['ms']:.3f} ms; level-advance launch (K={r['K']}, "
+              f"{r['NT']} threads) {r['k_ms'] * 1e3:.2f} us; tuned patch step {r['step_us']:.2f} us (tile "
+              f"{r['tile']}); general path {r['general_ms_per_step'] * 1e3:.2f} us/step",
+              file=sys.stderr, flush=True)
     # accuracy: FP32 vs FP64 (FP64 is parity-tested against the oracle) and
     # both against the exact solution when the run reaches T = 1
     def interior(blocks):
@@ -160,11 +177,13 @@ def main():
             ex.append(b)
         ae = interior(ex)
         err_exact = {"fp32": float(np.abs(a32 - ae).max()), "fp64": float(np.abs(a64 - ae).max())}
-    ms32, k32 = res["fp32"]["ms"], res["fp32"]["k_ms"]
+    ms32, k32, K32 = res["fp32"]["ms"], res["fp32"]["k_ms"], res["fp32"]["K"]
     ms64, k64 = res["fp64"]["ms"], res["fp64"]["k_ms"]
     ups32 = NCELL * args.steps / (ms32 * 1e-3)
     ups64 = NCELL * args.steps / (ms64 * 1e-3)
-    bytes32 = 8 * 4 * NCELL  # algorithmic: read 4 DOFs and write 4 DOFs per cell-update
+    # algorithmic bytes per launch: 8 words (read 4 DOFs, write 4 DOFs) per
+    # cell-update, K steps of all 512^2 cells
+    bytes32 = 8 * 4 * NCELL * K32
     achieved = bytes32 / (k32 * 1e-3) / 1e9
     line = {
         "metric": "cell-updates/s (FP32 vs FP64) of batched AMR AF step; % HBM roofline; L∞ err",
@@ -181,15 +200,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": "advection a=1 b=0.5, periodic unit square, one level of 16x16 patches of "
                                "32x32 cells (512^2), 2 ghost layers, seeded 8-mode Fourier data, T=1 "
-                               "(1280 steps, CFL 0.4); step = ghost fill + patch step, hipGraph replay",
-                   "patches": N0 * N0, "patch_cells": M, "tile_rows": res["fp32"]["tile"]},
+                               "(1280 steps, CFL 0.4); step = same-level ghost exchange + patch step, "
+                               "K steps per launch (af_level_advance, autotuned)",
+                   "patches": N0 * N0, "patch_cells": M, "steps_per_launch": K32,
+                   "threads_per_patch": res["fp32"]["NT"]},
         "fp64": {"value": ups64, "ms_per_step": ms64 / args.steps, "kernel_us": k64 * 1e3,
-                 "speedup_fp32_over_fp64": ups32 / ups64},
+                 "steps_per_launch": res["fp64"]["K"], "speedup_fp32_over_fp64": ups32 / ups64},
+        "general_path_us_per_step": {"fp32": res["fp32"]["general_ms_per_step"] * 1e3,
+                                     "fp64": res["fp64"]["general_ms_per_step"] * 1e3,
+                                     "what": "af_ghost_fill + af_patch_step per step, hipGraph replay"},
         "linf_fp32_vs_fp64_rel": linf_32_64,
         "linf_vs_exact_T1": err_exact,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_patch_step<float,adv,32,8>", "kernel_us": k32 * 1e3,
+                     "kernel": f"k_level_advance<float,adv,32,{K32},{res['fp32']['NT']}>", "kernel_us": k32 * 1e3,
                      "algorithmic_bytes_per_launch": bytes32},
     }
     if not args.no_cpu:

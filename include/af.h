@@ -220,6 +220,36 @@ af_status af_reduce_sum(af_ctx* ctx, const af_hier* h, const af_state* bufs,
                         uint32_t level_buf_mask, double* out, hipStream_t stream);
 
 /* ---------------------------------------------------------------------
+ * af_level_advance -- nsteps AF steps (Sec. 2) of all leaves of `level`, for
+ * a level whose every leaf has same-level leaves as its eight neighbours
+ * (e.g. a uniform level; else AF_ERR_STATE).  Each launch takes K steps
+ * (temporal blocking): a block gathers its patch and a K-cell halo straight
+ * from the neighbours' interiors (the values a same-level ghost fill would
+ * copy), advances K steps in LDS and writes the interior averages and the
+ * closed-square nodes to the other buffer.  Equal to nsteps x (af_ghost_fill
+ * + af_patch_step) up to FMA contraction.  The level's data moves between
+ * bufs[0] and bufs[1] (*level_buf_mask bit `level` updated after every
+ * launch); ghost layers of the result are NOT filled.
+ * --------------------------------------------------------------------- */
+af_status af_level_advance(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* level_buf_mask,
+                           int32_t level, double dt, int32_t nsteps, hipStream_t stream);
+/* level-advance kernel shapes (steps per launch K, block size) available for
+ * the context's problem; af_ctx_set_advance_shape picks one (autotuner). */
+int32_t af_ctx_advance_shapes(const af_ctx* ctx, int32_t* ks, int32_t* nts, int32_t cap);
+af_status af_ctx_set_advance_shape(af_ctx* ctx, int32_t k, int32_t nt);
+/* the shape af_level_advance will use (the tuned one, else the default) */
+af_status af_ctx_get_advance_shape(const af_ctx* ctx, int32_t* k, int32_t* nt);
+
+/* af_autotune -- picks, by timing `reps` launches of each candidate with HIP
+ * events on `stream`, the fastest patch-step tile height and (if the level's
+ * leaves all have same-level neighbours) the fastest level-advance shape for
+ * this context; best times per step (microseconds) are returned through the
+ * optional pointers (-1 if the level advance does not apply).  It steps the
+ * data in bufs (use scratch data).  Synchronises the stream. */
+af_status af_autotune(af_ctx* ctx, af_hier* h, af_state* bufs, int32_t level, double dt, int32_t reps,
+                      double* best_step_us, double* best_advance_us, hipStream_t stream);
+
+/* ---------------------------------------------------------------------
  * af_amr_coarse_step -- one coarse time step dt0 of the whole hierarchy
  * with subcycling (Sec. 3.2): full fill; then advance(0): step level l with
  * dt0/2^l (layer-1 region for the first of each pair of fine substeps),

@@ -85,6 +85,24 @@ class Context:
     def tile(self, ty):
         check(_lib.load().af_ctx_set_tile(self.h, int(ty)))
 
+    def advance_shapes(self):
+        """(K, threads) pairs of the level-advance kernel for this problem."""
+        L = _lib.load()
+        n = L.af_ctx_advance_shapes(self.h, None, None, 0)
+        ks = np.zeros(max(n, 1), np.int32)
+        nts = np.zeros(max(n, 1), np.int32)
+        L.af_ctx_advance_shapes(self.h, ks.ctypes.data_as(ctypes.c_void_p), nts.ctypes.data_as(ctypes.c_void_p), n)
+        return [(int(k), int(t)) for k, t in zip(ks[:n], nts[:n])]
+
+    def set_advance_shape(self, k, nt):
+        check(_lib.load().af_ctx_set_advance_shape(self.h, int(k), int(nt)))
+
+    @property
+    def advance_shape(self):
+        k, nt = ctypes.c_int32(), ctypes.c_int32()
+        check(_lib.load().af_ctx_get_advance_shape(self.h, ctypes.byref(k), ctypes.byref(nt)))
+        return k.value, nt.value
+
     # ----------------------------------------------------------------- state
     def new_state(self, npatch, pitch=None):
         """Zeroed state tensor [4][ncomp][npatch][m+5][pitch] on the GPU."""
@@ -135,6 +153,20 @@ class Context:
 
     def reduce_sum(self, hier, bufs, mask, out):
         check(_lib.load().af_reduce_sum(self.h, hier.h, self._pair(bufs), int(mask), _ptr(out), _stream()))
+
+    def level_advance(self, hier, bufs, mask, level, dt, nsteps):
+        mk = ctypes.c_uint32(mask)
+        check(_lib.load().af_level_advance(self.h, hier.h, self._pair(bufs), ctypes.byref(mk), int(level),
+                                           float(dt), int(nsteps), _stream()))
+        return mk.value
+
+    def autotune(self, hier, bufs, level, dt, reps=20):
+        """Time every kernel shape and keep the fastest (steps the data in bufs).
+        Returns (best patch-step us, best level-advance us per step or -1)."""
+        a, b = ctypes.c_double(), ctypes.c_double()
+        check(_lib.load().af_autotune(self.h, hier.h, self._pair(bufs), int(level), float(dt), int(reps),
+                                      ctypes.byref(a), ctypes.byref(b), _stream()))
+        return a.value, b.value
 
     def amr_coarse_step(self, hier, bufs, mask, dt0, flux_reg, use_graph=False):
         mk = ctypes.c_uint32(mask)

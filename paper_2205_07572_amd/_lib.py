@@ -19,7 +19,9 @@ EXPORTS = [
     "af_hier_create", "af_hier_destroy", "af_hier_num_leaves", "af_hier_get_leaves",
     "af_hier_level_range", "af_hier_finest_level", "af_hier_side_relations", "af_hier_side_mask",
     "af_patch_step", "af_ghost_fill", "af_flux_correct", "af_regrid_tag", "af_hier_regrid",
-    "af_regrid_apply", "af_reduce_sum", "af_amr_coarse_step",
+    "af_regrid_apply", "af_reduce_sum", "af_amr_coarse_step", "af_level_advance",
+    "af_ctx_advance_shapes", "af_ctx_set_advance_shape", "af_autotune",
+    "af_ctx_get_advance_shape",
 ]
 
 
@@ -50,6 +52,10 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2205_07572_amd.build`")
+    # libaf.so and torch both need libamdhip64.so.7; the first one loaded
+    # serves the process, so torch (whose runtime owns the device memory and
+    # streams we are handed) is loaded first.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i32 = ctypes.c_int32
@@ -80,9 +86,15 @@ def load():
     L.af_regrid_apply.argtypes = [P, P, S, ctypes.c_uint32, P, S, P]
     L.af_reduce_sum.argtypes = [P, P, S, ctypes.c_uint32, P, P]
     L.af_amr_coarse_step.argtypes = [P, P, S, ctypes.POINTER(ctypes.c_uint32), D, P, i32, P]
+    L.af_level_advance.argtypes = [P, P, S, ctypes.POINTER(ctypes.c_uint32), i32, D, i32, P]
+    L.af_ctx_advance_shapes.argtypes = [P, P, P, i32]
+    L.af_ctx_advance_shapes.restype = i32
+    L.af_ctx_set_advance_shape.argtypes = [P, i32, i32]
+    L.af_autotune.argtypes = [P, P, S, i32, D, i32, P, P, P]
+    L.af_ctx_get_advance_shape.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     for name in EXPORTS:
         if name not in ("af_last_error", "af_hier_num_leaves", "af_ctx_get_tile", "af_hier_finest_level",
-                        "af_hier_side_mask"):
+                        "af_hier_side_mask", "af_ctx_advance_shapes"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

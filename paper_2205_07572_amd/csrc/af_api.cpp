@@ -40,6 +40,7 @@ struct af_ctx {
   af_problem P;
   int ncomp;
   int ty = 0;  // step tile height (rows per block)
+  int adv_k = 0, adv_nt = 0;  // level-advance steps per launch and block size (0 = default)
   // fill-set entries of one patch block (device)
   std::vector<int32_t> h_entries;
   int32_t* d_entries = nullptr;  // uploaded on first device use
@@ -79,6 +80,10 @@ struct af_hier {
   std::vector<int> face_off;  // per coarse level offset into d_faces
   std::vector<CFFace> all_faces;
   bool on_device = false;     // tables are uploaded on first device use
+  // per level: 3x3 same-level neighbourhoods (built on first use); empty
+  // vector = not built, nbr_ok[l] = 0 if some neighbour is not a same-level leaf
+  std::vector<int32_t*> d_nbr;
+  std::vector<int> nbr_ok;
   HierDev dev{};
   std::map<GraphKey, hipGraphExec_t> graphs;
 };
@@ -317,6 +322,7 @@ af_status af_hier_destroy(af_hier* h) {
   (void)hipFree(h->d_iy);
   (void)hipFree(h->d_side_mask);
   (void)hipFree(h->d_faces);
+  for (int32_t* p : h->d_nbr) (void)hipFree(p);
   delete h;
   return AF_OK;
 }
@@ -538,6 +544,222 @@ af_status af_reduce_sum(af_ctx* ctx, const af_hier* h, const af_state* bufs, uin
   AF_HIP(launch_sum(ctx->fp32(), make_buf(ctx, &bufs[0], &bufs[1], mask), h->dev, ctx->dx(0) * ctx->dy(0),
                     ctx->d_part, out, stream));
   return AF_OK;
+}
+
+// ----------------------------------------------------------------- level advance
+
+namespace {
+
+af_status level_neighbours(af_hier* h, int level, const int32_t** out) {
+  if (h->d_nbr.empty()) {
+    h->d_nbr.assign(h->H.lmax + 1, nullptr);
+    h->nbr_ok.assign(h->H.lmax + 1, -1);
+  }
+  if (h->nbr_ok[level] < 0) {
+    const int first = h->H.level_count[level] ? h->H.level_first[level] : 0;
+    const int count = h->H.level_count[level];
+    std::vector<int32_t> t(size_t(count) * 9);
+    int ok = 1;
+    for (int k = 0; k < count && ok; ++k) {
+      const Leaf& L = h->H.leaves[first + k];
+      for (int dy = -1; dy <= 1; ++dy)
+        for (int dx = -1; dx <= 1; ++dx) {
+          const int id = h->H.find(level, L.ix + dx, L.iy + dy);
+          if (id < 0) ok = 0;
+          t[size_t(k) * 9 + (dy + 1) * 3 + (dx + 1)] = id;
+        }
+    }
+    h->nbr_ok[level] = ok;
+    if (ok && count) {
+      hipError_t err;
+      h->d_nbr[level] = dev_upload(t, &err);
+      if (err != hipSuccess) return fail(AF_ERR_DEVICE, "neighbour table upload");
+    }
+  }
+  if (!h->nbr_ok[level])
+    return fail(AF_ERR_STATE, "af_level_advance: a patch of this level has a neighbour on another level");
+  *out = h->d_nbr[level];
+  return AF_OK;
+}
+
+void default_advance_shape(const af_ctx* c, int* k, int* nt) {
+  int ks[32], nts[32];
+  const int n = level_advance_shapes(c->fp32(), c->P.eq, c->P.m, ks, nts, 32);
+  *k = 0;
+  *nt = 0;
+  if (c->adv_k) {
+    for (int i = 0; i < n; ++i)
+      if (ks[i] == c->adv_k && nts[i] == c->adv_nt) { *k = ks[i]; *nt = nts[i]; return; }
+  }
+  // default: the largest K with the smallest block
+  for (int i = 0; i < n; ++i)
+    if (ks[i] > *k || (ks[i] == *k && nts[i] < *nt)) { *k = ks[i]; *nt = nts[i]; }
+}
+
+}  // namespace
+
+af_status af_ctx_set_advance_shape(af_ctx* ctx, int32_t k, int32_t nt) {
+  if (!ctx) return fail(AF_ERR_ARG, "null ctx");
+  int ks[32], nts[32];
+  const int n = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, ks, nts, 32);
+  for (int i = 0; i < n; ++i)
+    if (ks[i] == k && nts[i] == nt) {
+      ctx->adv_k = k;
+      ctx->adv_nt = nt;
+      return AF_OK;
+    }
+  return fail(AF_ERR_ARG, "unsupported level-advance shape for this problem");
+}
+
+af_status af_ctx_get_advance_shape(const af_ctx* ctx, int32_t* k, int32_t* nt) {
+  if (!ctx || !k || !nt) return fail(AF_ERR_ARG, "null argument");
+  int kk, nn;
+  default_advance_shape(ctx, &kk, &nn);
+  *k = kk;
+  *nt = nn;
+  return AF_OK;
+}
+
+int32_t af_ctx_advance_shapes(const af_ctx* ctx, int32_t* ks, int32_t* nts, int32_t cap) {
+  if (!ctx) return -1;
+  int k2[32], n2[32];
+  const int n = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, k2, n2, 32);
+  for (int i = 0; i < n && i < cap; ++i) {
+    if (ks) ks[i] = k2[i];
+    if (nts) nts[i] = n2[i];
+  }
+  return n;
+}
+
+af_status af_level_advance(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* mask, int32_t level, double dt,
+                           int32_t nsteps, hipStream_t stream) {
+  if (!ctx || !h || !mask) return fail(AF_ERR_ARG, "null argument");
+  af_status s = check_pair(ctx, h, bufs, "af_level_advance");
+  if (s != AF_OK) return s;
+  if (level < 0 || level > h->H.lmax) return fail(AF_ERR_ARG, "level out of range");
+  if (nsteps < 0) return fail(AF_ERR_ARG, "negative step count");
+  for (int k = 0; k < 4; ++k)
+    if (bufs[0].dof[k] == bufs[1].dof[k]) return fail(AF_ERR_ARG, "af_level_advance: the two buffers must differ");
+  if ((s = check_cfl(ctx, level, dt)) != AF_OK) return s;
+  const int count = h->H.level_count[level];
+  if (count == 0 || nsteps == 0) return AF_OK;
+  const int first = h->H.level_first[level];
+  const int32_t* nbr = nullptr;
+  if ((s = level_neighbours(h, level, &nbr)) != AF_OK) return s;
+  int K, NT;
+  default_advance_shape(ctx, &K, &NT);
+  if (K == 0) return fail(AF_ERR_ARG, "no level-advance kernel for this (precision, equation, m)");
+  const double dx = ctx->dx(level), dy = ctx->dy(level);
+  AdvanceLaunch L;
+  L.fp32 = ctx->fp32();
+  L.eq = ctx->P.eq;
+  L.m = ctx->P.m;
+  L.npatch = bufs[0].npatch;
+  L.pitch = bufs[0].pitch;
+  L.first = first;
+  L.count = count;
+  L.nbr = nbr;
+  L.dtdx = dt / dx;
+  L.dtdy = dt / dy;
+  L.a = ctx->P.a;
+  L.b = ctx->P.b;
+  L.c = ctx->P.c;
+  L.weights = weights_for(ctx, dt / dx, dt / dy);
+  int done = 0;
+  while (done < nsteps) {
+    // a tail shorter than K runs with the K = 1 (or 2) kernel of the same family
+    int kk = K, nt = NT;
+    if (nsteps - done < K) {
+      int ks[32], nts[32];
+      const int n = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, ks, nts, 32);
+      kk = 0;
+      for (int i = 0; i < n; ++i)
+        if (ks[i] <= nsteps - done && (ks[i] > kk || (ks[i] == kk && nts[i] < nt))) { kk = ks[i]; nt = nts[i]; }
+      if (kk == 0) return fail(AF_ERR_STATE, "no level-advance kernel short enough for the remaining steps");
+    }
+    L.k = kk;
+    L.nt = nt;
+    const int cur = (*mask >> level) & 1;
+    for (int k = 0; k < 4; ++k) {
+      L.in[k] = bufs[cur].dof[k];
+      L.out[k] = bufs[cur ^ 1].dof[k];
+    }
+    AF_HIP(launch_level_advance(L, stream));
+    *mask ^= (1u << level);
+    done += kk;
+  }
+  return AF_OK;
+}
+
+// ----------------------------------------------------------------- autotuner
+
+af_status af_autotune(af_ctx* ctx, af_hier* h, af_state* bufs, int32_t level, double dt, int32_t reps,
+                      double* best_step_us, double* best_advance_us, hipStream_t stream) {
+  if (!ctx || !h) return fail(AF_ERR_ARG, "null argument");
+  af_status s = check_pair(ctx, h, bufs, "af_autotune");
+  if (s != AF_OK) return s;
+  if (reps < 1) return fail(AF_ERR_ARG, "reps must be >= 1");
+  const int count = level >= 0 && level <= h->H.lmax ? h->H.level_count[level] : 0;
+  if (count == 0) return fail(AF_ERR_ARG, "level has no leaves");
+  const int first = h->H.level_first[level];
+  hipEvent_t e0, e1;
+  AF_HIP(hipEventCreate(&e0));
+  AF_HIP(hipEventCreate(&e1));
+  auto timed = [&](auto&& body, double* us) -> af_status {
+    af_status st = body();  // warm-up launch
+    if (st != AF_OK) return st;
+    if (hipEventRecord(e0, stream) != hipSuccess) return fail(AF_ERR_DEVICE, "event record");
+    for (int r = 0; r < reps; ++r)
+      if ((st = body()) != AF_OK) return st;
+    if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+      return fail(AF_ERR_DEVICE, "event sync");
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    *us = 1e3 * double(ms) / reps;
+    return AF_OK;
+  };
+  // patch-step tile height
+  double best = 1e300;
+  int best_ty = ctx->ty;
+  const int tys[5] = {2, 4, 8, 16, 32};
+  for (int ty : tys) {
+    if (!step_shape_supported(ctx->P.m, ty)) continue;
+    ctx->ty = ty;
+    double us;
+    s = timed([&]() { return af_patch_step(ctx, &bufs[0], &bufs[1], first, count, level, dt, 0, nullptr, nullptr, stream); },
+              &us);
+    if (s != AF_OK) break;
+    if (us < best) { best = us; best_ty = ty; }
+  }
+  ctx->ty = best_ty;
+  if (best_step_us) *best_step_us = best;
+  // level-advance shape (per step), if the level allows it
+  double best_adv = -1.0;
+  const int32_t* nbr = nullptr;
+  if (s == AF_OK && level_neighbours(h, level, &nbr) == AF_OK) {
+    int ks[32], nts[32];
+    const int n = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, ks, nts, 32);
+    double b2 = 1e300;
+    int bk = 0, bn = 0;
+    for (int i = 0; i < n; ++i) {
+      ctx->adv_k = ks[i];
+      ctx->adv_nt = nts[i];
+      uint32_t mk = 0;
+      double us;
+      s = timed([&]() { return af_level_advance(ctx, h, bufs, &mk, level, dt, ks[i], stream); }, &us);
+      if (s != AF_OK) break;
+      us /= ks[i];
+      if (us < b2) { b2 = us; bk = ks[i]; bn = nts[i]; }
+    }
+    ctx->adv_k = bk;
+    ctx->adv_nt = bn;
+    best_adv = b2;
+  }
+  g_err.clear();
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (best_advance_us) *best_advance_us = best_adv;
+  return s;
 }
 
 // ----------------------------------------------------------------- AMR driver

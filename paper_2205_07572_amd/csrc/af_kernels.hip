@@ -5,6 +5,8 @@
 // [m+5][pitch] (see include/af.h).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "af_internal.h"
 #include "af_launch.h"
 
@@ -236,6 +238,163 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
         }
       }
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Level advance: K steps of every patch of a level whose eight neighbours
+// are leaves of the same level, in one launch (temporal blocking).
+//
+// A block owns one patch.  It gathers the patch and a K-cell halo from the
+// interiors of the 3x3 neighbourhood (each DOF from the patch owning its
+// cell, Sec. 2 ownership: exactly the values a same-level ghost fill copies),
+// then takes K steps in LDS on shrinking regions (step s updates cells
+// [-(K-1-s), m+K-1-s)), and finally writes the interior averages and the
+// closed-square nodes.  Step s reads only data of step s-1 that lie inside
+// its own block, so K fused steps equal K separate fill+step passes.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct AdvanceArgs {
+  const T* in[4];
+  T* out[4];
+  int32_t npatch, pitch, first;
+  const int32_t* nbr;  // [count][9]: 3x3 neighbourhood, (dy+1)*3 + (dx+1)
+  T dtdx, dtdy, a, b, c;
+};
+
+template <typename T, int EQ, int M, int K, int NT>
+__global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, const typename WSel<T, EQ>::type W) {
+  constexpr int NCOMP = EQ ? 3 : 1;
+  constexpr int E = M + 2 * K + 1;  // node extent of the gathered block
+  constexpr int EMAX = M + 2 * K - 1;  // extended cells of the first step
+  constexpr int CPT = (EMAX * EMAX + NT - 1) / NT;
+  __shared__ T st[4][NCOMP][E][E];
+  __shared__ T ts[3][NCOMP][E][E];
+  __shared__ int32_t nb[9];
+
+  const int pl = blockIdx.x;
+  const int patch = A.first + pl;
+  if (threadIdx.x < 9) nb[threadIdx.x] = A.nbr[pl * 9 + threadIdx.x];
+  __syncthreads();
+  const size_t plane = size_t(M + 5) * A.pitch;
+
+  // ---- gather: LDS position (r, c) holds local index (c - K, r - K)
+  for (int e = threadIdx.x; e < 4 * NCOMP * E * E; e += NT) {
+    const int cc = e % E;
+    int t = e / E;
+    const int rr = t % E;
+    t /= E;
+    const int comp = t % NCOMP, kind = t / NCOMP;
+    const int i = cc - K, j = rr - K;
+    const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
+    const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
+    const int src = nb[(oy + 1) * 3 + (ox + 1)];
+    const int li = i - ox * M, lj = j - oy * M;
+    st[kind][comp][rr][cc] =
+        A.in[kind][(size_t(comp) * A.npatch + src) * plane + size_t(lj + kGhost) * A.pitch + (li + kGhost)];
+  }
+  __syncthreads();
+
+  const T inv36 = T(1) / T(36);
+#pragma unroll 1
+  for (int s = 0; s < K; ++s) {
+    const int lo = -(K - 1 - s), hi = M + (K - 1 - s);
+    const int span = hi - lo, EC = span + 1;
+    T fnew[CPT][3][NCOMP];
+    // ---- node values of the extended cells [lo, hi]^2
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int e = threadIdx.x + u * NT;
+      if (e >= EC * EC) break;
+      const int r = lo + e / EC + K, c = lo + e % EC + K;  // LDS position of cell (i, j)
+      const bool has_x = (r - K) < hi, has_y = (c - K) < hi;
+      if constexpr (EQ == 0) {
+#pragma unroll
+        for (int kind = 0; kind < 3; ++kind) {
+          if ((kind == NK_XEDGE && !has_x) || (kind == NK_YEDGE && !has_y)) continue;
+          const T h = adv_eval<T, E, E>(st, r + W.off[kind][0][1], c + W.off[kind][0][0], W.w[kind][0]);
+          const T f = adv_eval<T, E, E>(st, r + W.off[kind][1][1], c + W.off[kind][1][0], W.w[kind][1]);
+          ts[kind][0][r][c] = (st[kind + 1][0][r][c] + T(4) * h) + f;
+          fnew[u][kind][0] = f;
+        }
+      } else {
+        T res[2][3];
+        ac_eval<T, E, E, kNbCorner>(st, r, c, kNbCornerTab, W.corner, res);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          ts[NK_CORNER][q][r][c] = (st[1][q][r][c] + T(4) * res[0][q]) + res[1][q];
+          fnew[u][NK_CORNER][q] = res[1][q];
+        }
+        if (has_x) {
+          ac_eval<T, E, E, kNbEdge>(st, r, c, kNbXedgeTab, W.xedge, res);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            ts[NK_XEDGE][q][r][c] = (st[2][q][r][c] + T(4) * res[0][q]) + res[1][q];
+            fnew[u][NK_XEDGE][q] = res[1][q];
+          }
+        }
+        if (has_y) {
+          ac_eval<T, E, E, kNbEdge>(st, r, c, kNbYedgeTab, W.yedge, res);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            ts[NK_YEDGE][q][r][c] = (st[3][q][r][c] + T(4) * res[0][q]) + res[1][q];
+            fnew[u][NK_YEDGE][q] = res[1][q];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    // ---- commit the new point values, then update the averages of [lo, hi)^2
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int e = threadIdx.x + u * NT;
+      if (e >= EC * EC) break;
+      const int r = lo + e / EC + K, c = lo + e % EC + K;
+      const bool has_x = (r - K) < hi, has_y = (c - K) < hi;
+#pragma unroll
+      for (int q = 0; q < NCOMP; ++q) {
+        st[1][q][r][c] = fnew[u][NK_CORNER][q];
+        if (has_x) st[2][q][r][c] = fnew[u][NK_XEDGE][q];
+        if (has_y) st[3][q][r][c] = fnew[u][NK_YEDGE][q];
+      }
+      if (!has_x || !has_y) continue;  // cell (i,j) with i or j == hi is not updated
+      T FL[NCOMP], FR[NCOMP], GB[NCOMP], GT[NCOMP];
+#pragma unroll
+      for (int q = 0; q < NCOMP; ++q) {
+        FL[q] = face_sum(ts[NK_CORNER][q][r][c], ts[NK_XEDGE][q][r][c], ts[NK_CORNER][q][r + 1][c]);
+        FR[q] = face_sum(ts[NK_CORNER][q][r][c + 1], ts[NK_XEDGE][q][r][c + 1], ts[NK_CORNER][q][r + 1][c + 1]);
+        GB[q] = face_sum(ts[NK_CORNER][q][r][c], ts[NK_YEDGE][q][r][c], ts[NK_CORNER][q][r][c + 1]);
+        GT[q] = face_sum(ts[NK_CORNER][q][r + 1][c], ts[NK_YEDGE][q][r + 1][c], ts[NK_CORNER][q][r + 1][c + 1]);
+      }
+      T fL[NCOMP], fR[NCOMP], gB[NCOMP], gT[NCOMP];
+      if constexpr (EQ == 0) {
+        fL[0] = A.a * FL[0] * inv36; fR[0] = A.a * FR[0] * inv36;
+        gB[0] = A.b * GB[0] * inv36; gT[0] = A.b * GT[0] * inv36;
+      } else {
+        fL[0] = A.c * FL[1] * inv36; fL[1] = A.c * FL[0] * inv36; fL[2] = T(0);
+        fR[0] = A.c * FR[1] * inv36; fR[1] = A.c * FR[0] * inv36; fR[2] = T(0);
+        gB[0] = A.c * GB[2] * inv36; gB[1] = T(0); gB[2] = A.c * GB[0] * inv36;
+        gT[0] = A.c * GT[2] * inv36; gT[1] = T(0); gT[2] = A.c * GT[0] * inv36;
+      }
+#pragma unroll
+      for (int q = 0; q < NCOMP; ++q)
+        st[0][q][r][c] = st[0][q][r][c] - A.dtdx * (fR[q] - fL[q]) - A.dtdy * (gT[q] - gB[q]);
+    }
+    __syncthreads();
+  }
+
+  // ---- write the interior averages and the closed-square nodes
+  constexpr int NN = (M + 1) * (M + 1);
+  for (int e = threadIdx.x; e < NCOMP * NN; e += NT) {
+    const int q = e / NN, f = e - q * NN;
+    const int i = f % (M + 1), j = f / (M + 1);
+    const int r = j + K, c = i + K;
+    const size_t g = (size_t(q) * A.npatch + patch) * plane + size_t(j + kGhost) * A.pitch + (i + kGhost);
+    A.out[1][g] = st[1][q][r][c];
+    if (j < M) A.out[2][g] = st[2][q][r][c];
+    if (i < M) A.out[3][g] = st[3][q][r][c];
+    if (i < M && j < M) A.out[0][g] = st[0][q][r][c];
   }
 }
 
@@ -692,6 +851,60 @@ bool step_shape_supported(int m, int ty) {
     case 128: return ty == 2;
     default: return false;
   }
+}
+
+template <typename T, int EQ, int M, int K, int NT>
+static hipError_t launch_adv_t(const AdvanceLaunch& s, hipStream_t st) {
+  AdvanceArgs<T> A;
+  for (int k = 0; k < 4; ++k) {
+    A.in[k] = static_cast<const T*>(s.in[k]);
+    A.out[k] = static_cast<T*>(s.out[k]);
+  }
+  A.npatch = s.npatch; A.pitch = s.pitch; A.first = s.first; A.nbr = s.nbr;
+  A.dtdx = T(s.dtdx); A.dtdy = T(s.dtdy); A.a = T(s.a); A.b = T(s.b); A.c = T(s.c);
+  if constexpr (EQ == 0)
+    hipLaunchKernelGGL((k_level_advance<T, 0, M, K, NT>), dim3(unsigned(s.count)), dim3(NT), 0, st, A,
+                       *static_cast<const AdvWeights<T>*>(s.weights));
+  else
+    hipLaunchKernelGGL((k_level_advance<T, 1, M, K, NT>), dim3(unsigned(s.count)), dim3(NT), 0, st, A,
+                       *static_cast<const AcWeights<T>*>(s.weights));
+  return hipGetLastError();
+}
+
+// Supported (m, K, threads) shapes of the level advance, per precision and
+// equation (LDS: 7 E^2 ncomp words with E = m + 2K + 1).
+#define AF_ADV_SHAPES(X)                 \
+  X(float, 0, 32, 1, 256) X(float, 0, 32, 2, 256) X(float, 0, 32, 2, 512) X(float, 0, 32, 4, 512)  \
+  X(float, 0, 32, 4, 1024) X(float, 0, 32, 8, 1024) X(float, 0, 16, 1, 256) X(float, 0, 16, 2, 256)  \
+  X(float, 0, 16, 4, 256)                                                                             \
+  X(float, 0, 64, 1, 1024) X(float, 0, 64, 2, 1024)                                                   \
+  X(double, 0, 32, 1, 256) X(double, 0, 32, 2, 512) X(double, 0, 32, 4, 1024) X(double, 0, 16, 1, 256) \
+  X(double, 0, 16, 2, 256)                                                                            \
+  X(double, 0, 16, 4, 256)                                                                            \
+  X(float, 1, 16, 1, 256) X(float, 1, 16, 2, 256) X(float, 1, 32, 1, 512) X(float, 1, 32, 2, 512)     \
+  X(double, 1, 16, 1, 256) X(double, 1, 16, 2, 256)
+
+hipError_t launch_level_advance(const AdvanceLaunch& s, hipStream_t st) {
+  if (s.count <= 0) return hipSuccess;
+#define AF_ADV_CASE(T_, EQ_, M_, K_, NT_)                                                                  \
+  if ((std::is_same<T_, float>::value == s.fp32) && s.eq == EQ_ && s.m == M_ && s.k == K_ && s.nt == NT_) \
+    return launch_adv_t<T_, EQ_, M_, K_, NT_>(s, st);
+  AF_ADV_SHAPES(AF_ADV_CASE)
+#undef AF_ADV_CASE
+  return hipErrorInvalidValue;
+}
+
+int level_advance_shapes(bool fp32, int eq, int m, int* ks, int* nts, int cap) {
+  int n = 0;
+#define AF_ADV_LIST(T_, EQ_, M_, K_, NT_)                                                  \
+  if ((std::is_same<T_, float>::value == fp32) && eq == EQ_ && m == M_ && n < cap) { \
+    ks[n] = K_;                                                                           \
+    nts[n] = NT_;                                                                         \
+    ++n;                                                                                  \
+  }
+  AF_ADV_SHAPES(AF_ADV_LIST)
+#undef AF_ADV_LIST
+  return n;
 }
 
 template <typename T>

@@ -20,6 +20,17 @@ struct StepLaunch {
   const void* weights;  // AdvWeights<T> or AcWeights<T> matching fp32/eq
 };
 
+struct AdvanceLaunch {
+  bool fp32;
+  int eq, m, k, nt;
+  const void* in[4];
+  void* out[4];
+  int npatch, pitch, first, count;
+  const int32_t* nbr;
+  double dtdx, dtdy, a, b, c;
+  const void* weights;
+};
+
 struct BufLaunch {
   void* p[2][4];
   int npatch, pitch, m, ncomp;
@@ -27,6 +38,9 @@ struct BufLaunch {
 };
 
 hipError_t launch_patch_step(const StepLaunch& s, hipStream_t st);
+hipError_t launch_level_advance(const AdvanceLaunch& s, hipStream_t st);
+// fills (K, threads) pairs available for (precision, equation, m); returns the count
+int level_advance_shapes(bool fp32, int eq, int m, int* ks, int* nts, int cap);
 bool step_shape_supported(int m, int ty);
 hipError_t launch_ghost_fill(bool fp32, const BufLaunch& b, const HierDev& H, const int32_t* entries,
                              int nentries, int first_target, int ntargets, int tmin, int smin, bool phase_b,
