@@ -331,3 +331,91 @@ def diagonal_leaves(n0, lcoarse):
 
 def sort_leaves(leaves):
     return sorted(leaves, key=lambda t: (t[0], t[2], t[1]))
+
+
+# ---------------------------------------------------------------------------
+# Exact acoustic solutions on the periodic unit square by Fourier series
+# ---------------------------------------------------------------------------
+
+class FourierAcoustics:
+    """Exact solution of p_t + c div u = 0, u_t + c grad p = 0 on the periodic
+    unit square for u(0) = 0 and p(0) = sum_k phat_k e^{i k.x}:
+      p = sum phat_k cos(c|k|t) e^{ik.x},
+      u = -sum i (k/|k|) phat_k sin(c|k|t) e^{ik.x}.
+    Modes are given on a tensor grid k = 2 pi (a, b), |a|,|b| <= nmax.  Values
+    on tensor products of coordinates are evaluated as small matrix products;
+    cell averages multiply each mode by sinc(k dx/2) sinc(k dy/2)."""
+
+    def __init__(self, phat, nmax, c=1.0):
+        self.phat = phat  # complex [2nmax+1][2nmax+1], index [a][b] for kx = 2 pi a, ky = 2 pi b
+        self.nmax = nmax
+        self.c = c
+        n = np.arange(-nmax, nmax + 1)
+        self.kx = 2 * np.pi * n
+
+    def _coeffs(self, t):
+        KX, KY = np.meshgrid(self.kx, self.kx, indexing="ij")
+        K = np.sqrt(KX ** 2 + KY ** 2)
+        Ksafe = np.where(K == 0, 1.0, K)
+        cp = self.phat * np.cos(self.c * K * t)
+        s = self.phat * np.sin(self.c * K * t)
+        cu = -1j * (KX / Ksafe) * s
+        cv = -1j * (KY / Ksafe) * s
+        return cp, cu, cv
+
+    def grid_values(self, xs, ys, t, dx=None, dy=None):
+        """(3, len(ys), len(xs)) values at the tensor grid (xs, ys); with dx, dy
+        given, averages over cells of that size centred there."""
+        fx = np.exp(1j * np.outer(xs, self.kx))  # [nx][K]
+        fy = np.exp(1j * np.outer(ys, self.kx))
+        if dx is not None:
+            fx = fx * np.sinc(self.kx * dx / 2 / np.pi)[None]
+            fy = fy * np.sinc(self.kx * dy / 2 / np.pi)[None]
+        out = []
+        for C in self._coeffs(t):
+            out.append(np.real(fy @ C.T @ fx.T))  # [ny][nx]
+        return np.stack(out)
+
+    def block(self, m, g, x0p, y0p, dx, dy, t):
+        """DOFs of one patch block at time t, as afsynth.dofs_block lays them out."""
+        S1 = m + 2 * g + 1
+        loc = np.arange(S1) - g
+        xn, yn = x0p + loc * dx, y0p + loc * dy
+        xc, yc = xn + 0.5 * dx, yn + 0.5 * dy
+        res = {"avg": self.grid_values(xc, yc, t, dx, dy), "corner": self.grid_values(xn, yn, t),
+               "xedge": self.grid_values(xn, yc, t), "yedge": self.grid_values(xc, yn, t)}
+        last = m + 2 * g  # the outer node line has no cell
+        res["avg"][:, last:, :] = 0.0
+        res["avg"][:, :, last:] = 0.0
+        res["xedge"][:, last:, :] = 0.0
+        res["yedge"][:, :, last:] = 0.0
+        return res
+
+
+def gaussian_pulse_exact(d: InitialData, alpha=200.0, c=1.0, nmax=28):
+    """Fourier-series exact solution of gaussian_pulse (phat_k = (pi/alpha)
+    e^{-|k|^2/(4 alpha)} e^{-i k.x0})."""
+    x0, y0 = d.center
+    n = np.arange(-nmax, nmax + 1)
+    KX, KY = np.meshgrid(2 * np.pi * n, 2 * np.pi * n, indexing="ij")
+    phat = (np.pi / alpha) * np.exp(-(KX ** 2 + KY ** 2) / (4 * alpha)) * np.exp(-1j * (KX * x0 + KY * y0))
+    return FourierAcoustics(phat, nmax, c)
+
+
+def wave_packet_exact(d: InitialData, alpha=50.0, c=1.0, half_width=14):
+    """Fourier-series exact solution of wave_packet: phat_k = (G(k-k0) +
+    G(k+k0))/2 with G the transform of the periodised Gaussian centred at x0,
+    modes within half_width of +-k0 (in units of 2 pi)."""
+    x0, y0 = d.center
+    k0x, k0y = d.k
+    a0, b0 = int(round(k0x / (2 * np.pi))), int(round(k0y / (2 * np.pi)))
+    nmax = max(abs(a0), abs(b0)) + half_width
+    n = np.arange(-nmax, nmax + 1)
+    KX, KY = np.meshgrid(2 * np.pi * n, 2 * np.pi * n, indexing="ij")
+
+    def g(qx, qy):
+        return (np.pi / alpha) * np.exp(-(qx ** 2 + qy ** 2) / (4 * alpha))
+
+    ph0 = np.exp(1j * (k0x * x0 + k0y * y0))  # transform of g e^{ik0.x} is ghat(k-k0) e^{-i(k-k0).x0}
+    phat = 0.5 * (g(KX - k0x, KY - k0y) * ph0 + g(KX + k0x, KY + k0y) / ph0) * np.exp(-1j * (KX * x0 + KY * y0))
+    return FourierAcoustics(phat, nmax, c)

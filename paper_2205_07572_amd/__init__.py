@@ -73,9 +73,12 @@ class Context:
         self.h = h
 
     def __del__(self):
-        if getattr(self, "h", None):
-            _lib.load().af_ctx_destroy(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None):
+                _lib.load().af_ctx_destroy(self.h)
+                self.h = None
+        except Exception:  # interpreter shutdown
+            pass
 
     @property
     def tile(self):
@@ -192,9 +195,12 @@ class Hierarchy:
             self.h = h
 
     def __del__(self):
-        if getattr(self, "h", None):
-            _lib.load().af_hier_destroy(self.h)
-            self.h = None
+        try:
+            if getattr(self, "h", None):
+                _lib.load().af_hier_destroy(self.h)
+                self.h = None
+        except Exception:  # interpreter shutdown
+            pass
 
     def __len__(self):
         return _lib.load().af_hier_num_leaves(self.h)
