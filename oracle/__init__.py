@@ -69,6 +69,14 @@ def lib():
         L.or_hier_balanced.restype = I
         L.or_refine_block.argtypes = [P, I, I, I, P, P, P, P]
         L.or_coarsen_block.argtypes = [P, P, P, P, P, P]
+        L.or_cnn_num_params.argtypes = [I]
+        L.or_cnn_num_params.restype = I
+        L.or_cnn_forward.argtypes = [I, P, P, I, P, I, P]
+        L.or_cnn_forward.restype = D
+        L.or_cnn_grad.argtypes = [I, P, P, I, P, I, P, P]
+        L.or_cnn_grad.restype = D
+        L.or_round_bf16.argtypes = [D]
+        L.or_round_bf16.restype = D
         _lib = L
     return _lib
 
@@ -251,3 +259,41 @@ class Hier:
         lib().or_coarsen_block(self.h, k4.ctypes.data_as(P), _p(outs["avg"]),
                                _p(outs["corner"]), _p(outs["xedge"]), _p(outs["yedge"]))
         return outs
+
+
+# ---------------------------------------------------------------------------
+# learned tagger reference (not part of the paper's method)
+# ---------------------------------------------------------------------------
+
+def cnn_num_params(nin=13):
+    return lib().or_cnn_num_params(int(nin))
+
+
+def cnn_forward(params, x, labels=None, bf16=False):
+    """x: [B][nin][16][16]; returns (logits [B][3], mean cross-entropy)."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    B, nin = xx.shape[0], xx.shape[1]
+    logits = np.zeros((B, 3))
+    lab = None if labels is None else np.ascontiguousarray(labels, dtype=np.int32)
+    loss = lib().or_cnn_forward(nin, _p(p), _p(xx), B, lab.ctypes.data_as(P) if lab is not None else None,
+                                int(bf16), _p(logits))
+    return logits, loss
+
+
+def cnn_grad(params, x, labels, bf16=False, want_acts=False):
+    """Gradient of the mean cross-entropy; optionally the activations of
+    sample 0 ([z1, a1, z2, a2, z3, a3], each [32][16][16])."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    B, nin = xx.shape[0], xx.shape[1]
+    g = np.zeros_like(p)
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    acts = np.zeros((6, 32, 16, 16)) if want_acts else None
+    loss = lib().or_cnn_grad(nin, _p(p), _p(xx), B, lab.ctypes.data_as(P), int(bf16), _p(g),
+                             _p(acts) if acts is not None else None)
+    return (loss, g, acts) if want_acts else (loss, g)
+
+
+def round_bf16(v):
+    return lib().or_round_bf16(float(v))

@@ -1371,3 +1371,206 @@ void or_coarsen_block(void* hp, const int* kid4, double* out_avg, double* out_co
 }
 
 }  // extern "C"
+
+// ===========================================================================
+// Learned regrid tagger: CPU reference (not part of the paper's method).
+//
+// Network: three 3x3 convolutions with zero "same" padding on 16x16 inputs
+// (13 -> 32 -> 32 -> 32 channels), each followed by ReLU; global average
+// pooling; a linear head 32 -> 3 (logits for coarsen / keep / refine);
+// softmax cross-entropy averaged over the batch.  Layout NCHW, parameters
+// W_l[co][ci][ky][kx], b_l[co], Wh[3][32], bh[3], packed in that order.
+// With `bf16` set, every convolution operand (layer input and weight) is
+// rounded first to FP32 and then to BF16 (round to nearest even), as the GPU
+// path does; all arithmetic is FP64.
+// ===========================================================================
+namespace {
+
+constexpr int kImg = 16, kPix = kImg * kImg, kWidth = 32, kClasses = 3;
+
+double round_bf16(double v) {
+  float f = float(v);
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7f800000u) == 0x7f800000u) return f;  // inf / nan unchanged
+  const uint32_t lsb = (u >> 16) & 1u;
+  u += 0x7fffu + lsb;
+  u &= 0xffff0000u;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+struct CnnShape {
+  int cin[3], cout[3];
+  size_t off_w[3], off_b[3], off_wh, off_bh, total;
+};
+
+CnnShape cnn_shape(int nin) {
+  CnnShape s;
+  size_t o = 0;
+  for (int l = 0; l < 3; ++l) {
+    s.cin[l] = l == 0 ? nin : kWidth;
+    s.cout[l] = kWidth;
+    s.off_w[l] = o;
+    o += size_t(s.cout[l]) * s.cin[l] * 9;
+    s.off_b[l] = o;
+    o += s.cout[l];
+  }
+  s.off_wh = o;
+  o += size_t(kClasses) * kWidth;
+  s.off_bh = o;
+  o += kClasses;
+  s.total = o;
+  return s;
+}
+
+// out[co][p] = b[co] + sum_{ci,ky,kx} in[ci][p + (ky-1, kx-1)] w[co][ci][ky][kx]
+void conv3(const double* in, int cin, const double* w, const double* b, int cout, bool bf16, double* out) {
+  for (int co = 0; co < cout; ++co)
+    for (int y = 0; y < kImg; ++y)
+      for (int x = 0; x < kImg; ++x) {
+        double s = b[co];
+        for (int ci = 0; ci < cin; ++ci)
+          for (int ky = 0; ky < 3; ++ky)
+            for (int kx = 0; kx < 3; ++kx) {
+              const int yy = y + ky - 1, xx = x + kx - 1;
+              if (yy < 0 || yy >= kImg || xx < 0 || xx >= kImg) continue;
+              double a = in[size_t(ci) * kPix + yy * kImg + xx];
+              double ww = w[((size_t(co) * cin + ci) * 3 + ky) * 3 + kx];
+              if (bf16) {
+                a = round_bf16(a);
+                ww = round_bf16(ww);
+              }
+              s += a * ww;
+            }
+        out[size_t(co) * kPix + y * kImg + x] = s;
+      }
+}
+
+struct CnnTape {
+  std::vector<double> a[4];  // a[0] input, a[l] post-ReLU output of layer l
+  std::vector<double> z[3];  // pre-activations
+  double pooled[kWidth], logits[kClasses], prob[kClasses];
+};
+
+void cnn_forward_one(const CnnShape& S, const double* P, const double* x, bool bf16, CnnTape& T) {
+  T.a[0].assign(x, x + size_t(S.cin[0]) * kPix);
+  for (int l = 0; l < 3; ++l) {
+    T.z[l].assign(size_t(S.cout[l]) * kPix, 0.0);
+    conv3(T.a[l].data(), S.cin[l], P + S.off_w[l], P + S.off_b[l], S.cout[l], bf16, T.z[l].data());
+    T.a[l + 1].resize(T.z[l].size());
+    for (size_t i = 0; i < T.z[l].size(); ++i) T.a[l + 1][i] = T.z[l][i] > 0.0 ? T.z[l][i] : 0.0;
+  }
+  for (int c = 0; c < kWidth; ++c) {
+    double s = 0.0;
+    for (int p = 0; p < kPix; ++p) s += T.a[3][size_t(c) * kPix + p];
+    T.pooled[c] = s / kPix;
+  }
+  double mx = -1e300;
+  for (int k = 0; k < kClasses; ++k) {
+    double s = P[S.off_bh + k];
+    for (int c = 0; c < kWidth; ++c) s += P[S.off_wh + size_t(k) * kWidth + c] * T.pooled[c];
+    T.logits[k] = s;
+    mx = std::max(mx, s);
+  }
+  double den = 0.0;
+  for (int k = 0; k < kClasses; ++k) den += std::exp(T.logits[k] - mx);
+  for (int k = 0; k < kClasses; ++k) T.prob[k] = std::exp(T.logits[k] - mx) / den;
+}
+
+}  // namespace
+
+extern "C" {
+
+int or_cnn_num_params(int nin) { return int(cnn_shape(nin).total); }
+
+// x: [B][nin][16][16]; logits: [B][3]; returns the mean cross-entropy when
+// labels (0 coarsen, 1 keep, 2 refine) are given, else 0.
+double or_cnn_forward(int nin, const double* params, const double* x, int B, const int* labels, int bf16,
+                      double* logits) {
+  const CnnShape S = cnn_shape(nin);
+  double loss = 0.0;
+  for (int b = 0; b < B; ++b) {
+    CnnTape T;
+    cnn_forward_one(S, params, x + size_t(b) * nin * kPix, bf16 != 0, T);
+    for (int k = 0; k < kClasses; ++k) logits[size_t(b) * kClasses + k] = T.logits[k];
+    if (labels) loss -= std::log(T.prob[labels[b]]);
+  }
+  return labels ? loss / B : 0.0;
+}
+
+// Gradient of the mean cross-entropy with respect to all parameters
+// (backpropagation through the network above).  Also returns the layer
+// activations of sample 0 if acts != NULL: [z1, a1, z2, a2, z3, a3] each
+// [32][16][16].
+double or_cnn_grad(int nin, const double* params, const double* x, int B, const int* labels, int bf16,
+                   double* grad, double* acts) {
+  const CnnShape S = cnn_shape(nin);
+  std::fill(grad, grad + S.total, 0.0);
+  double loss = 0.0;
+  const bool rb = bf16 != 0;
+  for (int b = 0; b < B; ++b) {
+    CnnTape T;
+    cnn_forward_one(S, params, x + size_t(b) * nin * kPix, rb, T);
+    loss -= std::log(T.prob[labels[b]]);
+    if (acts && b == 0)
+      for (int l = 0; l < 3; ++l) {
+        std::copy(T.z[l].begin(), T.z[l].end(), acts + size_t(2 * l) * kWidth * kPix);
+        std::copy(T.a[l + 1].begin(), T.a[l + 1].end(), acts + size_t(2 * l + 1) * kWidth * kPix);
+      }
+    // d loss_b / d logits = prob - onehot, scaled by 1/B
+    double dlog[kClasses];
+    for (int k = 0; k < kClasses; ++k) dlog[k] = (T.prob[k] - (k == labels[b] ? 1.0 : 0.0)) / B;
+    double dpool[kWidth] = {};
+    for (int k = 0; k < kClasses; ++k) {
+      grad[S.off_bh + k] += dlog[k];
+      for (int c = 0; c < kWidth; ++c) {
+        grad[S.off_wh + size_t(k) * kWidth + c] += dlog[k] * T.pooled[c];
+        dpool[c] += dlog[k] * params[S.off_wh + size_t(k) * kWidth + c];
+      }
+    }
+    // through the pooling: every pixel of channel c gets dpool[c]/256
+    std::vector<double> da(size_t(kWidth) * kPix);
+    for (int c = 0; c < kWidth; ++c)
+      for (int p = 0; p < kPix; ++p) da[size_t(c) * kPix + p] = dpool[c] / kPix;
+    for (int l = 2; l >= 0; --l) {
+      const int cin = S.cin[l], cout = S.cout[l];
+      // through the ReLU
+      std::vector<double> dz(da.size()), dzr;
+      for (size_t i = 0; i < da.size(); ++i) dz[i] = T.z[l][i] > 0.0 ? da[i] : 0.0;
+      dzr = dz;  // operand of the weight and input gradients (BF16 on request)
+      if (rb)
+        for (double& v : dzr) v = round_bf16(v);
+      const double* W = params + S.off_w[l];
+      double* gW = grad + S.off_w[l];
+      double* gb = grad + S.off_b[l];
+      std::vector<double> dain(size_t(cin) * kPix, 0.0);
+      for (int co = 0; co < cout; ++co)
+        for (int y = 0; y < kImg; ++y)
+          for (int x = 0; x < kImg; ++x) {
+            gb[co] += dz[size_t(co) * kPix + y * kImg + x];
+            const double g = dzr[size_t(co) * kPix + y * kImg + x];
+            for (int ci = 0; ci < cin; ++ci)
+              for (int ky = 0; ky < 3; ++ky)
+                for (int kx = 0; kx < 3; ++kx) {
+                  const int yy = y + ky - 1, xx = x + kx - 1;
+                  if (yy < 0 || yy >= kImg || xx < 0 || xx >= kImg) continue;
+                  double a = T.a[l][size_t(ci) * kPix + yy * kImg + xx];
+                  double w = W[((size_t(co) * cin + ci) * 3 + ky) * 3 + kx];
+                  if (rb) {
+                    a = round_bf16(a);
+                    w = round_bf16(w);
+                  }
+                  gW[((size_t(co) * cin + ci) * 3 + ky) * 3 + kx] += g * a;
+                  dain[size_t(ci) * kPix + yy * kImg + xx] += g * w;
+                }
+          }
+      da.swap(dain);
+    }
+  }
+  return loss / B;
+}
+
+double or_round_bf16(double v) { return round_bf16(v); }
+
+}  // extern "C"
