@@ -267,6 +267,54 @@ af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* 
 /* device uint8 [nleaves]: bit s set when side s borders another level */
 const uint8_t* af_hier_side_mask(const af_hier* h);
 
+/* =====================================================================
+ * Learned regrid tagger (a project addition; not part of the paper's
+ * method).  A CNN of three 3x3 convolutions (nin -> 32 -> 32 -> 32, zero
+ * padding, ReLU) on 16x16 patch fields, global average pooling and a linear
+ * head to 3 classes (coarsen, keep, refine), trained with softmax
+ * cross-entropy.  Convolutions run as BF16 implicit GEMMs on the matrix
+ * cores with FP32 accumulation; parameters, bias, ReLU, head, loss and the
+ * optimizer are FP32.  Parameters are packed W1[32][nin][3][3], b1, W2, b2,
+ * W3, b3, Wh[3][32], bh (host float arrays of af_cnn_num_params()).
+ * The object owns its parameters, optimizer state and workspace.
+ * ===================================================================== */
+typedef struct af_cnn af_cnn;
+const char* af_cnn_last_error(void);
+af_status af_cnn_create(int32_t nin, af_cnn** out);
+af_status af_cnn_destroy(af_cnn* cnn);
+int32_t af_cnn_num_params(const af_cnn* cnn);
+af_status af_cnn_set_params(af_cnn* cnn, const float* host_params); /* also resets the optimizer */
+af_status af_cnn_get_params(const af_cnn* cnn, float* host_params);
+/* per-channel standardisation of the features, host arrays [nin] */
+af_status af_cnn_set_normalization(af_cnn* cnn, const float* mean, const float* inv_std);
+/* x: device FP32 [B][nin][16][16]; logits: device FP32 [B][3]; acts: NULL or
+ * device FP32 [3][B*256][32] receiving the three layers' pre-activations
+ * (pixel-major, channel-minor). */
+af_status af_cnn_forward(af_cnn* cnn, const float* x, int32_t B, float* logits, float* acts,
+                         hipStream_t stream);
+/* mean cross-entropy over the batch (device float [1]) and its gradient
+ * (device float [num_params], or NULL for the internal buffer used by
+ * af_cnn_adam_step).  labels: device int32 [B], 0 coarsen, 1 keep, 2 refine. */
+af_status af_cnn_loss_grad(af_cnn* cnn, const float* x, const int32_t* labels, int32_t B, float* loss,
+                           float* grad, hipStream_t stream);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8) step t >= 1 with learning rate lr;
+ * grad NULL = the internal gradient of the last af_cnn_loss_grad. */
+af_status af_cnn_adam_step(af_cnn* cnn, const float* grad, float lr, int32_t t, hipStream_t stream);
+/* features of every leaf (m = 16 only): 12 channels (p,u,v) x (avg, corner,
+ * xedge, yedge) of the cells' owned DOFs, then the leaf level, standardised;
+ * x: device FP32 [nleaves][nin][16][16]. */
+af_status af_cnn_features(af_ctx* ctx, af_cnn* cnn, const af_hier* h, const af_state* bufs,
+                          uint32_t level_buf_mask, float* x, hipStream_t stream);
+/* learned tags with the plain criterion as fallback: refine if the network
+ * or the plain tag (device int8 [nleaves], from af_regrid_tag) says refine,
+ * coarsen only if both say coarsen, the plain tag if the network output is
+ * not finite; level limits as af_regrid_tag.  tags: device int8 [nleaves];
+ * learned: NULL or device int8 [nleaves] receiving the network's own tag
+ * (2 where it fell back). */
+af_status af_cnn_tag(af_ctx* ctx, af_cnn* cnn, const af_hier* h, const af_state* bufs,
+                     uint32_t level_buf_mask, const int8_t* plain, int8_t* tags, int8_t* learned,
+                     hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -77,6 +77,7 @@ def lib():
         L.or_cnn_grad.restype = D
         L.or_round_bf16.argtypes = [D]
         L.or_round_bf16.restype = D
+        L.or_cnn_conv.argtypes = [P, I, I, P, P, I, P]
         _lib = L
     return _lib
 
@@ -297,3 +298,13 @@ def cnn_grad(params, x, labels, bf16=False, want_acts=False):
 
 def round_bf16(v):
     return lib().or_round_bf16(float(v))
+
+
+def cnn_conv(x, w, b, bf16=False):
+    """One 3x3 convolution plus bias: x [B][cin][16][16] -> [B][32][16][16]."""
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    ww = np.ascontiguousarray(w, dtype=np.float64)
+    bb = np.ascontiguousarray(b, dtype=np.float64)
+    out = np.zeros((xx.shape[0], 32, 16, 16))
+    lib().or_cnn_conv(_p(xx), xx.shape[0], xx.shape[1], _p(ww), _p(bb), int(bf16), _p(out))
+    return out

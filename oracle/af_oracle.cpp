@@ -1573,4 +1573,11 @@ double or_cnn_grad(int nin, const double* params, const double* x, int B, const 
 
 double or_round_bf16(double v) { return round_bf16(v); }
 
+// One 3x3 convolution with bias (no activation): in [B][cin][16][16],
+// w [32][cin][3][3], b [32], out [B][32][16][16].
+void or_cnn_conv(const double* in, int B, int cin, const double* w, const double* b, int bf16, double* out) {
+  for (int s = 0; s < B; ++s)
+    conv3(in + size_t(s) * cin * kPix, cin, w, b, kWidth, bf16 != 0, out + size_t(s) * kWidth * kPix);
+}
+
 }  // extern "C"

@@ -259,3 +259,79 @@ def state_to_blocks(ctx: Context, t, npatch=None):
     host = t.detach().double().cpu().numpy()
     n = npatch or t.shape[2]
     return [{kind: host[k, :, p, :, :S1].copy() for k, kind in enumerate(KINDS)} for p in range(n)]
+
+
+class Tagger:
+    """Learned regrid tagger (libaf.so af_cnn_*): BF16 matrix-core CNN with
+    FP32 parameters and Adam."""
+
+    NIN = 13
+
+    def __init__(self, nin=NIN):
+        L = _lib.load()
+        h = ctypes.c_void_p()
+        _lib.check_cnn(L.af_cnn_create(int(nin), ctypes.byref(h)))
+        self.h = h
+        self.nin = nin
+        self.nparams = L.af_cnn_num_params(h)
+        self.t = 0
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                _lib.load().af_cnn_destroy(self.h)
+                self.h = None
+        except Exception:  # interpreter shutdown
+            pass
+
+    def set_params(self, p):
+        a = np.ascontiguousarray(p, dtype=np.float32)
+        assert a.size == self.nparams
+        _lib.check_cnn(_lib.load().af_cnn_set_params(self.h, a.ctypes.data_as(ctypes.c_void_p)))
+        self.t = 0
+
+    def get_params(self):
+        a = np.zeros(self.nparams, np.float32)
+        _lib.check_cnn(_lib.load().af_cnn_get_params(self.h, a.ctypes.data_as(ctypes.c_void_p)))
+        return a
+
+    def set_normalization(self, mean, inv_std):
+        m = np.ascontiguousarray(mean, dtype=np.float32)
+        s = np.ascontiguousarray(inv_std, dtype=np.float32)
+        _lib.check_cnn(_lib.load().af_cnn_set_normalization(self.h, m.ctypes.data_as(ctypes.c_void_p),
+                                                             s.ctypes.data_as(ctypes.c_void_p)))
+
+    def forward(self, x, acts=False):
+        torch = _torch()
+        B = x.shape[0]
+        logits = torch.zeros((B, 3), dtype=torch.float32, device="cuda")
+        a = torch.zeros((3, B * 256, 32), dtype=torch.float32, device="cuda") if acts else None
+        _lib.check_cnn(_lib.load().af_cnn_forward(self.h, _ptr(x), int(B), _ptr(logits), _ptr(a), _stream()))
+        return (logits, a) if acts else logits
+
+    def loss_grad(self, x, labels, grad=None):
+        torch = _torch()
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        _lib.check_cnn(_lib.load().af_cnn_loss_grad(self.h, _ptr(x), _ptr(labels), int(x.shape[0]), _ptr(loss),
+                                                    _ptr(grad), _stream()))
+        return loss
+
+    def adam_step(self, lr, grad=None):
+        self.t += 1
+        _lib.check_cnn(_lib.load().af_cnn_adam_step(self.h, _ptr(grad), ctypes.c_float(lr), int(self.t), _stream()))
+
+    def features(self, ctx, hier, bufs, mask):
+        torch = _torch()
+        x = torch.zeros((len(hier), self.nin, 16, 16), dtype=torch.float32, device="cuda")
+        _lib.check_cnn(_lib.load().af_cnn_features(ctx.h, self.h, hier.h, ctx._pair(bufs), int(mask), _ptr(x),
+                                                   _stream()))
+        return x
+
+    def tag(self, ctx, hier, bufs, mask, plain):
+        torch = _torch()
+        n = len(hier)
+        tags = torch.zeros(n, dtype=torch.int8, device="cuda")
+        learned = torch.zeros(n, dtype=torch.int8, device="cuda")
+        _lib.check_cnn(_lib.load().af_cnn_tag(ctx.h, self.h, hier.h, ctx._pair(bufs), int(mask), _ptr(plain),
+                                              _ptr(tags), _ptr(learned), _stream()))
+        return tags, learned

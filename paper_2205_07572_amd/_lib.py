@@ -22,6 +22,9 @@ EXPORTS = [
     "af_regrid_apply", "af_reduce_sum", "af_amr_coarse_step", "af_level_advance",
     "af_ctx_advance_shapes", "af_ctx_set_advance_shape", "af_autotune",
     "af_ctx_get_advance_shape",
+    "af_cnn_last_error", "af_cnn_create", "af_cnn_destroy", "af_cnn_num_params", "af_cnn_set_params",
+    "af_cnn_get_params", "af_cnn_set_normalization", "af_cnn_forward", "af_cnn_loss_grad",
+    "af_cnn_adam_step", "af_cnn_features", "af_cnn_tag",
 ]
 
 
@@ -92,9 +95,22 @@ def load():
     L.af_ctx_set_advance_shape.argtypes = [P, i32, i32]
     L.af_autotune.argtypes = [P, P, S, i32, D, i32, P, P, P]
     L.af_ctx_get_advance_shape.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.af_cnn_last_error.restype = ctypes.c_char_p
+    L.af_cnn_create.argtypes = [i32, ctypes.POINTER(P)]
+    L.af_cnn_destroy.argtypes = [P]
+    L.af_cnn_num_params.argtypes = [P]
+    L.af_cnn_num_params.restype = i32
+    L.af_cnn_set_params.argtypes = [P, P]
+    L.af_cnn_get_params.argtypes = [P, P]
+    L.af_cnn_set_normalization.argtypes = [P, P, P]
+    L.af_cnn_forward.argtypes = [P, P, i32, P, P, P]
+    L.af_cnn_loss_grad.argtypes = [P, P, P, i32, P, P, P]
+    L.af_cnn_adam_step.argtypes = [P, P, ctypes.c_float, i32, P]
+    L.af_cnn_features.argtypes = [P, P, P, S, ctypes.c_uint32, P, P]
+    L.af_cnn_tag.argtypes = [P, P, P, S, ctypes.c_uint32, P, P, P, P]
     for name in EXPORTS:
         if name not in ("af_last_error", "af_hier_num_leaves", "af_ctx_get_tile", "af_hier_finest_level",
-                        "af_hier_side_mask", "af_ctx_advance_shapes"):
+                        "af_hier_side_mask", "af_ctx_advance_shapes", "af_cnn_last_error", "af_cnn_num_params"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L
@@ -103,4 +119,10 @@ def load():
 def check(status):
     if status != AF_OK:
         msg = load().af_last_error()
+        raise AFError(status, msg.decode() if msg else "")
+
+
+def check_cnn(status):
+    if status != AF_OK:
+        msg = load().af_cnn_last_error()
         raise AFError(status, msg.decode() if msg else "")

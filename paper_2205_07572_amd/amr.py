@@ -4,7 +4,8 @@ the conservative fix, periodic regridding (Sec. 3).
 Only calls into libaf.so; tags cross to the host once per regrid (the only
 device-to-host transfer of the loop), the host computes the new leaf set
 (af_hier_regrid), the device transfers the DOFs (af_regrid_apply) and fills
-the ghosts, and the next coarse steps are captured anew as a hipGraph.
+the ghosts.  Coarse steps are launched eagerly by default; hipGraph replay
+(captured anew per hierarchy) is optional.
 """
 from __future__ import annotations
 

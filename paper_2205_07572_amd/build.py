@@ -15,7 +15,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libaf.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["af_kernels.hip", "af_api.cpp", "af_hier.cpp", "af_weights.cpp"]
+SOURCES = ["af_kernels.hip", "af_api.cpp", "af_hier.cpp", "af_weights.cpp", "af_cnn.hip"]
 HEADERS = ["af_internal.h", "af_launch.h", "af_hier.h", "af_weights.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

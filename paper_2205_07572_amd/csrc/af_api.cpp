@@ -691,6 +691,36 @@ af_status af_level_advance(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* ma
   return AF_OK;
 }
 
+// ----------------------------------------------------------------- tagger access
+
+struct AfTagView {
+  bool fp32;
+  int ncomp, m, npatch, pitch, lmax, nleaves;
+  const void* dof0[4];
+  const void* dof1[4];
+  const int32_t* plevel;
+};
+
+af_status af_internal_tag_view(const af_ctx* ctx, const af_hier* h, const af_state* bufs, AfTagView* v) {
+  if (!ctx || !h || !v) return fail(AF_ERR_ARG, "null argument");
+  af_status s = check_pair(ctx, h, bufs, "tag view");
+  if (s != AF_OK) return s;
+  if ((s = hier_device(const_cast<af_hier*>(h))) != AF_OK) return s;
+  v->fp32 = ctx->fp32();
+  v->ncomp = ctx->ncomp;
+  v->m = ctx->P.m;
+  v->npatch = bufs[0].npatch;
+  v->pitch = bufs[0].pitch;
+  v->lmax = ctx->P.lmax;
+  v->nleaves = int(h->H.leaves.size());
+  for (int k = 0; k < 4; ++k) {
+    v->dof0[k] = bufs[0].dof[k];
+    v->dof1[k] = bufs[1].dof[k];
+  }
+  v->plevel = h->d_level;
+  return AF_OK;
+}
+
 // ----------------------------------------------------------------- autotuner
 
 af_status af_autotune(af_ctx* ctx, af_hier* h, af_state* bufs, int32_t level, double dt, int32_t reps,
