@@ -36,6 +36,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-steps", type=int, default=48)
     p.add_argument("--general-steps", type=int, default=128)
+    p.add_argument("--sweep", action="store_true",
+                   help="roofline sweep: uniform grids up to 4096^2 (HBM resident); one JSON line per case")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 64 MiB device copy 20 times (HBM counter calibration)")
     return p.parse_args()
@@ -128,6 +130,50 @@ def time_path(prec, data, steps, warmup, dt, general_steps):
                 general_ms_per_step=g_ms / general_steps)
 
 
+def sweep():
+    """Kernel bandwidth on uniform grids of 32^2 patches from 1024^2 to
+    4096^2 cells (two state buffers of up to 2.9 GB in FP32, far beyond the
+    256 MB Infinity Cache), advection, FP32 and FP64: the autotuned level
+    advance and the plain patch step, each timed with HIP events over
+    repeated launches on the stream they run on."""
+    import torch
+    import afsynth
+    import paper_2205_07572_amd as af
+    data = afsynth.fourier_modes(1)
+    for n0 in (32, 64, 128):
+        N = n0 * M
+        for name, prec, wb in (("fp32", af.FP32, 4), ("fp64", af.FP64, 8)):
+            prob = af.Problem(eq=af.ADVECTION, prec=prec, m=M, n0x=n0, n0y=n0, lmax=0, a=1.0, b=0.5)
+            ctx = af.Context(prob)
+            h = af.Hierarchy(ctx, afsynth.uniform_leaves(n0, n0, 0))
+            d0 = afsynth.dofs_periodic(data, N, N, nq=2)
+            blk = afsynth.periodic_to_blocks(d0, M)
+            t = ctx.new_state(n0 * n0)
+            host = np.stack([blk[k] for k in af.KINDS])  # [4][P][ncomp][S1][S1]
+            t.copy_(torch.from_numpy(host.transpose(0, 2, 1, 3, 4).copy()).to(t.dtype))
+            bufs = [t, torch.zeros_like(t)]
+            dt = 0.4 / N
+            step_us, adv_us = ctx.autotune(h, bufs, 0, dt, reps=5)
+            K, NT = ctx.advance_shape
+            nl = max(4, 64 // K)
+            ms, _ = _event_ms(lambda: [ctx.level_advance(h, bufs, 0, 0, dt, K) for _ in range(nl)])
+            adv_launch_us = ms * 1e3 / nl
+            ms, _ = _event_ms(lambda: [ctx.patch_step(bufs[0], bufs[1], 0, n0 * n0, 0, dt, 0) for _ in range(nl)])
+            step_launch_us = ms * 1e3 / nl
+            alg = 8 * wb * N * N
+            print(json.dumps({"sweep": True, "cells": N * N, "prec": name, "state_bytes_per_buffer": t.numel() * wb,
+                              "level_advance": {"K": K, "threads": NT, "launch_us": adv_launch_us,
+                                                "gbs": alg * K / (adv_launch_us * 1e-6) / 1e9,
+                                                "frac": alg * K / (adv_launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                                                "cell_updates_per_s": N * N * K / (adv_launch_us * 1e-6)},
+                              "patch_step": {"tile_rows": ctx.tile, "launch_us": step_launch_us,
+                                             "gbs": alg / (step_launch_us * 1e-6) / 1e9,
+                                             "frac": alg / (step_launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS}}),
+                  flush=True)
+            del bufs, t
+            torch.cuda.empty_cache()
+
+
 def cpu_baseline(data, nsteps, dt):
     import afsynth
     import oracle
@@ -142,6 +188,9 @@ def main():
     args = parse()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.sweep:
+        sweep()
         return
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: --gpus must be 1 (multi-GPU sharding is design-only)"}))

@@ -38,6 +38,27 @@ struct StepArgs {
   const uint8_t* side_mask;
 };
 
+// Row-major walk e = start, start + stride, ... over an nx-wide grid without
+// a division per element: (x, y) advance by (stride mod nx, stride div nx)
+// with a carry.
+struct Walk2 {
+  int x, y, dx, dy, nx;
+  __device__ __forceinline__ Walk2(int start, int stride, int nx_) : nx(nx_) {
+    y = start / nx;
+    x = start - y * nx;
+    dy = stride / nx;
+    dx = stride - dy * nx;
+  }
+  __device__ __forceinline__ void next() {
+    x += dx;
+    y += dy;
+    if (x >= nx) {
+      x -= nx;
+      ++y;
+    }
+  }
+};
+
 template <typename T, int NCOMP, int NR, int NC>
 struct StepLds {
   T in[4][NCOMP][NR][NC];
@@ -64,6 +85,23 @@ __device__ __forceinline__ T adv_eval(const T (&s)[4][1][NR][NC], int r, int c, 
   v += w[7] * s[3][0][r][c];
   v += w[8] * s[3][0][r + 1][c];
   return v;
+}
+
+// Both time levels of a node kind evaluated from one source cell (the usual
+// case): one pass over the 9 raw DOFs feeds both dot products.
+template <typename T, int NR, int NC>
+__device__ __forceinline__ void adv_eval2(const T (&s)[4][1][NR][NC], int r, int c, const T* w0, const T* w1,
+                                          T* h, T* f) {
+  const T d[9] = {s[0][0][r][c],     s[1][0][r][c],     s[1][0][r][c + 1], s[1][0][r + 1][c], s[1][0][r + 1][c + 1],
+                  s[2][0][r][c],     s[2][0][r][c + 1], s[3][0][r][c],     s[3][0][r + 1][c]};
+  T a = w0[0] * d[0], b = w1[0] * d[0];
+#pragma unroll
+  for (int k = 1; k < 9; ++k) {
+    a += w0[k] * d[k];
+    b += w1[k] * d[k];
+  }
+  *h = a;
+  *f = b;
 }
 
 // Acoustic node evaluation over a fixed neighbourhood table.
@@ -126,24 +164,31 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
   const int SR = nrow + 3, SC = span + 3;
   const size_t plane = size_t(M + 5) * A.pitch;
 
-  // ---- stage rows j in [jlo-1, jhi+1], cols i in [ilo-1, ihi+1]
-  for (int e = threadIdx.x; e < 4 * NCOMP * SR * SC; e += kThreads) {
-    const int cc = e % SC;
-    int t = e / SC;
-    const int rr = t % SR;
-    t /= SR;
-    const int comp = t % NCOMP, kind = t / NCOMP;
-    const int i = ilo - 1 + cc, j = jlo - 1 + rr;
-    L.in[kind][comp][rr][cc] =
-        A.in[kind][(size_t(comp) * A.npatch + patch) * plane + size_t(j + kGhost) * A.pitch + (i + kGhost)];
+  // ---- stage rows j in [jlo-1, jhi+1], cols i in [ilo-1, ihi+1]; the rows
+  // of all 4*NCOMP planes are walked as one (4 NCOMP SR) x SC grid
+  {
+    Walk2 w(threadIdx.x, kThreads, SC);
+    for (; w.y < 4 * NCOMP * SR; w.next()) {
+      const int kc = w.y / SR, rr = w.y - kc * SR;  // division by a small runtime value, once per element row
+      const int comp = kc % NCOMP, kind = kc / NCOMP;
+      const int i = ilo - 1 + w.x, j = jlo - 1 + rr;
+      L.in[kind][comp][rr][w.x] =
+          A.in[kind][(size_t(comp) * A.npatch + patch) * plane + size_t(j + kGhost) * A.pitch + (i + kGhost)];
+    }
   }
   __syncthreads();
 
   // ---- point values of the extended cells [ilo, ihi] x [jlo, jhi]
   const int EC = span + 1, ER = nrow + 1;
   const bool last_tile = (jhi == ihi);
-  for (int e = threadIdx.x; e < EC * ER; e += kThreads) {
-    const int ii = e % EC, jj = e / EC;
+  bool shared_src = true;  // uniform: both time levels read the same source cell
+  if constexpr (EQ == 0) {
+#pragma unroll
+    for (int kind = 0; kind < 3; ++kind)
+      shared_src = shared_src && W.off[kind][0][0] == W.off[kind][1][0] && W.off[kind][0][1] == W.off[kind][1][1];
+  }
+  for (Walk2 w(threadIdx.x, kThreads, EC); w.y < ER; w.next()) {
+    const int ii = w.x, jj = w.y;
     const int i = ilo + ii, j = jlo + jj;
     const int r = jj + 1, c = ii + 1;  // staged position of cell (i,j)
     const bool wrow = (jj < nrow) || last_tile;
@@ -155,8 +200,13 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
       for (int kind = 0; kind < 3; ++kind) {
         if (kind == NK_XEDGE && !has_x) continue;
         if (kind == NK_YEDGE && !has_y) continue;
-        const T h = adv_eval<T, NR, NC>(L.in, r + W.off[kind][0][1], c + W.off[kind][0][0], W.w[kind][0]);
-        const T f = adv_eval<T, NR, NC>(L.in, r + W.off[kind][1][1], c + W.off[kind][1][0], W.w[kind][1]);
+        T h, f;
+        if (shared_src) {
+          adv_eval2<T, NR, NC>(L.in, r + W.off[kind][0][1], c + W.off[kind][0][0], W.w[kind][0], W.w[kind][1], &h, &f);
+        } else {
+          h = adv_eval<T, NR, NC>(L.in, r + W.off[kind][0][1], c + W.off[kind][0][0], W.w[kind][0]);
+          f = adv_eval<T, NR, NC>(L.in, r + W.off[kind][1][1], c + W.off[kind][1][0], W.w[kind][1]);
+        }
         const T cur = L.in[kind + 1][0][r][c];
         L.tsum[kind][0][jj][ii] = (cur + T(4) * h) + f;
         if (wrow) A.out[kind + 1][size_t(patch) * plane + obase] = f;
@@ -192,8 +242,8 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
   // ---- fluxes and conservative update (eq. 2dfv) of cells [ilo,ihi) x [jlo,jhi)
   const uint8_t smask = (A.reg && A.side_mask) ? A.side_mask[patch] : uint8_t(0);
   const T inv36 = T(1) / T(36);
-  for (int e = threadIdx.x; e < span * nrow; e += kThreads) {
-    const int ii = e % span, jj = e / span;
+  for (Walk2 w(threadIdx.x, kThreads, span); w.y < nrow; w.next()) {
+    const int ii = w.x, jj = w.y;
     const int i = ilo + ii, j = jlo + jj;
     const size_t obase = size_t(j + kGhost) * A.pitch + (i + kGhost);
     T FL[NCOMP], FR[NCOMP], GB[NCOMP], GT[NCOMP];
@@ -266,9 +316,9 @@ struct AdvanceArgs {
 template <typename T, int EQ, int M, int K, int NT>
 __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, const typename WSel<T, EQ>::type W) {
   constexpr int NCOMP = EQ ? 3 : 1;
-  constexpr int E = M + 2 * K + 1;  // node extent of the gathered block
-  constexpr int EMAX = M + 2 * K - 1;  // extended cells of the first step
-  constexpr int CPT = (EMAX * EMAX + NT - 1) / NT;
+  constexpr int E = M + 2 * K + 1;     // node extent of the gathered block
+  constexpr int EMAX = M + 2 * K - 1;  // extended cells per side in the first step
+  constexpr int CPT = (EMAX * EMAX + NT - 1) / NT;  // extended cells per thread (first step)
   __shared__ T st[4][NCOMP][E][E];
   __shared__ T ts[3][NCOMP][E][E];
   __shared__ int32_t nb[9];
@@ -280,106 +330,120 @@ __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, co
   const size_t plane = size_t(M + 5) * A.pitch;
 
   // ---- gather: LDS position (r, c) holds local index (c - K, r - K)
-  for (int e = threadIdx.x; e < 4 * NCOMP * E * E; e += NT) {
-    const int cc = e % E;
-    int t = e / E;
-    const int rr = t % E;
-    t /= E;
-    const int comp = t % NCOMP, kind = t / NCOMP;
-    const int i = cc - K, j = rr - K;
-    const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
+  for (Walk2 w(threadIdx.x, NT, E); w.y < 4 * NCOMP * E; w.next()) {
+    const int rr = w.y % E, kc = w.y / E;  // E is a compile-time constant
+    const int comp = kc % NCOMP, kind = kc / NCOMP;
+    const int j = rr - K, i = w.x - K;
     const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
+    const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
     const int src = nb[(oy + 1) * 3 + (ox + 1)];
     const int li = i - ox * M, lj = j - oy * M;
-    st[kind][comp][rr][cc] =
+    st[kind][comp][rr][w.x] =
         A.in[kind][(size_t(comp) * A.npatch + src) * plane + size_t(lj + kGhost) * A.pitch + (li + kGhost)];
   }
   __syncthreads();
 
+  bool shared_src = true;  // uniform: both time levels use the same source cell
+  if constexpr (EQ == 0) {
+#pragma unroll
+    for (int kind = 0; kind < 3; ++kind)
+      shared_src = shared_src && W.off[kind][0][0] == W.off[kind][1][0] && W.off[kind][0][1] == W.off[kind][1][1];
+  }
   const T inv36 = T(1) / T(36);
 #pragma unroll 1
   for (int s = 0; s < K; ++s) {
     const int lo = -(K - 1 - s), hi = M + (K - 1 - s);
-    const int span = hi - lo, EC = span + 1;
+    const int EC = hi - lo + 1;
     T fnew[CPT][3][NCOMP];
     // ---- node values of the extended cells [lo, hi]^2
+    {
+      Walk2 w(threadIdx.x, NT, EC);
 #pragma unroll
-    for (int u = 0; u < CPT; ++u) {
-      const int e = threadIdx.x + u * NT;
-      if (e >= EC * EC) break;
-      const int r = lo + e / EC + K, c = lo + e % EC + K;  // LDS position of cell (i, j)
-      const bool has_x = (r - K) < hi, has_y = (c - K) < hi;
-      if constexpr (EQ == 0) {
+      for (int u = 0; u < CPT; ++u, w.next()) {
+        const int ii = w.x, jj = w.y;
+        if (jj >= EC) break;
+        const int r = lo + jj + K, c = lo + ii + K;  // LDS position of cell (i, j)
+        const bool has_x = jj < EC - 1, has_y = ii < EC - 1;
+        if constexpr (EQ == 0) {
 #pragma unroll
-        for (int kind = 0; kind < 3; ++kind) {
-          if ((kind == NK_XEDGE && !has_x) || (kind == NK_YEDGE && !has_y)) continue;
-          const T h = adv_eval<T, E, E>(st, r + W.off[kind][0][1], c + W.off[kind][0][0], W.w[kind][0]);
-          const T f = adv_eval<T, E, E>(st, r + W.off[kind][1][1], c + W.off[kind][1][0], W.w[kind][1]);
-          ts[kind][0][r][c] = (st[kind + 1][0][r][c] + T(4) * h) + f;
-          fnew[u][kind][0] = f;
-        }
-      } else {
-        T res[2][3];
-        ac_eval<T, E, E, kNbCorner>(st, r, c, kNbCornerTab, W.corner, res);
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          ts[NK_CORNER][q][r][c] = (st[1][q][r][c] + T(4) * res[0][q]) + res[1][q];
-          fnew[u][NK_CORNER][q] = res[1][q];
-        }
-        if (has_x) {
-          ac_eval<T, E, E, kNbEdge>(st, r, c, kNbXedgeTab, W.xedge, res);
-#pragma unroll
-          for (int q = 0; q < 3; ++q) {
-            ts[NK_XEDGE][q][r][c] = (st[2][q][r][c] + T(4) * res[0][q]) + res[1][q];
-            fnew[u][NK_XEDGE][q] = res[1][q];
+          for (int kind = 0; kind < 3; ++kind) {
+            if ((kind == NK_XEDGE && !has_x) || (kind == NK_YEDGE && !has_y)) continue;
+            T h, f;
+            if (shared_src) {
+              adv_eval2<T, E, E>(st, r + W.off[kind][0][1], c + W.off[kind][0][0], W.w[kind][0], W.w[kind][1], &h, &f);
+            } else {
+              h = adv_eval<T, E, E>(st, r + W.off[kind][0][1], c + W.off[kind][0][0], W.w[kind][0]);
+              f = adv_eval<T, E, E>(st, r + W.off[kind][1][1], c + W.off[kind][1][0], W.w[kind][1]);
+            }
+            ts[kind][0][r][c] = (st[kind + 1][0][r][c] + T(4) * h) + f;
+            fnew[u][kind][0] = f;
           }
-        }
-        if (has_y) {
-          ac_eval<T, E, E, kNbEdge>(st, r, c, kNbYedgeTab, W.yedge, res);
+        } else {
+          T res[2][3];
+          ac_eval<T, E, E, kNbCorner>(st, r, c, kNbCornerTab, W.corner, res);
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
-            ts[NK_YEDGE][q][r][c] = (st[3][q][r][c] + T(4) * res[0][q]) + res[1][q];
-            fnew[u][NK_YEDGE][q] = res[1][q];
+            ts[NK_CORNER][q][r][c] = (st[1][q][r][c] + T(4) * res[0][q]) + res[1][q];
+            fnew[u][NK_CORNER][q] = res[1][q];
+          }
+          if (has_x) {
+            ac_eval<T, E, E, kNbEdge>(st, r, c, kNbXedgeTab, W.xedge, res);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              ts[NK_XEDGE][q][r][c] = (st[2][q][r][c] + T(4) * res[0][q]) + res[1][q];
+              fnew[u][NK_XEDGE][q] = res[1][q];
+            }
+          }
+          if (has_y) {
+            ac_eval<T, E, E, kNbEdge>(st, r, c, kNbYedgeTab, W.yedge, res);
+#pragma unroll
+            for (int q = 0; q < 3; ++q) {
+              ts[NK_YEDGE][q][r][c] = (st[3][q][r][c] + T(4) * res[0][q]) + res[1][q];
+              fnew[u][NK_YEDGE][q] = res[1][q];
+            }
           }
         }
       }
     }
     __syncthreads();
     // ---- commit the new point values, then update the averages of [lo, hi)^2
+    {
+      Walk2 w(threadIdx.x, NT, EC);
 #pragma unroll
-    for (int u = 0; u < CPT; ++u) {
-      const int e = threadIdx.x + u * NT;
-      if (e >= EC * EC) break;
-      const int r = lo + e / EC + K, c = lo + e % EC + K;
-      const bool has_x = (r - K) < hi, has_y = (c - K) < hi;
+      for (int u = 0; u < CPT; ++u, w.next()) {
+        const int ii = w.x, jj = w.y;
+        if (jj >= EC) break;
+        const int r = lo + jj + K, c = lo + ii + K;
+        const bool has_x = jj < EC - 1, has_y = ii < EC - 1;
 #pragma unroll
-      for (int q = 0; q < NCOMP; ++q) {
-        st[1][q][r][c] = fnew[u][NK_CORNER][q];
-        if (has_x) st[2][q][r][c] = fnew[u][NK_XEDGE][q];
-        if (has_y) st[3][q][r][c] = fnew[u][NK_YEDGE][q];
+        for (int q = 0; q < NCOMP; ++q) {
+          st[1][q][r][c] = fnew[u][NK_CORNER][q];
+          if (has_x) st[2][q][r][c] = fnew[u][NK_XEDGE][q];
+          if (has_y) st[3][q][r][c] = fnew[u][NK_YEDGE][q];
+        }
+        if (!has_x || !has_y) continue;  // cells with i or j == hi are not updated
+        T FL[NCOMP], FR[NCOMP], GB[NCOMP], GT[NCOMP];
+#pragma unroll
+        for (int q = 0; q < NCOMP; ++q) {
+          FL[q] = face_sum(ts[NK_CORNER][q][r][c], ts[NK_XEDGE][q][r][c], ts[NK_CORNER][q][r + 1][c]);
+          FR[q] = face_sum(ts[NK_CORNER][q][r][c + 1], ts[NK_XEDGE][q][r][c + 1], ts[NK_CORNER][q][r + 1][c + 1]);
+          GB[q] = face_sum(ts[NK_CORNER][q][r][c], ts[NK_YEDGE][q][r][c], ts[NK_CORNER][q][r][c + 1]);
+          GT[q] = face_sum(ts[NK_CORNER][q][r + 1][c], ts[NK_YEDGE][q][r + 1][c], ts[NK_CORNER][q][r + 1][c + 1]);
+        }
+        T fL[NCOMP], fR[NCOMP], gB[NCOMP], gT[NCOMP];
+        if constexpr (EQ == 0) {
+          fL[0] = A.a * FL[0] * inv36; fR[0] = A.a * FR[0] * inv36;
+          gB[0] = A.b * GB[0] * inv36; gT[0] = A.b * GT[0] * inv36;
+        } else {
+          fL[0] = A.c * FL[1] * inv36; fL[1] = A.c * FL[0] * inv36; fL[2] = T(0);
+          fR[0] = A.c * FR[1] * inv36; fR[1] = A.c * FR[0] * inv36; fR[2] = T(0);
+          gB[0] = A.c * GB[2] * inv36; gB[1] = T(0); gB[2] = A.c * GB[0] * inv36;
+          gT[0] = A.c * GT[2] * inv36; gT[1] = T(0); gT[2] = A.c * GT[0] * inv36;
+        }
+#pragma unroll
+        for (int q = 0; q < NCOMP; ++q)
+          st[0][q][r][c] = st[0][q][r][c] - A.dtdx * (fR[q] - fL[q]) - A.dtdy * (gT[q] - gB[q]);
       }
-      if (!has_x || !has_y) continue;  // cell (i,j) with i or j == hi is not updated
-      T FL[NCOMP], FR[NCOMP], GB[NCOMP], GT[NCOMP];
-#pragma unroll
-      for (int q = 0; q < NCOMP; ++q) {
-        FL[q] = face_sum(ts[NK_CORNER][q][r][c], ts[NK_XEDGE][q][r][c], ts[NK_CORNER][q][r + 1][c]);
-        FR[q] = face_sum(ts[NK_CORNER][q][r][c + 1], ts[NK_XEDGE][q][r][c + 1], ts[NK_CORNER][q][r + 1][c + 1]);
-        GB[q] = face_sum(ts[NK_CORNER][q][r][c], ts[NK_YEDGE][q][r][c], ts[NK_CORNER][q][r][c + 1]);
-        GT[q] = face_sum(ts[NK_CORNER][q][r + 1][c], ts[NK_YEDGE][q][r + 1][c], ts[NK_CORNER][q][r + 1][c + 1]);
-      }
-      T fL[NCOMP], fR[NCOMP], gB[NCOMP], gT[NCOMP];
-      if constexpr (EQ == 0) {
-        fL[0] = A.a * FL[0] * inv36; fR[0] = A.a * FR[0] * inv36;
-        gB[0] = A.b * GB[0] * inv36; gT[0] = A.b * GT[0] * inv36;
-      } else {
-        fL[0] = A.c * FL[1] * inv36; fL[1] = A.c * FL[0] * inv36; fL[2] = T(0);
-        fR[0] = A.c * FR[1] * inv36; fR[1] = A.c * FR[0] * inv36; fR[2] = T(0);
-        gB[0] = A.c * GB[2] * inv36; gB[1] = T(0); gB[2] = A.c * GB[0] * inv36;
-        gT[0] = A.c * GT[2] * inv36; gT[1] = T(0); gT[2] = A.c * GT[0] * inv36;
-      }
-#pragma unroll
-      for (int q = 0; q < NCOMP; ++q)
-        st[0][q][r][c] = st[0][q][r][c] - A.dtdx * (fR[q] - fL[q]) - A.dtdy * (gT[q] - gB[q]);
     }
     __syncthreads();
   }
