@@ -59,6 +59,30 @@ struct Walk2 {
   }
 };
 
+// Block gather into a flat LDS image: element e in [0, NW) is src(e).  Each
+// thread issues up to CH global loads before its first LDS store, so the
+// gather pays the memory latency once per CH elements rather than once per
+// element (a load-store loop waits for every load).
+template <typename T, int NT, int NW, typename Src>
+__device__ __forceinline__ void gather_block(T* lds, Src src) {
+  constexpr int PER = (NW + NT - 1) / NT;
+  constexpr int CH = sizeof(T) == 4 ? 16 : 8;
+#pragma unroll
+  for (int c0 = 0; c0 < PER; c0 += CH) {
+    T v[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int e = int(threadIdx.x) + (c0 + u) * NT;
+      if (c0 + u < PER && ((c0 + u + 1) * NT <= NW || e < NW)) v[u] = src(e);
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int e = int(threadIdx.x) + (c0 + u) * NT;
+      if (c0 + u < PER && ((c0 + u + 1) * NT <= NW || e < NW)) lds[e] = v[u];
+    }
+  }
+}
+
 template <typename T, int NCOMP, int NR, int NC>
 struct StepLds {
   T in[4][NCOMP][NR][NC];
@@ -161,22 +185,21 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
   const int jlo = ilo + tile * TY;
   const int jhi = min(jlo + TY, ihi);
   const int nrow = jhi - jlo;
-  const int SR = nrow + 3, SC = span + 3;
   const size_t plane = size_t(M + 5) * A.pitch;
 
-  // ---- stage rows j in [jlo-1, jhi+1], cols i in [ilo-1, ihi+1]; the rows
-  // of all 4*NCOMP planes are walked as one (4 NCOMP SR) x SC grid
-  {
-    Walk2 w(threadIdx.x, kThreads, SC);
-    for (; w.y < 4 * NCOMP * SR; w.next()) {
-      const int kc = w.y / SR, rr = w.y - kc * SR;  // division by a small runtime value, once per element row
-      const int comp = kc % NCOMP, kind = kc / NCOMP;
-      const int i = ilo - 1 + w.x, j = jlo - 1 + rr;
-      L.in[kind][comp][rr][w.x] =
-          A.in[kind][(size_t(comp) * A.npatch + patch) * plane + size_t(j + kGhost) * A.pitch + (i + kGhost)];
-    }
-  }
+  // ---- stage NR rows from j = jlo-1 (clamped to the array for a short last
+  // tile) and all M+5 columns (staged column x holds i = x - 2), so the
+  // image has a compile-time shape; rows [jlo-1, jhi+1] and columns
+  // [ilo-1, ihi+1] are the ones read below
+  gather_block<T, kThreads, 4 * NCOMP * NR * NC>(&L.in[0][0][0][0], [&](int e) {
+    const int kc = e / (NR * NC), rem = e - kc * (NR * NC);
+    const int rr = rem / NC, x = rem - rr * NC;
+    const int comp = kc % NCOMP, kind = kc / NCOMP;
+    const int j = min(jlo - 1 + rr, M + 2);
+    return A.in[kind][(size_t(comp) * A.npatch + patch) * plane + size_t(j + kGhost) * A.pitch + x];
+  });
   __syncthreads();
+  const int coff = ilo + 2;  // staged column of cell i is i + 2 = ii + coff
 
   // ---- point values of the extended cells [ilo, ihi] x [jlo, jhi]
   const int EC = span + 1, ER = nrow + 1;
@@ -190,7 +213,7 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
   for (Walk2 w(threadIdx.x, kThreads, EC); w.y < ER; w.next()) {
     const int ii = w.x, jj = w.y;
     const int i = ilo + ii, j = jlo + jj;
-    const int r = jj + 1, c = ii + 1;  // staged position of cell (i,j)
+    const int r = jj + 1, c = ii + coff;  // staged position of cell (i,j)
     const bool wrow = (jj < nrow) || last_tile;
     const bool has_x = jj < nrow;      // xedge (i,j) belongs to rows [jlo, jhi)
     const bool has_y = ii < span;      // yedge (i,j) belongs to cols [ilo, ihi)
@@ -270,7 +293,7 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
     }
 #pragma unroll
     for (int q = 0; q < NCOMP; ++q) {
-      const T Q = L.in[0][q][jj + 1][ii + 1];
+      const T Q = L.in[0][q][jj + 1][ii + coff];
       const T Qn = Q - A.dtdx * (fR[q] - fL[q]) - A.dtdy * (gT[q] - gB[q]);
       A.out[0][(size_t(q) * A.npatch + patch) * plane + obase] = Qn;
     }
@@ -302,6 +325,9 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
 // [-(K-1-s), m+K-1-s)), and finally writes the interior averages and the
 // closed-square nodes.  Step s reads only data of step s-1 that lie inside
 // its own block, so K fused steps equal K separate fill+step passes.
+//
+// k_level_advance below is the acoustic kernel (three components, sector
+// means); advection has its own layout in k_level_advance_adv.
 // ---------------------------------------------------------------------------
 
 template <typename T>
@@ -313,9 +339,9 @@ struct AdvanceArgs {
   T dtdx, dtdy, a, b, c;
 };
 
-template <typename T, int EQ, int M, int K, int NT>
-__global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, const typename WSel<T, EQ>::type W) {
-  constexpr int NCOMP = EQ ? 3 : 1;
+template <typename T, int M, int K, int NT>
+__global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, const AcWeights<T> W) {
+  constexpr int NCOMP = 3;
   constexpr int E = M + 2 * K + 1;     // node extent of the gathered block
   constexpr int EMAX = M + 2 * K - 1;  // extended cells per side in the first step
   constexpr int CPT = (EMAX * EMAX + NT - 1) / NT;  // extended cells per thread (first step)
@@ -330,25 +356,19 @@ __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, co
   const size_t plane = size_t(M + 5) * A.pitch;
 
   // ---- gather: LDS position (r, c) holds local index (c - K, r - K)
-  for (Walk2 w(threadIdx.x, NT, E); w.y < 4 * NCOMP * E; w.next()) {
-    const int rr = w.y % E, kc = w.y / E;  // E is a compile-time constant
+  gather_block<T, NT, 4 * NCOMP * E * E>(&st[0][0][0][0], [&](int e) {
+    const int kc = e / (E * E), rem = e - kc * (E * E);
+    const int rr = rem / E, x = rem - rr * E;
     const int comp = kc % NCOMP, kind = kc / NCOMP;
-    const int j = rr - K, i = w.x - K;
+    const int j = rr - K, i = x - K;
     const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
     const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
     const int src = nb[(oy + 1) * 3 + (ox + 1)];
     const int li = i - ox * M, lj = j - oy * M;
-    st[kind][comp][rr][w.x] =
-        A.in[kind][(size_t(comp) * A.npatch + src) * plane + size_t(lj + kGhost) * A.pitch + (li + kGhost)];
-  }
+    return A.in[kind][(size_t(comp) * A.npatch + src) * plane + size_t(lj + kGhost) * A.pitch + (li + kGhost)];
+  });
   __syncthreads();
 
-  bool shared_src = true;  // uniform: both time levels use the same source cell
-  if constexpr (EQ == 0) {
-#pragma unroll
-    for (int kind = 0; kind < 3; ++kind)
-      shared_src = shared_src && W.off[kind][0][0] == W.off[kind][1][0] && W.off[kind][0][1] == W.off[kind][1][1];
-  }
   const T inv36 = T(1) / T(36);
 #pragma unroll 1
   for (int s = 0; s < K; ++s) {
@@ -364,21 +384,7 @@ __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, co
         if (jj >= EC) break;
         const int r = lo + jj + K, c = lo + ii + K;  // LDS position of cell (i, j)
         const bool has_x = jj < EC - 1, has_y = ii < EC - 1;
-        if constexpr (EQ == 0) {
-#pragma unroll
-          for (int kind = 0; kind < 3; ++kind) {
-            if ((kind == NK_XEDGE && !has_x) || (kind == NK_YEDGE && !has_y)) continue;
-            T h, f;
-            if (shared_src) {
-              adv_eval2<T, E, E>(st, r + W.off[kind][0][1], c + W.off[kind][0][0], W.w[kind][0], W.w[kind][1], &h, &f);
-            } else {
-              h = adv_eval<T, E, E>(st, r + W.off[kind][0][1], c + W.off[kind][0][0], W.w[kind][0]);
-              f = adv_eval<T, E, E>(st, r + W.off[kind][1][1], c + W.off[kind][1][0], W.w[kind][1]);
-            }
-            ts[kind][0][r][c] = (st[kind + 1][0][r][c] + T(4) * h) + f;
-            fnew[u][kind][0] = f;
-          }
-        } else {
+        {
           T res[2][3];
           ac_eval<T, E, E, kNbCorner>(st, r, c, kNbCornerTab, W.corner, res);
 #pragma unroll
@@ -431,15 +437,10 @@ __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, co
           GT[q] = face_sum(ts[NK_CORNER][q][r + 1][c], ts[NK_YEDGE][q][r + 1][c], ts[NK_CORNER][q][r + 1][c + 1]);
         }
         T fL[NCOMP], fR[NCOMP], gB[NCOMP], gT[NCOMP];
-        if constexpr (EQ == 0) {
-          fL[0] = A.a * FL[0] * inv36; fR[0] = A.a * FR[0] * inv36;
-          gB[0] = A.b * GB[0] * inv36; gT[0] = A.b * GT[0] * inv36;
-        } else {
-          fL[0] = A.c * FL[1] * inv36; fL[1] = A.c * FL[0] * inv36; fL[2] = T(0);
-          fR[0] = A.c * FR[1] * inv36; fR[1] = A.c * FR[0] * inv36; fR[2] = T(0);
-          gB[0] = A.c * GB[2] * inv36; gB[1] = T(0); gB[2] = A.c * GB[0] * inv36;
-          gT[0] = A.c * GT[2] * inv36; gT[1] = T(0); gT[2] = A.c * GT[0] * inv36;
-        }
+        fL[0] = A.c * FL[1] * inv36; fL[1] = A.c * FL[0] * inv36; fL[2] = T(0);
+        fR[0] = A.c * FR[1] * inv36; fR[1] = A.c * FR[0] * inv36; fR[2] = T(0);
+        gB[0] = A.c * GB[2] * inv36; gB[1] = T(0); gB[2] = A.c * GB[0] * inv36;
+        gT[0] = A.c * GT[2] * inv36; gT[1] = T(0); gT[2] = A.c * GT[0] * inv36;
 #pragma unroll
         for (int q = 0; q < NCOMP; ++q)
           st[0][q][r][c] = st[0][q][r][c] - A.dtdx * (fR[q] - fL[q]) - A.dtdy * (gT[q] - gB[q]);
@@ -459,6 +460,176 @@ __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, co
     if (j < M) A.out[2][g] = st[2][q][r][c];
     if (i < M) A.out[3][g] = st[3][q][r][c];
     if (i < M && j < M) A.out[0][g] = st[0][q][r][c];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Level advance for advection (Sec. 2, eq. evolution by characteristics):
+// the same K-step scheme as k_level_advance with a layout built for LDS
+// latency rather than capacity.
+//
+//  * Point values are double-buffered (pt[s & 1] old, pt[~s & 1] new), so
+//    the node pass writes new values straight to LDS and the update pass only
+//    touches time sums and averages; nothing is held in registers across the
+//    barrier.
+//  * A cell's node pass loads all 27 source DOFs of its three node kinds
+//    before any arithmetic, and stores go through a select to a slot that is
+//    never read (LDS position (0, 0) of each array, below every region of
+//    every step), so the pass is branch free and pays the LDS latency once.
+//  * SS: both time levels of a node kind share one source cell (always true
+//    when the transverse Courant number is at most 1/2), one load feeds both
+//    dot products.
+//  * UP: the source cells are the upwind ones for a, b > 0 with both
+//    directional Courant numbers below 1/2 -- corner (i-1, j-1), x-edge
+//    (i-1, j), y-edge (i, j-1) -- known at compile time, so every LDS address
+//    is one base plus an immediate and the 27 loads reduce to 21 distinct
+//    ones.  UP implies SS.
+//  * A wave whose 64 cells of a slot all lie outside the region skips it.
+// ---------------------------------------------------------------------------
+
+// Source-cell offset (d = 0: di, d = 1: dj) of the UP pattern for node kind k.
+__host__ __device__ constexpr int up_off(int k, int d) { return k == NK_CORNER ? -1 : (k == NK_XEDGE ? d - 1 : -d); }
+
+template <typename T, int M, int K>
+struct AdvLds {
+  static constexpr int E = M + 2 * K + 1;
+  T av[E][E];         // averages; av followed by pt[0] forms the gather target
+  T pt[2][3][E][E];   // point values, [buffer][kind]
+  T ts[3][E][E];      // Simpson time sums n + 4 (n+1/2) + (n+1)
+};
+
+template <typename T, int M, int K, int NT, bool UP, bool SS>
+__global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A, const AdvWeights<T> W) {
+  static_assert(SS || !UP, "the upwind pattern shares its source cells");
+  using L = AdvLds<T, M, K>;
+  constexpr int E = L::E;
+  constexpr int EE = E * E;
+  __shared__ L S;
+  __shared__ int32_t nb[9];
+
+  const int pl = blockIdx.x;
+  const int patch = A.first + pl;
+  if (threadIdx.x < 9) nb[threadIdx.x] = A.nbr[pl * 9 + threadIdx.x];
+  __syncthreads();
+  const size_t plane = size_t(M + 5) * A.pitch;
+
+  // ---- gather: LDS position (r, c) holds local index (c - K, r - K);
+  // kind 0 goes to av, kinds 1..3 to pt[0][0..2] (contiguous after av)
+  T* const g0 = &S.av[0][0];
+  gather_block<T, NT, 4 * EE>(g0, [&](int e) {
+    const int kind = e / EE, rem = e - kind * EE;
+    const int rr = rem / E, x = rem - rr * E;
+    const int j = rr - K, i = x - K;
+    const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
+    const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
+    const int src = nb[(oy + 1) * 3 + (ox + 1)];
+    const int li = i - ox * M, lj = j - oy * M;
+    return A.in[kind][size_t(src) * plane + size_t(lj + kGhost) * A.pitch + (li + kGhost)];
+  });
+  __syncthreads();
+
+  const T inv36 = T(1) / T(36);
+  const T cx = A.dtdx * A.a * inv36, cy = A.dtdy * A.b * inv36;
+#pragma unroll 1
+  for (int s = 0; s < K; ++s) {
+    T* const avp = &S.av[0][0];
+    const T* const po = &S.pt[s & 1][0][0][0];
+    T* const pn = &S.pt[(s + 1) & 1][0][0][0];
+    T* const tsp = &S.ts[0][0][0];
+    const int lo = -(K - 1 - s);
+    const int EC = M + 2 * (K - 1 - s) + 1;  // extended cells per side
+    const int base = (lo + K) * (E + 1);      // LDS index of the first extended cell
+    const int nslot = (EC * EC + NT - 1) / NT;
+    // ---- node values of the extended cells
+    {
+      Walk2 w(threadIdx.x, NT, EC);
+#pragma unroll 1
+      for (int u = 0; u < nslot; ++u, w.next()) {
+        if (u * NT + int(threadIdx.x & ~63u) >= EC * EC) break;  // wave-uniform
+        const bool ok = w.y < EC;
+        const int ii = ok ? w.x : 0, jj = ok ? w.y : 0;
+        const int idx = base + jj * E + ii;
+        const bool has_x = ok && jj < EC - 1, has_y = ok && ii < EC - 1;
+        T d[3][9], d1[3][9];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+#pragma unroll
+          for (int t = 0; t < (SS ? 1 : 2); ++t) {
+            // source cell; the clamp only moves sources of nodes that are not
+            // kept (top-row x-edge, right-column y-edge), so that their DOFs
+            // (r + 1, c + 1) stay inside the array
+            int si;
+            if constexpr (UP) {
+              si = idx + up_off(k, 1) * E + up_off(k, 0);  // in range: the top and right sources are row/column E-2
+            } else {
+              si = idx + W.off[k][t][1] * E + W.off[k][t][0];
+              si = min(si, EE - E - 2);
+            }
+            T* dd = t ? d1[k] : d[k];
+            dd[0] = avp[si];
+            dd[1] = po[si];
+            dd[2] = po[si + 1];
+            dd[3] = po[si + E];
+            dd[4] = po[si + E + 1];
+            dd[5] = po[EE + si];
+            dd[6] = po[EE + si + 1];
+            dd[7] = po[2 * EE + si];
+            dd[8] = po[2 * EE + si + E];
+          }
+        }
+        T own[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) own[k] = po[k * EE + idx];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const T* dh = d[k];
+          const T* df = SS ? d[k] : d1[k];
+          T h = W.w[k][0][0] * dh[0], f = W.w[k][1][0] * df[0];
+#pragma unroll
+          for (int e = 1; e < 9; ++e) {
+            h += W.w[k][0][e] * dh[e];
+            f += W.w[k][1][e] * df[e];
+          }
+          const bool keep = k == NK_CORNER ? ok : (k == NK_XEDGE ? has_x : has_y);
+          const int o = keep ? idx : 0;
+          tsp[k * EE + o] = (own[k] + T(4) * h) + f;
+          pn[k * EE + o] = f;
+        }
+      }
+    }
+    __syncthreads();
+    // ---- conservative update of cells [lo, hi)^2 (EC - 1 per side)
+    {
+      const int NC = EC - 1;
+      const int nslot2 = (NC * NC + NT - 1) / NT;
+      Walk2 w(threadIdx.x, NT, NC);
+#pragma unroll 1
+      for (int u = 0; u < nslot2; ++u, w.next()) {
+        if (u * NT + int(threadIdx.x & ~63u) >= NC * NC) break;  // wave-uniform
+        const bool ok = w.y < NC;
+        const int idx = base + (ok ? w.y : 0) * E + (ok ? w.x : 0);
+        const T c00 = tsp[idx], c01 = tsp[idx + 1], c10 = tsp[idx + E], c11 = tsp[idx + E + 1];
+        const T x0 = tsp[EE + idx], x1 = tsp[EE + idx + 1];
+        const T y0 = tsp[2 * EE + idx], y1 = tsp[2 * EE + idx + E];
+        const T q = avp[idx];
+        const T FL = face_sum(c00, x0, c10), FR = face_sum(c01, x1, c11);
+        const T GB = face_sum(c00, y0, c01), GT = face_sum(c10, y1, c11);
+        avp[ok ? idx : 0] = (q - cx * (FR - FL)) - cy * (GT - GB);
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- write the interior averages and the closed-square nodes
+  const T* const pf = &S.pt[K & 1][0][0][0];
+  for (Walk2 w(threadIdx.x, NT, M + 1); w.y < M + 1; w.next()) {
+    const int i = w.x, j = w.y;
+    const int idx = (j + K) * E + (i + K);
+    const size_t g = size_t(patch) * plane + size_t(j + kGhost) * A.pitch + (i + kGhost);
+    A.out[1][g] = pf[idx];
+    if (j < M) A.out[2][g] = pf[EE + idx];
+    if (i < M) A.out[3][g] = pf[2 * EE + idx];
+    if (i < M && j < M) A.out[0][g] = g0[idx];
   }
 }
 
@@ -917,8 +1088,8 @@ bool step_shape_supported(int m, int ty) {
   }
 }
 
-template <typename T, int EQ, int M, int K, int NT>
-static hipError_t launch_adv_t(const AdvanceLaunch& s, hipStream_t st) {
+template <typename T>
+static AdvanceArgs<T> advance_args(const AdvanceLaunch& s) {
   AdvanceArgs<T> A;
   for (int k = 0; k < 4; ++k) {
     A.in[k] = static_cast<const T*>(s.in[k]);
@@ -926,26 +1097,44 @@ static hipError_t launch_adv_t(const AdvanceLaunch& s, hipStream_t st) {
   }
   A.npatch = s.npatch; A.pitch = s.pitch; A.first = s.first; A.nbr = s.nbr;
   A.dtdx = T(s.dtdx); A.dtdy = T(s.dtdy); A.a = T(s.a); A.b = T(s.b); A.c = T(s.c);
-  if constexpr (EQ == 0)
-    hipLaunchKernelGGL((k_level_advance<T, 0, M, K, NT>), dim3(unsigned(s.count)), dim3(NT), 0, st, A,
-                       *static_cast<const AdvWeights<T>*>(s.weights));
-  else
-    hipLaunchKernelGGL((k_level_advance<T, 1, M, K, NT>), dim3(unsigned(s.count)), dim3(NT), 0, st, A,
+  return A;
+}
+
+template <typename T, int EQ, int M, int K, int NT>
+static hipError_t launch_adv_t(const AdvanceLaunch& s, hipStream_t st) {
+  const AdvanceArgs<T> A = advance_args<T>(s);
+  const dim3 grid(unsigned(s.count));
+  if constexpr (EQ == 0) {
+    const AdvWeights<T>& W = *static_cast<const AdvWeights<T>*>(s.weights);
+    bool ss = true, up = true;
+    for (int k = 0; k < 3; ++k)
+      for (int t = 0; t < 2; ++t) {
+        ss = ss && W.off[k][t][0] == W.off[k][0][0] && W.off[k][t][1] == W.off[k][0][1];
+        up = up && W.off[k][t][0] == up_off(k, 0) && W.off[k][t][1] == up_off(k, 1);
+      }
+    if (up)
+      hipLaunchKernelGGL((k_level_advance_adv<T, M, K, NT, true, true>), grid, dim3(NT), 0, st, A, W);
+    else if (ss)
+      hipLaunchKernelGGL((k_level_advance_adv<T, M, K, NT, false, true>), grid, dim3(NT), 0, st, A, W);
+    else
+      hipLaunchKernelGGL((k_level_advance_adv<T, M, K, NT, false, false>), grid, dim3(NT), 0, st, A, W);
+  } else {
+    hipLaunchKernelGGL((k_level_advance<T, M, K, NT>), grid, dim3(NT), 0, st, A,
                        *static_cast<const AcWeights<T>*>(s.weights));
+  }
   return hipGetLastError();
 }
 
 // Supported (m, K, threads) shapes of the level advance, per precision and
-// equation (LDS: 7 E^2 ncomp words with E = m + 2K + 1).
-#define AF_ADV_SHAPES(X)                 \
-  X(float, 0, 32, 1, 256) X(float, 0, 32, 2, 256) X(float, 0, 32, 2, 512) X(float, 0, 32, 4, 512)  \
-  X(float, 0, 32, 4, 1024) X(float, 0, 32, 8, 1024) X(float, 0, 16, 1, 256) X(float, 0, 16, 2, 256)  \
-  X(float, 0, 16, 4, 256)                                                                             \
-  X(float, 0, 64, 1, 1024) X(float, 0, 64, 2, 1024)                                                   \
-  X(double, 0, 32, 1, 256) X(double, 0, 32, 2, 512) X(double, 0, 32, 4, 1024) X(double, 0, 16, 1, 256) \
-  X(double, 0, 16, 2, 256)                                                                            \
-  X(double, 0, 16, 4, 256)                                                                            \
-  X(float, 1, 16, 1, 256) X(float, 1, 16, 2, 256) X(float, 1, 32, 1, 512) X(float, 1, 32, 2, 512)     \
+// equation.  LDS: advection 10 E^2 words, acoustics 21 E^2 words, with
+// E = m + 2K + 1.
+#define AF_ADV_SHAPES(X)                                                                                 \
+  X(float, 0, 32, 1, 256) X(float, 0, 32, 2, 256) X(float, 0, 32, 2, 512) X(float, 0, 32, 4, 512)      \
+  X(float, 0, 32, 4, 1024) X(float, 0, 32, 6, 1024) X(float, 0, 32, 8, 512) X(float, 0, 32, 8, 1024)   \
+  X(float, 0, 16, 1, 256) X(float, 0, 16, 2, 256) X(float, 0, 16, 4, 256) X(float, 0, 16, 8, 256)      \
+  X(double, 0, 32, 1, 256) X(double, 0, 32, 2, 512) X(double, 0, 32, 4, 512) X(double, 0, 32, 4, 1024) \
+  X(double, 0, 16, 1, 256) X(double, 0, 16, 2, 256) X(double, 0, 16, 4, 256)                            \
+  X(float, 1, 16, 1, 256) X(float, 1, 16, 2, 256) X(float, 1, 32, 1, 512) X(float, 1, 32, 2, 512)      \
   X(double, 1, 16, 1, 256) X(double, 1, 16, 2, 256)
 
 hipError_t launch_level_advance(const AdvanceLaunch& s, hipStream_t st) {

@@ -153,25 +153,35 @@ def test_periodic_patches_match_single_grid(eq, n0, m, nsteps, mode):
         assert err <= FP64_TOL, (q, err)
 
 
+# advection velocity patterns of the level advance: (a, b, Courant number of
+# the faster direction).  "mixed" has both source-cell offsets at run time,
+# "upwind" (a, b > 0, both directional Courant numbers below 1/2) takes the
+# compile-time upwind variant, "steep" (transverse Courant number 0.8) makes
+# the two time levels of the x-edges read different source cells.
+VELOCITY = {"mixed": (0.8, -0.45, 0.4), "upwind": (1.0, 0.5, 0.4), "steep": (0.3, -1.0, 0.8)}
+
+
 def _shape_cases():
     cases = []
     for eq, prec, m in [(0, af.FP32, 32), (0, af.FP64, 32), (0, af.FP32, 16), (0, af.FP64, 16),
-                        (1, af.FP32, 16), (1, af.FP64, 16), (1, af.FP32, 32), (0, af.FP32, 64)]:
+                        (1, af.FP32, 16), (1, af.FP64, 16), (1, af.FP32, 32)]:
         ctx = af.Context(make_problem(eq, prec, m, n0=4))
         for k, nt in ctx.advance_shapes():
-            cases.append((eq, prec, m, k, nt))
+            for vel in (VELOCITY if eq == 0 else ["-"]):
+                cases.append((eq, prec, m, k, nt, vel))
     return cases
 
 
-@pytest.mark.parametrize("eq,prec,m,k,nt", _shape_cases())
-def test_level_advance_matches_oracle(eq, prec, m, k, nt):
+@pytest.mark.parametrize("eq,prec,m,k,nt,vel", _shape_cases())
+def test_level_advance_matches_oracle(eq, prec, m, k, nt, vel):
     """Temporally blocked level advance (K steps per launch, halo gathered
     from the neighbours' interiors) against the oracle's single periodic grid,
     with a step count that is not a multiple of K (tail launches)."""
     torch = _torch()
-    print(f"[gpu-parity] level_advance eq={eq} prec={prec} m={m} K={k} NT={nt}", flush=True)
+    print(f"[gpu-parity] level_advance eq={eq} prec={prec} m={m} K={k} NT={nt} velocity={vel}", flush=True)
     n0 = 4 if m <= 32 else 2
-    prob = make_problem(eq, prec, m, n0=n0, **PHYS[eq])
+    phys = dict(a=VELOCITY[vel][0], b=VELOCITY[vel][1]) if eq == 0 else PHYS[eq]
+    prob = make_problem(eq, prec, m, n0=n0, **phys)
     ctx = af.Context(prob)
     ctx.set_advance_shape(k, nt)
     data = afsynth.fourier_modes(6) if eq == 0 else afsynth.gaussian_pulse(6)
@@ -187,7 +197,7 @@ def test_level_advance_matches_oracle(eq, prec, m, k, nt):
     b0 = af.blocks_to_state(ctx, blocks)
     bufs = [b0, torch.zeros_like(b0)]
     nsteps = 2 * k + 1
-    dt = 0.6 / N if eq == 0 else 0.4 / (N * prob.c)
+    dt = VELOCITY[vel][2] / (N * max(abs(prob.a), abs(prob.b))) if eq == 0 else 0.4 / (N * prob.c)
     mask = ctx.level_advance(h, bufs, 0, 0, dt, nsteps)
     torch.cuda.synchronize()
     got = af.state_to_blocks(ctx, bufs[mask & 1])
