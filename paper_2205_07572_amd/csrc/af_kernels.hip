@@ -490,18 +490,31 @@ __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, co
 // Source-cell offset (d = 0: di, d = 1: dj) of the UP pattern for node kind k.
 __host__ __device__ constexpr int up_off(int k, int d) { return k == NK_CORNER ? -1 : (k == NK_XEDGE ? d - 1 : -d); }
 
-template <typename T, int M, int K>
+// Rows per strip: a thread takes R vertically adjacent cells of one column,
+// with R the smallest value that lets one pass of NT threads cover the first
+// (largest) region.
+template <int M, int K, int NT>
+struct StripRows {
+  static constexpr int EC0 = M + 2 * K - 1;
+  static constexpr int S = NT / EC0 > 0 ? NT / EC0 : 1;
+  static constexpr int R0 = (EC0 + S - 1) / S;
+  static constexpr int value = R0 > 6 ? 6 : R0;
+};
+
+template <typename T, int M, int K, int R>
 struct AdvLds {
   static constexpr int E = M + 2 * K + 1;
   T av[E][E];         // averages; av followed by pt[0] forms the gather target
   T pt[2][3][E][E];   // point values, [buffer][kind]
   T ts[3][E][E];      // Simpson time sums n + 4 (n+1/2) + (n+1)
+  T pad[R][E];        // strips of the top region read up to R - 1 rows past an array
 };
 
 template <typename T, int M, int K, int NT, bool UP, bool SS>
 __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A, const AdvWeights<T> W) {
   static_assert(SS || !UP, "the upwind pattern shares its source cells");
-  using L = AdvLds<T, M, K>;
+  constexpr int R = StripRows<M, K, NT>::value;
+  using L = AdvLds<T, M, K, R>;
   constexpr int E = L::E;
   constexpr int EE = E * E;
   __shared__ L S;
@@ -541,7 +554,56 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
     const int base = (lo + K) * (E + 1);      // LDS index of the first extended cell
     const int nslot = (EC * EC + NT - 1) / NT;
     // ---- node values of the extended cells
-    {
+    if constexpr (UP) {
+      // strips of R rows: task t -> column t % EC, strip t / EC; the window
+      // holds rows [rb-1, rb+R] and columns [c-1, c+1] of every array (the
+      // loads that no cell uses are dropped by the compiler)
+      const int ns = (EC + R - 1) / R;
+      const int ntask = EC * ns;
+#pragma unroll 1
+      for (int t0 = 0; t0 + int(threadIdx.x & ~63u) < ntask; t0 += NT) {  // wave-uniform
+        const int t = t0 + int(threadIdx.x);
+        const bool tok = t < ntask;
+        const int q = tok ? t / EC : 0;
+        const int ci = tok ? t - q * EC : 0;
+        const int b0 = base + q * R * E + ci;
+        T wa[R + 2][3], w0[R + 2][3], w1[R + 2][3], w2[R + 2][3];
+#pragma unroll
+        for (int rr = 0; rr < R + 2; ++rr)
+#pragma unroll
+          for (int cc = 0; cc < 3; ++cc) {
+            const int o = b0 + (rr - 1) * E + (cc - 1);
+            wa[rr][cc] = avp[o];
+            w0[rr][cc] = po[o];
+            w1[rr][cc] = po[EE + o];
+            w2[rr][cc] = po[2 * EE + o];
+          }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const int jj = q * R + u;
+          const bool ok = tok && jj < EC;
+          const bool has_x = ok && jj < EC - 1, has_y = ok && ci < EC - 1;
+          const int idx = b0 + u * E;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            const int wr = u + 1 + up_off(k, 1), wc = 1 + up_off(k, 0);  // source cell in the window
+            const T d[9] = {wa[wr][wc],     w0[wr][wc],     w0[wr][wc + 1], w0[wr + 1][wc], w0[wr + 1][wc + 1],
+                            w1[wr][wc],     w1[wr][wc + 1], w2[wr][wc],     w2[wr + 1][wc]};
+            T h = W.w[k][0][0] * d[0], f = W.w[k][1][0] * d[0];
+#pragma unroll
+            for (int e = 1; e < 9; ++e) {
+              h += W.w[k][0][e] * d[e];
+              f += W.w[k][1][e] * d[e];
+            }
+            const T own = k == NK_CORNER ? w0[u + 1][1] : (k == NK_XEDGE ? w1[u + 1][1] : w2[u + 1][1]);
+            const bool keep = k == NK_CORNER ? ok : (k == NK_XEDGE ? has_x : has_y);
+            const int o = keep ? idx : 0;
+            tsp[k * EE + o] = (own + T(4) * h) + f;
+            pn[k * EE + o] = f;
+          }
+        }
+      }
+    } else {
       Walk2 w(threadIdx.x, NT, EC);
 #pragma unroll 1
       for (int u = 0; u < nslot; ++u, w.next()) {
@@ -598,23 +660,35 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
       }
     }
     __syncthreads();
-    // ---- conservative update of cells [lo, hi)^2 (EC - 1 per side)
+    // ---- conservative update of cells [lo, hi)^2 (EC - 1 per side), in
+    // strips of R rows; the y-face between two rows of a strip is summed once
     {
       const int NC = EC - 1;
-      const int nslot2 = (NC * NC + NT - 1) / NT;
-      Walk2 w(threadIdx.x, NT, NC);
+      const int ns = (NC + R - 1) / R;
+      const int ntask = NC * ns;
 #pragma unroll 1
-      for (int u = 0; u < nslot2; ++u, w.next()) {
-        if (u * NT + int(threadIdx.x & ~63u) >= NC * NC) break;  // wave-uniform
-        const bool ok = w.y < NC;
-        const int idx = base + (ok ? w.y : 0) * E + (ok ? w.x : 0);
-        const T c00 = tsp[idx], c01 = tsp[idx + 1], c10 = tsp[idx + E], c11 = tsp[idx + E + 1];
-        const T x0 = tsp[EE + idx], x1 = tsp[EE + idx + 1];
-        const T y0 = tsp[2 * EE + idx], y1 = tsp[2 * EE + idx + E];
-        const T q = avp[idx];
-        const T FL = face_sum(c00, x0, c10), FR = face_sum(c01, x1, c11);
-        const T GB = face_sum(c00, y0, c01), GT = face_sum(c10, y1, c11);
-        avp[ok ? idx : 0] = (q - cx * (FR - FL)) - cy * (GT - GB);
+      for (int t0 = 0; t0 + int(threadIdx.x & ~63u) < ntask; t0 += NT) {  // wave-uniform
+        const int t = t0 + int(threadIdx.x);
+        const bool tok = t < ntask;
+        const int q = tok ? t / NC : 0;
+        const int ci = tok ? t - q * NC : 0;
+        const int b0 = base + q * R * E + ci;
+        T G[R + 1], FL[R], FR[R], Q[R];  // every load before the first store
+#pragma unroll
+        for (int u = 0; u <= R; ++u)
+          G[u] = face_sum(tsp[b0 + u * E], tsp[2 * EE + b0 + u * E], tsp[b0 + u * E + 1]);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const int idx = b0 + u * E;
+          FL[u] = face_sum(tsp[idx], tsp[EE + idx], tsp[idx + E]);
+          FR[u] = face_sum(tsp[idx + 1], tsp[EE + idx + 1], tsp[idx + E + 1]);
+          Q[u] = avp[idx];
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const bool ok = tok && q * R + u < NC;
+          avp[ok ? b0 + u * E : 0] = (Q[u] - cx * (FR[u] - FL[u])) - cy * (G[u + 1] - G[u]);
+        }
       }
     }
     __syncthreads();
