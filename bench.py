@@ -26,6 +26,11 @@ NCELL = (M * N0) ** 2
 T_FINAL = 1.0
 NSTEPS_T = 1280
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch of the level-advance kernel on this workload, from
+# rocprofv3 FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00 (scales from a plain 64 MiB
+# copy), keyed by (precision, K, threads); valid only for the kernel source
+# the counters were taken on (profiles/k_level_advance_adv_512sq.md).
+PROFILED_TRAFFIC = {("fp32", 8, 1024): 19.77e6, ("fp64", 4, 512): 29.66e6}
 
 
 def parse():
@@ -261,9 +266,11 @@ def main():
         "linf_fp32_vs_fp64_rel": linf_32_64,
         "linf_vs_exact_T1": err_exact,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"k_level_advance<float,adv,32,{K32},{res['fp32']['NT']}>", "kernel_us": k32 * 1e3,
-                     "algorithmic_bytes_per_launch": bytes32},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": PROFILED_TRAFFIC.get(("fp32", K32, res["fp32"]["NT"])),
+                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
+                     "kernel": f"k_level_advance_adv<float,32,{K32},{res['fp32']['NT']},upwind>",
+                     "kernel_us": k32 * 1e3, "algorithmic_bytes_per_launch": bytes32},
     }
     if not args.no_cpu:
         v, el = cpu_baseline(data, args.cpu_steps, dt)
