@@ -45,6 +45,8 @@ struct af_ctx {
   std::vector<int32_t> h_entries;
   int32_t* d_entries = nullptr;  // uploaded on first device use
   int nentries = 0;
+  // coarse -> fine fill weights (device)
+  FillWeights* d_fillw = nullptr;
   // reduction workspace
   double* d_part = nullptr;
   int part_cap = 0;
@@ -86,6 +88,9 @@ struct af_hier {
   std::vector<int> nbr_ok;
   HierDev dev{};
   std::map<GraphKey, hipGraphExec_t> graphs;
+  // ghost-fill plans per lowest source level (built on first use)
+  std::vector<int4*> d_plan;
+  std::vector<uint32_t*> d_plan_flags;
 };
 
 namespace {
@@ -168,7 +173,10 @@ BufLaunch make_buf(const af_ctx* c, const af_state* b0, const af_state* b1, uint
 af_status ctx_device(af_ctx* c) {
   if (c->d_entries) return AF_OK;
   hipError_t err;
-  c->d_entries = dev_upload(c->h_entries, &err);
+  std::vector<FillWeights> fw(1);
+  make_fill_weights(&fw[0]);
+  c->d_fillw = dev_upload(fw, &err);
+  if (err == hipSuccess) c->d_entries = dev_upload(c->h_entries, &err);
   if (err != hipSuccess) return fail(AF_ERR_DEVICE, std::string("fill table upload: ") + hipGetErrorString(err));
   return AF_OK;
 }
@@ -270,6 +278,7 @@ af_status af_ctx_create(const af_problem* prob, af_ctx** out) {
 af_status af_ctx_destroy(af_ctx* ctx) {
   if (!ctx) return AF_OK;
   (void)hipFree(ctx->d_entries);
+  (void)hipFree(ctx->d_fillw);
   (void)hipFree(ctx->d_part);
   delete ctx;
   return AF_OK;
@@ -323,6 +332,8 @@ af_status af_hier_destroy(af_hier* h) {
   (void)hipFree(h->d_side_mask);
   (void)hipFree(h->d_faces);
   for (int32_t* p : h->d_nbr) (void)hipFree(p);
+  for (int4* p : h->d_plan) (void)hipFree(p);
+  for (uint32_t* p : h->d_plan_flags) (void)hipFree(p);
   delete h;
   return AF_OK;
 }
@@ -415,25 +426,58 @@ af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t 
 
 // ----------------------------------------------------------------- fill etc.
 
-af_status af_ghost_fill(af_ctx* ctx, const af_hier* h, af_state* bufs, uint32_t mask, int32_t tmin, int32_t smin,
+namespace {
+
+// The fill plan of hierarchy h for sources of level >= smin (smin <= lmax),
+// resolved on the device on first use.  The plan depends on the leaf set and
+// m only, so it serves every buffer pair and every lower target bound.
+af_status fill_plan(af_ctx* ctx, af_hier* h, int smin, hipStream_t stream) {
+  if (int(h->d_plan.size()) <= h->H.lmax) {
+    h->d_plan.resize(h->H.lmax + 1, nullptr);
+    h->d_plan_flags.resize(h->H.lmax + 1, nullptr);
+  }
+  if (h->d_plan[smin]) return AF_OK;
+  af_status s;
+  if ((s = ctx_device(ctx)) != AF_OK || (s = hier_device(h)) != AF_OK) return s;
+  const size_t n = h->H.leaves.size();
+  int4* plan = nullptr;
+  uint32_t* flags = nullptr;
+  AF_HIP(hipMalloc(&plan, std::max<size_t>(1, n * size_t(ctx->nentries)) * sizeof(int4)));
+  if (hipMalloc(&flags, std::max<size_t>(1, n) * sizeof(uint32_t)) != hipSuccess) {
+    (void)hipFree(plan);
+    return fail(AF_ERR_DEVICE, "fill plan allocation");
+  }
+  h->d_plan[smin] = plan;
+  h->d_plan_flags[smin] = flags;
+  AF_HIP(launch_fill_plan(h->dev, ctx->d_entries, ctx->nentries, ctx->P.m, smin, plan, flags, stream));
+  return AF_OK;
+}
+
+}  // namespace
+
+af_status af_ghost_fill(af_ctx* ctx, const af_hier* hc, af_state* bufs, uint32_t mask, int32_t tmin, int32_t smin,
                         hipStream_t stream) {
-  if (!ctx || !h) return fail(AF_ERR_ARG, "null argument");
+  if (!ctx || !hc) return fail(AF_ERR_ARG, "null argument");
+  af_hier* h = const_cast<af_hier*>(hc);
   af_status s = check_pair(ctx, h, bufs, "af_ghost_fill");
   if (s != AF_OK) return s;
   if (tmin < 0 || smin < 0) return fail(AF_ERR_ARG, "negative level bound");
+  if (smin > h->H.lmax) return AF_OK;  // no level may serve as a source
   int first = -1;
   for (int l = tmin; l <= h->H.lmax && first < 0; ++l)
     if (h->H.level_count[l]) first = h->H.level_first[l];
   if (first < 0) return AF_OK;
-  if ((s = ctx_device(ctx)) != AF_OK || (s = hier_device(const_cast<af_hier*>(h))) != AF_OK) return s;
+  if ((s = fill_plan(ctx, h, smin, stream)) != AF_OK) return s;
   // the coarse->fine phase is needed only if some target level has leaves
   // one level down that may serve as sources
   bool need_b = false;
   for (int l = std::max(tmin, 1); l <= h->H.lmax; ++l)
     if (h->H.level_count[l] && h->H.level_count[l - 1] && l - 1 >= smin) need_b = true;
   const int n = int(h->H.leaves.size()) - first;
-  AF_HIP(launch_ghost_fill(ctx->fp32(), make_buf(ctx, &bufs[0], &bufs[1], mask), h->dev, ctx->d_entries,
-                           ctx->nentries, first, n, tmin, smin, need_b, stream));
+  const BufLaunch b = make_buf(ctx, &bufs[0], &bufs[1], mask);
+  for (int phase = 0; phase < (need_b ? 2 : 1); ++phase)
+    AF_HIP(launch_fill_apply(ctx->fp32(), b, h->dev, ctx->d_entries, ctx->nentries, h->d_plan[smin],
+                             h->d_plan_flags[smin], ctx->d_fillw, first, n, phase, stream));
   return AF_OK;
 }
 
@@ -859,8 +903,11 @@ af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* 
   const GraphKey key{*mask, dt0, bufs[0].dof[0], bufs[1].dof[0], flux_reg};
   auto it = h->graphs.find(key);
   if (it == h->graphs.end()) {
-    // weights are computed on the host outside the capture
-    for (int l = 0; l <= h->H.finest; ++l) weights_for(ctx, dt0 / (1 << l) / ctx->dx(l), dt0 / (1 << l) / ctx->dy(l));
+    // weights and fill plans are made outside the capture
+    for (int l = 0; l <= h->H.finest; ++l) {
+      weights_for(ctx, dt0 / (1 << l) / ctx->dx(l), dt0 / (1 << l) / ctx->dy(l));
+      if ((s = fill_plan(ctx, h, l, stream)) != AF_OK) return s;
+    }
     hipStream_t cs;
     AF_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipGraph_t g;

@@ -84,6 +84,24 @@ struct CFFace {
   int32_t fine, fk;          // fine leaf facing it, index of the first of two fine faces
 };
 
+// Ghost-fill plan: one op per fill-set DOF of every leaf, holding the source
+// that the fill rules resolve to for a given lower bound on source levels.
+//   x: source leaf, or -1 for "keep the target's own value"
+//   y: fill_info(op, source kind, source level, position, phase)
+//   z, w: source (i, j) -- the element, fine cell or coarse cell
+enum FillOpKind { FO_COPY = 0, FO_MEAN4 = 1, FO_EVAL = 2, FO_QAVG = 3 };
+constexpr int kFillPoints = 25;  // EVAL positions (xi, eta) in {-1, -1/2, 0, 1/2, 1}^2: cx + 5 cy
+constexpr int kFillQuarters = 4; // QAVG quarter qx + 2 qy, at positions kFillPoints + ...
+__host__ __device__ constexpr int32_t fill_info(int op, int skind, int slevel, int pos, int phase) {
+  return op | (skind << 2) | (slevel << 4) | (pos << 8) | (phase << 16);
+}
+
+// Weights of a cell's raw DOFs (kCellDofs order) for the reconstruction at
+// the 25 EVAL positions and for the averages over its 4 quarters.
+struct FillWeights {
+  double w[kFillPoints + kFillQuarters][kCellDofs];
+};
+
 // Regrid transfer descriptor for one new leaf.
 struct Transfer {
   int32_t mode;       // 0 copy, 1 refine from parent, 2 coarsen from children

@@ -179,11 +179,13 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
   const int ilo = -region, ihi = M + region;
   const int span = ihi - ilo;
   const int tiles = (span + TY - 1) / TY;
+  const int rows = (span + tiles - 1) / tiles;  // balanced tile height, at most TY
   const int pl = blockIdx.x / tiles;
   const int patch = A.first + pl;
   const int tile = blockIdx.x - pl * tiles;
-  const int jlo = ilo + tile * TY;
-  const int jhi = min(jlo + TY, ihi);
+  const int jlo = ilo + tile * rows;
+  const int jhi = min(jlo + rows, ihi);
+  if (jlo >= jhi) return;  // block-uniform; cannot happen for the compiled (m, TY) pairs
   const int nrow = jhi - jlo;
   const size_t plane = size_t(M + 5) * A.pitch;
 
@@ -793,130 +795,180 @@ __device__ double quarter_avg(const Bufs<T>& B, int level, int comp, int patch, 
 
 // ---------------------------------------------------------------------------
 // Ghost fill (Sec. 3.1, 3.2).  entries: packed (kind << 24) | ((i+2) << 12) |
-// (j+2) for every DOF of the fill set.  Phase 0: same-level and finer
-// sources; phase 1: coarser sources.
+// (j+2) for every DOF of the fill set of a patch.
+//
+// The source of each fill-set DOF depends only on the leaf set and on the
+// lowest level allowed to serve as a source, so it is resolved once per
+// hierarchy (k_fill_plan) into an op; every fill then applies the ops
+// (k_fill_apply).  Phase 0 applies same-level and finer sources, phase 1
+// (after it, since a coarse reconstruction reads nodes that phase 0 may
+// rewrite on coarse-fine lines) the coarser ones.
 // ---------------------------------------------------------------------------
+
+// Source of fill-set DOF `code` of leaf t: averages from the same level, else
+// the mean of four finer averages, else the Simpson average of the coarser
+// reconstruction over the covered quarter; nodes from the finest leaf whose
+// closed square holds them (candidates of one level in the order (hi,hi),
+// (lo,hi), (hi,lo), (lo,lo)), the coarser reconstruction last.  Sources
+// below level smin are not used; a DOF with no source keeps its value.
+__device__ int4 fill_resolve(const HierDev& H, int m, int smin, int t, int32_t code) {
+  const int4 none = make_int4(-1, 0, 0, 0);
+  const int kind = code >> 24, i = ((code >> 12) & 0xfff) - kGhost, j = (code & 0xfff) - kGhost;
+  const int lt = H.plevel[t];
+  const long long I = (long long)H.pix[t] * m + i, J = (long long)H.piy[t] * m + j;
+  if (kind == 0) {
+    int src = -1, rel = 0;
+    if (lt >= smin) src = lut_find(H, lt, fdiv(I, m), fdiv(J, m));
+    if (src < 0 && lt + 1 <= H.lmax && lt + 1 >= smin) {
+      src = lut_find(H, lt + 1, fdiv(2 * I, m), fdiv(2 * J, m));
+      rel = 1;
+    }
+    if (src < 0 && lt - 1 >= 0 && lt - 1 >= smin) {
+      src = lut_find(H, lt - 1, fdiv(I, 2 * m), fdiv(J, 2 * m));
+      rel = -1;
+    }
+    if (src < 0) return none;
+    if (rel == 0)
+      return make_int4(src, fill_info(FO_COPY, 0, lt, 0, 0), int(I - fdiv(I, m) * m), int(J - fdiv(J, m) * m));
+    if (rel == 1)
+      return make_int4(src, fill_info(FO_MEAN4, 0, lt + 1, 0, 0), int(2 * I - fdiv(2 * I, m) * m),
+                       int(2 * J - fdiv(2 * J, m) * m));
+    const long long CI = fdiv(I, 2), CJ = fdiv(J, 2);
+    const int qx = (I - 2 * CI == 0) ? 0 : 1, qy = (J - 2 * CJ == 0) ? 0 : 1;
+    return make_int4(src, fill_info(FO_QAVG, 0, lt - 1, kFillPoints + qx + 2 * qy, 1), int(CI - fdiv(CI, m) * m),
+                     int(CJ - fdiv(CJ, m) * m));
+  }
+  // node position in level-(lt+1) half-cell units
+  const long long FX = 4 * I + (kind == 3 ? 2 : 0);
+  const long long FY = 4 * J + (kind == 2 ? 2 : 0);
+  int src = -1, rel = 0, sh = 0;
+  long long sx = 0, sy = 0;  // source-local position in level-(lt+1) half-cell units
+  for (int k = lt + 1; k >= lt - 1 && src < 0; --k) {
+    if (k < 0 || k > H.lmax || k < smin) continue;
+    sh = lt + 1 - k;
+    const long long P = 2LL * m << sh;
+    const long long hx = fdiv(FX, P), hy = fdiv(FY, P);
+    const bool bx = (FX - hx * P) == 0, by = (FY - hy * P) == 0;
+    const int ox[4] = {0, 1, 0, 1}, oy[4] = {0, 0, 1, 1};
+    for (int o = 0; o < 4; ++o) {
+      if (ox[o] && !bx) continue;
+      if (oy[o] && !by) continue;
+      const int id = lut_find(H, k, hx - ox[o], hy - oy[o]);
+      if (id < 0) continue;
+      src = id;
+      rel = k - lt;
+      sx = FX - (hx - ox[o]) * P;
+      sy = FY - (hy - oy[o]) * P;
+      break;
+    }
+  }
+  if (src < 0) return none;
+  const long long unit = 1LL << sh;
+  if (rel >= 0) {
+    const long long X = sx / unit, Y = sy / unit;  // source half-cell units
+    if (rel == 0 && src == t) {
+      // the target itself: keep unless the match is a periodic image
+      const long long Xt = 2 * i + (kind == 3 ? 1 : 0), Yt = 2 * j + (kind == 2 ? 1 : 0);
+      if (X == Xt && Y == Yt) return none;
+    }
+    const int ls = lt + rel;
+    const bool ex = (X % 2) == 0, ey = (Y % 2) == 0;
+    if (ex && ey) return make_int4(src, fill_info(FO_COPY, 1, ls, 0, 0), int(X / 2), int(Y / 2));
+    if (ex) return make_int4(src, fill_info(FO_COPY, 2, ls, 0, 0), int(X / 2), int((Y - 1) / 2));
+    return make_int4(src, fill_info(FO_COPY, 3, ls, 0, 0), int((X - 1) / 2), int(Y / 2));
+  }
+  // coarser: reconstruction of the covering cell at a quarter-step point
+  // (sx, sy are multiples of 2: fine nodes sit on a half-of-half-cell grid)
+  const long long cx2 = sx / 2, cy2 = sy / 2;  // coarse quarter-cell units
+  int ci = int(cx2 / 4), cj = int(cy2 / 4);
+  ci = min(max(ci, 0), m - 1);
+  cj = min(max(cj, 0), m - 1);
+  const int px = int(cx2 - 4LL * ci), py = int(cy2 - 4LL * cj);  // 0..4: xi = px/2 - 1
+  return make_int4(src, fill_info(FO_EVAL, 0, lt - 1, px + 5 * py, 1), ci, cj);
+}
+
+// One block per leaf: the plan row of the leaf and a flag word (bit p: the
+// leaf has ops of phase p).
+__global__ __launch_bounds__(kThreads) void k_fill_plan(const HierDev H, const int32_t* entries, int nentries, int m,
+                                                        int smin, int4* plan, uint32_t* flags) {
+  const int t = blockIdx.x;
+  int has0 = 0, has1 = 0;
+  for (int e = threadIdx.x; e < nentries; e += kThreads) {
+    const int4 op = fill_resolve(H, m, smin, t, entries[e]);
+    plan[size_t(t) * nentries + e] = op;
+    if (op.x >= 0) {
+      if ((op.y >> 16) & 1) has1 = 1;
+      else has0 = 1;
+    }
+  }
+  has0 = __syncthreads_or(has0);
+  has1 = __syncthreads_or(has1);
+  if (threadIdx.x == 0) flags[t] = uint32_t(has0) | (uint32_t(has1) << 1);
+}
 
 template <typename T>
 struct FillArgs {
   Bufs<T> B;
-  HierDev H;
+  const int32_t* plevel;
   const int32_t* entries;
-  int32_t nentries, chunks, first_target, tmin, smin, phase;
+  const int4* plan;
+  const uint32_t* flags;
+  const FillWeights* W;
+  int32_t nentries, chunks, first_target, phase;
 };
 
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_ghost_fill(const FillArgs<T> A) {
+__global__ __launch_bounds__(kThreads) void k_fill_apply(const FillArgs<T> A) {
   const int tl = blockIdx.x / A.chunks;
   const int chunk = blockIdx.x - tl * A.chunks;
   const int t = A.first_target + tl;
-  const HierDev& H = A.H;
-  const int m = A.B.m, nc = A.B.ncomp;
-  const int lt = H.plevel[t];
-  const long long tx = H.pix[t], ty = H.piy[t];
+  if (!((A.flags[t] >> A.phase) & 1u)) return;  // block-uniform
+  const Bufs<T>& B = A.B;
+  const int lt = A.plevel[t], nc = B.ncomp;
+  const size_t cstride = size_t(B.npatch) * (B.m + 5) * B.pitch;  // component stride
   for (int e = chunk * kThreads + threadIdx.x; e < A.nentries; e += A.chunks * kThreads) {
+    const int4 op = A.plan[size_t(t) * A.nentries + e];
+    if (op.x < 0 || ((op.y >> 16) & 1) != A.phase) continue;
     const int32_t code = A.entries[e];
     const int kind = code >> 24, i = ((code >> 12) & 0xfff) - kGhost, j = (code & 0xfff) - kGhost;
-    const long long I = tx * m + i, J = ty * m + j;
-    if (kind == 0) {
-      int src = -1, rel = 0;
-      if (lt >= A.smin) {
-        src = lut_find(H, lt, fdiv(I, m), fdiv(J, m));
-        rel = 0;
-      }
-      if (src < 0 && lt + 1 <= H.lmax && lt + 1 >= A.smin) {
-        src = lut_find(H, lt + 1, fdiv(2 * I, m), fdiv(2 * J, m));
-        rel = 1;
-      }
-      if (src < 0 && lt - 1 >= 0 && lt - 1 >= A.smin) {
-        src = lut_find(H, lt - 1, fdiv(I, 2 * m), fdiv(J, 2 * m));
-        rel = -1;
-      }
-      if (src < 0) continue;
-      if ((A.phase == 0) != (rel >= 0)) continue;
-      const int ls = lt + rel;
-      T* dst = buf_of(A.B, lt, 0);
-      const T* sav = buf_of(A.B, ls, 0);
+    const int fo = op.y & 3, skind = (op.y >> 2) & 3, ls = (op.y >> 4) & 15, pos = (op.y >> 8) & 255;
+    T* const dst = buf_of(B, lt, kind) + at(B, 0, t, i, j);
+    if (fo == FO_COPY) {
+      const T* s = buf_of(B, ls, skind) + at(B, 0, op.x, op.z, op.w);
+      for (int q = 0; q < nc; ++q) dst[q * cstride] = s[q * cstride];
+    } else if (fo == FO_MEAN4) {
+      // mean of the four fine averages (fine -> coarse transfer)
+      const T* s = buf_of(B, ls, 0) + at(B, 0, op.x, op.z, op.w);
+      const int P = B.pitch;
       for (int q = 0; q < nc; ++q) {
-        double val;
-        if (rel == 0) {
-          const int li = int(I - fdiv(I, m) * m), lj = int(J - fdiv(J, m) * m);
-          val = sav[at(A.B, q, src, li, lj)];
-        } else if (rel == 1) {
-          const int fi = int(2 * I - fdiv(2 * I, m) * m), fj = int(2 * J - fdiv(2 * J, m) * m);
-          // mean of the four fine averages (fine -> coarse transfer)
-          val = 0.25 * ((double(sav[at(A.B, q, src, fi, fj)]) + double(sav[at(A.B, q, src, fi + 1, fj)])) +
-                        (double(sav[at(A.B, q, src, fi, fj + 1)]) + double(sav[at(A.B, q, src, fi + 1, fj + 1)])));
-        } else {
-          const long long CI = fdiv(I, 2), CJ = fdiv(J, 2);
-          const int ci = int(CI - fdiv(CI, m) * m), cj = int(CJ - fdiv(CJ, m) * m);
-          val = quarter_avg(A.B, ls, q, src, ci, cj, (I - 2 * CI == 0) ? -1.0 : 0.0, (J - 2 * CJ == 0) ? -1.0 : 0.0);
-        }
-        dst[at(A.B, q, t, i, j)] = T(val);
+        const T* v = s + q * cstride;
+        dst[q * cstride] = T(0.25 * ((double(v[0]) + double(v[1])) + (double(v[P]) + double(v[P + 1]))));
       }
     } else {
-      // node position in level-(lt+1) half-cell units
-      const long long FX = 4 * I + (kind == 3 ? 2 : 0);
-      const long long FY = 4 * J + (kind == 2 ? 2 : 0);
-      int src = -1, rel = 0;
-      long long sx = 0, sy = 0;  // source-local position in fine units
-      int sh = 0;
-      for (int k = lt + 1; k >= lt - 1 && src < 0; --k) {
-        if (k < 0 || k > H.lmax || k < A.smin) continue;
-        sh = lt + 1 - k;
-        const long long unit = 1LL << sh, P = 2LL * m * unit;
-        const long long hx = fdiv(FX, P), hy = fdiv(FY, P);
-        const bool bx = (FX - hx * P) == 0, by = (FY - hy * P) == 0;
-        const int ox[4] = {0, 1, 0, 1}, oy[4] = {0, 0, 1, 1};
-        for (int o = 0; o < 4; ++o) {
-          if (ox[o] && !bx) continue;
-          if (oy[o] && !by) continue;
-          const int id = lut_find(H, k, hx - ox[o], hy - oy[o]);
-          if (id < 0) continue;
-          src = id;
-          rel = k - lt;
-          sx = FX - (hx - ox[o]) * P;
-          sy = FY - (hy - oy[o]) * P;
-          break;
-        }
-      }
-      if (src < 0) continue;
-      if ((A.phase == 0) != (rel >= 0)) continue;
-      const long long unit = 1LL << sh;
-      if (rel == 0 && src == t) {
-        // the target itself: skip unless the match is a periodic image
-        const long long X = sx / unit, Y = sy / unit;
-        const long long Xt = 2 * i + (kind == 3 ? 1 : 0), Yt = 2 * j + (kind == 2 ? 1 : 0);
-        if (X == Xt && Y == Yt) continue;
-      }
-      const int ls = lt + rel;
-      T* dst = buf_of(A.B, lt, kind);
+      // coarse reconstruction: point value (EVAL) or quarter average (QAVG)
+      const double* w = A.W->w[pos];
+      const int P = B.pitch;
+      const size_t o = at(B, 0, op.x, op.z, op.w);
+      const T* av = buf_of(B, ls, 0) + o;
+      const T* co = buf_of(B, ls, 1) + o;
+      const T* xe = buf_of(B, ls, 2) + o;
+      const T* ye = buf_of(B, ls, 3) + o;
       for (int q = 0; q < nc; ++q) {
-        double val;
-        if (rel >= 0) {
-          const long long X = sx / unit, Y = sy / unit;  // source half-cell units
-          const bool ex = (X % 2) == 0, ey = (Y % 2) == 0;
-          if (ex && ey) val = buf_of(A.B, ls, 1)[at(A.B, q, src, int(X / 2), int(Y / 2))];
-          else if (ex) val = buf_of(A.B, ls, 2)[at(A.B, q, src, int(X / 2), int((Y - 1) / 2))];
-          else val = buf_of(A.B, ls, 3)[at(A.B, q, src, int((X - 1) / 2), int(Y / 2))];
-        } else {
-          const double xs = double(sx) / 4.0, ys = double(sy) / 4.0;  // coarse half-cell units
-          int ci = int(floor(xs / 2.0)), cj = int(floor(ys / 2.0));
-          ci = min(max(ci, 0), m - 1);
-          cj = min(max(cj, 0), m - 1);
-          val = eval_cell(A.B, ls, q, src, ci, cj, xs - (2.0 * ci + 1.0), ys - (2.0 * cj + 1.0));
-        }
-        dst[at(A.B, q, t, i, j)] = T(val);
+        const size_t c = q * cstride;
+        double v = w[0] * double(av[c]);
+        v += w[1] * double(co[c]);
+        v += w[2] * double(co[c + 1]);
+        v += w[3] * double(co[c + P]);
+        v += w[4] * double(co[c + P + 1]);
+        v += w[5] * double(xe[c]);
+        v += w[6] * double(xe[c + 1]);
+        v += w[7] * double(ye[c]);
+        v += w[8] * double(ye[c + P]);
+        dst[c] = T(v);
       }
     }
   }
 }
-
-// ---------------------------------------------------------------------------
-// Conservative fix (Sec. 3.2).  faces are grouped by coarse cell; the first
-// thread of a group applies all of its faces, so no two threads touch one
-// cell.
-// ---------------------------------------------------------------------------
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_flux_correct(Bufs<T> B, const CFFace* faces, int nfaces,
@@ -1243,34 +1295,39 @@ static Bufs<T> make_bufs(const BufLaunch& b) {
   return B;
 }
 
+hipError_t launch_fill_plan(const HierDev& H, const int32_t* entries, int nentries, int m, int smin, int4* plan,
+                            uint32_t* flags, hipStream_t st) {
+  if (H.nleaves <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_plan, dim3(unsigned(H.nleaves)), dim3(kThreads), 0, st, H, entries, nentries, m, smin, plan,
+                     flags);
+  return hipGetLastError();
+}
+
 template <typename T>
-static hipError_t ghost_fill_t(const BufLaunch& b, const HierDev& H, const int32_t* entries, int nentries,
-                               int first_target, int ntargets, int tmin, int smin, bool phase_b,
-                               hipStream_t st) {
+static hipError_t fill_apply_t(const BufLaunch& b, const HierDev& H, const int32_t* entries, int nentries,
+                               const int4* plan, const uint32_t* flags, const FillWeights* W, int first_target,
+                               int ntargets, int phase, hipStream_t st) {
   FillArgs<T> A;
   A.B = make_bufs<T>(b);
-  A.H = H;
+  A.plevel = H.plevel;
   A.entries = entries;
+  A.plan = plan;
+  A.flags = flags;
+  A.W = W;
   A.nentries = nentries;
   A.chunks = (nentries + kThreads - 1) / kThreads;
   A.first_target = first_target;
-  A.tmin = tmin;
-  A.smin = smin;
-  for (int phase = 0; phase < (phase_b ? 2 : 1); ++phase) {
-    A.phase = phase;
-    hipLaunchKernelGGL(k_ghost_fill<T>, dim3(unsigned(ntargets * A.chunks)), dim3(kThreads), 0, st, A);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+  A.phase = phase;
+  hipLaunchKernelGGL(k_fill_apply<T>, dim3(unsigned(ntargets * A.chunks)), dim3(kThreads), 0, st, A);
+  return hipGetLastError();
 }
 
-hipError_t launch_ghost_fill(bool fp32, const BufLaunch& b, const HierDev& H, const int32_t* entries,
-                             int nentries, int first_target, int ntargets, int tmin, int smin, bool phase_b,
-                             hipStream_t st) {
+hipError_t launch_fill_apply(bool fp32, const BufLaunch& b, const HierDev& H, const int32_t* entries, int nentries,
+                             const int4* plan, const uint32_t* flags, const FillWeights* W, int first_target,
+                             int ntargets, int phase, hipStream_t st) {
   if (ntargets <= 0) return hipSuccess;
-  return fp32 ? ghost_fill_t<float>(b, H, entries, nentries, first_target, ntargets, tmin, smin, phase_b, st)
-              : ghost_fill_t<double>(b, H, entries, nentries, first_target, ntargets, tmin, smin, phase_b, st);
+  return fp32 ? fill_apply_t<float>(b, H, entries, nentries, plan, flags, W, first_target, ntargets, phase, st)
+              : fill_apply_t<double>(b, H, entries, nentries, plan, flags, W, first_target, ntargets, phase, st);
 }
 
 hipError_t launch_flux_correct(bool fp32, const BufLaunch& b, const CFFace* faces, int nfaces, double* reg,

@@ -42,9 +42,14 @@ hipError_t launch_level_advance(const AdvanceLaunch& s, hipStream_t st);
 // fills (K, threads) pairs available for (precision, equation, m); returns the count
 int level_advance_shapes(bool fp32, int eq, int m, int* ks, int* nts, int cap);
 bool step_shape_supported(int m, int ty);
-hipError_t launch_ghost_fill(bool fp32, const BufLaunch& b, const HierDev& H, const int32_t* entries,
-                             int nentries, int first_target, int ntargets, int tmin, int smin, bool phase_b,
-                             hipStream_t st);
+// resolves the fill sources of every leaf (sources of level >= smin) into
+// plan[nleaves][nentries] and flags[nleaves] (bit p: ops of phase p)
+hipError_t launch_fill_plan(const HierDev& H, const int32_t* entries, int nentries, int m, int smin, int4* plan,
+                            uint32_t* flags, hipStream_t st);
+// applies the phase-`phase` ops of leaves [first_target, first_target + ntargets)
+hipError_t launch_fill_apply(bool fp32, const BufLaunch& b, const HierDev& H, const int32_t* entries, int nentries,
+                             const int4* plan, const uint32_t* flags, const FillWeights* W, int first_target,
+                             int ntargets, int phase, hipStream_t st);
 hipError_t launch_flux_correct(bool fp32, const BufLaunch& b, const CFFace* faces, int nfaces, double* reg,
                                int level, double inv_area, hipStream_t st);
 hipError_t launch_tag(bool fp32, const BufLaunch& b, const HierDev& H, int mode, int comp, double inv2dx0,

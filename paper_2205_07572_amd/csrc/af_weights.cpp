@@ -218,6 +218,24 @@ void make_ac_weights(double c_dtdx, double c_dtdy, AcWeights<T>* W) {
   }
 }
 
+void make_fill_weights(FillWeights* W) {
+  // points: xi = cx/2 - 1, eta = cy/2 - 1
+  for (int cy = 0; cy < 5; ++cy)
+    for (int cx = 0; cx < 5; ++cx)
+      for (int d = 0; d < kCellDofs; ++d) W->w[cx + 5 * cy][d] = poly_eval(dof_basis(d), 0.5 * cx - 1.0, 0.5 * cy - 1.0);
+  // quarter [qx - 1, qx] x [qy - 1, qy]: tensor Simpson, exact for the biquadratic
+  static const double sw[3] = {1.0, 4.0, 1.0};
+  for (int qy = 0; qy < 2; ++qy)
+    for (int qx = 0; qx < 2; ++qx)
+      for (int d = 0; d < kCellDofs; ++d) {
+        const Poly2 b = dof_basis(d);
+        double s = 0.0;
+        for (int p = 0; p < 3; ++p)
+          for (int q = 0; q < 3; ++q) s += sw[p] * sw[q] * poly_eval(b, qx - 1.0 + 0.5 * p, qy - 1.0 + 0.5 * q);
+        W->w[kFillPoints + qx + 2 * qy][d] = s / 36.0;
+      }
+}
+
 template void make_adv_weights<float>(double, double, AdvWeights<float>*);
 template void make_adv_weights<double>(double, double, AdvWeights<double>*);
 template void make_ac_weights<float>(double, double, AcWeights<float>*);

@@ -13,4 +13,8 @@ void make_adv_weights(double a_dtdx, double b_dtdy, AdvWeights<T>* W);
 template <typename T>
 void make_ac_weights(double c_dtdx, double c_dtdy, AcWeights<T>* W);
 
+// Reconstruction weights for the coarse -> fine fill (Sec. 3.1): values at
+// the quarter-step points of the reference square and quarter averages.
+void make_fill_weights(FillWeights* W);
+
 }  // namespace af
