@@ -39,8 +39,9 @@ def parse():
     p.add_argument("--steps", type=int, default=NSTEPS_T)
     p.add_argument("--warmup", type=int, default=20)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--cpu-steps", type=int, default=48)
+    p.add_argument("--cpu-steps", type=int, default=144)
     p.add_argument("--general-steps", type=int, default=128)
+    p.add_argument("--no-amr", action="store_true", help="skip the adaptive acoustics runs")
     p.add_argument("--sweep", action="store_true",
                    help="roofline sweep: uniform grids up to 4096^2 (HBM resident); one JSON line per case")
     p.add_argument("--copy-probe", action="store_true",
@@ -135,51 +136,147 @@ def time_path(prec, data, steps, warmup, dt, general_steps):
                 general_ms_per_step=g_ms / general_steps)
 
 
+# FP32 / FP64 vector peaks (MI355X published figures, TFLOP/s); packed FP32
+# instructions are disabled in this build, so FP32 kernels can reach at most
+# half of the FP32 figure.
+PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+# algorithmic flops per cell-update of the collapsed stencils: advection 6
+# node values x 9 FMA + 3 time sums (2 ops) + 4 face sums (2 ops) + update
+# (6 ops); acoustics: corner 25-entry, x- and y-edge 15-entry stencils, each
+# with 7 dot products at 2 time levels (770 FMA), + 9 time sums + 12 face
+# sums x 2 + 3-component update (about 24 ops)
+FLOPS_PER_UPDATE = {0: 2 * 54 + 6 + 8 + 6, 1: 2 * 770 + 18 + 24 + 24}
+
+
 def sweep():
-    """Kernel bandwidth on uniform grids of 32^2 patches from 1024^2 to
-    4096^2 cells (two state buffers of up to 2.9 GB in FP32, far beyond the
-    256 MB Infinity Cache), advection, FP32 and FP64: the autotuned level
-    advance and the plain patch step, each timed with HIP events over
-    repeated launches on the stream they run on."""
+    """Roofline sweep on uniform periodic grids from 1024^2 to 4096^2 cells
+    (state up to 6.3 GB per buffer, far beyond the 256 MB Infinity Cache):
+    advection and acoustics, 32^2 and 16^2 patches, FP32 and FP64.  Launch
+    times come from the autotuner, which times back-to-back launches of
+    every kernel shape with HIP events on the stream they run on.  State
+    values are random (timing does not depend on them).  One JSON line per
+    case."""
     import torch
     import afsynth
     import paper_2205_07572_amd as af
-    data = afsynth.fourier_modes(1)
-    for n0 in (32, 64, 128):
-        N = n0 * M
+    cases = [(0, 32, 1024), (0, 32, 2048), (0, 32, 4096), (0, 16, 4096),
+             (1, 16, 1024), (1, 16, 2048), (1, 16, 4096), (1, 32, 4096)]
+    for eq, m, N in cases:
+        n0 = N // m
         for name, prec, wb in (("fp32", af.FP32, 4), ("fp64", af.FP64, 8)):
-            prob = af.Problem(eq=af.ADVECTION, prec=prec, m=M, n0x=n0, n0y=n0, lmax=0, a=1.0, b=0.5)
+            phys = dict(a=1.0, b=0.5) if eq == 0 else dict(c=1.0)
+            prob = af.Problem(eq=eq, prec=prec, m=m, n0x=n0, n0y=n0, lmax=0, **phys)
             ctx = af.Context(prob)
             h = af.Hierarchy(ctx, afsynth.uniform_leaves(n0, n0, 0))
-            d0 = afsynth.dofs_periodic(data, N, N, nq=2)
-            blk = afsynth.periodic_to_blocks(d0, M)
             t = ctx.new_state(n0 * n0)
-            host = np.stack([blk[k] for k in af.KINDS])  # [4][P][ncomp][S1][S1]
-            t.copy_(torch.from_numpy(host.transpose(0, 2, 1, 3, 4).copy()).to(t.dtype))
+            g = torch.Generator(device="cuda").manual_seed(N + m + eq)
+            t.copy_(torch.randn(t.shape, generator=g, device="cuda", dtype=t.dtype))
             bufs = [t, torch.zeros_like(t)]
-            dt = 0.4 / N
-            step_us, adv_us = ctx.autotune(h, bufs, 0, dt, reps=5)
-            K, NT = ctx.advance_shape
-            nl = max(4, 64 // K)
-            ms, _ = _event_ms(lambda: [ctx.level_advance(h, bufs, 0, 0, dt, K) for _ in range(nl)])
-            adv_launch_us = ms * 1e3 / nl
-            ms, _ = _event_ms(lambda: [ctx.patch_step(bufs[0], bufs[1], 0, n0 * n0, 0, dt, 0) for _ in range(nl)])
-            step_launch_us = ms * 1e3 / nl
-            alg = 8 * wb * N * N
-            print(json.dumps({"sweep": True, "cells": N * N, "prec": name, "state_bytes_per_buffer": t.numel() * wb,
-                              "level_advance": {"K": K, "threads": NT, "launch_us": adv_launch_us,
-                                                "gbs": alg * K / (adv_launch_us * 1e-6) / 1e9,
-                                                "frac": alg * K / (adv_launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
-                                                "cell_updates_per_s": N * N * K / (adv_launch_us * 1e-6)},
-                              "patch_step": {"tile_rows": ctx.tile, "launch_us": step_launch_us,
-                                             "gbs": alg / (step_launch_us * 1e-6) / 1e9,
-                                             "frac": alg / (step_launch_us * 1e-6) / 1e9 / HBM_PEAK_GBS}}),
-                  flush=True)
+            dt = (0.4 if eq == 0 else 0.4) / N
+            step_us, adv_us = ctx.autotune(h, bufs, 0, dt, reps=10)
+            ncomp = 1 if eq == 0 else 3
+            alg = 8 * ncomp * wb * N * N  # algorithmic bytes per step
+            flops = FLOPS_PER_UPDATE[eq] * N * N
+            line = {"sweep": True, "equation": ["advection", "acoustics"][eq], "patch": m, "cells": N * N,
+                    "prec": name, "state_bytes_per_buffer": t.numel() * wb,
+                    "patch_step": {"tile_rows": ctx.tile, "launch_us": step_us,
+                                   "gbs": alg / (step_us * 1e-6) / 1e9,
+                                   "hbm_frac": alg / (step_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                                   "alu_frac": flops / (step_us * 1e-6) / 1e12 / PEAK_TFLOPS[name],
+                                   "cell_updates_per_s": N * N / (step_us * 1e-6)}}
+            if adv_us > 0:
+                K, NT = ctx.advance_shape
+                line["level_advance"] = {"K": K, "threads": NT, "launch_us": adv_us * K,
+                                         "gbs": alg / (adv_us * 1e-6) / 1e9,
+                                         "hbm_frac": alg / (adv_us * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                                         "alu_frac": flops / (adv_us * 1e-6) / 1e12 / PEAK_TFLOPS[name],
+                                         "cell_updates_per_s": N * N / (adv_us * 1e-6)}
+            print(json.dumps(line), flush=True)
             del bufs, t
             torch.cuda.empty_cache()
 
 
+def amr_runs():
+    """Adaptive acoustics, the two AMR workloads, FP32 bulk and FP64, to
+    T = 0.5 with plain gradient tagging every 4 coarse steps:
+      config3: Gaussian pulse exp(-200 |x - x0|^2), 3 levels, refine at
+               |grad p| >= 1, coarsen below 0.25;
+      config4: wave packet exp(-50 |x - x0|^2) cos(k.x), |k| = 80 pi, 4
+               levels, refine at 8, coarsen below 2.
+    Base 8x8 patches of 16^2, CFL 0.4 on every level (subcycling), seed 0.
+    Cell-updates/s counts step time only (device events around the coarse
+    steps); time to solution includes the regrids.  The error is the
+    L-infinity error of the pressure averages over all leaves against the
+    exact Fourier solution."""
+    import math
+    import torch
+    import afsynth
+    import paper_2205_07572_amd as af
+    from paper_2205_07572_amd.amr import TagRule, initial_hierarchy
+    specs = {"config3": (2, afsynth.gaussian_pulse(0), lambda d: afsynth.gaussian_pulse_exact(d, 200.0),
+                         TagRule(af.TAG_GRADIENT, 0, 1.0, 0.25)),
+             "config4": (3, afsynth.wave_packet(0), afsynth.wave_packet_exact, TagRule(af.TAG_GRADIENT, 0, 8.0, 2.0))}
+    T, every, m = 0.5, 4, 16
+    out = {}
+    for name, (lmax, data, exact_of, rule) in specs.items():
+        exact = exact_of(data)
+        res = {}
+        for pname, prec in (("fp32", af.FP32), ("fp64", af.FP64)):
+            prob = af.Problem(eq=af.ACOUSTICS, prec=prec, m=m, n0x=8, n0y=8, lmax=lmax, c=1.0)
+
+            def block_fn(l, ix, iy, prob=prob):
+                dx = prob.dx(l)
+                return afsynth.dofs_block(data, m, 2, ix * m * dx, iy * m * dx, dx, dx, 4)
+
+            run = initial_hierarchy(prob, block_fn, rule)
+            n = math.ceil(T / (0.4 * prob.dx(0)))
+            dt0 = T / n
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            step = 0
+            while step < n:
+                k = min(every, n - step)
+                run.coarse_steps(dt0, k)
+                step += k
+                if step < n:
+                    run.regrid(rule)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            leaves = run.hier.leaves()
+            blocks = run.blocks()
+            err = 0.0
+            for l in sorted({lv for lv, _, _ in leaves}):
+                dx = prob.dx(l)
+                nl = 8 * m << l
+                xs = (np.arange(nl) + 0.5) * dx
+                E = exact.grid_values(xs, xs, T, dx, dx)[0]  # [y][x] pressure averages
+                for b, (lv, ix, iy) in zip(blocks, leaves):
+                    if lv == l:
+                        d = b["avg"][0, 2:2 + m, 2:2 + m] - E[iy * m:(iy + 1) * m, ix * m:(ix + 1) * m]
+                        err = max(err, float(np.abs(d).max()))
+            st = run.stats
+            hist = st.leaves_history
+            res[pname] = {"coarse_steps": st.coarse_steps, "regrids": st.regrids,
+                          "cell_updates": st.cell_updates, "step_s": st.step_seconds,
+                          "cell_updates_per_s": st.cell_updates / st.step_seconds,
+                          "us_per_coarse_step": 1e6 * st.step_seconds / st.coarse_steps,
+                          "regrid_s": st.regrid_seconds, "time_to_solution_s": wall,
+                          "leaves_mean": float(np.mean(hist)) if hist else len(leaves), "leaves_max": max(hist or [0]),
+                          "leaves_per_level_final": np.bincount([lv for lv, _, _ in leaves]).tolist(),
+                          "linf_p_vs_exact": err}
+            print(f"[bench] {name} {pname}: {st.coarse_steps} coarse steps, {res[pname]['cell_updates_per_s']:.3e} "
+                  f"cell-updates/s, {res[pname]['us_per_coarse_step']:.0f} us/coarse step, leaves "
+                  f"{res[pname]['leaves_mean']:.0f} (max {res[pname]['leaves_max']}), time to solution {wall:.3f} s, "
+                  f"L-inf p {err:.3e}", file=sys.stderr, flush=True)
+            del run
+            torch.cuda.empty_cache()
+        out[name] = res
+    return out
+
+
 def cpu_baseline(data, nsteps, dt):
+    """The FP64 oracle, single-threaded, on `nsteps` steps of the benchmark
+    grid."""
     import afsynth
     import oracle
     d0 = afsynth.dofs_periodic(data, M * N0, M * N0, nq=4)
@@ -187,6 +284,41 @@ def cpu_baseline(data, nsteps, dt):
     oracle.run_periodic(0, d0, dt, nsteps, a=1.0, b=0.5)
     el = time.perf_counter() - t0
     return NCELL * nsteps / el, el
+
+
+_ORACLE_CHILD = """
+import sys, time
+import numpy as np
+sys.path.insert(0, sys.argv[1])
+import oracle
+z = np.load(sys.argv[2])
+d0 = {k: (z[k].item() if z[k].ndim == 0 else z[k]) for k in z.files}
+t0 = time.perf_counter()
+oracle.run_periodic(0, d0, float(sys.argv[3]), int(sys.argv[4]), a=1.0, b=0.5)
+print(time.perf_counter() - t0)
+"""
+
+
+def cpu_baseline_allcore(data, nsteps, dt, nproc):
+    """All-core oracle throughput: nproc independent single-threaded oracle
+    processes (fresh interpreters that never touch the GPU), each stepping
+    its own copy of the benchmark grid; aggregate cell-updates/s over the
+    wall time of the slowest."""
+    import subprocess
+    import tempfile
+    import afsynth
+    d0 = afsynth.dofs_periodic(data, M * N0, M * N0, nq=4)
+    with tempfile.TemporaryDirectory() as tmp:
+        path = os.path.join(tmp, "d0.npz")
+        np.savez(path, **{k: np.asarray(v) for k, v in d0.items()})
+        t0 = time.perf_counter()
+        procs = [subprocess.Popen([sys.executable, "-c", _ORACLE_CHILD, ROOT, path, repr(dt), str(nsteps)],
+                                  stdout=subprocess.PIPE, text=True) for _ in range(nproc)]
+        outs = [p.communicate()[0] for p in procs]
+        wall = time.perf_counter() - t0
+        if any(p.returncode != 0 for p in procs):
+            raise RuntimeError("oracle child failed")
+    return nproc * NCELL * nsteps / wall, wall, [float(o.strip()) for o in outs]
 
 
 def main():
@@ -272,11 +404,21 @@ def main():
                      "kernel": f"k_level_advance_adv<float,32,{K32},{res['fp32']['NT']},upwind>",
                      "kernel_us": k32 * 1e3, "algorithmic_bytes_per_launch": bytes32},
     }
+    if not args.no_amr:
+        line["amr"] = amr_runs()
     if not args.no_cpu:
         v, el = cpu_baseline(data, args.cpu_steps, dt)
         line["cpu_baseline"] = {"value": v, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
                                 "sample": f"{args.cpu_steps} of the 1280 steps on the 512^2 grid "
                                           f"(single-threaded FP64 oracle, {el:.1f} s)"}
+        nproc = min(16, len(os.sched_getaffinity(0)))
+        va, wa, each = cpu_baseline_allcore(data, args.cpu_steps // 3, dt, nproc)
+        line["cpu_baseline_allcore"] = {"value": va, "unit": "cell-updates/s", "cores": nproc, "kind": "oracle",
+                                        "sample": f"{nproc} independent oracle processes, {args.cpu_steps // 3} "
+                                                  f"steps of the 512^2 grid each, {wa:.1f} s wall "
+                                                  f"(slowest process {max(each):.1f} s)"}
+        print(f"[bench] oracle: {v:.3e} cell-updates/s on 1 core, {va:.3e} on {nproc} cores", file=sys.stderr,
+              flush=True)
     print(json.dumps(line), flush=True)
 
 

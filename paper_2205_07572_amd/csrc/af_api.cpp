@@ -827,7 +827,7 @@ af_status af_autotune(af_ctx* ctx, af_hier* h, af_state* bufs, int32_t level, do
     }
     ctx->adv_k = bk;
     ctx->adv_nt = bn;
-    best_adv = b2;
+    if (bk > 0) best_adv = b2;  // stays -1 when no shape is compiled for (precision, equation, m)
   }
   g_err.clear();
   (void)hipEventDestroy(e0);

@@ -453,3 +453,18 @@ def test_edge_cases_and_errors():
     assert e.value.status == af._lib.AF_ERR_LAYOUT
     torch.cuda.synchronize()
     assert float(u.abs().max()) == 0.0
+
+
+def test_autotune_without_level_advance_shape():
+    """A level whose leaves all have same-level neighbours but no compiled
+    level-advance shape (acoustics, FP64, m = 32): the autotuner still tunes
+    the patch step and reports -1 for the level advance."""
+    torch = _torch()
+    n0, m = 2, 32
+    prob = make_problem(1, af.FP64, m, n0=n0)
+    ctx = af.Context(prob)
+    assert ctx.advance_shapes() == []
+    h = af.Hierarchy(ctx, afsynth.uniform_leaves(n0, n0, 0))
+    b = ctx.new_state(n0 * n0)
+    step_us, adv_us = ctx.autotune(h, [b, torch.zeros_like(b)], 0, 0.4 / (n0 * m), reps=1)
+    assert step_us > 0 and adv_us == -1
