@@ -199,6 +199,38 @@ def wave_packet(seed: int, alpha=50.0):
     return d
 
 
+def solid_body(q0, omega=np.pi, xc=0.0, yc=0.0):
+    """Data q0(x, y) (scalar function) under solid-body rotation
+    a = -omega (y - yc), b = omega (x - xc) (Sec. 4.2): the exact solution at
+    time t is q0 at the point turned back by -omega t about (xc, yc)."""
+
+    def f(x, y):
+        return np.asarray(q0(np.asarray(x, float), np.asarray(y, float)))[None]
+
+    def exact(x, y, t):
+        c, s = np.cos(omega * t), np.sin(omega * t)
+        rx, ry = np.asarray(x, float) - xc, np.asarray(y, float) - yc
+        return f(xc + rx * c + ry * s, yc - rx * s + ry * c)
+
+    return InitialData(1, f, exact)
+
+
+def disc_q0(r0=0.15, width=0.02, xc=0.5, yc=0.5):
+    """The smoothed disc H(r + r0) - H(r - r0), H(r) = (tanh(r/w)+1)/2, of
+    eq. AdvH as a plain function of (x, y) (not periodised)."""
+
+    def q0(x, y):
+        r = np.sqrt((x - xc) ** 2 + (y - yc) ** 2)
+        return 0.5 * (np.tanh((r + r0) / width) - np.tanh((r - r0) / width))
+
+    return q0
+
+
+def gauss_q0(x0, y0, alpha):
+    """exp(-alpha |x - x0|^2) as a plain function of (x, y)."""
+    return lambda x, y: np.exp(-alpha * ((x - x0) ** 2 + (y - y0) ** 2))
+
+
 def polynomial(coeffs, ncomp=1):
     """Polynomial data sum c[m][n] x^m y^n per component (coeffs: list of
     dicts {(m,n): c}); used for exactness checks."""

@@ -45,6 +45,9 @@ def lib():
         L.or_step_periodic.argtypes = [I, I, I, D, D, D, D, D, D, P, P, P, P]
         L.or_run_periodic.argtypes = [I, I, I, D, D, D, I, D, D, D, P, P, P, P]
         L.or_patch_step.argtypes = [I, I, I, D, D, D, D, D, D, I, P, P, P, P, P, P, P, P, P, I]
+        L.or_run_periodic_rot.argtypes = [I, I, D, D, D, D, D, I, D, D, D, P, P, P, P]
+        L.or_patch_step_rot.argtypes = [I, I, D, D, D, D, D, D, D, D, I, P, P, P, P, P, P, P, P, P, I]
+        L.or_hier_set_rotation.argtypes = [P, D, D, D]
         L.or_hier_new.argtypes = [I, I, I, I, I, D, D, D, D, D, D, D]
         L.or_hier_new.restype = P
         L.or_hier_free.argtypes = [P]
@@ -120,6 +123,33 @@ def run_periodic(eq, dofs, dt, nsteps, a=0.0, b=0.0, c=1.0):
     return out
 
 
+def run_periodic_rot(dofs, dt, nsteps, omega, xc=0.0, yc=0.0, x0=0.0, y0=0.0):
+    """Solid-body rotation a = -omega (y - yc), b = omega (x - xc) (Sec. 4.2)
+    on a periodic grid whose cell (0,0) has its lower-left corner at
+    (x0, y0); returns a new dict."""
+    out = {k: np.ascontiguousarray(dofs[k], dtype=np.float64).copy() for k in KINDS}
+    _, ny, nx = out["avg"].shape
+    lib().or_run_periodic_rot(nx, ny, float(x0), float(y0), float(dofs["dx"]), float(dofs["dy"]), float(dt),
+                              int(nsteps), float(omega), float(xc), float(yc), _p(out["avg"]),
+                              _p(out["corner"]), _p(out["xedge"]), _p(out["yedge"]))
+    out["dx"], out["dy"] = dofs["dx"], dofs["dy"]
+    return out
+
+
+def patch_step_rot(m, block, x0p, y0p, dx, dy, dt, omega, xc=0.0, yc=0.0, region=0, flux4=None,
+                   side_mask=0, g=2):
+    """patch_step for solid-body rotation; (x0p, y0p) is the lower-left
+    corner of the patch's cell (0,0)."""
+    ins = {k: np.ascontiguousarray(block[k], dtype=np.float64) for k in KINDS}
+    outs = {k: np.zeros_like(ins[k]) for k in KINDS}
+    fp = _p(flux4) if flux4 is not None else None
+    lib().or_patch_step_rot(int(m), int(g), float(x0p), float(y0p), float(dx), float(dy), float(dt),
+                            float(omega), float(xc), float(yc), int(region), _p(ins["avg"]), _p(ins["corner"]),
+                            _p(ins["xedge"]), _p(ins["yedge"]), _p(outs["avg"]), _p(outs["corner"]),
+                            _p(outs["xedge"]), _p(outs["yedge"]), fp, int(side_mask))
+    return outs
+
+
 def patch_step(eq, m, block, dx, dy, dt, region=0, a=0.0, b=0.0, c=1.0, flux4=None,
                side_mask=0, g=2):
     """One step on one patch block (dict kind -> [ncomp][S+1][S+1]).  Returns
@@ -141,13 +171,17 @@ class Hier:
     patches."""
 
     def __init__(self, eq, m, n0x, n0y, lmax, x0=0.0, y0=0.0, lx=1.0, ly=1.0, a=0.0, b=0.0,
-                 c=1.0):
+                 c=1.0, omega=0.0, xc=0.0, yc=0.0):
+        """eq 0 advection (a, b), 1 acoustics (c), 2 solid-body rotation
+        (omega about (xc, yc))."""
         self.eq, self.m, self.n0x, self.n0y, self.lmax = eq, m, n0x, n0y, lmax
         self.x0, self.y0, self.lx, self.ly = x0, y0, lx, ly
-        self.ncomp = 3 if eq else 1
+        self.ncomp = 3 if eq == 1 else 1
         self.S1 = m + 5
         self.h = lib().or_hier_new(int(eq), int(m), int(n0x), int(n0y), int(lmax), float(x0),
                                    float(y0), float(lx), float(ly), float(a), float(b), float(c))
+        if eq == 2:
+            lib().or_hier_set_rotation(self.h, float(omega), float(xc), float(yc))
 
     def __del__(self):
         if getattr(self, "h", None):

@@ -217,6 +217,7 @@ enum Kind { K_AVG = 0, K_CORNER = 1, K_XEDGE = 2, K_YEDGE = 3 };
 struct Grid {
   int ncomp = 1;
   double dx = 1.0, dy = 1.0;
+  double ox = 0.0, oy = 0.0;  // physical position of the left / bottom face of cell 0
   virtual ~Grid() = default;
   virtual double get(int kind, int comp, int i, int j) const = 0;
   Cell cell(int comp, int i, int j) const {
@@ -274,9 +275,10 @@ struct BlockGrid : Grid {
 // ---------------------------------------------------------------------------
 
 struct Physics {
-  int eq = 0;            // 0 advection, 1 acoustics
+  int eq = 0;            // 0 advection, 1 acoustics, 2 solid-body rotation
   double a = 0, b = 0;   // advection velocity
   double c = 1;          // speed of sound
+  double omega = 0, xc = 0, yc = 0;  // rotation: a = -omega (y - yc), b = omega (x - xc)
 };
 
 void node_pos(int kind, int i, int j, double* X, double* Y) {
@@ -310,6 +312,38 @@ double advect_point(const Grid& g, const Physics& ph, int kind, int i, int j, do
   double xi, eta;
   locate(fx, ph.a, &ci, &xi);
   locate(fy, ph.b, &cj, &eta);
+  return cell_eval(g.cell(0, ci, cj), xi, eta);
+}
+
+// Physical position of a node (cell units X, Y as in node_pos).
+void node_xy(const Grid& g, int kind, int i, int j, double* x, double* y) {
+  double X, Y;
+  node_pos(kind, i, j, &X, &Y);
+  *x = g.ox + (X + 0.5) * g.dx;
+  *y = g.oy + (Y + 0.5) * g.dy;
+}
+
+// Velocity components of the advecting field at a physical point.
+double vel_a(const Physics& ph, double x, double y) { (void)x; return ph.eq == 2 ? -ph.omega * (y - ph.yc) : ph.a; }
+double vel_b(const Physics& ph, double x, double y) { (void)y; return ph.eq == 2 ? ph.omega * (x - ph.xc) : ph.b; }
+
+// Solid-body rotation (Sec. 4.2): the characteristic through the node is a
+// circle about (xc, yc); its position a time tau earlier is the node turned
+// by -omega tau (eq. characteristics_advtwo with t = -tau), and q^n is
+// evaluated there.  A foot on a face goes to the cell between foot and node,
+// as for constant advection.
+double rotate_point(const Grid& g, const Physics& ph, int kind, int i, int j, double tau) {
+  double x, y;
+  node_xy(g, kind, i, j, &x, &y);
+  const double th = ph.omega * tau;
+  const double rx = x - ph.xc, ry = y - ph.yc;
+  const double fx = ph.xc + rx * std::cos(th) + ry * std::sin(th);
+  const double fy = ph.yc - rx * std::sin(th) + ry * std::cos(th);
+  const double sx = (fx - g.ox) / g.dx - 0.5, sy = (fy - g.oy) / g.dy - 0.5;  // cell units
+  int ci, cj;
+  double xi, eta;
+  locate(sx, x - fx, &ci, &xi);
+  locate(sy, y - fy, &cj, &eta);
   return cell_eval(g.cell(0, ci, cj), xi, eta);
 }
 
@@ -379,25 +413,28 @@ void evolve_point(const Grid& g, const Physics& ph, int kind, int i, int j, doub
                   double out[3]) {
   if (ph.eq == 0) {
     out[0] = advect_point(g, ph, kind, i, j, tau);
+  } else if (ph.eq == 2) {
+    out[0] = rotate_point(g, ph, kind, i, j, tau);
   } else {
     acoustic_point(g, ph, kind, i, j, tau, out);
   }
 }
 
-// Physical flux functions: advection f = a q, g = b q; acoustics
-// f = c (u, p, 0), g = c (v, 0, p) for q = (p, u, v) (Sec. 2.3).
-void flux_x(const Physics& ph, const double* q, double* f) {
-  if (ph.eq == 0) {
-    f[0] = ph.a * q[0];
+// Physical flux functions: advection f = a q, g = b q with the velocity
+// component at the node (constant, or that of the rotation field, Sec. 4.2);
+// acoustics f = c (u, p, 0), g = c (v, 0, p) for q = (p, u, v) (Sec. 2.3).
+void flux_x(const Physics& ph, double vel, const double* q, double* f) {
+  if (ph.eq != 1) {
+    f[0] = vel * q[0];
   } else {
     f[0] = ph.c * q[1];
     f[1] = ph.c * q[0];
     f[2] = 0.0;
   }
 }
-void flux_y(const Physics& ph, const double* q, double* f) {
-  if (ph.eq == 0) {
-    f[0] = ph.b * q[0];
+void flux_y(const Physics& ph, double vel, const double* q, double* f) {
+  if (ph.eq != 1) {
+    f[0] = vel * q[0];
   } else {
     f[0] = ph.c * q[2];
     f[1] = 0.0;
@@ -406,9 +443,10 @@ void flux_y(const Physics& ph, const double* q, double* f) {
 }
 
 // Simpson space-time flux (eq. Simpson-2d): nodes lo/mid/hi along the face at
-// times n, n+1/2, n+1, weights (1,4,1) x (1,4,1) / 36.
-void simpson_flux(const Physics& ph, bool xface, const double* n_lo, const double* n_mid,
-                  const double* n_hi, const double* h_lo, const double* h_mid,
+// times n, n+1/2, n+1, weights (1,4,1) x (1,4,1) / 36.  vel: the normal
+// velocity component at the three nodes (advection-type equations).
+void simpson_flux(const Physics& ph, bool xface, const double vel[3], const double* n_lo,
+                  const double* n_mid, const double* n_hi, const double* h_lo, const double* h_mid,
                   const double* h_hi, const double* f_lo, const double* f_mid,
                   const double* f_hi, int ncomp, double* F) {
   const double* pts[9] = {n_lo, n_mid, n_hi, h_lo, h_mid, h_hi, f_lo, f_mid, f_hi};
@@ -416,7 +454,7 @@ void simpson_flux(const Physics& ph, bool xface, const double* n_lo, const doubl
   for (int c = 0; c < ncomp; ++c) F[c] = 0.0;
   for (int k = 0; k < 9; ++k) {
     double f[3];
-    if (xface) flux_x(ph, pts[k], f); else flux_y(ph, pts[k], f);
+    if (xface) flux_x(ph, vel[k % 3], pts[k], f); else flux_y(ph, vel[k % 3], pts[k], f);
     for (int c = 0; c < ncomp; ++c) F[c] += w[k] * f[c];
   }
   for (int c = 0; c < ncomp; ++c) F[c] /= 36.0;
@@ -476,7 +514,14 @@ StepResult af_step_range(const Grid& g, const Physics& ph, double dt, int i0, in
   for (int j = j0; j < j1; ++j)
     for (int i = i0; i <= i1; ++i) {
       // x-face at x_{i-1/2}, y in [y_{j-1/2}, y_{j+1/2}]: corner (i,j), xedge (i,j), corner (i,j+1)
-      simpson_flux(ph, true, &cur[K_CORNER][nid(i, j)], &cur[K_XEDGE][nid(i, j)],
+      double vel[3], x, y;
+      node_xy(g, K_CORNER, i, j, &x, &y);
+      vel[0] = vel_a(ph, x, y);
+      node_xy(g, K_XEDGE, i, j, &x, &y);
+      vel[1] = vel_a(ph, x, y);
+      node_xy(g, K_CORNER, i, j + 1, &x, &y);
+      vel[2] = vel_a(ph, x, y);
+      simpson_flux(ph, true, vel, &cur[K_CORNER][nid(i, j)], &cur[K_XEDGE][nid(i, j)],
                    &cur[K_CORNER][nid(i, j + 1)], &half[K_CORNER][nid(i, j)],
                    &half[K_XEDGE][nid(i, j)], &half[K_CORNER][nid(i, j + 1)],
                    &full[K_CORNER][nid(i, j)], &full[K_XEDGE][nid(i, j)],
@@ -486,7 +531,14 @@ StepResult af_step_range(const Grid& g, const Physics& ph, double dt, int i0, in
   for (int j = j0; j <= j1; ++j)
     for (int i = i0; i < i1; ++i) {
       // y-face at y_{j-1/2}: corner (i,j), yedge (i,j), corner (i+1,j)
-      simpson_flux(ph, false, &cur[K_CORNER][nid(i, j)], &cur[K_YEDGE][nid(i, j)],
+      double vel[3], x, y;
+      node_xy(g, K_CORNER, i, j, &x, &y);
+      vel[0] = vel_b(ph, x, y);
+      node_xy(g, K_YEDGE, i, j, &x, &y);
+      vel[1] = vel_b(ph, x, y);
+      node_xy(g, K_CORNER, i + 1, j, &x, &y);
+      vel[2] = vel_b(ph, x, y);
+      simpson_flux(ph, false, vel, &cur[K_CORNER][nid(i, j)], &cur[K_YEDGE][nid(i, j)],
                    &cur[K_CORNER][nid(i + 1, j)], &half[K_CORNER][nid(i, j)],
                    &half[K_YEDGE][nid(i, j)], &half[K_CORNER][nid(i + 1, j)],
                    &full[K_CORNER][nid(i, j)], &full[K_YEDGE][nid(i, j)],
@@ -566,6 +618,8 @@ struct Hier {
     BlockGrid bg;
     bg.m = m; bg.g = g; bg.ncomp = ncomp;
     bg.dx = dx(L.level); bg.dy = dy(L.level);
+    bg.ox = x0 + L.ix * m * bg.dx;
+    bg.oy = y0 + L.iy * m * bg.dy;
     for (int k = 0; k < 4; ++k) bg.arr[k] = L.blk[k].data();
     return bg;
   }
@@ -1165,16 +1219,17 @@ double or_sector_mean(const double* coef16, int quad, double R, double* r_dmean)
 }
 
 // --- periodic single grid ---------------------------------------------------
-// One AF step on a periodic nx x ny grid, in place.  Arrays [ncomp][ny][nx].
-void or_step_periodic(int eq, int nx, int ny, double dx, double dy, double dt, double a,
-                      double b, double c, double* avg, double* corner, double* xedge,
-                      double* yedge) {
+}  // extern "C"
+
+namespace {
+
+// One AF step on a periodic grid in place; arrays [ncomp][ny][nx].
+void step_periodic(const Physics& ph, int nx, int ny, double x0, double y0, double dx, double dy,
+                   double dt, double* avg, double* corner, double* xedge, double* yedge) {
   PeriodicGrid pg;
-  pg.nx = nx; pg.ny = ny; pg.dx = dx; pg.dy = dy;
-  pg.ncomp = eq ? 3 : 1;
+  pg.nx = nx; pg.ny = ny; pg.dx = dx; pg.dy = dy; pg.ox = x0; pg.oy = y0;
+  pg.ncomp = ph.eq == 1 ? 3 : 1;
   pg.arr[K_AVG] = avg; pg.arr[K_CORNER] = corner; pg.arr[K_XEDGE] = xedge; pg.arr[K_YEDGE] = yedge;
-  Physics ph;
-  ph.eq = eq; ph.a = a; ph.b = b; ph.c = c;
   const StepResult r = af_step_range(pg, ph, dt, 0, nx, 0, ny);
   const int nc = pg.ncomp, NI = nx + 1;
   std::vector<double> na(size_t(nc) * nx * ny), nco(na.size()), nxe(na.size()), nye(na.size());
@@ -1194,32 +1249,15 @@ void or_step_periodic(int eq, int nx, int ny, double dx, double dy, double dt, d
   std::memcpy(yedge, nye.data(), na.size() * sizeof(double));
 }
 
-// Several steps on the periodic grid (saves ctypes round trips).
-void or_run_periodic(int eq, int nx, int ny, double dx, double dy, double dt, int nsteps,
-                     double a, double b, double c, double* avg, double* corner, double* xedge,
-                     double* yedge) {
-  for (int s = 0; s < nsteps; ++s)
-    or_step_periodic(eq, nx, ny, dx, dy, dt, a, b, c, avg, corner, xedge, yedge);
-}
-
-// --- one patch block --------------------------------------------------------
-// blocks: four arrays [ncomp][(m+2g+1)^2], row-major (row = j+g, col = i+g).
-// region 0 = interior, 1 = interior + ghost layer 1.  `out` receives the
-// updated averages of the region's cells and the new values of all nodes on
-// their boundaries (other entries are copied from `in`).  flux4 (may be NULL)
-// receives F * face-length * dt on the four sides of the interior block,
-// [side W,E,S,N][m][ncomp], accumulated (+=) for sides whose bit is set in
-// side_mask.
-void or_patch_step(int eq, int m, int g, double dx, double dy, double dt, double a, double b,
-                   double c, int region, const double* in_avg, const double* in_corner,
-                   const double* in_xedge, const double* in_yedge, double* out_avg,
-                   double* out_corner, double* out_xedge, double* out_yedge, double* flux4,
-                   int side_mask) {
+// One step of one patch block; see or_patch_step.
+void patch_step(const Physics& ph, int m, int g, double x0p, double y0p, double dx, double dy,
+                double dt, int region, const double* in_avg, const double* in_corner,
+                const double* in_xedge, const double* in_yedge, double* out_avg, double* out_corner,
+                double* out_xedge, double* out_yedge, double* flux4, int side_mask) {
   BlockGrid bg;
-  bg.m = m; bg.g = g; bg.dx = dx; bg.dy = dy; bg.ncomp = eq ? 3 : 1;
+  bg.m = m; bg.g = g; bg.dx = dx; bg.dy = dy; bg.ox = x0p; bg.oy = y0p;
+  bg.ncomp = ph.eq == 1 ? 3 : 1;
   bg.arr[K_AVG] = in_avg; bg.arr[K_CORNER] = in_corner; bg.arr[K_XEDGE] = in_xedge; bg.arr[K_YEDGE] = in_yedge;
-  Physics ph;
-  ph.eq = eq; ph.a = a; ph.b = b; ph.c = c;
   const int lo = region ? -1 : 0, hi = region ? m + 1 : m;
   const StepResult r = af_step_range(bg, ph, dt, lo, hi, lo, hi);
   const int nc = bg.ncomp, NI = r.ni + 1;
@@ -1259,17 +1297,93 @@ void or_patch_step(int eq, int m, int g, double dx, double dy, double dt, double
   }
 }
 
+Physics physics(int eq, double a, double b, double c) {
+  Physics ph;
+  ph.eq = eq; ph.a = a; ph.b = b; ph.c = c;
+  return ph;
+}
+
+Physics rotation(double omega, double xc, double yc) {
+  Physics ph;
+  ph.eq = 2; ph.omega = omega; ph.xc = xc; ph.yc = yc;
+  return ph;
+}
+
+}  // namespace
+
+extern "C" {
+
+// One AF step on a periodic nx x ny grid, in place.  Arrays [ncomp][ny][nx].
+// eq 0 advection (a, b), 1 acoustics (c).
+void or_step_periodic(int eq, int nx, int ny, double dx, double dy, double dt, double a,
+                      double b, double c, double* avg, double* corner, double* xedge,
+                      double* yedge) {
+  step_periodic(physics(eq, a, b, c), nx, ny, 0.0, 0.0, dx, dy, dt, avg, corner, xedge, yedge);
+}
+
+// Several steps on the periodic grid (saves ctypes round trips).
+void or_run_periodic(int eq, int nx, int ny, double dx, double dy, double dt, int nsteps,
+                     double a, double b, double c, double* avg, double* corner, double* xedge,
+                     double* yedge) {
+  const Physics ph = physics(eq, a, b, c);
+  for (int s = 0; s < nsteps; ++s) step_periodic(ph, nx, ny, 0.0, 0.0, dx, dy, dt, avg, corner, xedge, yedge);
+}
+
+// Solid-body rotation a = -omega (y - yc), b = omega (x - xc) on the periodic
+// grid whose cell (0,0) has its lower-left corner at (x0, y0) (Sec. 4.2).
+void or_run_periodic_rot(int nx, int ny, double x0, double y0, double dx, double dy, double dt,
+                         int nsteps, double omega, double xc, double yc, double* avg,
+                         double* corner, double* xedge, double* yedge) {
+  const Physics ph = rotation(omega, xc, yc);
+  for (int s = 0; s < nsteps; ++s) step_periodic(ph, nx, ny, x0, y0, dx, dy, dt, avg, corner, xedge, yedge);
+}
+
+// --- one patch block --------------------------------------------------------
+// blocks: four arrays [ncomp][(m+2g+1)^2], row-major (row = j+g, col = i+g).
+// region 0 = interior, 1 = interior + ghost layer 1.  `out` receives the
+// updated averages of the region's cells and the new values of all nodes on
+// their boundaries (other entries are copied from `in`).  flux4 (may be NULL)
+// receives F * face-length * dt on the four sides of the interior block,
+// [side W,E,S,N][m][ncomp], accumulated (+=) for sides whose bit is set in
+// side_mask.
+void or_patch_step(int eq, int m, int g, double dx, double dy, double dt, double a, double b,
+                   double c, int region, const double* in_avg, const double* in_corner,
+                   const double* in_xedge, const double* in_yedge, double* out_avg,
+                   double* out_corner, double* out_xedge, double* out_yedge, double* flux4,
+                   int side_mask) {
+  patch_step(physics(eq, a, b, c), m, g, 0.0, 0.0, dx, dy, dt, region, in_avg, in_corner, in_xedge,
+             in_yedge, out_avg, out_corner, out_xedge, out_yedge, flux4, side_mask);
+}
+
+// The same for solid-body rotation; (x0p, y0p) is the lower-left corner of
+// the patch's cell (0,0).
+void or_patch_step_rot(int m, int g, double x0p, double y0p, double dx, double dy, double dt,
+                       double omega, double xc, double yc, int region, const double* in_avg,
+                       const double* in_corner, const double* in_xedge, const double* in_yedge,
+                       double* out_avg, double* out_corner, double* out_xedge, double* out_yedge,
+                       double* flux4, int side_mask) {
+  patch_step(rotation(omega, xc, yc), m, g, x0p, y0p, dx, dy, dt, region, in_avg, in_corner, in_xedge,
+             in_yedge, out_avg, out_corner, out_xedge, out_yedge, flux4, side_mask);
+}
+
 // --- AMR hierarchy ------------------------------------------------------------
 void* or_hier_new(int eq, int m, int n0x, int n0y, int lmax, double x0, double y0, double lx,
                   double ly, double a, double b, double c) {
   Hier* h = new Hier();
   h->ph.eq = eq; h->ph.a = a; h->ph.b = b; h->ph.c = c;
-  h->m = m; h->g = 2; h->ncomp = eq ? 3 : 1;
+  h->m = m; h->g = 2; h->ncomp = eq == 1 ? 3 : 1;
   h->n0x = n0x; h->n0y = n0y; h->lmax = lmax;
   h->x0 = x0; h->y0 = y0; h->lx = lx; h->ly = ly;
   return h;
 }
 void or_hier_free(void* hp) { delete static_cast<Hier*>(hp); }
+
+// Switch the hierarchy's equation to solid-body rotation about (xc, yc).
+void or_hier_set_rotation(void* hp, double omega, double xc, double yc) {
+  Hier* h = static_cast<Hier*>(hp);
+  h->ph = rotation(omega, xc, yc);
+  h->ncomp = 1;
+}
 
 // Replace the leaf set (data zeroed).  Leaves are kept in the given order.
 void or_hier_set_leaves(void* hp, int n, const int* level, const int* ix, const int* iy) {
