@@ -10,8 +10,9 @@
  * midpoint Q_{i-1/2,j}, the bottom-left corner Q_{i-1/2,j-1/2} and the
  * bottom-edge midpoint Q_{i,j-1/2}.  A step reconstructs the continuous
  * biquadratic in every cell, evolves the point values to t+dt/2 and t+dt
- * with the exact operators of linear advection (Sec. 2.1) or acoustics
- * (Sec. 2.3, Eymann-Roe formula), forms Simpson space-time fluxes
+ * with the exact operators of linear advection (Sec. 2.1), of advection in
+ * the solid-body rotation field (Sec. 4.2, exact characteristic circles) or
+ * of acoustics (Sec. 2.3, Eymann-Roe formula), forms Simpson space-time fluxes
  * (eq. Simpson-2d) and updates the averages conservatively (eq. 2dfv).
  * Patches exchange data through two ghost layers (Sec. 3.1, 3.2), finer
  * levels subcycle (Sec. 3.2) and the coarse-fine flux mismatch is repaired
@@ -31,8 +32,8 @@
  * State layout (af_state)
  *  Four arrays dof[k], k = AF_AVG, AF_CORNER, AF_XEDGE, AF_YEDGE, each of
  *  shape [ncomp][npatch][m+5][pitch] of the problem precision (double for
- *  AF_FP64, float for AF_FP32), ncomp = 1 (advection, q) or 3 (acoustics,
- *  p,u,v).  Row r, column c of a patch plane hold the DOF of local index
+ *  AF_FP64, float for AF_FP32), ncomp = 1 (advection and rotation, q) or 3
+ *  (acoustics, p,u,v).  Row r, column c of a patch plane hold the DOF of local index
  *  (i,j) = (c-2, r-2): cells of the interior are i,j in [0,m), the two ghost
  *  layers extend to [-2, m+2).  Valid entries: avg i,j in [-2,m+2); corner
  *  i,j in [-2,m+2]; xedge (point (x_{i-1/2}, y_j)) i in [-2,m+2], j in
@@ -59,7 +60,11 @@ typedef enum {
   AF_ERR_STATE = -6     /* call not valid in the object's current state */
 } af_status;
 
-typedef enum { AF_ADVECTION = 0, AF_ACOUSTICS = 1 } af_equation;
+/* AF_ROTATION: q_t + (a q)_x + (b q)_y = 0 with a = -omega (y - yc),
+ * b = omega (x - xc) (Sec. 4.2, eq. solidbody).  The field is not periodic;
+ * the data are, so results are those of the paper's test as long as the
+ * data vanish near the domain boundary. */
+typedef enum { AF_ADVECTION = 0, AF_ACOUSTICS = 1, AF_ROTATION = 2 } af_equation;
 typedef enum { AF_FP64 = 0, AF_FP32 = 1 } af_precision;
 enum { AF_AVG = 0, AF_CORNER = 1, AF_XEDGE = 2, AF_YEDGE = 3 };
 enum { AF_SIDE_W = 0, AF_SIDE_E = 1, AF_SIDE_S = 2, AF_SIDE_N = 3 };
@@ -80,6 +85,8 @@ typedef struct {
   double x0, y0, lx, ly; /* periodic domain */
   double a, b;         /* advection velocity (eq. advection2d) */
   double c;            /* speed of sound (eq. acoustics) */
+  double omega;        /* AF_ROTATION: angular velocity (pi in Sec. 4.2) */
+  double xc, yc;       /* AF_ROTATION: centre of rotation */
 } af_problem;
 
 typedef struct {
@@ -134,7 +141,8 @@ af_status af_hier_side_relations(const af_hier* h, int8_t* rel);
  *              layers must be current) and written to `out`.
  *   level      the patches' level; dx = lx/(n0x m 2^level), likewise dy.
  *   dt         time step; AF_ERR_CFL if max(|a| dt/dx, |b| dt/dy) > 1
- *              (advection, eq. cfl-adv) or c dt / min(dx,dy) > 1/2
+ *              (advection, eq. cfl-adv; for AF_ROTATION with the largest
+ *              |a| and |b| on the domain) or c dt / min(dx,dy) > 1/2
  *              (acoustics, eq. cfl-acoustics).
  *   region     AF_REGION_INTERIOR: averages of cells [0,m)^2 and all nodes
  *              of the closed square [0,m]^2 are written;
@@ -145,10 +153,15 @@ af_status af_hier_side_relations(const af_hier* h, int8_t* rel);
  *              bit is set in side_mask[patch] the step ADDS F*dy*dt (x-faces)
  *              or G*dx*dt (y-faces) of the m boundary faces of the interior.
  *   side_mask  device uint8 [npatch]; NULL = no recording.
+ *   leaf_xy    device int32 [npatch][2]: (ix, iy) of each patch at its
+ *              level (af_hier_leaf_xy), which places the patch at
+ *              (x0 + ix m dx, y0 + iy m dy).  Required for AF_ROTATION
+ *              (AF_ERR_ARG if NULL), ignored otherwise.
  * --------------------------------------------------------------------- */
 af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t first,
                         int32_t count, int32_t level, double dt, int32_t region,
-                        double* flux_reg, const uint8_t* side_mask, hipStream_t stream);
+                        double* flux_reg, const uint8_t* side_mask, const int32_t* leaf_xy,
+                        hipStream_t stream);
 
 /* ---------------------------------------------------------------------
  * af_ghost_fill -- ghost data exchange between patches (Sec. 3.1 and
@@ -266,6 +279,10 @@ af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* 
 
 /* device uint8 [nleaves]: bit s set when side s borders another level */
 const uint8_t* af_hier_side_mask(const af_hier* h);
+/* Device int32 [nleaves][2] of the leaves' (ix, iy), the leaf_xy argument of
+ * af_patch_step; owned by the hierarchy, uploaded on first use (NULL on a
+ * device error). */
+const int32_t* af_hier_leaf_xy(const af_hier* h);
 
 /* =====================================================================
  * Learned regrid tagger (a project addition; not part of the paper's

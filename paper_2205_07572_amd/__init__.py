@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import AFError, check
 
-ADVECTION, ACOUSTICS = 0, 1
+ADVECTION, ACOUSTICS, ROTATION = 0, 1, 2
 FP64, FP32 = 0, 1
 KINDS = ("avg", "corner", "xedge", "yedge")
 REGION_INTERIOR, REGION_LAYER1 = 0, 1
@@ -50,6 +50,9 @@ class Problem:
     a: float = 1.0
     b: float = 0.5
     c: float = 1.0
+    omega: float = 0.0   # ROTATION: a = -omega (y - yc), b = omega (x - xc)
+    xc: float = 0.0
+    yc: float = 0.0
 
     @property
     def ncomp(self):
@@ -67,7 +70,7 @@ class Context:
         self.prob = prob
         L = _lib.load()
         cp = _lib.af_problem(prob.eq, prob.prec, prob.m, prob.n0x, prob.n0y, prob.lmax, prob.x0, prob.y0,
-                             prob.lx, prob.ly, prob.a, prob.b, prob.c)
+                             prob.lx, prob.ly, prob.a, prob.b, prob.c, prob.omega, prob.xc, prob.yc)
         h = ctypes.c_void_p()
         check(L.af_ctx_create(ctypes.byref(cp), ctypes.byref(h)))
         self.h = h
@@ -125,11 +128,14 @@ class Context:
 
     # ----------------------------------------------------------------- calls
     def patch_step(self, tin, tout, first, count, level, dt, region=REGION_INTERIOR, flux_reg=None,
-                   side_mask=None):
+                   side_mask=None, leaf_xy=None):
+        """leaf_xy: device (ix, iy) table of the patches (Hierarchy.leaf_xy_ptr()
+        or an int32 tensor [npatch][2]); needed for ROTATION."""
         sin, sout = self.cstate(tin), self.cstate(tout)
         sm = ctypes.c_void_p(side_mask) if isinstance(side_mask, int) else _ptr(side_mask)
+        xy = ctypes.c_void_p(leaf_xy) if isinstance(leaf_xy, int) else _ptr(leaf_xy)
         check(_lib.load().af_patch_step(self.h, ctypes.byref(sin), ctypes.byref(sout), int(first), int(count),
-                                        int(level), float(dt), int(region), _ptr(flux_reg), sm, _stream()))
+                                        int(level), float(dt), int(region), _ptr(flux_reg), sm, xy, _stream()))
 
     def _pair(self, bufs):
         arr = (_lib.af_state * 2)()
@@ -227,6 +233,9 @@ class Hierarchy:
 
     def side_mask_ptr(self):
         return _lib.load().af_hier_side_mask(self.h)
+
+    def leaf_xy_ptr(self):
+        return _lib.load().af_hier_leaf_xy(self.h)
 
     def regrid(self, tags):
         t = np.ascontiguousarray(tags, dtype=np.int8)

@@ -18,6 +18,7 @@ EXPORTS = [
     "af_last_error", "af_ctx_create", "af_ctx_destroy", "af_ctx_set_tile", "af_ctx_get_tile",
     "af_hier_create", "af_hier_destroy", "af_hier_num_leaves", "af_hier_get_leaves",
     "af_hier_level_range", "af_hier_finest_level", "af_hier_side_relations", "af_hier_side_mask",
+    "af_hier_leaf_xy",
     "af_patch_step", "af_ghost_fill", "af_flux_correct", "af_regrid_tag", "af_hier_regrid",
     "af_regrid_apply", "af_reduce_sum", "af_amr_coarse_step", "af_level_advance",
     "af_ctx_advance_shapes", "af_ctx_set_advance_shape", "af_autotune",
@@ -33,7 +34,8 @@ class af_problem(ctypes.Structure):
                 ("n0x", ctypes.c_int32), ("n0y", ctypes.c_int32), ("lmax", ctypes.c_int32),
                 ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("lx", ctypes.c_double),
                 ("ly", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double),
-                ("c", ctypes.c_double)]
+                ("c", ctypes.c_double), ("omega", ctypes.c_double), ("xc", ctypes.c_double),
+                ("yc", ctypes.c_double)]
 
 
 class af_state(ctypes.Structure):
@@ -81,7 +83,9 @@ def load():
     L.af_hier_side_relations.argtypes = [P, P]
     L.af_hier_side_mask.argtypes = [P]
     L.af_hier_side_mask.restype = P
-    L.af_patch_step.argtypes = [P, S, S, i32, i32, i32, D, i32, P, P, P]
+    L.af_patch_step.argtypes = [P, S, S, i32, i32, i32, D, i32, P, P, P, P]
+    L.af_hier_leaf_xy.argtypes = [P]
+    L.af_hier_leaf_xy.restype = P
     L.af_ghost_fill.argtypes = [P, P, S, ctypes.c_uint32, i32, i32, P]
     L.af_flux_correct.argtypes = [P, P, S, ctypes.c_uint32, i32, P, P]
     L.af_regrid_tag.argtypes = [P, P, S, ctypes.c_uint32, i32, i32, D, D, P, P, P]
@@ -110,7 +114,7 @@ def load():
     L.af_cnn_tag.argtypes = [P, P, P, S, ctypes.c_uint32, P, P, P, P]
     for name in EXPORTS:
         if name not in ("af_last_error", "af_hier_num_leaves", "af_ctx_get_tile", "af_hier_finest_level",
-                        "af_hier_side_mask", "af_ctx_advance_shapes", "af_cnn_last_error", "af_cnn_num_params"):
+                        "af_hier_side_mask", "af_hier_leaf_xy", "af_ctx_advance_shapes", "af_cnn_last_error", "af_cnn_num_params"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

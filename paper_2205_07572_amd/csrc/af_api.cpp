@@ -78,6 +78,7 @@ struct af_hier {
   int32_t* d_ix = nullptr;
   int32_t* d_iy = nullptr;
   uint8_t* d_side_mask = nullptr;
+  int32_t* d_xy = nullptr;     // [n][2] (ix, iy)
   CFFace* d_faces = nullptr;
   std::vector<int> face_off;  // per coarse level offset into d_faces
   std::vector<CFFace> all_faces;
@@ -123,6 +124,13 @@ af_status check_cfl(const af_ctx* c, int level, double dt) {
   if (c->P.eq == AF_ADVECTION) {
     const double cfl = std::max(std::fabs(c->P.a) * dt / dx, std::fabs(c->P.b) * dt / dy);
     if (cfl > 1.0 + 1e-12) return fail(AF_ERR_CFL, "advection CFL > 1 (eq. cfl-adv)");
+  } else if (c->P.eq == AF_ROTATION) {
+    // largest |a| = |omega| |y - yc| and |b| = |omega| |x - xc| on the domain
+    const double w = std::fabs(c->P.omega);
+    const double amax = w * std::max(std::fabs(c->P.y0 - c->P.yc), std::fabs(c->P.y0 + c->P.ly - c->P.yc));
+    const double bmax = w * std::max(std::fabs(c->P.x0 - c->P.xc), std::fabs(c->P.x0 + c->P.lx - c->P.xc));
+    const double cfl = std::max(amax * dt / dx, bmax * dt / dy);
+    if (cfl > 1.0 + 1e-12) return fail(AF_ERR_CFL, "rotation CFL > 1 (eq. cfl-adv with the largest speed)");
   } else {
     const double cfl = c->P.c * dt / std::min(dx, dy);
     if (cfl > 0.5 + 1e-12) return fail(AF_ERR_CFL, "acoustic CFL > 1/2 (eq. cfl-acoustics)");
@@ -184,11 +192,13 @@ af_status ctx_device(af_ctx* c) {
 af_status hier_device(af_hier* h) {
   if (h->on_device) return AF_OK;
   const int n = int(h->H.leaves.size());
-  std::vector<int32_t> lv(n), vx(n), vy(n);
+  std::vector<int32_t> lv(n), vx(n), vy(n), xy(2 * size_t(n));
   for (int k = 0; k < n; ++k) {
     lv[k] = h->H.leaves[k].level;
     vx[k] = h->H.leaves[k].ix;
     vy[k] = h->H.leaves[k].iy;
+    xy[2 * k] = vx[k];
+    xy[2 * k + 1] = vy[k];
   }
   hipError_t err;
   h->d_lut = dev_upload(h->H.lut, &err);
@@ -196,6 +206,7 @@ af_status hier_device(af_hier* h) {
   if (err == hipSuccess) h->d_ix = dev_upload(vx, &err);
   if (err == hipSuccess) h->d_iy = dev_upload(vy, &err);
   if (err == hipSuccess) h->d_side_mask = dev_upload(h->H.side_mask, &err);
+  if (err == hipSuccess) h->d_xy = dev_upload(xy, &err);
   if (err == hipSuccess) h->d_faces = dev_upload(h->all_faces, &err);
   if (err != hipSuccess) return fail(AF_ERR_DEVICE, std::string("hierarchy upload: ") + hipGetErrorString(err));
   HierDev& D = h->dev;
@@ -233,7 +244,9 @@ const char* af_last_error(void) { return g_err.c_str(); }
 af_status af_ctx_create(const af_problem* prob, af_ctx** out) {
   if (!prob || !out) return fail(AF_ERR_ARG, "null argument");
   const af_problem& P = *prob;
-  if (P.eq != AF_ADVECTION && P.eq != AF_ACOUSTICS) return fail(AF_ERR_ARG, "unknown equation");
+  if (P.eq != AF_ADVECTION && P.eq != AF_ACOUSTICS && P.eq != AF_ROTATION) return fail(AF_ERR_ARG, "unknown equation");
+  if (P.eq == AF_ROTATION && !(std::isfinite(P.omega) && std::isfinite(P.xc) && std::isfinite(P.yc)))
+    return fail(AF_ERR_ARG, "rotation parameters must be finite");
   if (P.prec != AF_FP64 && P.prec != AF_FP32) return fail(AF_ERR_ARG, "unknown precision");
   if (!(P.m == 8 || P.m == 16 || P.m == 32 || P.m == 64 || P.m == 128))
     return fail(AF_ERR_ARG, "m must be 8, 16, 32, 64 or 128");
@@ -330,6 +343,7 @@ af_status af_hier_destroy(af_hier* h) {
   (void)hipFree(h->d_ix);
   (void)hipFree(h->d_iy);
   (void)hipFree(h->d_side_mask);
+  (void)hipFree(h->d_xy);
   (void)hipFree(h->d_faces);
   for (int32_t* p : h->d_nbr) (void)hipFree(p);
   for (int4* p : h->d_plan) (void)hipFree(p);
@@ -375,11 +389,16 @@ const uint8_t* af_hier_side_mask(const af_hier* h) {
   return h->d_side_mask;
 }
 
+const int32_t* af_hier_leaf_xy(const af_hier* h) {
+  if (!h || hier_device(const_cast<af_hier*>(h)) != AF_OK) return nullptr;
+  return h->d_xy;
+}
+
 // ----------------------------------------------------------------- step
 
 af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t first, int32_t count,
                         int32_t level, double dt, int32_t region, double* flux_reg, const uint8_t* side_mask,
-                        hipStream_t stream) {
+                        const int32_t* leaf_xy, hipStream_t stream) {
   if (!ctx) return fail(AF_ERR_ARG, "null ctx");
   if (count < 0 || first < 0) return fail(AF_ERR_ARG, "negative patch range");
   if (region != AF_REGION_INTERIOR && region != AF_REGION_LAYER1) return fail(AF_ERR_ARG, "bad region");
@@ -394,9 +413,12 @@ af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t 
     if (in->dof[k] == out->dof[k]) return fail(AF_ERR_ARG, "af_patch_step: in and out must be distinct");
   s = check_cfl(ctx, level, dt);
   if (s != AF_OK) return s;
+  if (ctx->P.eq == AF_ROTATION && !leaf_xy) return fail(AF_ERR_ARG, "af_patch_step: rotation needs leaf_xy");
   if (count == 0) return AF_OK;
   const double dx = ctx->dx(level), dy = ctx->dy(level);
   StepLaunch L;
+  RotParams<float> rp32;
+  RotParams<double> rp64;
   L.fp32 = ctx->fp32();
   L.eq = ctx->P.eq;
   L.m = ctx->P.m;
@@ -419,7 +441,24 @@ af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t 
   L.len_dt_y = dx * dt;
   L.reg = flux_reg;
   L.side_mask = flux_reg ? side_mask : nullptr;
-  L.weights = weights_for(ctx, dt / dx, dt / dy);
+  L.leaf_xy = leaf_xy;
+  if (ctx->P.eq == AF_ROTATION) {
+    // the rotation angle depends on dt itself, not on dt/dx: no cache
+    const double th[2] = {ctx->P.omega * 0.5 * dt, ctx->P.omega * dt};
+    for (int t = 0; t < 2; ++t) {
+      rp64.cs[t] = std::cos(th[t]);
+      rp64.sn[t] = std::sin(th[t]);
+    }
+    rp64.x0 = ctx->P.x0; rp64.y0 = ctx->P.y0; rp64.dx = dx; rp64.dy = dy;
+    rp64.omega = ctx->P.omega; rp64.xc = ctx->P.xc; rp64.yc = ctx->P.yc;
+    rp32.cs[0] = float(rp64.cs[0]); rp32.cs[1] = float(rp64.cs[1]);
+    rp32.sn[0] = float(rp64.sn[0]); rp32.sn[1] = float(rp64.sn[1]);
+    rp32.x0 = float(rp64.x0); rp32.y0 = float(rp64.y0); rp32.dx = float(dx); rp32.dy = float(dy);
+    rp32.omega = float(rp64.omega); rp32.xc = float(rp64.xc); rp32.yc = float(rp64.yc);
+    L.weights = ctx->fp32() ? static_cast<const void*>(&rp32) : static_cast<const void*>(&rp64);
+  } else {
+    L.weights = weights_for(ctx, dt / dx, dt / dy);
+  }
   AF_HIP(launch_patch_step(L, stream));
   return AF_OK;
 }
@@ -773,6 +812,7 @@ af_status af_autotune(af_ctx* ctx, af_hier* h, af_state* bufs, int32_t level, do
   af_status s = check_pair(ctx, h, bufs, "af_autotune");
   if (s != AF_OK) return s;
   if (reps < 1) return fail(AF_ERR_ARG, "reps must be >= 1");
+  if ((s = hier_device(h)) != AF_OK) return s;
   const int count = level >= 0 && level <= h->H.lmax ? h->H.level_count[level] : 0;
   if (count == 0) return fail(AF_ERR_ARG, "level has no leaves");
   const int first = h->H.level_first[level];
@@ -800,7 +840,9 @@ af_status af_autotune(af_ctx* ctx, af_hier* h, af_state* bufs, int32_t level, do
     if (!step_shape_supported(ctx->P.m, ty)) continue;
     ctx->ty = ty;
     double us;
-    s = timed([&]() { return af_patch_step(ctx, &bufs[0], &bufs[1], first, count, level, dt, 0, nullptr, nullptr, stream); },
+    s = timed([&]() {
+          return af_patch_step(ctx, &bufs[0], &bufs[1], first, count, level, dt, 0, nullptr, nullptr, h->d_xy, stream);
+        },
               &us);
     if (s != AF_OK) break;
     if (us < best) { best = us; best_ty = ty; }
@@ -857,7 +899,7 @@ struct Driver {
     mask ^= (1u << l);
     if (count == 0) return AF_OK;
     return af_patch_step(ctx, &bufs[cur], &bufs[cur ^ 1], first, count, l, dt, region, reg,
-                         h->d_side_mask, st);
+                         h->d_side_mask, h->d_xy, st);
   }
 
   af_status advance(int l, double dt, bool first_of_pair, int finest) {

@@ -84,6 +84,16 @@ struct CFFace {
   int32_t fine, fk;          // fine leaf facing it, index of the first of two fine faces
 };
 
+// Solid-body rotation (Sec. 4.2) for one step: the node positions of a patch
+// and the rotation that traces a node back over tau = dt/2 (index 0) and dt
+// (index 1).
+template <typename T>
+struct RotParams {
+  T cs[2], sn[2];     // cos, sin of omega tau
+  T x0, y0, dx, dy;   // domain origin, cell size of the level
+  T omega, xc, yc;    // a = -omega (y - yc), b = omega (x - xc)
+};
+
 // Ghost-fill plan: one op per fill-set DOF of every leaf, holding the source
 // that the fill rules resolve to for a given lower bound on source levels.
 //   x: source leaf, or -1 for "keep the target's own value"

@@ -29,6 +29,7 @@ template <typename T>
 struct StepArgs {
   const T* in[4];
   T* out[4];
+  const int32_t* leaf_xy;  // [npatch][2] patch (ix, iy); rotation only
   int32_t npatch, pitch, first, region;
   T dtdx, dtdy;            // dt/dx, dt/dy
   T a, b, c;               // physics
@@ -166,11 +167,47 @@ template <typename T>
 struct WSel<T, 0> { using type = AdvWeights<T>; };
 template <typename T>
 struct WSel<T, 1> { using type = AcWeights<T>; };
+template <typename T>
+struct WSel<T, 2> { using type = RotParams<T>; };
+
+// Cell of a foot at coordinate s (cell units: cell k spans [k-1/2, k+1/2])
+// and the reference coordinate in it; a foot on a face goes to the cell
+// between it and the node (disp = node - foot), as for constant advection.
+template <typename T>
+__device__ __forceinline__ int foot_cell(T s, T disp) {
+  return int(disp < T(0) ? ceil(s + T(0.5)) - T(1) : floor(s + T(0.5)));
+}
+
+// Reconstruction (Sec. 2, eq. poly) of the staged cell at LDS (r, c),
+// evaluated at reference point (xi, eta): tensor Lagrange interpolant of the
+// 9 nodal values, centre value from "average = Simpson sum".
+template <typename T, int NR, int NC>
+__device__ __forceinline__ T rot_eval(const T (&s)[4][1][NR][NC], int r, int c, T xi, T eta) {
+  const T lx[3] = {T(0.5) * xi * (xi - T(1)), T(1) - xi * xi, T(0.5) * xi * (xi + T(1))};
+  const T ly[3] = {T(0.5) * eta * (eta - T(1)), T(1) - eta * eta, T(0.5) * eta * (eta + T(1))};
+  T q[3][3];  // [x node][y node]
+  q[0][0] = s[1][0][r][c];
+  q[2][0] = s[1][0][r][c + 1];
+  q[0][2] = s[1][0][r + 1][c];
+  q[2][2] = s[1][0][r + 1][c + 1];
+  q[0][1] = s[2][0][r][c];
+  q[2][1] = s[2][0][r][c + 1];
+  q[1][0] = s[3][0][r][c];
+  q[1][2] = s[3][0][r + 1][c];
+  q[1][1] = (T(36) * s[0][0][r][c] - (q[0][0] + q[2][0] + q[0][2] + q[2][2]) -
+             T(4) * (q[0][1] + q[2][1] + q[1][0] + q[1][2])) / T(16);
+  T v = T(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) v += q[a][b] * lx[a] * ly[b];
+  return v;
+}
 
 template <typename T, int EQ, int M, int TY>
 __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
                                                          const typename WSel<T, EQ>::type W) {
-  constexpr int NCOMP = EQ ? 3 : 1;
+  constexpr int NCOMP = EQ == 1 ? 3 : 1;
   constexpr int NR = TY + 3;
   constexpr int NC = M + 5;
   __shared__ StepLds<T, NCOMP, NR, NC> L;
@@ -202,6 +239,12 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
   });
   __syncthreads();
   const int coff = ilo + 2;  // staged column of cell i is i + 2 = ii + coff
+  // rotation: lower-left corner of the patch's cell (0,0)
+  T px0 = T(0), py0 = T(0);
+  if constexpr (EQ == 2) {
+    px0 = W.x0 + T(A.leaf_xy[2 * patch] * M) * W.dx;
+    py0 = W.y0 + T(A.leaf_xy[2 * patch + 1] * M) * W.dy;
+  }
 
   // ---- point values of the extended cells [ilo, ihi] x [jlo, jhi]
   const int EC = span + 1, ER = nrow + 1;
@@ -235,6 +278,34 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
         const T cur = L.in[kind + 1][0][r][c];
         L.tsum[kind][0][jj][ii] = (cur + T(4) * h) + f;
         if (wrow) A.out[kind + 1][size_t(patch) * plane + obase] = f;
+      }
+    } else if constexpr (EQ == 2) {
+      // solid-body rotation (Sec. 4.2): the node turned back by -omega tau
+      // about (xc, yc) is the foot; q^n there from its cell's reconstruction
+#pragma unroll
+      for (int kind = 0; kind < 3; ++kind) {
+        if (kind == NK_XEDGE && !has_x) continue;
+        if (kind == NK_YEDGE && !has_y) continue;
+        const T X = kind == NK_YEDGE ? T(i) : T(i) - T(0.5);  // node in cell units
+        const T Y = kind == NK_XEDGE ? T(j) : T(j) - T(0.5);
+        const T x = px0 + (X + T(0.5)) * W.dx, y = py0 + (Y + T(0.5)) * W.dy;
+        const T rx = x - W.xc, ry = y - W.yc;
+        T val[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const T fx = W.xc + rx * W.cs[t] + ry * W.sn[t];
+          const T fy = W.yc - rx * W.sn[t] + ry * W.cs[t];
+          const T sx = (fx - px0) / W.dx - T(0.5), sy = (fy - py0) / W.dy - T(0.5);
+          // source cell, kept in the range a Courant number <= 1 allows
+          // (the halo holds it): nodes on x-faces i-1..i, else i-1..i+1
+          int ci = foot_cell(sx, x - fx), cj = foot_cell(sy, y - fy);
+          ci = min(max(ci, i - 1), kind == NK_YEDGE ? i + 1 : i);
+          cj = min(max(cj, j - 1), kind == NK_XEDGE ? j + 1 : j);
+          val[t] = rot_eval<T, NR, NC>(L.in, r + (cj - j), c + (ci - i), T(2) * (sx - T(ci)), T(2) * (sy - T(cj)));
+        }
+        const T cur = L.in[kind + 1][0][r][c];
+        L.tsum[kind][0][jj][ii] = (cur + T(4) * val[0]) + val[1];
+        if (wrow) A.out[kind + 1][size_t(patch) * plane + obase] = val[1];
       }
     } else {
       T res[2][3];
@@ -287,6 +358,22 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
     if constexpr (EQ == 0) {
       fL[0] = A.a * FL[0] * inv36; fR[0] = A.a * FR[0] * inv36;
       gB[0] = A.b * GB[0] * inv36; gT[0] = A.b * GT[0] * inv36;
+    } else if constexpr (EQ == 2) {
+      // rotation: f = a(node) q with a = -omega (y - yc) on x-faces (a depends
+      // on y only) and g = b(node) q with b = omega (x - xc) on y-faces
+      const T a0 = -W.omega * (py0 + T(j) * W.dy - W.yc);
+      const T a1 = -W.omega * (py0 + (T(j) + T(0.5)) * W.dy - W.yc);
+      const T a2 = -W.omega * (py0 + T(j + 1) * W.dy - W.yc);
+      const T b0 = W.omega * (px0 + T(i) * W.dx - W.xc);
+      const T b1 = W.omega * (px0 + (T(i) + T(0.5)) * W.dx - W.xc);
+      const T b2 = W.omega * (px0 + T(i + 1) * W.dx - W.xc);
+      const auto& ts = L.tsum;
+      fL[0] = (a0 * ts[NK_CORNER][0][jj][ii] + T(4) * a1 * ts[NK_XEDGE][0][jj][ii] + a2 * ts[NK_CORNER][0][jj + 1][ii]) * inv36;
+      fR[0] = (a0 * ts[NK_CORNER][0][jj][ii + 1] + T(4) * a1 * ts[NK_XEDGE][0][jj][ii + 1] +
+               a2 * ts[NK_CORNER][0][jj + 1][ii + 1]) * inv36;
+      gB[0] = (b0 * ts[NK_CORNER][0][jj][ii] + T(4) * b1 * ts[NK_YEDGE][0][jj][ii] + b2 * ts[NK_CORNER][0][jj][ii + 1]) * inv36;
+      gT[0] = (b0 * ts[NK_CORNER][0][jj + 1][ii] + T(4) * b1 * ts[NK_YEDGE][0][jj + 1][ii] +
+               b2 * ts[NK_CORNER][0][jj + 1][ii + 1]) * inv36;
     } else {
       fL[0] = A.c * FL[1] * inv36; fL[1] = A.c * FL[0] * inv36; fL[2] = T(0);
       fR[0] = A.c * FR[1] * inv36; fR[1] = A.c * FR[0] * inv36; fR[2] = T(0);
@@ -1170,17 +1257,12 @@ static hipError_t launch_step_t(const StepLaunch& s, hipStream_t st) {
   A.dtdx = T(s.dtdx); A.dtdy = T(s.dtdy);
   A.a = T(s.a); A.b = T(s.b); A.c = T(s.c);
   A.len_dt_x = s.len_dt_x; A.len_dt_y = s.len_dt_y;
-  A.reg = s.reg; A.side_mask = s.side_mask;
+  A.reg = s.reg; A.side_mask = s.side_mask; A.leaf_xy = s.leaf_xy;
   const int span = M + 2 * s.region;
   const int tiles = (span + TY - 1) / TY;
   const dim3 grid(unsigned(s.count * tiles));
-  if constexpr (EQ == 0) {
-    hipLaunchKernelGGL((k_patch_step<T, 0, M, TY>), grid, dim3(kThreads), 0, st, A,
-                       *static_cast<const AdvWeights<T>*>(s.weights));
-  } else {
-    hipLaunchKernelGGL((k_patch_step<T, 1, M, TY>), grid, dim3(kThreads), 0, st, A,
-                       *static_cast<const AcWeights<T>*>(s.weights));
-  }
+  hipLaunchKernelGGL((k_patch_step<T, EQ, M, TY>), grid, dim3(kThreads), 0, st, A,
+                     *static_cast<const typename WSel<T, EQ>::type*>(s.weights));
   return hipGetLastError();
 }
 
@@ -1199,8 +1281,12 @@ static hipError_t launch_step_m(const StepLaunch& s, hipStream_t st) {
 
 hipError_t launch_patch_step(const StepLaunch& s, hipStream_t st) {
   if (s.count <= 0) return hipSuccess;
-  if (s.fp32) return s.eq ? launch_step_m<float, 1>(s, st) : launch_step_m<float, 0>(s, st);
-  return s.eq ? launch_step_m<double, 1>(s, st) : launch_step_m<double, 0>(s, st);
+  switch (s.eq) {
+    case 0: return s.fp32 ? launch_step_m<float, 0>(s, st) : launch_step_m<double, 0>(s, st);
+    case 1: return s.fp32 ? launch_step_m<float, 1>(s, st) : launch_step_m<double, 1>(s, st);
+    case 2: return s.fp32 ? launch_step_m<float, 2>(s, st) : launch_step_m<double, 2>(s, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 bool step_shape_supported(int m, int ty) {

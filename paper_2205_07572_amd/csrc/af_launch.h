@@ -17,7 +17,8 @@ struct StepLaunch {
   double len_dt_x, len_dt_y;
   double* reg;
   const uint8_t* side_mask;
-  const void* weights;  // AdvWeights<T> or AcWeights<T> matching fp32/eq
+  const int32_t* leaf_xy;  // [npatch][2] patch (ix, iy); rotation only
+  const void* weights;  // AdvWeights<T>, AcWeights<T> or RotParams<T> matching fp32/eq
 };
 
 struct AdvanceLaunch {
