@@ -274,6 +274,69 @@ def amr_runs():
     return out
 
 
+def rotation_runs():
+    """Solid-body rotation (a = -pi y, b = pi x on [-1, 1]^2, the smoothed
+    disc of the advection test centred at (0.5, 0.5)), uniform levels 6 and 7
+    (1024^2 and 2048^2 as 32^2 patches) to a half rotation at Courant number
+    0.6 of the largest axis speed: cell-updates/s of the general path
+    (ghost fill + patch step per step) in FP64 and FP32, and the L1 error of
+    the averages (area-weighted, divided by the domain area) next to the
+    paper's Table 2 values."""
+    import math
+    import torch
+    import afsynth
+    import paper_2205_07572_amd as af
+    m, T, omega = 32, 1.0, math.pi
+    paper = {6: 4.599185e-06, 7: 5.826258e-07}
+    data = afsynth.solid_body(afsynth.disc_q0(0.15, 0.02, 0.5, 0.5), omega)
+    out = {}
+    for level in (6, 7):
+        N = 16 << level
+        n0 = N // m
+        d0 = afsynth.dofs_periodic(data, N, N, x0=-1.0, y0=-1.0, lx=2.0, ly=2.0, nq=4)
+        blk = afsynth.periodic_to_blocks(d0, m)
+        ex = afsynth.dofs_periodic(afsynth.InitialData(1, lambda x, y: data.exact(x, y, T)), N, N, x0=-1.0,
+                                   y0=-1.0, lx=2.0, ly=2.0, nq=4)["avg"][0]
+        dx = 2.0 / N
+        n = math.ceil(T / (0.6 * dx / omega))
+        res = {}
+        for pname, prec in (("fp64", af.FP64), ("fp32", af.FP32)):
+            prob = af.Problem(eq=af.ROTATION, prec=prec, m=m, n0x=n0, n0y=n0, lmax=0, x0=-1.0, y0=-1.0, lx=2.0,
+                              ly=2.0, omega=omega)
+            ctx = af.Context(prob)
+            leaves = afsynth.uniform_leaves(n0, n0, 0)
+            h = af.Hierarchy(ctx, leaves)
+            b0 = af.blocks_to_state(ctx, [{k: blk[k][p] for k in af.KINDS} for p in range(n0 * n0)])
+            bufs = [b0, torch.zeros_like(b0)]
+            reg = torch.zeros((len(leaves), 4, m, 1), dtype=torch.float64, device="cuda")
+            ctx.autotune(h, [b0.clone(), torch.zeros_like(b0)], 0, T / n, reps=3)
+            mask = 0
+            ms, mask = _event_ms(lambda: _rot_steps(ctx, h, bufs, reg, n, T / n))
+            got = af.state_to_blocks(ctx, bufs[mask & 1])
+            avg = np.zeros((N, N))
+            for p, (_, ix, iy) in enumerate(leaves):
+                avg[iy * m:(iy + 1) * m, ix * m:(ix + 1) * m] = got[p]["avg"][0, 2:2 + m, 2:2 + m]
+            l1 = float(np.abs(avg - ex).sum() * dx * dx / 4.0)
+            res[pname] = {"steps": n, "ms": ms, "cell_updates_per_s": N * N * n / (ms * 1e-3), "l1": l1,
+                          "l1_over_paper": l1 / paper[level]}
+            print(f"[bench] rotation level {level} ({N}^2) {pname}: {n} steps in {ms:.1f} ms, "
+                  f"{res[pname]['cell_updates_per_s']:.3e} cell-updates/s, L1 {l1:.4e} "
+                  f"({res[pname]['l1_over_paper']:.3f} x Table 2)", file=sys.stderr, flush=True)
+            del bufs, b0
+            torch.cuda.empty_cache()
+        out[f"level{level}"] = res
+    out["eoc_fp64"] = math.log2(out["level6"]["fp64"]["l1"] / out["level7"]["fp64"]["l1"])
+    out["paper_eoc"] = 2.9807
+    return out
+
+
+def _rot_steps(ctx, h, bufs, reg, n, dt):
+    mask = 0
+    for _ in range(n):
+        mask = ctx.amr_coarse_step(h, bufs, mask, dt, reg)
+    return mask
+
+
 def cpu_baseline(data, nsteps, dt):
     """The FP64 oracle, single-threaded, on `nsteps` steps of the benchmark
     grid."""
@@ -406,6 +469,7 @@ def main():
     }
     if not args.no_amr:
         line["amr"] = amr_runs()
+        line["rotation"] = rotation_runs()
     if not args.no_cpu:
         v, el = cpu_baseline(data, args.cpu_steps, dt)
         line["cpu_baseline"] = {"value": v, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
