@@ -226,6 +226,23 @@ def disc_q0(r0=0.15, width=0.02, xc=0.5, yc=0.5):
     return q0
 
 
+def swirl_gaussians():
+    """Initial data eq. id_swirl of the swirl test (Sec. 4.3): two Gaussians
+    exp(-100 |x - (0.5, 0.25)|^2) + exp(-100 |x - (0.5, 0.75)|^2) on the
+    periodic unit square, periodised over the 3x3 images.  The swirl field
+    reverses at t = 1/2, so at t = 1 the exact solution is the initial data."""
+
+    def q0(x, y):
+        return (_periodic_gauss(x, y, 0.5, 0.25, 100.0) + _periodic_gauss(x, y, 0.5, 0.75, 100.0))[None]
+
+    def exact(x, y, t):
+        if abs(t - round(t)) > 1e-12:
+            raise ValueError("the swirl solution is known in closed form at integer times only")
+        return q0(x, y)
+
+    return InitialData(1, q0, exact)
+
+
 def gauss_q0(x0, y0, alpha):
     """exp(-alpha |x - x0|^2) as a plain function of (x, y)."""
     return lambda x, y: np.exp(-alpha * ((x - x0) ** 2 + (y - y0) ** 2))

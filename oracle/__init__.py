@@ -48,6 +48,14 @@ def lib():
         L.or_run_periodic_rot.argtypes = [I, I, D, D, D, D, D, I, D, D, D, P, P, P, P]
         L.or_patch_step_rot.argtypes = [I, I, D, D, D, D, D, D, D, D, I, P, P, P, P, P, P, P, P, P, I]
         L.or_hier_set_rotation.argtypes = [P, D, D, D]
+        L.or_run_periodic_swirl.argtypes = [I, I, D, D, D, D, D, I, D, P, P, P, P]
+        L.or_patch_step_swirl.argtypes = [I, I, D, D, D, D, D, D, I, P, P, P, P, P, P, P, P, P, I]
+        L.or_swirl_foot.argtypes = [D, D, D, D, D, D, P, P]
+        L.or_hier_set_swirl.argtypes = [P]
+        L.or_hier_run_global.argtypes = [P, D, I]
+        L.or_hier_set_time.argtypes = [P, D]
+        L.or_hier_get_time.argtypes = [P]
+        L.or_hier_get_time.restype = D
         L.or_hier_new.argtypes = [I, I, I, I, I, D, D, D, D, D, D, D]
         L.or_hier_new.restype = P
         L.or_hier_free.argtypes = [P]
@@ -150,6 +158,39 @@ def patch_step_rot(m, block, x0p, y0p, dx, dy, dt, omega, xc=0.0, yc=0.0, region
     return outs
 
 
+def run_periodic_swirl(dofs, dt, nsteps, t0=0.0, x0=0.0, y0=0.0):
+    """Swirl flow of Sec. 4.3 on a periodic grid whose cell (0,0) has its
+    lower-left corner at (x0, y0), from time t0; returns a new dict."""
+    out = {k: np.ascontiguousarray(dofs[k], dtype=np.float64).copy() for k in KINDS}
+    _, ny, nx = out["avg"].shape
+    lib().or_run_periodic_swirl(nx, ny, float(x0), float(y0), float(dofs["dx"]), float(dofs["dy"]), float(dt),
+                                int(nsteps), float(t0), _p(out["avg"]), _p(out["corner"]), _p(out["xedge"]),
+                                _p(out["yedge"]))
+    out["dx"], out["dy"] = dofs["dx"], dofs["dy"]
+    return out
+
+
+def patch_step_swirl(m, block, x0p, y0p, dx, dy, dt, t, region=0, flux4=None, side_mask=0, g=2):
+    """patch_step for the swirl flow, the step starting at time t."""
+    ins = {k: np.ascontiguousarray(block[k], dtype=np.float64) for k in KINDS}
+    outs = {k: np.zeros_like(ins[k]) for k in KINDS}
+    fp = _p(flux4) if flux4 is not None else None
+    lib().or_patch_step_swirl(int(m), int(g), float(x0p), float(y0p), float(dx), float(dy), float(dt), float(t),
+                              int(region), _p(ins["avg"]), _p(ins["corner"]), _p(ins["xedge"]), _p(ins["yedge"]),
+                              _p(outs["avg"]), _p(outs["corner"]), _p(outs["xedge"]), _p(outs["yedge"]), fp,
+                              int(side_mask))
+    return outs
+
+
+def swirl_foot(x, y, t, tau, dx, dy):
+    """Foot of the swirl characteristic through (x, y) at t + tau, traced back
+    to t by the oracle's Runge-Kutta step on a grid of spacing (dx, dy)."""
+    fx, fy = ctypes.c_double(), ctypes.c_double()
+    lib().or_swirl_foot(float(x), float(y), float(t), float(tau), float(dx), float(dy), ctypes.byref(fx),
+                        ctypes.byref(fy))
+    return fx.value, fy.value
+
+
 def patch_step(eq, m, block, dx, dy, dt, region=0, a=0.0, b=0.0, c=1.0, flux4=None,
                side_mask=0, g=2):
     """One step on one patch block (dict kind -> [ncomp][S+1][S+1]).  Returns
@@ -173,7 +214,7 @@ class Hier:
     def __init__(self, eq, m, n0x, n0y, lmax, x0=0.0, y0=0.0, lx=1.0, ly=1.0, a=0.0, b=0.0,
                  c=1.0, omega=0.0, xc=0.0, yc=0.0):
         """eq 0 advection (a, b), 1 acoustics (c), 2 solid-body rotation
-        (omega about (xc, yc))."""
+        (omega about (xc, yc)), 3 the swirl flow of Sec. 4.3."""
         self.eq, self.m, self.n0x, self.n0y, self.lmax = eq, m, n0x, n0y, lmax
         self.x0, self.y0, self.lx, self.ly = x0, y0, lx, ly
         self.ncomp = 3 if eq == 1 else 1
@@ -182,6 +223,8 @@ class Hier:
                                    float(y0), float(lx), float(ly), float(a), float(b), float(c))
         if eq == 2:
             lib().or_hier_set_rotation(self.h, float(omega), float(xc), float(yc))
+        elif eq == 3:
+            lib().or_hier_set_swirl(self.h)
 
     def __del__(self):
         if getattr(self, "h", None):
@@ -259,7 +302,20 @@ class Hier:
         lib().or_hier_coarse_step(self.h, float(dt0))
 
     def run(self, dt0, nsteps):
+        """nsteps subcycled coarse steps of dt0 (Sec. 3.2)."""
         lib().or_hier_run(self.h, float(dt0), int(nsteps))
+
+    def run_global(self, dt, nsteps):
+        """nsteps steps of dt on every level at once (no subcycling)."""
+        lib().or_hier_run_global(self.h, float(dt), int(nsteps))
+
+    @property
+    def time(self):
+        return lib().or_hier_get_time(self.h)
+
+    @time.setter
+    def time(self, t):
+        lib().or_hier_set_time(self.h, float(t))
 
     def tag(self, mode, comp, theta_r, theta_c):
         n = lib().or_hier_num_leaves(self.h)

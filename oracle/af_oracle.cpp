@@ -275,10 +275,11 @@ struct BlockGrid : Grid {
 // ---------------------------------------------------------------------------
 
 struct Physics {
-  int eq = 0;            // 0 advection, 1 acoustics, 2 solid-body rotation
+  int eq = 0;            // 0 advection, 1 acoustics, 2 solid-body rotation, 3 swirl
   double a = 0, b = 0;   // advection velocity
   double c = 1;          // speed of sound
   double omega = 0, xc = 0, yc = 0;  // rotation: a = -omega (y - yc), b = omega (x - xc)
+  double t = 0;          // time at the start of the step (swirl)
 };
 
 void node_pos(int kind, int i, int j, double* X, double* Y) {
@@ -340,6 +341,45 @@ double rotate_point(const Grid& g, const Physics& ph, int kind, int i, int j, do
   const double fx = ph.xc + rx * std::cos(th) + ry * std::sin(th);
   const double fy = ph.yc - rx * std::sin(th) + ry * std::cos(th);
   const double sx = (fx - g.ox) / g.dx - 0.5, sy = (fy - g.oy) / g.dy - 0.5;  // cell units
+  int ci, cj;
+  double xi, eta;
+  locate(sx, x - fx, &ci, &xi);
+  locate(sy, y - fy, &cj, &eta);
+  return cell_eval(g.cell(0, ci, cj), xi, eta);
+}
+
+// Swirl flow (Sec. 4.3): stream function
+//   Psi(x, y, t) = sin^2(pi x) sin^2(pi y) cos(pi t) / pi
+// and the velocity of eq. swirlODE, its centred differences over one cell of
+// the grid the step runs on.
+double swirl_psi(double x, double y, double t) {
+  const double sx = std::sin(kPi * x), sy = std::sin(kPi * y);
+  return sx * sx * sy * sy * std::cos(kPi * t) / kPi;
+}
+void swirl_vel(const Grid& g, double x, double y, double t, double* a, double* b) {
+  *a = -(swirl_psi(x, y + 0.5 * g.dy, t) - swirl_psi(x, y - 0.5 * g.dy, t)) / g.dy;
+  *b = (swirl_psi(x + 0.5 * g.dx, y, t) - swirl_psi(x - 0.5 * g.dx, y, t)) / g.dx;
+}
+
+// The characteristic through (x, y) at time t + tau traced back to t by one
+// step of the classical fourth-order Runge-Kutta method (Sec. 4.3).
+void swirl_trace(const Grid& g, double x, double y, double t, double tau, double* fx, double* fy) {
+  const double t1 = t + tau, h = -tau;
+  double a1, b1, a2, b2, a3, b3, a4, b4;
+  swirl_vel(g, x, y, t1, &a1, &b1);
+  swirl_vel(g, x + 0.5 * h * a1, y + 0.5 * h * b1, t1 + 0.5 * h, &a2, &b2);
+  swirl_vel(g, x + 0.5 * h * a2, y + 0.5 * h * b2, t1 + 0.5 * h, &a3, &b3);
+  swirl_vel(g, x + h * a3, y + h * b3, t1 + h, &a4, &b4);
+  *fx = x + h / 6.0 * (a1 + 2.0 * a2 + 2.0 * a3 + a4);
+  *fy = y + h / 6.0 * (b1 + 2.0 * b2 + 2.0 * b3 + b4);
+}
+
+// q^n at the foot of the node's characteristic (Sec. 4.3).
+double swirl_point(const Grid& g, const Physics& ph, int kind, int i, int j, double tau) {
+  double x, y, fx, fy;
+  node_xy(g, kind, i, j, &x, &y);
+  swirl_trace(g, x, y, ph.t, tau, &fx, &fy);
+  const double sx = (fx - g.ox) / g.dx - 0.5, sy = (fy - g.oy) / g.dy - 0.5;
   int ci, cj;
   double xi, eta;
   locate(sx, x - fx, &ci, &xi);
@@ -415,6 +455,8 @@ void evolve_point(const Grid& g, const Physics& ph, int kind, int i, int j, doub
     out[0] = advect_point(g, ph, kind, i, j, tau);
   } else if (ph.eq == 2) {
     out[0] = rotate_point(g, ph, kind, i, j, tau);
+  } else if (ph.eq == 3) {
+    out[0] = swirl_point(g, ph, kind, i, j, tau);
   } else {
     acoustic_point(g, ph, kind, i, j, tau, out);
   }
@@ -444,8 +486,8 @@ void flux_y(const Physics& ph, double vel, const double* q, double* f) {
 
 // Simpson space-time flux (eq. Simpson-2d): nodes lo/mid/hi along the face at
 // times n, n+1/2, n+1, weights (1,4,1) x (1,4,1) / 36.  vel: the normal
-// velocity component at the three nodes (advection-type equations).
-void simpson_flux(const Physics& ph, bool xface, const double vel[3], const double* n_lo,
+// velocity at the nine points in the same order (advection-type equations).
+void simpson_flux(const Physics& ph, bool xface, const double vel[9], const double* n_lo,
                   const double* n_mid, const double* n_hi, const double* h_lo, const double* h_mid,
                   const double* h_hi, const double* f_lo, const double* f_mid,
                   const double* f_hi, int ncomp, double* F) {
@@ -454,10 +496,36 @@ void simpson_flux(const Physics& ph, bool xface, const double vel[3], const doub
   for (int c = 0; c < ncomp; ++c) F[c] = 0.0;
   for (int k = 0; k < 9; ++k) {
     double f[3];
-    if (xface) flux_x(ph, vel[k % 3], pts[k], f); else flux_y(ph, vel[k % 3], pts[k], f);
+    if (xface) flux_x(ph, vel[k], pts[k], f); else flux_y(ph, vel[k], pts[k], f);
     for (int c = 0; c < ncomp; ++c) F[c] += w[k] * f[c];
   }
   for (int c = 0; c < ncomp; ++c) F[c] /= 36.0;
+}
+
+// Normal velocity at the nine Simpson points of the x-face at x_{i-1/2}, row
+// j (xface) or of the y-face at y_{j-1/2}, column i, ordered (time n, n+1/2,
+// n+1) x (lo, mid, hi node): constant; the rotation field at each node
+// (Sec. 4.2); or, for the swirl (eq. flux_swirl, eq. swirlF/G), the field at
+// the face midpoint at each of the three times.
+void face_velocities(const Grid& g, const Physics& ph, bool xface, int i, int j, double dt, double vel[9]) {
+  const int kind_lo = K_CORNER, kind_mid = xface ? K_XEDGE : K_YEDGE;
+  const int il = i, jl = j, ih = xface ? i : i + 1, jh = xface ? j + 1 : j;
+  double x[3], y[3];
+  node_xy(g, kind_lo, il, jl, &x[0], &y[0]);
+  node_xy(g, kind_mid, i, j, &x[1], &y[1]);
+  node_xy(g, kind_lo, ih, jh, &x[2], &y[2]);
+  for (int tl = 0; tl < 3; ++tl)
+    for (int n = 0; n < 3; ++n) {
+      double v;
+      if (ph.eq == 3) {
+        double a, b;
+        swirl_vel(g, x[1], y[1], ph.t + 0.5 * tl * dt, &a, &b);
+        v = xface ? a : b;
+      } else {
+        v = xface ? vel_a(ph, x[n], y[n]) : vel_b(ph, x[n], y[n]);
+      }
+      vel[3 * tl + n] = v;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -514,13 +582,8 @@ StepResult af_step_range(const Grid& g, const Physics& ph, double dt, int i0, in
   for (int j = j0; j < j1; ++j)
     for (int i = i0; i <= i1; ++i) {
       // x-face at x_{i-1/2}, y in [y_{j-1/2}, y_{j+1/2}]: corner (i,j), xedge (i,j), corner (i,j+1)
-      double vel[3], x, y;
-      node_xy(g, K_CORNER, i, j, &x, &y);
-      vel[0] = vel_a(ph, x, y);
-      node_xy(g, K_XEDGE, i, j, &x, &y);
-      vel[1] = vel_a(ph, x, y);
-      node_xy(g, K_CORNER, i, j + 1, &x, &y);
-      vel[2] = vel_a(ph, x, y);
+      double vel[9];
+      face_velocities(g, ph, true, i, j, dt, vel);
       simpson_flux(ph, true, vel, &cur[K_CORNER][nid(i, j)], &cur[K_XEDGE][nid(i, j)],
                    &cur[K_CORNER][nid(i, j + 1)], &half[K_CORNER][nid(i, j)],
                    &half[K_XEDGE][nid(i, j)], &half[K_CORNER][nid(i, j + 1)],
@@ -531,13 +594,8 @@ StepResult af_step_range(const Grid& g, const Physics& ph, double dt, int i0, in
   for (int j = j0; j <= j1; ++j)
     for (int i = i0; i < i1; ++i) {
       // y-face at y_{j-1/2}: corner (i,j), yedge (i,j), corner (i+1,j)
-      double vel[3], x, y;
-      node_xy(g, K_CORNER, i, j, &x, &y);
-      vel[0] = vel_b(ph, x, y);
-      node_xy(g, K_YEDGE, i, j, &x, &y);
-      vel[1] = vel_b(ph, x, y);
-      node_xy(g, K_CORNER, i + 1, j, &x, &y);
-      vel[2] = vel_b(ph, x, y);
+      double vel[9];
+      face_velocities(g, ph, false, i, j, dt, vel);
       simpson_flux(ph, false, vel, &cur[K_CORNER][nid(i, j)], &cur[K_YEDGE][nid(i, j)],
                    &cur[K_CORNER][nid(i + 1, j)], &half[K_CORNER][nid(i, j)],
                    &half[K_YEDGE][nid(i, j)], &half[K_CORNER][nid(i + 1, j)],
@@ -577,6 +635,7 @@ enum Side { S_W = 0, S_E = 1, S_S = 2, S_N = 3 };
 
 struct Hier {
   Physics ph;
+  double time = 0.0;  // time of the synchronised state
   int m = 16, g = 2, ncomp = 1;
   int n0x = 1, n0y = 1, lmax = 0;
   double x0 = 0, y0 = 0, lx = 1, ly = 1;
@@ -882,7 +941,8 @@ void step_leaf(Hier& h, Leaf& L, double dt, int region) {
   for (int k = 0; k < 4; ++k) L.blk[k] = nb[k];
 }
 
-void step_level(Hier& h, int l, double dt, int region) {
+void step_level(Hier& h, int l, double t, double dt, int region) {
+  h.ph.t = t;
   for (Leaf& L : h.leaves)
     if (L.level == l) step_leaf(h, L, dt, region);
 }
@@ -954,19 +1014,31 @@ int finest_level(const Hier& h) {
   return f;
 }
 
-void advance(Hier& h, int l, double dt, bool first, int lfin) {
-  step_level(h, l, dt, (l > 0 && first) ? 1 : 0);
+void advance(Hier& h, int l, double t, double dt, bool first, int lfin) {
+  step_level(h, l, t, dt, (l > 0 && first) ? 1 : 0);
   if (l + 1 <= lfin) {
-    advance(h, l + 1, 0.5 * dt, true, lfin);
+    advance(h, l + 1, t, 0.5 * dt, true, lfin);
     fill(h, l + 1, l + 1);
-    advance(h, l + 1, 0.5 * dt, false, lfin);
+    advance(h, l + 1, t + 0.5 * dt, 0.5 * dt, false, lfin);
     flux_correct(h, l);
   }
 }
 
 void coarse_step(Hier& h, double dt0) {
   fill(h, 0, 0);
-  advance(h, 0, dt0, true, finest_level(h));
+  advance(h, 0, h.time, dt0, true, finest_level(h));
+  h.time += dt0;
+}
+
+// Global time stepping (no subcycling, the corollary of Sec. 4.3): every
+// level takes one step dt from the same synchronised state, then each coarse
+// level's fluxes at finer neighbours are replaced by the fine ones.
+void global_step(Hier& h, double dt) {
+  fill(h, 0, 0);
+  const int lfin = finest_level(h);
+  for (int l = 0; l <= lfin; ++l) step_level(h, l, h.time, dt, 0);
+  for (int l = 0; l < lfin; ++l) flux_correct(h, l);
+  h.time += dt;
 }
 
 // ----- Transfers (Sec. 3.1) -------------------------------------------------
@@ -1338,6 +1410,18 @@ void or_run_periodic_rot(int nx, int ny, double x0, double y0, double dx, double
   for (int s = 0; s < nsteps; ++s) step_periodic(ph, nx, ny, x0, y0, dx, dy, dt, avg, corner, xedge, yedge);
 }
 
+// Swirl flow (Sec. 4.3) on the periodic grid, starting at time t0.
+void or_run_periodic_swirl(int nx, int ny, double x0, double y0, double dx, double dy, double dt,
+                           int nsteps, double t0, double* avg, double* corner, double* xedge,
+                           double* yedge) {
+  Physics ph;
+  ph.eq = 3;
+  for (int s = 0; s < nsteps; ++s) {
+    ph.t = t0 + s * dt;
+    step_periodic(ph, nx, ny, x0, y0, dx, dy, dt, avg, corner, xedge, yedge);
+  }
+}
+
 // --- one patch block --------------------------------------------------------
 // blocks: four arrays [ncomp][(m+2g+1)^2], row-major (row = j+g, col = i+g).
 // region 0 = interior, 1 = interior + ghost layer 1.  `out` receives the
@@ -1366,6 +1450,28 @@ void or_patch_step_rot(int m, int g, double x0p, double y0p, double dx, double d
              in_yedge, out_avg, out_corner, out_xedge, out_yedge, flux4, side_mask);
 }
 
+// The same for the swirl flow, the step starting at time t.
+void or_patch_step_swirl(int m, int g, double x0p, double y0p, double dx, double dy, double dt,
+                         double t, int region, const double* in_avg, const double* in_corner,
+                         const double* in_xedge, const double* in_yedge, double* out_avg,
+                         double* out_corner, double* out_xedge, double* out_yedge, double* flux4,
+                         int side_mask) {
+  Physics ph;
+  ph.eq = 3;
+  ph.t = t;
+  patch_step(ph, m, g, x0p, y0p, dx, dy, dt, region, in_avg, in_corner, in_xedge, in_yedge, out_avg,
+             out_corner, out_xedge, out_yedge, flux4, side_mask);
+}
+
+// Swirl foot of one node (for pins): the point reached from (x, y) at time
+// t + tau by the Runge-Kutta step back to t, on a grid of spacing (dx, dy).
+void or_swirl_foot(double x, double y, double t, double tau, double dx, double dy, double* fx, double* fy) {
+  PeriodicGrid g;
+  g.dx = dx;
+  g.dy = dy;
+  swirl_trace(g, x, y, t, tau, fx, fy);
+}
+
 // --- AMR hierarchy ------------------------------------------------------------
 void* or_hier_new(int eq, int m, int n0x, int n0y, int lmax, double x0, double y0, double lx,
                   double ly, double a, double b, double c) {
@@ -1377,6 +1483,14 @@ void* or_hier_new(int eq, int m, int n0x, int n0y, int lmax, double x0, double y
   return h;
 }
 void or_hier_free(void* hp) { delete static_cast<Hier*>(hp); }
+
+// Switch the hierarchy's equation to the swirl flow of Sec. 4.3.
+void or_hier_set_swirl(void* hp) {
+  Hier* h = static_cast<Hier*>(hp);
+  h->ph = Physics();
+  h->ph.eq = 3;
+  h->ncomp = 1;
+}
 
 // Switch the hierarchy's equation to solid-body rotation about (xc, yc).
 void or_hier_set_rotation(void* hp, double omega, double xc, double yc) {
@@ -1427,13 +1541,20 @@ void or_hier_side_relations(void* hp, int* rel) {
 }
 void or_hier_fill(void* hp, int tmin, int smin) { fill(*static_cast<Hier*>(hp), tmin, smin); }
 void or_hier_step_level(void* hp, int level, double dt, int region) {
-  step_level(*static_cast<Hier*>(hp), level, dt, region);
+  Hier& h = *static_cast<Hier*>(hp);
+  step_level(h, level, h.time, dt, region);
 }
 void or_hier_flux_correct(void* hp, int level) { flux_correct(*static_cast<Hier*>(hp), level); }
 void or_hier_coarse_step(void* hp, double dt0) { coarse_step(*static_cast<Hier*>(hp), dt0); }
 void or_hier_run(void* hp, double dt0, int nsteps) {
   for (int s = 0; s < nsteps; ++s) coarse_step(*static_cast<Hier*>(hp), dt0);
 }
+// Global time stepping (no subcycling): nsteps steps of dt for every level.
+void or_hier_run_global(void* hp, double dt, int nsteps) {
+  for (int s = 0; s < nsteps; ++s) global_step(*static_cast<Hier*>(hp), dt);
+}
+void or_hier_set_time(void* hp, double t) { static_cast<Hier*>(hp)->time = t; }
+double or_hier_get_time(void* hp) { return static_cast<Hier*>(hp)->time; }
 void or_hier_tag(void* hp, int mode, int comp, double tr, double tc, int8_t* tags, double* values) {
   Hier& h = *static_cast<Hier*>(hp);
   for (size_t k = 0; k < h.leaves.size(); ++k)
