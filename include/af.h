@@ -63,8 +63,14 @@ typedef enum {
 /* AF_ROTATION: q_t + (a q)_x + (b q)_y = 0 with a = -omega (y - yc),
  * b = omega (x - xc) (Sec. 4.2, eq. solidbody).  The field is not periodic;
  * the data are, so results are those of the paper's test as long as the
- * data vanish near the domain boundary. */
-typedef enum { AF_ADVECTION = 0, AF_ACOUSTICS = 1, AF_ROTATION = 2 } af_equation;
+ * data vanish near the domain boundary.
+ * AF_SWIRL: the same equation with the time-dependent field of Sec. 4.3,
+ * a = -(Psi(x, y + dy/2, t) - Psi(x, y - dy/2, t))/dy, b = (Psi(x + dx/2, y,
+ * t) - Psi(x - dx/2, y, t))/dx, Psi = sin^2(pi x) sin^2(pi y) cos(pi t)/pi
+ * (eq. swirlODE, dx, dy of the level), feet by one classical Runge-Kutta
+ * step backwards in time, fluxes with the face-midpoint velocity at each
+ * Simpson time (eq. swirlF, swirlG).  |a|, |b| <= 1. */
+typedef enum { AF_ADVECTION = 0, AF_ACOUSTICS = 1, AF_ROTATION = 2, AF_SWIRL = 3 } af_equation;
 typedef enum { AF_FP64 = 0, AF_FP32 = 1 } af_precision;
 enum { AF_AVG = 0, AF_CORNER = 1, AF_XEDGE = 2, AF_YEDGE = 3 };
 enum { AF_SIDE_W = 0, AF_SIDE_E = 1, AF_SIDE_S = 2, AF_SIDE_N = 3 };
@@ -142,8 +148,9 @@ af_status af_hier_side_relations(const af_hier* h, int8_t* rel);
  *   level      the patches' level; dx = lx/(n0x m 2^level), likewise dy.
  *   dt         time step; AF_ERR_CFL if max(|a| dt/dx, |b| dt/dy) > 1
  *              (advection, eq. cfl-adv; for AF_ROTATION with the largest
- *              |a| and |b| on the domain) or c dt / min(dx,dy) > 1/2
- *              (acoustics, eq. cfl-acoustics).
+ *              |a| and |b| on the domain, for AF_SWIRL with |a|, |b| = 1)
+ *              or c dt / min(dx,dy) > 1/2 (acoustics, eq. cfl-acoustics).
+ *   t          time at the start of the step (used by AF_SWIRL only).
  *   region     AF_REGION_INTERIOR: averages of cells [0,m)^2 and all nodes
  *              of the closed square [0,m]^2 are written;
  *              AF_REGION_LAYER1: cells [-1,m+1)^2 and nodes [-1,m+1]^2.
@@ -155,11 +162,11 @@ af_status af_hier_side_relations(const af_hier* h, int8_t* rel);
  *   side_mask  device uint8 [npatch]; NULL = no recording.
  *   leaf_xy    device int32 [npatch][2]: (ix, iy) of each patch at its
  *              level (af_hier_leaf_xy), which places the patch at
- *              (x0 + ix m dx, y0 + iy m dy).  Required for AF_ROTATION
- *              (AF_ERR_ARG if NULL), ignored otherwise.
+ *              (x0 + ix m dx, y0 + iy m dy).  Required for AF_ROTATION and
+ *              AF_SWIRL (AF_ERR_ARG if NULL), ignored otherwise.
  * --------------------------------------------------------------------- */
 af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t first,
-                        int32_t count, int32_t level, double dt, int32_t region,
+                        int32_t count, int32_t level, double dt, double t, int32_t region,
                         double* flux_reg, const uint8_t* side_mask, const int32_t* leaf_xy,
                         hipStream_t stream);
 
@@ -264,17 +271,24 @@ af_status af_autotune(af_ctx* ctx, af_hier* h, af_state* bufs, int32_t level, do
 
 /* ---------------------------------------------------------------------
  * af_amr_coarse_step -- one coarse time step dt0 of the whole hierarchy
- * with subcycling (Sec. 3.2): full fill; then advance(0): step level l with
- * dt0/2^l (layer-1 region for the first of each pair of fine substeps),
- * recursively advance level l+1 twice with a same-or-finer fill between,
- * then the conservative fix of level l.  Levels ping-pong between bufs[0]
- * and bufs[1]; *level_buf_mask is updated.  flux_reg: FP64
- * [npatch][4][m][ncomp], zero on entry (left zero on exit).  side_mask:
- * device uint8 [npatch] from af_hier_side_mask.  use_graph != 0 replays a
- * hipGraph captured on first use for this (hierarchy, mask, dt0).
+ * from time t0 with subcycling (Sec. 3.2): full fill; then advance(0): step
+ * level l with dt0/2^l (layer-1 region for the first of each pair of fine
+ * substeps), recursively advance level l+1 twice with a same-or-finer fill
+ * between, then the conservative fix of level l.  Levels ping-pong between
+ * bufs[0] and bufs[1]; *level_buf_mask is updated.  flux_reg: FP64
+ * [npatch][4][m][ncomp], zero on entry (left zero on exit).
+ * flags: AF_STEP_GRAPH replays a hipGraph captured on first use for this
+ * (hierarchy, mask, dt0, and t0 for AF_SWIRL; at most 64 graphs are kept per
+ * hierarchy, the stream is drained and the cache emptied when it is full, so
+ * AF_SWIRL graphs are reused only at repeated t0); AF_STEP_GLOBAL takes one
+ * step of dt0 on every level at once, without subcycling (global time
+ * stepping, the corollary of Sec. 4.3; dt0 must satisfy the finest level's
+ * CFL): full fill, every level steps its interior, then the conservative
+ * fix of every level.
  * --------------------------------------------------------------------- */
+enum { AF_STEP_GRAPH = 1, AF_STEP_GLOBAL = 2 };
 af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* level_buf_mask,
-                             double dt0, double* flux_reg, int32_t use_graph,
+                             double t0, double dt0, double* flux_reg, int32_t flags,
                              hipStream_t stream);
 
 /* device uint8 [nleaves]: bit s set when side s borders another level */

@@ -14,7 +14,8 @@ import numpy as np
 from . import _lib
 from ._lib import AFError, check
 
-ADVECTION, ACOUSTICS, ROTATION = 0, 1, 2
+ADVECTION, ACOUSTICS, ROTATION, SWIRL = 0, 1, 2, 3
+STEP_GRAPH, STEP_GLOBAL = 1, 2
 FP64, FP32 = 0, 1
 KINDS = ("avg", "corner", "xedge", "yedge")
 REGION_INTERIOR, REGION_LAYER1 = 0, 1
@@ -128,14 +129,16 @@ class Context:
 
     # ----------------------------------------------------------------- calls
     def patch_step(self, tin, tout, first, count, level, dt, region=REGION_INTERIOR, flux_reg=None,
-                   side_mask=None, leaf_xy=None):
+                   side_mask=None, leaf_xy=None, t=0.0):
         """leaf_xy: device (ix, iy) table of the patches (Hierarchy.leaf_xy_ptr()
-        or an int32 tensor [npatch][2]); needed for ROTATION."""
+        or an int32 tensor [npatch][2]); needed for ROTATION and SWIRL.  t: time
+        at the start of the step (SWIRL)."""
         sin, sout = self.cstate(tin), self.cstate(tout)
         sm = ctypes.c_void_p(side_mask) if isinstance(side_mask, int) else _ptr(side_mask)
         xy = ctypes.c_void_p(leaf_xy) if isinstance(leaf_xy, int) else _ptr(leaf_xy)
         check(_lib.load().af_patch_step(self.h, ctypes.byref(sin), ctypes.byref(sout), int(first), int(count),
-                                        int(level), float(dt), int(region), _ptr(flux_reg), sm, xy, _stream()))
+                                        int(level), float(dt), float(t), int(region), _ptr(flux_reg), sm, xy,
+                                        _stream()))
 
     def _pair(self, bufs):
         arr = (_lib.af_state * 2)()
@@ -177,10 +180,13 @@ class Context:
                                       ctypes.byref(a), ctypes.byref(b), _stream()))
         return a.value, b.value
 
-    def amr_coarse_step(self, hier, bufs, mask, dt0, flux_reg, use_graph=False):
+    def amr_coarse_step(self, hier, bufs, mask, dt0, flux_reg, use_graph=False, t0=0.0, global_step=False):
+        """One coarse step dt0 from time t0: subcycled (default) or, with
+        global_step, one step dt0 of every level at once."""
         mk = ctypes.c_uint32(mask)
-        check(_lib.load().af_amr_coarse_step(self.h, hier.h, self._pair(bufs), ctypes.byref(mk), float(dt0),
-                                             _ptr(flux_reg), int(bool(use_graph)), _stream()))
+        flags = (STEP_GRAPH if use_graph else 0) | (STEP_GLOBAL if global_step else 0)
+        check(_lib.load().af_amr_coarse_step(self.h, hier.h, self._pair(bufs), ctypes.byref(mk), float(t0),
+                                             float(dt0), _ptr(flux_reg), int(flags), _stream()))
         return mk.value
 
 

@@ -83,7 +83,7 @@ def load():
     L.af_hier_side_relations.argtypes = [P, P]
     L.af_hier_side_mask.argtypes = [P]
     L.af_hier_side_mask.restype = P
-    L.af_patch_step.argtypes = [P, S, S, i32, i32, i32, D, i32, P, P, P, P]
+    L.af_patch_step.argtypes = [P, S, S, i32, i32, i32, D, D, i32, P, P, P, P]
     L.af_hier_leaf_xy.argtypes = [P]
     L.af_hier_leaf_xy.restype = P
     L.af_ghost_fill.argtypes = [P, P, S, ctypes.c_uint32, i32, i32, P]
@@ -92,7 +92,7 @@ def load():
     L.af_hier_regrid.argtypes = [P, P, P, ctypes.POINTER(P)]
     L.af_regrid_apply.argtypes = [P, P, S, ctypes.c_uint32, P, S, P]
     L.af_reduce_sum.argtypes = [P, P, S, ctypes.c_uint32, P, P]
-    L.af_amr_coarse_step.argtypes = [P, P, S, ctypes.POINTER(ctypes.c_uint32), D, P, i32, P]
+    L.af_amr_coarse_step.argtypes = [P, P, S, ctypes.POINTER(ctypes.c_uint32), D, D, P, i32, P]
     L.af_level_advance.argtypes = [P, P, S, ctypes.POINTER(ctypes.c_uint32), i32, D, i32, P]
     L.af_ctx_advance_shapes.argtypes = [P, P, P, i32]
     L.af_ctx_advance_shapes.restype = i32

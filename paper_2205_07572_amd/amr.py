@@ -47,6 +47,7 @@ class AMRRun:
         self.hier = Hierarchy(self.ctx, leaves)
         self.capacity = capacity or max(len(leaves), 64)
         self.block_fn = block_fn  # (level, ix, iy) -> block dict (initial data)
+        self.time = 0.0  # time of the synchronised state (time-dependent fields)
         self._alloc(self.capacity)
         self._load_blocks([block_fn(*l) for l in self.hier.leaves()])
         self.stats = AMRStats()
@@ -85,7 +86,9 @@ class AMRRun:
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(n):
-            self.mask = self.ctx.amr_coarse_step(self.hier, self.bufs, self.mask, dt0, self.reg, use_graph)
+            self.mask = self.ctx.amr_coarse_step(self.hier, self.bufs, self.mask, dt0, self.reg, use_graph,
+                                                 t0=self.time)
+            self.time += dt0
         e1.record()
         torch.cuda.synchronize()
         self.stats.step_seconds += e0.elapsed_time(e1) * 1e-3

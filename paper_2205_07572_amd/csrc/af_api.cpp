@@ -59,14 +59,18 @@ struct af_ctx {
   size_t elem() const { return fp32() ? 4 : 8; }
 };
 
+constexpr size_t kMaxGraphs = 64;  // executable graphs kept per hierarchy
+
 struct GraphKey {
   uint32_t mask;
   double dt0;
   const void* b0;
   const void* b1;
   const double* reg;
+  double t0;    // only for time-dependent fields (else 0)
+  int32_t flags;
   bool operator<(const GraphKey& o) const {
-    return std::tie(mask, dt0, b0, b1, reg) < std::tie(o.mask, o.dt0, o.b0, o.b1, o.reg);
+    return std::tie(mask, dt0, b0, b1, reg, t0, flags) < std::tie(o.mask, o.dt0, o.b0, o.b1, o.reg, o.t0, o.flags);
   }
 };
 
@@ -124,6 +128,10 @@ af_status check_cfl(const af_ctx* c, int level, double dt) {
   if (c->P.eq == AF_ADVECTION) {
     const double cfl = std::max(std::fabs(c->P.a) * dt / dx, std::fabs(c->P.b) * dt / dy);
     if (cfl > 1.0 + 1e-12) return fail(AF_ERR_CFL, "advection CFL > 1 (eq. cfl-adv)");
+  } else if (c->P.eq == AF_SWIRL) {
+    // |a|, |b| <= max |grad Psi| = 1 (centred differences of Psi keep the bound)
+    const double cfl = std::max(dt / dx, dt / dy);
+    if (cfl > 1.0 + 1e-12) return fail(AF_ERR_CFL, "swirl CFL > 1 (eq. cfl-adv with |a|, |b| <= 1)");
   } else if (c->P.eq == AF_ROTATION) {
     // largest |a| = |omega| |y - yc| and |b| = |omega| |x - xc| on the domain
     const double w = std::fabs(c->P.omega);
@@ -244,7 +252,8 @@ const char* af_last_error(void) { return g_err.c_str(); }
 af_status af_ctx_create(const af_problem* prob, af_ctx** out) {
   if (!prob || !out) return fail(AF_ERR_ARG, "null argument");
   const af_problem& P = *prob;
-  if (P.eq != AF_ADVECTION && P.eq != AF_ACOUSTICS && P.eq != AF_ROTATION) return fail(AF_ERR_ARG, "unknown equation");
+  if (P.eq != AF_ADVECTION && P.eq != AF_ACOUSTICS && P.eq != AF_ROTATION && P.eq != AF_SWIRL)
+    return fail(AF_ERR_ARG, "unknown equation");
   if (P.eq == AF_ROTATION && !(std::isfinite(P.omega) && std::isfinite(P.xc) && std::isfinite(P.yc)))
     return fail(AF_ERR_ARG, "rotation parameters must be finite");
   if (P.prec != AF_FP64 && P.prec != AF_FP32) return fail(AF_ERR_ARG, "unknown precision");
@@ -397,8 +406,8 @@ const int32_t* af_hier_leaf_xy(const af_hier* h) {
 // ----------------------------------------------------------------- step
 
 af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t first, int32_t count,
-                        int32_t level, double dt, int32_t region, double* flux_reg, const uint8_t* side_mask,
-                        const int32_t* leaf_xy, hipStream_t stream) {
+                        int32_t level, double dt, double t, int32_t region, double* flux_reg,
+                        const uint8_t* side_mask, const int32_t* leaf_xy, hipStream_t stream) {
   if (!ctx) return fail(AF_ERR_ARG, "null ctx");
   if (count < 0 || first < 0) return fail(AF_ERR_ARG, "negative patch range");
   if (region != AF_REGION_INTERIOR && region != AF_REGION_LAYER1) return fail(AF_ERR_ARG, "bad region");
@@ -413,12 +422,16 @@ af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t 
     if (in->dof[k] == out->dof[k]) return fail(AF_ERR_ARG, "af_patch_step: in and out must be distinct");
   s = check_cfl(ctx, level, dt);
   if (s != AF_OK) return s;
-  if (ctx->P.eq == AF_ROTATION && !leaf_xy) return fail(AF_ERR_ARG, "af_patch_step: rotation needs leaf_xy");
+  if ((ctx->P.eq == AF_ROTATION || ctx->P.eq == AF_SWIRL) && !leaf_xy)
+    return fail(AF_ERR_ARG, "af_patch_step: rotation and swirl need leaf_xy");
+  if (!std::isfinite(t)) return fail(AF_ERR_ARG, "af_patch_step: t must be finite");
   if (count == 0) return AF_OK;
   const double dx = ctx->dx(level), dy = ctx->dy(level);
   StepLaunch L;
   RotParams<float> rp32;
   RotParams<double> rp64;
+  SwirlParams<float> sp32;
+  SwirlParams<double> sp64;
   L.fp32 = ctx->fp32();
   L.eq = ctx->P.eq;
   L.m = ctx->P.m;
@@ -456,6 +469,27 @@ af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t 
     rp32.x0 = float(rp64.x0); rp32.y0 = float(rp64.y0); rp32.dx = float(dx); rp32.dy = float(dy);
     rp32.omega = float(rp64.omega); rp32.xc = float(rp64.xc); rp32.yc = float(rp64.yc);
     L.weights = ctx->fp32() ? static_cast<const void*>(&rp32) : static_cast<const void*>(&rp64);
+  } else if (ctx->P.eq == AF_SWIRL) {
+    // cos(pi s) at every time the step needs, formed as the traces form them
+    // (t + tau, then stage offsets -tau/2, -tau)
+    constexpr double kPi = 3.14159265358979323846264338327950288;
+    const double tau[2] = {0.5 * dt, dt};
+    for (int k = 0; k < 2; ++k) {
+      const double t1 = t + tau[k], hh = -tau[k];
+      sp64.tau[k] = tau[k];
+      sp64.cos_rk[k][0] = std::cos(kPi * t1);
+      sp64.cos_rk[k][1] = std::cos(kPi * (t1 + 0.5 * hh));
+      sp64.cos_rk[k][2] = std::cos(kPi * (t1 + hh));
+    }
+    for (int k = 0; k < 3; ++k) sp64.cos_fx[k] = std::cos(kPi * (t + 0.5 * k * dt));
+    sp64.x0 = ctx->P.x0; sp64.y0 = ctx->P.y0; sp64.dx = dx; sp64.dy = dy;
+    sp32.x0 = float(sp64.x0); sp32.y0 = float(sp64.y0); sp32.dx = float(dx); sp32.dy = float(dy);
+    for (int k = 0; k < 2; ++k) {
+      sp32.tau[k] = float(sp64.tau[k]);
+      for (int q = 0; q < 3; ++q) sp32.cos_rk[k][q] = float(sp64.cos_rk[k][q]);
+    }
+    for (int k = 0; k < 3; ++k) sp32.cos_fx[k] = float(sp64.cos_fx[k]);
+    L.weights = ctx->fp32() ? static_cast<const void*>(&sp32) : static_cast<const void*>(&sp64);
   } else {
     L.weights = weights_for(ctx, dt / dx, dt / dy);
   }
@@ -841,7 +875,8 @@ af_status af_autotune(af_ctx* ctx, af_hier* h, af_state* bufs, int32_t level, do
     ctx->ty = ty;
     double us;
     s = timed([&]() {
-          return af_patch_step(ctx, &bufs[0], &bufs[1], first, count, level, dt, 0, nullptr, nullptr, h->d_xy, stream);
+          return af_patch_step(ctx, &bufs[0], &bufs[1], first, count, level, dt, 0.0, 0, nullptr, nullptr, h->d_xy,
+                               stream);
         },
               &us);
     if (s != AF_OK) break;
@@ -890,25 +925,25 @@ struct Driver {
   double* reg;
   hipStream_t st;
 
-  af_status step_level(int l, double dt, int region) {
+  af_status step_level(int l, double t, double dt, int region) {
     int first, count;
     af_hier_level_range(h, l, &first, &count);
     const int cur = (mask >> l) & 1;
     // an empty level still flips, so that the mask after a coarse step is
-    // always "bit 0 flipped"
+    // always "bit 0 flipped" (subcycled) or "bits 0..finest flipped" (global)
     mask ^= (1u << l);
     if (count == 0) return AF_OK;
-    return af_patch_step(ctx, &bufs[cur], &bufs[cur ^ 1], first, count, l, dt, region, reg,
+    return af_patch_step(ctx, &bufs[cur], &bufs[cur ^ 1], first, count, l, dt, t, region, reg,
                          h->d_side_mask, h->d_xy, st);
   }
 
-  af_status advance(int l, double dt, bool first_of_pair, int finest) {
-    af_status s = step_level(l, dt, (l > 0 && first_of_pair) ? AF_REGION_LAYER1 : AF_REGION_INTERIOR);
+  af_status advance(int l, double t, double dt, bool first_of_pair, int finest) {
+    af_status s = step_level(l, t, dt, (l > 0 && first_of_pair) ? AF_REGION_LAYER1 : AF_REGION_INTERIOR);
     if (s != AF_OK) return s;
     if (l + 1 <= finest) {
-      if ((s = advance(l + 1, 0.5 * dt, true, finest)) != AF_OK) return s;
+      if ((s = advance(l + 1, t, 0.5 * dt, true, finest)) != AF_OK) return s;
       if ((s = af_ghost_fill(ctx, h, bufs, mask, l + 1, l + 1, st)) != AF_OK) return s;
-      if ((s = advance(l + 1, 0.5 * dt, false, finest)) != AF_OK) return s;
+      if ((s = advance(l + 1, t + 0.5 * dt, 0.5 * dt, false, finest)) != AF_OK) return s;
       int first, count;
       af_hier_level_range(h, l, &first, &count);
       if (count) {
@@ -918,36 +953,68 @@ struct Driver {
     return AF_OK;
   }
 
-  af_status coarse_step(double dt0) {
+  af_status coarse_step(double t0, double dt0) {
     af_status s = af_ghost_fill(ctx, h, bufs, mask, 0, 0, st);
     if (s != AF_OK) return s;
-    return advance(0, dt0, true, h->H.finest);
+    return advance(0, t0, dt0, true, h->H.finest);
+  }
+
+  // Global time stepping: every level steps its interior from the same
+  // synchronised state, then every coarse level takes the fine fluxes.
+  af_status global_step(double t0, double dt) {
+    af_status s = af_ghost_fill(ctx, h, bufs, mask, 0, 0, st);
+    if (s != AF_OK) return s;
+    for (int l = 0; l <= h->H.finest; ++l)
+      if ((s = step_level(l, t0, dt, AF_REGION_INTERIOR)) != AF_OK) return s;
+    for (int l = 0; l < h->H.finest; ++l) {
+      int first, count;
+      af_hier_level_range(h, l, &first, &count);
+      if (count && (s = af_flux_correct(ctx, h, bufs, mask, l, reg, st)) != AF_OK) return s;
+    }
+    return AF_OK;
+  }
+
+  af_status run(int32_t flags, double t0, double dt0) {
+    return (flags & AF_STEP_GLOBAL) ? global_step(t0, dt0) : coarse_step(t0, dt0);
   }
 };
 
 }  // namespace
 
-af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* mask, double dt0, double* flux_reg,
-                             int32_t use_graph, hipStream_t stream) {
+af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* mask, double t0, double dt0,
+                             double* flux_reg, int32_t flags, hipStream_t stream) {
   if (!ctx || !h || !mask || !flux_reg) return fail(AF_ERR_ARG, "null argument");
   af_status s = check_pair(ctx, h, bufs, "af_amr_coarse_step");
   if (s != AF_OK) return s;
-  // every level's CFL is that of level 0 (dt_l / dx_l fixed)
-  s = check_cfl(ctx, 0, dt0);
+  if (flags & ~(AF_STEP_GRAPH | AF_STEP_GLOBAL)) return fail(AF_ERR_ARG, "unknown flags");
+  if (!std::isfinite(t0)) return fail(AF_ERR_ARG, "t0 must be finite");
+  const bool global = flags & AF_STEP_GLOBAL;
+  // subcycled: every level's CFL is that of level 0 (dt_l / dx_l fixed);
+  // global: the finest level's
+  s = check_cfl(ctx, global ? h->H.finest : 0, dt0);
   if (s != AF_OK) return s;
   if ((s = ctx_device(ctx)) != AF_OK || (s = hier_device(h)) != AF_OK) return s;
   Driver D{ctx, h, bufs, *mask, flux_reg, stream};
-  if (!use_graph) {
-    s = D.coarse_step(dt0);
+  if (!(flags & AF_STEP_GRAPH)) {
+    s = D.run(flags, t0, dt0);
     if (s == AF_OK) *mask = D.mask;
     return s;
   }
-  const GraphKey key{*mask, dt0, bufs[0].dof[0], bufs[1].dof[0], flux_reg};
+  const GraphKey key{*mask, dt0, bufs[0].dof[0], bufs[1].dof[0], flux_reg, ctx->P.eq == AF_SWIRL ? t0 : 0.0,
+                     flags};
   auto it = h->graphs.find(key);
   if (it == h->graphs.end()) {
+    // a time-dependent field keys its graphs by t0 as well, so the cache is
+    // bounded: when full, drain the stream and start over
+    if (h->graphs.size() >= kMaxGraphs) {
+      AF_HIP(hipStreamSynchronize(stream));
+      for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
+      h->graphs.clear();
+    }
     // weights and fill plans are made outside the capture
     for (int l = 0; l <= h->H.finest; ++l) {
-      weights_for(ctx, dt0 / (1 << l) / ctx->dx(l), dt0 / (1 << l) / ctx->dy(l));
+      const double dtl = global ? dt0 : dt0 / (1 << l);
+      if (ctx->P.eq == AF_ADVECTION || ctx->P.eq == AF_ACOUSTICS) weights_for(ctx, dtl / ctx->dx(l), dtl / ctx->dy(l));
       if ((s = fill_plan(ctx, h, l, stream)) != AF_OK) return s;
     }
     hipStream_t cs;
@@ -959,7 +1026,7 @@ af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* 
       return fail(AF_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(e));
     }
     Driver G{ctx, h, bufs, *mask, flux_reg, cs};
-    s = G.coarse_step(dt0);
+    s = G.run(flags, t0, dt0);
     e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);
     if (s != AF_OK) return s;
@@ -971,9 +1038,9 @@ af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* 
     it = h->graphs.emplace(key, ex).first;
   }
   AF_HIP(hipGraphLaunch(it->second, stream));
-  // the mask after a coarse step: level 0 flips, finer levels take an even
-  // number of steps
-  *mask ^= 1u;
+  // the mask after a coarse step: subcycled, level 0 flips and finer levels
+  // take an even number of steps; global, every level up to the finest flips
+  *mask ^= global ? ((2u << h->H.finest) - 1u) : 1u;
   return AF_OK;
 }
 

@@ -94,6 +94,17 @@ struct RotParams {
   T omega, xc, yc;    // a = -omega (y - yc), b = omega (x - xc)
 };
 
+// Swirl flow (Sec. 4.3) for one step starting at time t: the velocity is the
+// centred difference of Psi = sin^2(pi x) sin^2(pi y) cos(pi s) / pi over one
+// cell; cos(pi s) is supplied for every time the step needs.
+template <typename T>
+struct SwirlParams {
+  T x0, y0, dx, dy;  // domain origin, cell size of the level
+  T tau[2];          // dt/2, dt: the two traces back to t
+  T cos_rk[2][3];    // cos(pi s) at the Runge-Kutta times t+tau, t+tau/2, t of each trace
+  T cos_fx[3];       // cos(pi s) at t, t+dt/2, t+dt (Simpson times of the fluxes)
+};
+
 // Ghost-fill plan: one op per fill-set DOF of every leaf, holding the source
 // that the fill rules resolve to for a given lower bound on source levels.
 //   x: source leaf, or -1 for "keep the target's own value"

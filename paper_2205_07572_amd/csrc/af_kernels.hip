@@ -84,10 +84,11 @@ __device__ __forceinline__ void gather_block(T* lds, Src src) {
   }
 }
 
-template <typename T, int NCOMP, int NR, int NC>
+template <typename T, int NCOMP, int NR, int NC, int NT2>
 struct StepLds {
   T in[4][NCOMP][NR][NC];
-  T tsum[3][NCOMP][NR - 2][NC - 2];
+  T tsum[3][NCOMP][NR - 2][NC - 2];   // time sums; for the swirl the values at t+dt/2
+  T tsum2[NT2][NCOMP][NR - 2][NC - 2];  // swirl: the values at t+dt
 };
 
 // Simpson space-time sum of one face from the time sums of its three nodes
@@ -169,6 +170,23 @@ template <typename T>
 struct WSel<T, 1> { using type = AcWeights<T>; };
 template <typename T>
 struct WSel<T, 2> { using type = RotParams<T>; };
+template <typename T>
+struct WSel<T, 3> { using type = SwirlParams<T>; };
+
+constexpr double kPiD = 3.14159265358979323846264338327950288;
+
+// Swirl stream function and velocity (Sec. 4.3, eq. swirlODE) with
+// c = cos(pi t): centred differences over one cell of the level.
+template <typename T>
+__device__ __forceinline__ T swirl_psi(T x, T y, T c) {
+  const T sx = sin(T(kPiD) * x), sy = sin(T(kPiD) * y);
+  return sx * sx * sy * sy * c / T(kPiD);
+}
+template <typename T>
+__device__ __forceinline__ void swirl_vel(const SwirlParams<T>& W, T x, T y, T c, T* a, T* b) {
+  *a = -(swirl_psi(x, y + T(0.5) * W.dy, c) - swirl_psi(x, y - T(0.5) * W.dy, c)) / W.dy;
+  *b = (swirl_psi(x + T(0.5) * W.dx, y, c) - swirl_psi(x - T(0.5) * W.dx, y, c)) / W.dx;
+}
 
 // Cell of a foot at coordinate s (cell units: cell k spans [k-1/2, k+1/2])
 // and the reference coordinate in it; a foot on a face goes to the cell
@@ -210,7 +228,7 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
   constexpr int NCOMP = EQ == 1 ? 3 : 1;
   constexpr int NR = TY + 3;
   constexpr int NC = M + 5;
-  __shared__ StepLds<T, NCOMP, NR, NC> L;
+  __shared__ StepLds<T, NCOMP, NR, NC, EQ == 3 ? 3 : 1> L;
 
   const int region = A.region;
   const int ilo = -region, ihi = M + region;
@@ -239,9 +257,9 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
   });
   __syncthreads();
   const int coff = ilo + 2;  // staged column of cell i is i + 2 = ii + coff
-  // rotation: lower-left corner of the patch's cell (0,0)
+  // rotation, swirl: lower-left corner of the patch's cell (0,0)
   T px0 = T(0), py0 = T(0);
-  if constexpr (EQ == 2) {
+  if constexpr (EQ == 2 || EQ == 3) {
     px0 = W.x0 + T(A.leaf_xy[2 * patch] * M) * W.dx;
     py0 = W.y0 + T(A.leaf_xy[2 * patch + 1] * M) * W.dy;
   }
@@ -279,9 +297,11 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
         L.tsum[kind][0][jj][ii] = (cur + T(4) * h) + f;
         if (wrow) A.out[kind + 1][size_t(patch) * plane + obase] = f;
       }
-    } else if constexpr (EQ == 2) {
-      // solid-body rotation (Sec. 4.2): the node turned back by -omega tau
-      // about (xc, yc) is the foot; q^n there from its cell's reconstruction
+    } else if constexpr (EQ == 2 || EQ == 3) {
+      // solid-body rotation (Sec. 4.2): the foot is the node turned back by
+      // -omega tau about (xc, yc); swirl (Sec. 4.3): one classical Runge-Kutta
+      // step back along the characteristic.  q^n there from its cell's
+      // reconstruction.
 #pragma unroll
       for (int kind = 0; kind < 3; ++kind) {
         if (kind == NK_XEDGE && !has_x) continue;
@@ -289,12 +309,24 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
         const T X = kind == NK_YEDGE ? T(i) : T(i) - T(0.5);  // node in cell units
         const T Y = kind == NK_XEDGE ? T(j) : T(j) - T(0.5);
         const T x = px0 + (X + T(0.5)) * W.dx, y = py0 + (Y + T(0.5)) * W.dy;
-        const T rx = x - W.xc, ry = y - W.yc;
         T val[2];
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-          const T fx = W.xc + rx * W.cs[t] + ry * W.sn[t];
-          const T fy = W.yc - rx * W.sn[t] + ry * W.cs[t];
+          T fx, fy;
+          if constexpr (EQ == 2) {
+            const T rx = x - W.xc, ry = y - W.yc;
+            fx = W.xc + rx * W.cs[t] + ry * W.sn[t];
+            fy = W.yc - rx * W.sn[t] + ry * W.cs[t];
+          } else {
+            const T h = -W.tau[t];
+            T a1, b1, a2, b2, a3, b3, a4, b4;
+            swirl_vel(W, x, y, W.cos_rk[t][0], &a1, &b1);
+            swirl_vel(W, x + T(0.5) * h * a1, y + T(0.5) * h * b1, W.cos_rk[t][1], &a2, &b2);
+            swirl_vel(W, x + T(0.5) * h * a2, y + T(0.5) * h * b2, W.cos_rk[t][1], &a3, &b3);
+            swirl_vel(W, x + h * a3, y + h * b3, W.cos_rk[t][2], &a4, &b4);
+            fx = x + h / T(6) * (a1 + T(2) * a2 + T(2) * a3 + a4);
+            fy = y + h / T(6) * (b1 + T(2) * b2 + T(2) * b3 + b4);
+          }
           const T sx = (fx - px0) / W.dx - T(0.5), sy = (fy - py0) / W.dy - T(0.5);
           // source cell, kept in the range a Courant number <= 1 allows
           // (the halo holds it): nodes on x-faces i-1..i, else i-1..i+1
@@ -303,8 +335,13 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
           cj = min(max(cj, j - 1), kind == NK_XEDGE ? j + 1 : j);
           val[t] = rot_eval<T, NR, NC>(L.in, r + (cj - j), c + (ci - i), T(2) * (sx - T(ci)), T(2) * (sy - T(cj)));
         }
-        const T cur = L.in[kind + 1][0][r][c];
-        L.tsum[kind][0][jj][ii] = (cur + T(4) * val[0]) + val[1];
+        if constexpr (EQ == 2) {
+          const T cur = L.in[kind + 1][0][r][c];
+          L.tsum[kind][0][jj][ii] = (cur + T(4) * val[0]) + val[1];
+        } else {
+          L.tsum[kind][0][jj][ii] = val[0];
+          L.tsum2[kind][0][jj][ii] = val[1];
+        }
         if (wrow) A.out[kind + 1][size_t(patch) * plane + obase] = val[1];
       }
     } else {
@@ -358,6 +395,39 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
     if constexpr (EQ == 0) {
       fL[0] = A.a * FL[0] * inv36; fR[0] = A.a * FR[0] * inv36;
       gB[0] = A.b * GB[0] * inv36; gT[0] = A.b * GT[0] * inv36;
+    } else if constexpr (EQ == 3) {
+      // swirl (eq. swirlF, swirlG): the face-midpoint velocity at t, t+dt/2,
+      // t+dt times the Simpson sum of the three nodes at that time
+      const int rr = jj + 1, cc = ii + coff;  // staged position of cell (i, j)
+      const auto& Q0 = L.in;
+      const auto& Qh = L.tsum;
+      const auto& Qf = L.tsum2;
+      const T xl = px0 + T(i) * W.dx, xr = px0 + T(i + 1) * W.dx, xm = px0 + (T(i) + T(0.5)) * W.dx;
+      const T yb = py0 + T(j) * W.dy, yt = py0 + T(j + 1) * W.dy, ym = py0 + (T(j) + T(0.5)) * W.dy;
+      T aL[3], aR[3], bB[3], bT[3], unused;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        swirl_vel(W, xl, ym, W.cos_fx[k], &aL[k], &unused);
+        swirl_vel(W, xr, ym, W.cos_fx[k], &aR[k], &unused);
+        swirl_vel(W, xm, yb, W.cos_fx[k], &unused, &bB[k]);
+        swirl_vel(W, xm, yt, W.cos_fx[k], &unused, &bT[k]);
+      }
+      const T SL[3] = {face_sum(Q0[1][0][rr][cc], Q0[2][0][rr][cc], Q0[1][0][rr + 1][cc]),
+                       face_sum(Qh[NK_CORNER][0][jj][ii], Qh[NK_XEDGE][0][jj][ii], Qh[NK_CORNER][0][jj + 1][ii]),
+                       face_sum(Qf[NK_CORNER][0][jj][ii], Qf[NK_XEDGE][0][jj][ii], Qf[NK_CORNER][0][jj + 1][ii])};
+      const T SR[3] = {face_sum(Q0[1][0][rr][cc + 1], Q0[2][0][rr][cc + 1], Q0[1][0][rr + 1][cc + 1]),
+                       face_sum(Qh[NK_CORNER][0][jj][ii + 1], Qh[NK_XEDGE][0][jj][ii + 1], Qh[NK_CORNER][0][jj + 1][ii + 1]),
+                       face_sum(Qf[NK_CORNER][0][jj][ii + 1], Qf[NK_XEDGE][0][jj][ii + 1], Qf[NK_CORNER][0][jj + 1][ii + 1])};
+      const T SB[3] = {face_sum(Q0[1][0][rr][cc], Q0[3][0][rr][cc], Q0[1][0][rr][cc + 1]),
+                       face_sum(Qh[NK_CORNER][0][jj][ii], Qh[NK_YEDGE][0][jj][ii], Qh[NK_CORNER][0][jj][ii + 1]),
+                       face_sum(Qf[NK_CORNER][0][jj][ii], Qf[NK_YEDGE][0][jj][ii], Qf[NK_CORNER][0][jj][ii + 1])};
+      const T ST[3] = {face_sum(Q0[1][0][rr + 1][cc], Q0[3][0][rr + 1][cc], Q0[1][0][rr + 1][cc + 1]),
+                       face_sum(Qh[NK_CORNER][0][jj + 1][ii], Qh[NK_YEDGE][0][jj + 1][ii], Qh[NK_CORNER][0][jj + 1][ii + 1]),
+                       face_sum(Qf[NK_CORNER][0][jj + 1][ii], Qf[NK_YEDGE][0][jj + 1][ii], Qf[NK_CORNER][0][jj + 1][ii + 1])};
+      fL[0] = (aL[0] * SL[0] + T(4) * aL[1] * SL[1] + aL[2] * SL[2]) * inv36;
+      fR[0] = (aR[0] * SR[0] + T(4) * aR[1] * SR[1] + aR[2] * SR[2]) * inv36;
+      gB[0] = (bB[0] * SB[0] + T(4) * bB[1] * SB[1] + bB[2] * SB[2]) * inv36;
+      gT[0] = (bT[0] * ST[0] + T(4) * bT[1] * ST[1] + bT[2] * ST[2]) * inv36;
     } else if constexpr (EQ == 2) {
       // rotation: f = a(node) q with a = -omega (y - yc) on x-faces (a depends
       // on y only) and g = b(node) q with b = omega (x - xc) on y-faces
@@ -1285,6 +1355,7 @@ hipError_t launch_patch_step(const StepLaunch& s, hipStream_t st) {
     case 0: return s.fp32 ? launch_step_m<float, 0>(s, st) : launch_step_m<double, 0>(s, st);
     case 1: return s.fp32 ? launch_step_m<float, 1>(s, st) : launch_step_m<double, 1>(s, st);
     case 2: return s.fp32 ? launch_step_m<float, 2>(s, st) : launch_step_m<double, 2>(s, st);
+    case 3: return s.fp32 ? launch_step_m<float, 3>(s, st) : launch_step_m<double, 3>(s, st);
     default: return hipErrorInvalidValue;
   }
 }
