@@ -330,6 +330,82 @@ def rotation_runs():
     return out
 
 
+def swirl_runs():
+    """Swirl flow of Sec. 4.3 (Psi = sin^2(pi x) sin^2(pi y) cos(pi t) / pi on
+    the periodic unit square, the two Gaussians of eq. id_swirl) to t = 1 at
+    Courant number 0.6 of the largest speed (1): uniform levels 4, 5 and 6
+    (256^2 to 1024^2 cells as 32^2 patches) in FP64 and FP32, and the
+    diagonal refinement 3-4 (128^2 with the diagonal patches at 256^2, 16^2
+    patches) with subcycling and with global time stepping.  Reports
+    cell-updates/s of the general path (ghost fill + patch step per step) and
+    the L1 error of the averages against the initial data (the exact solution
+    at t = 1), next to the paper's Table 3."""
+    import math
+    import torch
+    import afsynth
+    import paper_2205_07572_amd as af
+    paper = {4: 5.722927e-06, 5: 7.268088e-07}
+    data = afsynth.swirl_gaussians()
+    out = {}
+
+    def run(prec, m, n0, lmax, leaves, n, dt, global_step):
+        prob = af.Problem(eq=af.SWIRL, prec=prec, m=m, n0x=n0, n0y=n0, lmax=lmax)
+        ctx = af.Context(prob)
+        h = af.Hierarchy(ctx, leaves)
+        blocks = []
+        for (l, ix, iy) in leaves:
+            dx = prob.dx(l)
+            blocks.append(afsynth.dofs_block(data, m, 2, ix * m * dx, iy * m * dx, dx, dx, 4))
+        b0 = af.blocks_to_state(ctx, blocks)
+        bufs = [b0, torch.zeros_like(b0)]
+        reg = torch.zeros((len(leaves), 4, m, 1), dtype=torch.float64, device="cuda")
+        ctx.ghost_fill(h, bufs, 0, 0, 0)
+
+        def steps():
+            mask = 0
+            for k in range(n):
+                mask = ctx.amr_coarse_step(h, bufs, mask, dt, reg, t0=k * dt, global_step=global_step)
+            return mask
+
+        ms, mask = _event_ms(steps)
+        got = af.state_to_blocks(ctx, bufs[0]), af.state_to_blocks(ctx, bufs[1])
+        l1, updates = 0.0, 0
+        for k, (l, ix, iy) in enumerate(leaves):
+            b = got[(mask >> l) & 1][k]["avg"][0, 2:2 + m, 2:2 + m]
+            l1 += float(np.abs(b - blocks[k]["avg"][0, 2:2 + m, 2:2 + m]).sum()) * prob.dx(l) ** 2
+            updates += m * m * n * (1 if global_step else 1 << l)
+        del bufs, b0
+        torch.cuda.empty_cache()
+        return ms, l1, updates
+
+    for level in (4, 5, 6):
+        N, m = 16 << level, 32
+        n0 = N // m
+        n = math.ceil(1.0 / (0.6 / N))
+        res = {}
+        for pname, prec in (("fp64", af.FP64), ("fp32", af.FP32)):
+            ms, l1, upd = run(prec, m, n0, 0, afsynth.uniform_leaves(n0, n0, 0), n, 1.0 / n, False)
+            res[pname] = {"steps": n, "ms": ms, "cell_updates_per_s": upd / (ms * 1e-3), "l1": l1}
+            if level in paper:
+                res[pname]["l1_over_paper"] = l1 / paper[level]
+            print(f"[bench] swirl level {level} ({N}^2) {pname}: {n} steps in {ms:.1f} ms, "
+                  f"{res[pname]['cell_updates_per_s']:.3e} cell-updates/s, L1 {l1:.4e}", file=sys.stderr,
+                  flush=True)
+        out[f"level{level}"] = res
+    out["eoc_4_5_fp64"] = math.log2(out["level4"]["fp64"]["l1"] / out["level5"]["fp64"]["l1"])
+    out["paper_eoc_4_5"] = 2.9771
+    m, n0 = 16, 8  # level 3 = 128^2 cells
+    leaves = afsynth.diagonal_leaves(n0, 0)
+    for mode, glob in (("subcycled", False), ("global", True)):
+        n = math.ceil(1.0 / (0.6 / (n0 * m * (2 if glob else 1))))
+        ms, l1, upd = run(af.FP64, m, n0, 1, leaves, n, 1.0 / n, glob)
+        out[f"diag3_4_{mode}_fp64"] = {"steps": n, "ms": ms, "cell_updates_per_s": upd / (ms * 1e-3), "l1": l1}
+        print(f"[bench] swirl diagonal 3-4 {mode}: {n} coarse steps in {ms:.1f} ms, L1 {l1:.4e}", file=sys.stderr,
+              flush=True)
+    out["paper_amr_3_4"] = {"subcycled": 5.758274e-06, "global": 5.724930e-06}
+    return out
+
+
 def _rot_steps(ctx, h, bufs, reg, n, dt):
     mask = 0
     for _ in range(n):
@@ -470,6 +546,7 @@ def main():
     if not args.no_amr:
         line["amr"] = amr_runs()
         line["rotation"] = rotation_runs()
+        line["swirl"] = swirl_runs()
     if not args.no_cpu:
         v, el = cpu_baseline(data, args.cpu_steps, dt)
         line["cpu_baseline"] = {"value": v, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",

@@ -483,7 +483,10 @@ af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t 
     }
     for (int k = 0; k < 3; ++k) sp64.cos_fx[k] = std::cos(kPi * (t + 0.5 * k * dt));
     sp64.x0 = ctx->P.x0; sp64.y0 = ctx->P.y0; sp64.dx = dx; sp64.dy = dy;
+    sp64.kx = std::sin(kPi * dx) / (kPi * dx);
+    sp64.ky = std::sin(kPi * dy) / (kPi * dy);
     sp32.x0 = float(sp64.x0); sp32.y0 = float(sp64.y0); sp32.dx = float(dx); sp32.dy = float(dy);
+    sp32.kx = float(sp64.kx); sp32.ky = float(sp64.ky);
     for (int k = 0; k < 2; ++k) {
       sp32.tau[k] = float(sp64.tau[k]);
       for (int q = 0; q < 3; ++q) sp32.cos_rk[k][q] = float(sp64.cos_rk[k][q]);

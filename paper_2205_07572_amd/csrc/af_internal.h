@@ -100,6 +100,7 @@ struct RotParams {
 template <typename T>
 struct SwirlParams {
   T x0, y0, dx, dy;  // domain origin, cell size of the level
+  T kx, ky;          // sin(pi dx) / (pi dx), sin(pi dy) / (pi dy)
   T tau[2];          // dt/2, dt: the two traces back to t
   T cos_rk[2][3];    // cos(pi s) at the Runge-Kutta times t+tau, t+tau/2, t of each trace
   T cos_fx[3];       // cos(pi s) at t, t+dt/2, t+dt (Simpson times of the fluxes)

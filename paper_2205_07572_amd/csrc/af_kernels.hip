@@ -175,17 +175,24 @@ struct WSel<T, 3> { using type = SwirlParams<T>; };
 
 constexpr double kPiD = 3.14159265358979323846264338327950288;
 
-// Swirl stream function and velocity (Sec. 4.3, eq. swirlODE) with
-// c = cos(pi t): centred differences over one cell of the level.
-template <typename T>
-__device__ __forceinline__ T swirl_psi(T x, T y, T c) {
-  const T sx = sin(T(kPiD) * x), sy = sin(T(kPiD) * y);
-  return sx * sx * sy * sy * c / T(kPiD);
-}
+// Swirl velocity (Sec. 4.3, eq. swirlODE): centred differences over one
+// cell of the level of Psi = sin^2(pi x) sin^2(pi y) cos(pi t) / pi.  With
+// sin^2 A - sin^2 B = sin(A + B) sin(A - B) the differences are products,
+//   a = -cos(pi t) ky sin^2(pi x) sin(2 pi y),
+//   b =  cos(pi t) kx sin(2 pi x) sin^2(pi y),   k = sin(pi h) / (pi h),
+// the same numbers without the cancellation of the difference of two close
+// values (which costs FP32 about log10(1/h) digits) and with two sincospi
+// calls instead of eight sines.
+__device__ __forceinline__ void sincos_pi(float v, float* s, float* c) { sincospif(v, s, c); }
+__device__ __forceinline__ void sincos_pi(double v, double* s, double* c) { sincospi(v, s, c); }
+
 template <typename T>
 __device__ __forceinline__ void swirl_vel(const SwirlParams<T>& W, T x, T y, T c, T* a, T* b) {
-  *a = -(swirl_psi(x, y + T(0.5) * W.dy, c) - swirl_psi(x, y - T(0.5) * W.dy, c)) / W.dy;
-  *b = (swirl_psi(x + T(0.5) * W.dx, y, c) - swirl_psi(x - T(0.5) * W.dx, y, c)) / W.dx;
+  T sx, cx, sy, cy;
+  sincos_pi(x, &sx, &cx);
+  sincos_pi(y, &sy, &cy);
+  *a = -c * W.ky * (sx * sx) * (T(2) * sy * cy);
+  *b = c * W.kx * (T(2) * sx * cx) * (sy * sy);
 }
 
 // Cell of a foot at coordinate s (cell units: cell k spans [k-1/2, k+1/2])
@@ -404,13 +411,25 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
       const auto& Qf = L.tsum2;
       const T xl = px0 + T(i) * W.dx, xr = px0 + T(i + 1) * W.dx, xm = px0 + (T(i) + T(0.5)) * W.dx;
       const T yb = py0 + T(j) * W.dy, yt = py0 + T(j + 1) * W.dy, ym = py0 + (T(j) + T(0.5)) * W.dy;
-      T aL[3], aR[3], bB[3], bT[3], unused;
+      // the spatial factors of the face-midpoint velocities, then one
+      // cos(pi s) per Simpson time
+      T sxl, cxl, sxr, cxr, sxm, cxm, syb, cyb, syt, cyt, sym, cym;
+      sincos_pi(xl, &sxl, &cxl);
+      sincos_pi(xr, &sxr, &cxr);
+      sincos_pi(xm, &sxm, &cxm);
+      sincos_pi(yb, &syb, &cyb);
+      sincos_pi(yt, &syt, &cyt);
+      sincos_pi(ym, &sym, &cym);
+      const T s2ym = T(2) * sym * cym, s2xm = T(2) * sxm * cxm;
+      const T AL = -W.ky * (sxl * sxl) * s2ym, AR = -W.ky * (sxr * sxr) * s2ym;
+      const T BB = W.kx * s2xm * (syb * syb), BT = W.kx * s2xm * (syt * syt);
+      T aL[3], aR[3], bB[3], bT[3];
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        swirl_vel(W, xl, ym, W.cos_fx[k], &aL[k], &unused);
-        swirl_vel(W, xr, ym, W.cos_fx[k], &aR[k], &unused);
-        swirl_vel(W, xm, yb, W.cos_fx[k], &unused, &bB[k]);
-        swirl_vel(W, xm, yt, W.cos_fx[k], &unused, &bT[k]);
+        aL[k] = W.cos_fx[k] * AL;
+        aR[k] = W.cos_fx[k] * AR;
+        bB[k] = W.cos_fx[k] * BB;
+        bT[k] = W.cos_fx[k] * BT;
       }
       const T SL[3] = {face_sum(Q0[1][0][rr][cc], Q0[2][0][rr][cc], Q0[1][0][rr + 1][cc]),
                        face_sum(Qh[NK_CORNER][0][jj][ii], Qh[NK_XEDGE][0][jj][ii], Qh[NK_CORNER][0][jj + 1][ii]),
