@@ -403,6 +403,69 @@ def swirl_runs():
         print(f"[bench] swirl diagonal 3-4 {mode}: {n} coarse steps in {ms:.1f} ms, L1 {l1:.4e}", file=sys.stderr,
               flush=True)
     out["paper_amr_3_4"] = {"subcycled": 5.758274e-06, "global": 5.724930e-06}
+    out["adaptive"] = swirl_adaptive_runs(data)
+    return out
+
+
+def swirl_adaptive_runs(data):
+    """Adaptive swirl runs (Table 3, rows 3-4 and 3-5): base level 3
+    (8x8 patches of 16^2 = 128^2 cells), a patch refined where max - min of
+    its averages exceeds 0.001 (the criterion of Sec. 4.1) and coarsened below
+    it, regridded every coarse step (every 2^lmax global steps), FP64, to
+    t = 1 with CFL 0.6 on every level.  L1 error of the leaf averages against
+    the initial data (the exact solution at t = 1)."""
+    import math
+    import torch
+    import afsynth
+    import paper_2205_07572_amd as af
+    from paper_2205_07572_amd.amr import TagRule, initial_hierarchy
+    paper = {"subcycled": {1: 5.758274e-06, 2: 7.346642e-07}, "global": {1: 5.724930e-06, 2: 7.305236e-07}}
+    rule = TagRule(af.TAG_MAXMIN, 0, 1e-3, 1e-3)
+    m, n0 = 16, 8
+    out = {}
+    for lmax in (1, 2):
+        for mode in ("subcycled", "global"):
+            glob = mode == "global"
+            prob = af.Problem(eq=af.SWIRL, prec=af.FP64, m=m, n0x=n0, n0y=n0, lmax=lmax)
+
+            def block_fn(l, ix, iy, prob=prob):
+                dx = prob.dx(l)
+                return afsynth.dofs_block(data, m, 2, ix * m * dx, iy * m * dx, dx, dx, 4)
+
+            run = initial_hierarchy(prob, block_fn, rule)
+            n = math.ceil(1.0 / (0.6 * prob.dx(lmax if glob else 0)))
+            dt, every = 1.0 / n, (1 << lmax) if glob else 1
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            step = 0
+            while step < n:
+                k = min(every, n - step)
+                run.coarse_steps(dt, k, global_step=glob)
+                step += k
+                if step < n:
+                    run.regrid(rule)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            l1 = 0.0
+            for b, (l, ix, iy) in zip(run.blocks(), run.hier.leaves()):
+                ex = block_fn(l, ix, iy)["avg"][0, 2:2 + m, 2:2 + m]
+                l1 += float(np.abs(b["avg"][0, 2:2 + m, 2:2 + m] - ex).sum()) * prob.dx(l) ** 2
+            st = run.stats
+            hist = st.leaves_history
+            key = f"3-{3 + lmax}_{mode}"
+            out[key] = {"steps": st.coarse_steps, "regrids": st.regrids,
+                        "cell_updates_per_s": st.cell_updates / st.step_seconds, "time_to_solution_s": wall,
+                        "leaves_mean": float(np.mean(hist)) if hist else len(run.hier),
+                        "l1": l1, "l1_over_paper": l1 / paper[mode][lmax]}
+            print(f"[bench] swirl adaptive {key}: {st.coarse_steps} steps, {st.regrids} regrids, "
+                  f"{out[key]['cell_updates_per_s']:.3e} cell-updates/s, {wall:.2f} s to solution, leaves "
+                  f"{out[key]['leaves_mean']:.0f}, L1 {l1:.4e} ({out[key]['l1_over_paper']:.3f} x Table 3)",
+                  file=sys.stderr, flush=True)
+            del run
+            torch.cuda.empty_cache()
+    for mode in ("subcycled", "global"):
+        out[f"eoc_{mode}"] = math.log2(out[f"3-4_{mode}"]["l1"] / out[f"3-5_{mode}"]["l1"])
+    out["paper_eoc"] = {"subcycled": 2.9705, "global": 2.9703}
     return out
 
 

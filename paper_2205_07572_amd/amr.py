@@ -80,20 +80,24 @@ class AMRRun:
         m2 = self.prob.m ** 2
         return sum(m2 << l for l, _, _ in self.hier.leaves())
 
-    def coarse_steps(self, dt0, n, use_graph=False):
+    def coarse_steps(self, dt0, n, use_graph=False, global_step=False):
+        """n coarse steps of dt0 with subcycling, or with global_step n steps
+        of dt0 on every level at once (dt0 then bounded by the finest level's
+        CFL)."""
         torch = self.torch
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(n):
             self.mask = self.ctx.amr_coarse_step(self.hier, self.bufs, self.mask, dt0, self.reg, use_graph,
-                                                 t0=self.time)
+                                                 t0=self.time, global_step=global_step)
             self.time += dt0
         e1.record()
         torch.cuda.synchronize()
         self.stats.step_seconds += e0.elapsed_time(e1) * 1e-3
         self.stats.coarse_steps += n
-        self.stats.cell_updates += n * self.cell_updates_per_coarse_step()
+        per = len(self.hier) * self.prob.m ** 2 if global_step else self.cell_updates_per_coarse_step()
+        self.stats.cell_updates += n * per
 
     def total(self):
         out = self.torch.zeros(self.prob.ncomp, dtype=self.torch.float64, device="cuda")
@@ -112,10 +116,15 @@ class AMRRun:
 
     def regrid(self, rule: TagRule = None, tags=None):
         """Tag (or use the given tags), build the new leaf set, transfer the
-        DOFs and fill the ghosts.  Returns the tags used."""
+        DOFs and fill the ghosts.  Returns the tags used.  The transfer reads
+        a filled state either way, so that boundary nodes on coarse-fine
+        lines hold the finest leaf's values (the fill rule of Sec. 3.1) before
+        a coarse leaf hands them to its children."""
         t0 = time.perf_counter()
         if tags is None:
-            tags, _ = self.tags(rule)
+            tags, _ = self.tags(rule)  # fills, then tags
+        else:
+            self.ctx.ghost_fill(self.hier, self.bufs, self.mask, 0, 0)
         new = self.hier.regrid(tags)
         n = len(new)
         cap = self.capacity

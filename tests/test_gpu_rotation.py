@@ -228,3 +228,44 @@ def test_rotation_table2_soft_pin():
     assert 0.8 <= e6 / paper["6"] <= 1.35
     assert 0.8 <= e7 / paper["7"] <= 1.35
     assert abs(eoc - paper["eoc_6_7"]) <= 0.02
+
+
+def test_rotation_adaptive_run_with_tag_replay():
+    """Adaptive rotation run (max - min tags, the criterion of Sec. 4.1):
+    three cycles of (2 coarse steps, regrid) against the oracle with the
+    oracle's tags replayed; the position-dependent field follows the leaves
+    through every change of layout."""
+    from harness import oracle_blocks
+    from paper_2205_07572_amd.amr import TagRule, initial_hierarchy
+    print("[gpu-rotation] adaptive run", flush=True)
+    m, n0, lmax = 8, 4, 2
+    prob = _problem(af.FP64, m, n0, lmax)
+    data = afsynth.solid_body(afsynth.gauss_q0(0.3, 0.1, 30.0), OMEGA)
+
+    def block_fn(l, ix, iy):
+        dx = prob.dx(l)
+        return afsynth.dofs_block(data, m, 2, -1.0 + ix * m * dx, -1.0 + iy * m * dx, dx, dx, 4)
+
+    rule = TagRule(af.TAG_MAXMIN, 0, 0.05, 0.01)
+    run = initial_hierarchy(prob, block_fn, rule)
+    o = oracle.Hier(2, m, n0, n0, lmax, x0=-1.0, y0=-1.0, lx=2.0, ly=2.0, omega=OMEGA)
+    o.set_leaves(run.hier.leaves())
+    for k, b in enumerate(run.blocks()):
+        o.set_block(k, b)
+    dt0 = 0.6 * prob.dx(0) / OMEGA
+    changed = 0
+    for cycle in range(3):
+        run.coarse_steps(dt0, 2)
+        o.run(dt0, 2)
+        err = rel_linf(run.blocks(), oracle_blocks(o), closed_masks(m))
+        assert err.max() <= FP64_TOL, (cycle, err)
+        o.fill()
+        otags, _ = o.tag(rule.mode, rule.comp, rule.theta_r, rule.theta_c)
+        before = run.hier.leaves()
+        run.regrid(tags=otags)
+        o.regrid(otags)
+        assert run.hier.leaves() == o.leaves()
+        changed += run.hier.leaves() != before
+    err = rel_linf(run.blocks(), oracle_blocks(o), closed_masks(m))
+    assert err.max() <= FP64_TOL, err
+    assert changed >= 2

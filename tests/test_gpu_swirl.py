@@ -216,3 +216,51 @@ def test_swirl_table3_soft_pin():
     assert 0.8 <= e4 / paper["4"] <= 1.25
     assert 0.8 <= e5 / paper["5"] <= 1.25
     assert abs(eoc - paper["eoc_4_5"]) <= 0.05
+
+
+@pytest.mark.parametrize("global_step", [False, True])
+def test_swirl_adaptive_run_with_tag_replay(global_step):
+    """Adaptive swirl run (max - min tags, the criterion of Sec. 4.1): three
+    cycles of (2 coarse steps, regrid) against the oracle with the oracle's
+    tags replayed; the time of the field is carried across regrids."""
+    from harness import oracle_blocks
+    from paper_2205_07572_amd.amr import TagRule, initial_hierarchy
+    print(f"[gpu-swirl] adaptive run global={global_step}", flush=True)
+    m, n0, lmax = 8, 4, 2
+    prob = _problem(af.FP64, m, n0, lmax)
+    data = afsynth.swirl_gaussians()
+
+    def block_fn(l, ix, iy):
+        dx = prob.dx(l)
+        return afsynth.dofs_block(data, m, 2, ix * m * dx, iy * m * dx, dx, dx, 4)
+
+    rule = TagRule(af.TAG_MAXMIN, 0, 0.05, 0.01)
+    run = initial_hierarchy(prob, block_fn, rule)
+    leaves = run.hier.leaves()
+    assert len(set(l for l, _, _ in leaves)) >= 2, leaves
+    o = oracle.Hier(3, m, n0, n0, lmax)
+    o.set_leaves(leaves)
+    for k, b in enumerate(run.blocks()):
+        o.set_block(k, b)
+    dt = 0.6 * prob.dx(lmax if global_step else 0)
+    changed = 0
+    nper = 2 << lmax if global_step else 2  # the same time per cycle either way
+    for cycle in range(3):
+        run.coarse_steps(dt, nper, global_step=global_step)
+        if global_step:
+            o.run_global(dt, nper)
+        else:
+            o.run(dt, nper)
+        assert abs(run.time - o.time) <= 1e-15
+        err = rel_linf(run.blocks(), oracle_blocks(o), closed_masks(m))
+        assert err.max() <= FP64_TOL, (cycle, err)
+        o.fill()
+        otags, _ = o.tag(rule.mode, rule.comp, rule.theta_r, rule.theta_c)
+        before = run.hier.leaves()
+        run.regrid(tags=otags)
+        o.regrid(otags)
+        assert run.hier.leaves() == o.leaves()
+        changed += run.hier.leaves() != before
+    err = rel_linf(run.blocks(), oracle_blocks(o), closed_masks(m))
+    assert err.max() <= FP64_TOL, err
+    assert changed >= 2
