@@ -243,6 +243,40 @@ def swirl_gaussians():
     return InitialData(1, q0, exact)
 
 
+def burgers_sinsin(amp=1.0, shift=0.1):
+    """Initial data eq. sinsin01 of the Burgers test (Sec. 4.4):
+    q0 = amp sin(2 pi x) sin(2 pi y) + shift on the periodic unit square.
+
+    The exact solution of q_t + (q^2/2)_x + (q^2/2)_y = 0 for smooth times
+    is the implicit q = q0(x - q t, y - q t) (characteristics along (1, 1)
+    carrying q).  Along s = x + y the data's slope is at most 2 pi amp, so
+    characteristics first cross at t* = 1 / (2 pi amp) (0.159 for amp = 1);
+    `exact` solves the relation by Newton's method for t < t*."""
+
+    def q0(x, y):
+        return (amp * np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y) + shift)[None]
+
+    def exact(x, y, t):
+        if t * 2 * np.pi * amp >= 1.0:
+            raise ValueError("the Burgers solution is smooth only before t* = 1 / (2 pi amp)")
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        q = q0(x, y)[0]
+        for _ in range(60):
+            u, v = x - q * t, y - q * t
+            su, cu = np.sin(2 * np.pi * u), np.cos(2 * np.pi * u)
+            sv, cv = np.sin(2 * np.pi * v), np.cos(2 * np.pi * v)
+            F = q - (amp * su * sv + shift)
+            dF = 1.0 + t * 2 * np.pi * amp * (cu * sv + su * cv)
+            dq = F / dF
+            q = q - dq
+            if np.abs(dq).max() < 1e-15:
+                break
+        return q[None]
+
+    return InitialData(1, q0, exact)
+
+
 def gauss_q0(x0, y0, alpha):
     """exp(-alpha |x - x0|^2) as a plain function of (x, y)."""
     return lambda x, y: np.exp(-alpha * ((x - x0) ** 2 + (y - y0) ** 2))
@@ -371,6 +405,22 @@ def diagonal_leaves(n0, lcoarse):
     for iy in range(n):
         for ix in range(n):
             if ix == iy:
+                for q in range(4):
+                    leaves.append((lcoarse + 1, 2 * ix + (q & 1), 2 * iy + (q >> 1)))
+            else:
+                leaves.append((lcoarse, ix, iy))
+    return sorted(leaves, key=lambda t: (t[0], t[2], t[1]))
+
+
+def antidiagonal_leaves(n0, lcoarse):
+    """Level lcoarse everywhere, with the patches on the diagonal from the
+    upper-left to the lower-right patch refined once (the static layout of
+    the Burgers test, Sec. 4.4)."""
+    n = n0 << lcoarse
+    leaves = []
+    for iy in range(n):
+        for ix in range(n):
+            if ix + iy == n - 1:
                 for q in range(4):
                     leaves.append((lcoarse + 1, 2 * ix + (q & 1), 2 * iy + (q >> 1)))
             else:

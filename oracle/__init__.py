@@ -51,6 +51,7 @@ def lib():
         L.or_run_periodic_swirl.argtypes = [I, I, D, D, D, D, D, I, D, P, P, P, P]
         L.or_patch_step_swirl.argtypes = [I, I, D, D, D, D, D, D, I, P, P, P, P, P, P, P, P, P, I]
         L.or_swirl_foot.argtypes = [D, D, D, D, D, D, P, P]
+        L.or_patch_step_burgers.argtypes = [I, I, D, D, D, I, I, P, P, P, P, P, P, P, P, P, I]
         L.or_hier_set_swirl.argtypes = [P]
         L.or_hier_run_global.argtypes = [P, D, I]
         L.or_hier_set_time.argtypes = [P, D]
@@ -182,6 +183,19 @@ def patch_step_swirl(m, block, x0p, y0p, dx, dy, dt, t, region=0, flux4=None, si
     return outs
 
 
+def patch_step_burgers(m, block, dx, dy, dt, iters=2, region=0, flux4=None, side_mask=0, g=2):
+    """patch_step for Burgers' equation (Sec. 2.2) with `iters` fixed-point
+    iterations per point value (the method uses two)."""
+    ins = {k: np.ascontiguousarray(block[k], dtype=np.float64) for k in KINDS}
+    outs = {k: np.zeros_like(ins[k]) for k in KINDS}
+    fp = _p(flux4) if flux4 is not None else None
+    lib().or_patch_step_burgers(int(m), int(g), float(dx), float(dy), float(dt), int(iters), int(region),
+                                _p(ins["avg"]), _p(ins["corner"]), _p(ins["xedge"]), _p(ins["yedge"]),
+                                _p(outs["avg"]), _p(outs["corner"]), _p(outs["xedge"]), _p(outs["yedge"]), fp,
+                                int(side_mask))
+    return outs
+
+
 def swirl_foot(x, y, t, tau, dx, dy):
     """Foot of the swirl characteristic through (x, y) at t + tau, traced back
     to t by the oracle's Runge-Kutta step on a grid of spacing (dx, dy)."""
@@ -214,7 +228,8 @@ class Hier:
     def __init__(self, eq, m, n0x, n0y, lmax, x0=0.0, y0=0.0, lx=1.0, ly=1.0, a=0.0, b=0.0,
                  c=1.0, omega=0.0, xc=0.0, yc=0.0):
         """eq 0 advection (a, b), 1 acoustics (c), 2 solid-body rotation
-        (omega about (xc, yc)), 3 the swirl flow of Sec. 4.3."""
+        (omega about (xc, yc)), 3 the swirl flow of Sec. 4.3, 4 Burgers
+        (Sec. 2.2)."""
         self.eq, self.m, self.n0x, self.n0y, self.lmax = eq, m, n0x, n0y, lmax
         self.x0, self.y0, self.lx, self.ly = x0, y0, lx, ly
         self.ncomp = 3 if eq == 1 else 1

@@ -25,6 +25,11 @@
 //     splitting the disc of radius R = c tau into the sectors that lie in the
 //     adjacent cells (possible because of eq. cfl-acoustics) and integrating
 //     the cell's Taylor polynomial about P over each sector in closed form.
+//   * Variable-coefficient advection: solid-body rotation (Sec. 4.2, the node
+//     turned back along its circle) and the swirl flow (Sec. 4.3, one RK4
+//     step back in the field of the stream function).
+//   * Burgers (Sec. 2.2, eq. burgers-sol, eq. Burgers-iterativ): two
+//     fixed-point iterations from the mean of the neighbouring averages.
 //   * Simpson space-time flux (Sec. 2, eq. Simpson-2d) and the finite-volume
 //     update (eq. 2dfv).
 //   * AMR (Sec. 3): quadtree of equal-size patches, 2:1 balance, two ghost
@@ -275,11 +280,12 @@ struct BlockGrid : Grid {
 // ---------------------------------------------------------------------------
 
 struct Physics {
-  int eq = 0;            // 0 advection, 1 acoustics, 2 solid-body rotation, 3 swirl
+  int eq = 0;            // 0 advection, 1 acoustics, 2 solid-body rotation, 3 swirl, 4 Burgers
   double a = 0, b = 0;   // advection velocity
   double c = 1;          // speed of sound
   double omega = 0, xc = 0, yc = 0;  // rotation: a = -omega (y - yc), b = omega (x - xc)
   double t = 0;          // time at the start of the step (swirl)
+  int iters = 2;         // Burgers: fixed-point iterations per point value
 };
 
 void node_pos(int kind, int i, int j, double* X, double* Y) {
@@ -387,6 +393,36 @@ double swirl_point(const Grid& g, const Physics& ph, int kind, int i, int j, dou
   return cell_eval(g.cell(0, ci, cj), xi, eta);
 }
 
+// Burgers (Sec. 2.2).  For smooth solutions the point value solves the
+// implicit relation q(P, t + tau) = q^n(P - q(P, t + tau) tau (1, 1))
+// (eq. burgers-sol).  It is found by fixed-point iteration (eq.
+// Burgers-iterativ): the starting speed is the mean of the cell averages
+// around the node (four for a corner, the two cells the edge separates for an
+// edge midpoint), and each iteration evaluates q^n at the foot of the current
+// speed.  `iters` iterations (two give third order).
+double burgers_point(const Grid& g, const Physics& ph, int kind, int i, int j, double tau) {
+  double Q;
+  if (kind == K_CORNER) {
+    Q = 0.25 * (g.get(K_AVG, 0, i - 1, j) + g.get(K_AVG, 0, i, j) + g.get(K_AVG, 0, i - 1, j - 1) +
+                g.get(K_AVG, 0, i, j - 1));
+  } else if (kind == K_XEDGE) {  // (x_{i-1/2}, y_j) between cells (i-1, j) and (i, j)
+    Q = 0.5 * (g.get(K_AVG, 0, i - 1, j) + g.get(K_AVG, 0, i, j));
+  } else {  // yedge (x_i, y_{j-1/2}) between cells (i, j) and (i, j-1)
+    Q = 0.5 * (g.get(K_AVG, 0, i, j) + g.get(K_AVG, 0, i, j - 1));
+  }
+  double X, Y;
+  node_pos(kind, i, j, &X, &Y);
+  for (int it = 0; it < ph.iters; ++it) {
+    const double fx = X - Q * tau / g.dx, fy = Y - Q * tau / g.dy;
+    int ci, cj;
+    double xi, eta;
+    locate(fx, Q, &ci, &xi);
+    locate(fy, Q, &cj, &eta);
+    Q = cell_eval(g.cell(0, ci, cj), xi, eta);
+  }
+  return Q;
+}
+
 // Acoustics (eq. ERFormula with R = c tau):
 //   p = M{p} + R dM{p}/dR - R M{div u},
 //   u = M{u} + R dM{u}/dR - R M{p_x},  v = M{v} + R dM{v}/dR - R M{p_y}.
@@ -457,6 +493,8 @@ void evolve_point(const Grid& g, const Physics& ph, int kind, int i, int j, doub
     out[0] = rotate_point(g, ph, kind, i, j, tau);
   } else if (ph.eq == 3) {
     out[0] = swirl_point(g, ph, kind, i, j, tau);
+  } else if (ph.eq == 4) {
+    out[0] = burgers_point(g, ph, kind, i, j, tau);
   } else {
     acoustic_point(g, ph, kind, i, j, tau, out);
   }
@@ -464,9 +502,12 @@ void evolve_point(const Grid& g, const Physics& ph, int kind, int i, int j, doub
 
 // Physical flux functions: advection f = a q, g = b q with the velocity
 // component at the node (constant, or that of the rotation field, Sec. 4.2);
-// acoustics f = c (u, p, 0), g = c (v, 0, p) for q = (p, u, v) (Sec. 2.3).
+// acoustics f = c (u, p, 0), g = c (v, 0, p) for q = (p, u, v) (Sec. 2.3);
+// Burgers f = g = q^2 / 2 (eq. burgers2d).
 void flux_x(const Physics& ph, double vel, const double* q, double* f) {
-  if (ph.eq != 1) {
+  if (ph.eq == 4) {
+    f[0] = 0.5 * q[0] * q[0];
+  } else if (ph.eq != 1) {
     f[0] = vel * q[0];
   } else {
     f[0] = ph.c * q[1];
@@ -475,7 +516,9 @@ void flux_x(const Physics& ph, double vel, const double* q, double* f) {
   }
 }
 void flux_y(const Physics& ph, double vel, const double* q, double* f) {
-  if (ph.eq != 1) {
+  if (ph.eq == 4) {
+    f[0] = 0.5 * q[0] * q[0];
+  } else if (ph.eq != 1) {
     f[0] = vel * q[0];
   } else {
     f[0] = ph.c * q[2];
@@ -1386,7 +1429,7 @@ Physics rotation(double omega, double xc, double yc) {
 extern "C" {
 
 // One AF step on a periodic nx x ny grid, in place.  Arrays [ncomp][ny][nx].
-// eq 0 advection (a, b), 1 acoustics (c).
+// eq 0 advection (a, b), 1 acoustics (c), 4 Burgers.
 void or_step_periodic(int eq, int nx, int ny, double dx, double dy, double dt, double a,
                       double b, double c, double* avg, double* corner, double* xedge,
                       double* yedge) {
@@ -1460,6 +1503,19 @@ void or_patch_step_swirl(int m, int g, double x0p, double y0p, double dx, double
   ph.eq = 3;
   ph.t = t;
   patch_step(ph, m, g, x0p, y0p, dx, dy, dt, region, in_avg, in_corner, in_xedge, in_yedge, out_avg,
+             out_corner, out_xedge, out_yedge, flux4, side_mask);
+}
+
+// Burgers (Sec. 2.2) on one patch block with a given number of fixed-point
+// iterations per point value (two in the method; other counts for pins).
+void or_patch_step_burgers(int m, int g, double dx, double dy, double dt, int iters, int region,
+                           const double* in_avg, const double* in_corner, const double* in_xedge,
+                           const double* in_yedge, double* out_avg, double* out_corner, double* out_xedge,
+                           double* out_yedge, double* flux4, int side_mask) {
+  Physics ph;
+  ph.eq = 4;
+  ph.iters = iters;
+  patch_step(ph, m, g, 0.0, 0.0, dx, dy, dt, region, in_avg, in_corner, in_xedge, in_yedge, out_avg,
              out_corner, out_xedge, out_yedge, flux4, side_mask);
 }
 
