@@ -53,7 +53,7 @@ extern "C" {
 typedef enum {
   AF_OK = 0,
   AF_ERR_ARG = -1,      /* bad argument value or combination */
-  AF_ERR_CFL = -2,      /* time step violates eq. cfl-adv or eq. cfl-acoustics */
+  AF_ERR_CFL = -2,      /* time step violates eq. cfl-adv (with the largest speed) or eq. cfl-acoustics */
   AF_ERR_LAYOUT = -3,   /* bad pitch / patch count / alignment */
   AF_ERR_BALANCE = -4,  /* leaf set is not a 2:1 corner-balanced cover */
   AF_ERR_DEVICE = -5,   /* HIP runtime error */
@@ -69,8 +69,15 @@ typedef enum {
  * t) - Psi(x - dx/2, y, t))/dx, Psi = sin^2(pi x) sin^2(pi y) cos(pi t)/pi
  * (eq. swirlODE, dx, dy of the level), feet by one classical Runge-Kutta
  * step backwards in time, fluxes with the face-midpoint velocity at each
- * Simpson time (eq. swirlF, swirlG).  |a|, |b| <= 1. */
-typedef enum { AF_ADVECTION = 0, AF_ACOUSTICS = 1, AF_ROTATION = 2, AF_SWIRL = 3 } af_equation;
+ * Simpson time (eq. swirlF, swirlG).  |a|, |b| <= 1.
+ * AF_BURGERS: q_t + (q^2/2)_x + (q^2/2)_y = 0 (Sec. 2.2, eq. burgers2d),
+ * unlimited.  Each point value is found from q = q^n(P - q tau (1, 1))
+ * (eq. burgers-sol) by two fixed-point iterations (eq. Burgers-iterativ)
+ * started from the mean of the cell averages around the node; fluxes are
+ * the Simpson rule of q^2/2.  qmax bounds |q| for the CFL check; the source
+ * cell of a foot is kept within the one-cell stencil, so a step whose
+ * iterates exceed qmax reads no memory outside the patch block. */
+typedef enum { AF_ADVECTION = 0, AF_ACOUSTICS = 1, AF_ROTATION = 2, AF_SWIRL = 3, AF_BURGERS = 4 } af_equation;
 typedef enum { AF_FP64 = 0, AF_FP32 = 1 } af_precision;
 enum { AF_AVG = 0, AF_CORNER = 1, AF_XEDGE = 2, AF_YEDGE = 3 };
 enum { AF_SIDE_W = 0, AF_SIDE_E = 1, AF_SIDE_S = 2, AF_SIDE_N = 3 };
@@ -93,6 +100,7 @@ typedef struct {
   double c;            /* speed of sound (eq. acoustics) */
   double omega;        /* AF_ROTATION: angular velocity (pi in Sec. 4.2) */
   double xc, yc;       /* AF_ROTATION: centre of rotation */
+  double qmax;         /* AF_BURGERS: bound on |q| over the run (CFL check) */
 } af_problem;
 
 typedef struct {

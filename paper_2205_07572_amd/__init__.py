@@ -14,7 +14,7 @@ import numpy as np
 from . import _lib
 from ._lib import AFError, check
 
-ADVECTION, ACOUSTICS, ROTATION, SWIRL = 0, 1, 2, 3
+ADVECTION, ACOUSTICS, ROTATION, SWIRL, BURGERS = 0, 1, 2, 3, 4
 STEP_GRAPH, STEP_GLOBAL = 1, 2
 FP64, FP32 = 0, 1
 KINDS = ("avg", "corner", "xedge", "yedge")
@@ -54,6 +54,7 @@ class Problem:
     omega: float = 0.0   # ROTATION: a = -omega (y - yc), b = omega (x - xc)
     xc: float = 0.0
     yc: float = 0.0
+    qmax: float = 0.0    # BURGERS: bound on |q| over the run (CFL check)
 
     @property
     def ncomp(self):
@@ -71,7 +72,8 @@ class Context:
         self.prob = prob
         L = _lib.load()
         cp = _lib.af_problem(prob.eq, prob.prec, prob.m, prob.n0x, prob.n0y, prob.lmax, prob.x0, prob.y0,
-                             prob.lx, prob.ly, prob.a, prob.b, prob.c, prob.omega, prob.xc, prob.yc)
+                             prob.lx, prob.ly, prob.a, prob.b, prob.c, prob.omega, prob.xc, prob.yc,
+                             prob.qmax)
         h = ctypes.c_void_p()
         check(L.af_ctx_create(ctypes.byref(cp), ctypes.byref(h)))
         self.h = h

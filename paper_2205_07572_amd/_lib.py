@@ -35,7 +35,7 @@ class af_problem(ctypes.Structure):
                 ("x0", ctypes.c_double), ("y0", ctypes.c_double), ("lx", ctypes.c_double),
                 ("ly", ctypes.c_double), ("a", ctypes.c_double), ("b", ctypes.c_double),
                 ("c", ctypes.c_double), ("omega", ctypes.c_double), ("xc", ctypes.c_double),
-                ("yc", ctypes.c_double)]
+                ("yc", ctypes.c_double), ("qmax", ctypes.c_double)]
 
 
 class af_state(ctypes.Structure):

@@ -132,6 +132,10 @@ af_status check_cfl(const af_ctx* c, int level, double dt) {
     // |a|, |b| <= max |grad Psi| = 1 (centred differences of Psi keep the bound)
     const double cfl = std::max(dt / dx, dt / dy);
     if (cfl > 1.0 + 1e-12) return fail(AF_ERR_CFL, "swirl CFL > 1 (eq. cfl-adv with |a|, |b| <= 1)");
+  } else if (c->P.eq == AF_BURGERS) {
+    // the speed is q in both directions, |q| <= qmax
+    const double cfl = c->P.qmax * std::max(dt / dx, dt / dy);
+    if (cfl > 1.0 + 1e-12) return fail(AF_ERR_CFL, "Burgers CFL > 1 (qmax dt / dx)");
   } else if (c->P.eq == AF_ROTATION) {
     // largest |a| = |omega| |y - yc| and |b| = |omega| |x - xc| on the domain
     const double w = std::fabs(c->P.omega);
@@ -252,7 +256,8 @@ const char* af_last_error(void) { return g_err.c_str(); }
 af_status af_ctx_create(const af_problem* prob, af_ctx** out) {
   if (!prob || !out) return fail(AF_ERR_ARG, "null argument");
   const af_problem& P = *prob;
-  if (P.eq != AF_ADVECTION && P.eq != AF_ACOUSTICS && P.eq != AF_ROTATION && P.eq != AF_SWIRL)
+  if (P.eq != AF_ADVECTION && P.eq != AF_ACOUSTICS && P.eq != AF_ROTATION && P.eq != AF_SWIRL &&
+      P.eq != AF_BURGERS)
     return fail(AF_ERR_ARG, "unknown equation");
   if (P.eq == AF_ROTATION && !(std::isfinite(P.omega) && std::isfinite(P.xc) && std::isfinite(P.yc)))
     return fail(AF_ERR_ARG, "rotation parameters must be finite");
@@ -262,6 +267,8 @@ af_status af_ctx_create(const af_problem* prob, af_ctx** out) {
   if (P.n0x < 1 || P.n0y < 1 || P.lmax < 0 || P.lmax >= kMaxLevels) return fail(AF_ERR_ARG, "bad patch counts or lmax");
   if (!(P.lx > 0 && P.ly > 0)) return fail(AF_ERR_ARG, "domain extents must be positive");
   if (P.eq == AF_ACOUSTICS && !(P.c > 0)) return fail(AF_ERR_ARG, "speed of sound must be positive");
+  if (P.eq == AF_BURGERS && !(P.qmax >= 0 && std::isfinite(P.qmax)))
+    return fail(AF_ERR_ARG, "qmax must be finite and >= 0");
   auto c = std::make_unique<af_ctx>();
   c->P = P;
   c->ncomp = P.eq == AF_ACOUSTICS ? 3 : 1;
@@ -432,6 +439,8 @@ af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t 
   RotParams<double> rp64;
   SwirlParams<float> sp32;
   SwirlParams<double> sp64;
+  BurgersParams<float> bp32;
+  BurgersParams<double> bp64;
   L.fp32 = ctx->fp32();
   L.eq = ctx->P.eq;
   L.m = ctx->P.m;
@@ -493,6 +502,15 @@ af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t 
     }
     for (int k = 0; k < 3; ++k) sp32.cos_fx[k] = float(sp64.cos_fx[k]);
     L.weights = ctx->fp32() ? static_cast<const void*>(&sp32) : static_cast<const void*>(&sp64);
+  } else if (ctx->P.eq == AF_BURGERS) {
+    for (int k = 0; k < 2; ++k) {
+      const double tau = (k + 1) * 0.5 * dt;
+      bp64.tdx[k] = tau / dx;
+      bp64.tdy[k] = tau / dy;
+      bp32.tdx[k] = float(bp64.tdx[k]);
+      bp32.tdy[k] = float(bp64.tdy[k]);
+    }
+    L.weights = ctx->fp32() ? static_cast<const void*>(&bp32) : static_cast<const void*>(&bp64);
   } else {
     L.weights = weights_for(ctx, dt / dx, dt / dy);
   }

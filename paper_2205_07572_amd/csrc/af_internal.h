@@ -106,6 +106,12 @@ struct SwirlParams {
   T cos_fx[3];       // cos(pi s) at t, t+dt/2, t+dt (Simpson times of the fluxes)
 };
 
+// Burgers (Sec. 2.2): tau / dx and tau / dy for tau = dt/2 and dt.
+template <typename T>
+struct BurgersParams {
+  T tdx[2], tdy[2];
+};
+
 // Ghost-fill plan: one op per fill-set DOF of every leaf, holding the source
 // that the fill rules resolve to for a given lower bound on source levels.
 //   x: source leaf, or -1 for "keep the target's own value"

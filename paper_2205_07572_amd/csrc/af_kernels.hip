@@ -172,6 +172,8 @@ template <typename T>
 struct WSel<T, 2> { using type = RotParams<T>; };
 template <typename T>
 struct WSel<T, 3> { using type = SwirlParams<T>; };
+template <typename T>
+struct WSel<T, 4> { using type = BurgersParams<T>; };
 
 constexpr double kPiD = 3.14159265358979323846264338327950288;
 
@@ -351,6 +353,44 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
         }
         if (wrow) A.out[kind + 1][size_t(patch) * plane + obase] = val[1];
       }
+    } else if constexpr (EQ == 4) {
+      // Burgers (Sec. 2.2): the point value solves q = q^n(P - q tau (1, 1));
+      // two fixed-point iterations from the mean of the averages around the
+      // node.  The time sum holds the fluxes q^2/2 (Simpson in time).
+      const auto& av = L.in[0][0];
+#pragma unroll
+      for (int kind = 0; kind < 3; ++kind) {
+        if (kind == NK_XEDGE && !has_x) continue;
+        if (kind == NK_YEDGE && !has_y) continue;
+        T Q0;
+        if (kind == NK_CORNER) {
+          Q0 = T(0.25) * ((av[r][c - 1] + av[r][c]) + (av[r - 1][c - 1] + av[r - 1][c]));
+        } else if (kind == NK_XEDGE) {
+          Q0 = T(0.5) * (av[r][c - 1] + av[r][c]);
+        } else {
+          Q0 = T(0.5) * (av[r][c] + av[r - 1][c]);
+        }
+        const T X = kind == NK_YEDGE ? T(i) : T(i) - T(0.5);  // node in cell units
+        const T Y = kind == NK_XEDGE ? T(j) : T(j) - T(0.5);
+        T val[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          T Q = Q0;
+#pragma unroll
+          for (int it = 0; it < 2; ++it) {
+            const T sx = X - Q * W.tdx[t], sy = Y - Q * W.tdy[t];
+            // source cell, kept in the range a Courant number <= 1 allows
+            int ci = foot_cell(sx, Q), cj = foot_cell(sy, Q);
+            ci = min(max(ci, i - 1), kind == NK_YEDGE ? i + 1 : i);
+            cj = min(max(cj, j - 1), kind == NK_XEDGE ? j + 1 : j);
+            Q = rot_eval<T, NR, NC>(L.in, r + (cj - j), c + (ci - i), T(2) * (sx - T(ci)), T(2) * (sy - T(cj)));
+          }
+          val[t] = Q;
+        }
+        const T cur = L.in[kind + 1][0][r][c];
+        L.tsum[kind][0][jj][ii] = (T(0.5) * cur * cur + T(2) * val[0] * val[0]) + T(0.5) * val[1] * val[1];
+        if (wrow) A.out[kind + 1][size_t(patch) * plane + obase] = val[1];
+      }
     } else {
       T res[2][3];
       ac_eval<T, NR, NC, kNbCorner>(L.in, r, c, kNbCornerTab, W.corner, res);
@@ -447,6 +487,10 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
       fR[0] = (aR[0] * SR[0] + T(4) * aR[1] * SR[1] + aR[2] * SR[2]) * inv36;
       gB[0] = (bB[0] * SB[0] + T(4) * bB[1] * SB[1] + bB[2] * SB[2]) * inv36;
       gT[0] = (bT[0] * ST[0] + T(4) * bT[1] * ST[1] + bT[2] * ST[2]) * inv36;
+    } else if constexpr (EQ == 4) {
+      // Burgers: the time sums already hold f = g = q^2/2
+      fL[0] = FL[0] * inv36; fR[0] = FR[0] * inv36;
+      gB[0] = GB[0] * inv36; gT[0] = GT[0] * inv36;
     } else if constexpr (EQ == 2) {
       // rotation: f = a(node) q with a = -omega (y - yc) on x-faces (a depends
       // on y only) and g = b(node) q with b = omega (x - xc) on y-faces
@@ -1375,6 +1419,7 @@ hipError_t launch_patch_step(const StepLaunch& s, hipStream_t st) {
     case 1: return s.fp32 ? launch_step_m<float, 1>(s, st) : launch_step_m<double, 1>(s, st);
     case 2: return s.fp32 ? launch_step_m<float, 2>(s, st) : launch_step_m<double, 2>(s, st);
     case 3: return s.fp32 ? launch_step_m<float, 3>(s, st) : launch_step_m<double, 3>(s, st);
+    case 4: return s.fp32 ? launch_step_m<float, 4>(s, st) : launch_step_m<double, 4>(s, st);
     default: return hipErrorInvalidValue;
   }
 }

@@ -1,0 +1,256 @@
+"""GPU parity for Burgers' equation (Sec. 2.2, Sec. 4.4): the patch step
+against the oracle's, subcycled, graph-replayed and globally stepped AMR
+against the oracle's recursion, conservation, an FP32 bound, third order
+against the exact solution before the shock, and an adaptive run with the
+gradient criterion of Sec. 4.4 and the oracle's tags replayed."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import afsynth
+import oracle
+import paper_2205_07572_amd as af
+from harness import KINDS, closed_masks, rel_linf
+
+pytestmark = pytest.mark.gpu
+FP64_TOL = 1e-12
+QMAX = 1.1  # sup |q0| of eq. sinsin01
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    torch = pytest.importorskip("torch")
+    if not os.path.exists("/dev/kfd"):
+        pytest.skip("no GPU on this machine")
+    assert torch.cuda.is_available(), "GPU present but torch.cuda.is_available() is False"
+
+
+def _problem(prec, m, n0, lmax=0, qmax=QMAX):
+    return af.Problem(eq=af.BURGERS, prec=prec, m=m, n0x=n0, n0y=n0, lmax=lmax, qmax=qmax)
+
+
+def _smooth_blocks(rng, n, m, dx):
+    """Random quadratic fields plus small DOF noise, |q| well below 1."""
+    from harness import valid_masks
+    vm = valid_masks(m)
+    out = []
+    for p in range(n):
+        terms = {(0, 0): rng.uniform(-0.3, 0.3)}
+        for a in range(3):
+            for b in range(3 - a):
+                if a + b:
+                    terms[(a, b)] = rng.uniform(-0.4, 0.4)
+        blk = afsynth.dofs_block(afsynth.polynomial([terms]), m, 2, -0.3 + 0.1 * p, 0.2 - 0.05 * p, dx, dx, 4)
+        for k in KINDS:
+            blk[k] = np.where(vm[k][None], blk[k] + 0.02 * rng.standard_normal(blk[k].shape), 0.0)
+        out.append(blk)
+    return out
+
+
+@pytest.mark.parametrize("m", [8, 16, 32])
+@pytest.mark.parametrize("region", [0, 1])
+def test_burgers_patch_step_parity_fp64(m, region):
+    import torch
+    print(f"[gpu-burgers] patch_step m={m} region={region}", flush=True)
+    rng = np.random.default_rng(31 * m + region)
+    n0 = 4
+    prob = _problem(af.FP64, m, n0)
+    ctx = af.Context(prob)
+    dx = prob.dx(0)
+    blocks = _smooth_blocks(rng, 4, m, dx)
+    dt = 0.5 * dx / QMAX
+    for ty in {8: [8], 16: [8, 16], 32: [4, 8]}[m]:
+        ctx.tile = ty
+        tin = af.blocks_to_state(ctx, blocks)
+        tout = torch.zeros_like(tin)
+        reg = torch.zeros((4, 4, m, 1), dtype=torch.float64, device="cuda")
+        mask = torch.full((4,), 15, dtype=torch.uint8, device="cuda")
+        ctx.patch_step(tin, tout, 0, 4, 0, dt, region, reg, mask)
+        torch.cuda.synchronize()
+        got = af.state_to_blocks(ctx, tout)
+        regs = reg.cpu().numpy()
+        mk = closed_masks(m, region)
+        for p in range(4):
+            flux4 = np.zeros((4, m, 1))
+            ref = oracle.patch_step(4, m, blocks[p], dx, dx, dt, region=region, flux4=flux4, side_mask=15)
+            err = rel_linf([got[p]], [ref], mk)
+            assert err.max() <= FP64_TOL, (ty, p, err)
+            np.testing.assert_allclose(regs[p], flux4, rtol=1e-12, atol=1e-14 * np.abs(flux4).max())
+
+
+def test_burgers_cfl_and_qmax_checks():
+    import torch
+    prob = _problem(af.FP64, 8, 2, qmax=2.0)
+    ctx = af.Context(prob)
+    t = ctx.new_state(1)
+    with pytest.raises(af.AFError) as e:
+        ctx.patch_step(t, torch.zeros_like(t), 0, 1, 0, 1.01 * prob.dx(0) / 2.0, 0)
+    assert e.value.status == af._lib.AF_ERR_CFL
+    ctx.patch_step(t, torch.zeros_like(t), 0, 1, 0, 0.99 * prob.dx(0) / 2.0, 0)
+    with pytest.raises(af.AFError) as e:
+        af.Context(_problem(af.FP64, 8, 2, qmax=float("nan")))
+    assert e.value.status == af._lib.AF_ERR_ARG
+
+
+def _layouts():
+    three = [(0, ix, iy) for iy in range(4) for ix in range(4) if not (1 <= ix <= 2 and 1 <= iy <= 2)]
+    three += [(1, ix, iy) for iy in range(2, 6) for ix in range(2, 6) if not (3 <= ix <= 4 and 3 <= iy <= 4)]
+    three += [(2, ix, iy) for iy in range(6, 10) for ix in range(6, 10)]
+    return {"antidiagonal": (4, 1, afsynth.antidiagonal_leaves(4, 0)), "three": (4, 2, afsynth.sort_leaves(three))}
+
+
+def _amr(prec, leaves, n0, lmax, m, nsteps, data, dt0, global_step=False, use_graph=False):
+    import torch
+    prob = _problem(prec, m, n0, lmax)
+    ctx = af.Context(prob)
+    h = af.Hierarchy(ctx, leaves)
+    blocks = []
+    for (l, ix, iy) in leaves:
+        dx = prob.dx(l)
+        blocks.append(afsynth.dofs_block(data, m, 2, ix * m * dx, iy * m * dx, dx, dx, 4))
+    b0 = af.blocks_to_state(ctx, blocks)
+    bufs = [b0, torch.zeros_like(b0)]
+    reg = torch.zeros((len(leaves), 4, m, 1), dtype=torch.float64, device="cuda")
+    s_in = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s_out = torch.zeros_like(s_in)
+    mask = 0
+    ctx.ghost_fill(h, bufs, mask, 0, 0)
+    ctx.reduce_sum(h, bufs, mask, s_in)
+    for k in range(nsteps):
+        mask = ctx.amr_coarse_step(h, bufs, mask, dt0, reg, use_graph=use_graph, global_step=global_step)
+    ctx.reduce_sum(h, bufs, mask, s_out)
+    torch.cuda.synchronize()
+    g0, g1 = af.state_to_blocks(ctx, bufs[0]), af.state_to_blocks(ctx, bufs[1])
+    got = [g1[k] if (mask >> leaves[k][0]) & 1 else g0[k] for k in range(len(leaves))]
+    assert float(reg.abs().max()) == 0.0
+    return got, blocks, float(s_in.item()), float(s_out.item()), prob
+
+
+@pytest.mark.parametrize("layout", ["antidiagonal", "three"])
+@pytest.mark.parametrize("mode", ["subcycled", "subcycled-graph", "global"])
+def test_burgers_amr_parity_fp64(layout, mode):
+    n0, lmax, leaves = _layouts()[layout]
+    print(f"[gpu-burgers] amr {layout} {mode}", flush=True)
+    m, nsteps = 8, 4
+    data = afsynth.burgers_sinsin()
+    glob = mode == "global"
+    prob = _problem(af.FP64, m, n0, lmax)
+    dt0 = 0.5 * prob.dx(lmax if glob else 0) / QMAX
+    got, blocks, s_in, s_out, _ = _amr(af.FP64, leaves, n0, lmax, m, nsteps, data, dt0, global_step=glob,
+                                       use_graph=mode.endswith("graph"))
+    h = oracle.Hier(4, m, n0, n0, lmax)
+    h.set_leaves(leaves)
+    for k, b in enumerate(blocks):
+        h.set_block(k, b)
+    h.fill(0, 0)
+    if glob:
+        h.run_global(dt0, nsteps)
+    else:
+        h.run(dt0, nsteps)
+    ref = [h.get_block(k) for k in range(len(leaves))]
+    err = rel_linf(got, ref, closed_masks(m, 0))
+    assert err.max() <= FP64_TOL, err
+    assert abs(s_out - s_in) <= 1e-13 * (1.0 + abs(s_in))
+
+
+def test_burgers_fp32_error_bound():
+    n0, lmax, leaves = _layouts()["antidiagonal"]
+    m = 16
+    data = afsynth.burgers_sinsin()
+    prob = _problem(af.FP32, m, n0, lmax)
+    dt0 = 0.5 * prob.dx(0) / QMAX
+    got, blocks, s_in, s_out, _ = _amr(af.FP32, leaves, n0, lmax, m, 3, data, dt0)
+    h = oracle.Hier(4, m, n0, n0, lmax)
+    h.set_leaves(leaves)
+    for k, b in enumerate(blocks):
+        h.set_block(k, {kk: v.astype(np.float32).astype(np.float64) for kk, v in b.items()})
+    h.fill(0, 0)
+    h.run(dt0, 3)
+    ref = [h.get_block(k) for k in range(len(leaves))]
+    err = rel_linf(got, ref, closed_masks(m, 0))
+    print(f"[gpu-burgers] fp32 rel L-inf {err.max():.2e}, sum drift {abs(s_out - s_in):.2e}", flush=True)
+    assert err.max() <= 1e-5, err
+    assert abs(s_out - s_in) <= 1e-6
+
+
+def _uniform_l1(level, T=0.05, cfl=0.5, m=32, prec=af.FP64):
+    """Uniform level `level` (16 * 2^level cells per side), eq. sinsin01 to
+    T at CFL `cfl` of |q| <= 1.1; L1 error of the averages against the exact
+    implicit solution."""
+    import torch
+    N = 16 << level
+    n0 = N // m
+    data = afsynth.burgers_sinsin()
+    prob = _problem(prec, m, n0)
+    ctx = af.Context(prob)
+    leaves = afsynth.uniform_leaves(n0, n0, 0)
+    h = af.Hierarchy(ctx, leaves)
+    d0 = afsynth.dofs_periodic(data, N, N, nq=4)
+    blk = afsynth.periodic_to_blocks(d0, m)
+    b0 = af.blocks_to_state(ctx, [{k: blk[k][p] for k in KINDS} for p in range(n0 * n0)])
+    bufs = [b0, torch.zeros_like(b0)]
+    reg = torch.zeros((len(leaves), 4, m, 1), dtype=torch.float64, device="cuda")
+    n = math.ceil(T / (cfl / N / QMAX))
+    mask = 0
+    for _ in range(n):
+        mask = ctx.amr_coarse_step(h, bufs, mask, T / n, reg)
+    got = af.state_to_blocks(ctx, bufs[mask & 1])
+    avg = np.zeros((N, N))
+    for p, (_, ix, iy) in enumerate(leaves):
+        avg[iy * m:(iy + 1) * m, ix * m:(ix + 1) * m] = got[p]["avg"][0, 2:2 + m, 2:2 + m]
+    ex = afsynth.InitialData(1, lambda x, y: data.exact(x, y, T))
+    ref = afsynth.dofs_periodic(ex, N, N, nq=4)["avg"][0]
+    return float(np.abs(avg - ref).sum()) / N ** 2
+
+
+def test_burgers_third_order_before_the_shock():
+    """Sec. 4.4 reports third order at t = 0.05 without numbers: uniform levels
+    3, 4, 5 (128^2 to 512^2) give EOCs near 3."""
+    e = [_uniform_l1(lv) for lv in (3, 4, 5)]
+    eoc = [math.log2(e[k] / e[k + 1]) for k in range(2)]
+    print(f"[gpu-burgers] L1 {e}, EOC {eoc}", flush=True)
+    assert all(2.5 <= v <= 3.5 for v in eoc), eoc
+
+
+def test_burgers_adaptive_run_with_tag_replay():
+    """Adaptive run with the centred-gradient criterion of Sec. 4.4 (its
+    threshold 15 lowered to 8, which the steepening gradient crosses within
+    the run: it starts at 2 pi and grows as 2 pi / (1 - 2 pi t)): three
+    cycles of (2 coarse steps, regrid) against the oracle with its tags
+    replayed."""
+    from harness import oracle_blocks
+    from paper_2205_07572_amd.amr import TagRule, initial_hierarchy
+    print("[gpu-burgers] adaptive run", flush=True)
+    m, n0, lmax = 8, 4, 2
+    prob = _problem(af.FP64, m, n0, lmax)
+    data = afsynth.burgers_sinsin()
+
+    def block_fn(l, ix, iy):
+        dx = prob.dx(l)
+        return afsynth.dofs_block(data, m, 2, ix * m * dx, iy * m * dx, dx, dx, 4)
+
+    rule = TagRule(af.TAG_GRADIENT, 0, 8.0, 4.0)
+    run = initial_hierarchy(prob, block_fn, rule)
+    o = oracle.Hier(4, m, n0, n0, lmax)
+    o.set_leaves(run.hier.leaves())
+    for k, b in enumerate(run.blocks()):
+        o.set_block(k, b)
+    dt0 = 0.5 * prob.dx(0) / QMAX
+    changed = 0
+    for cycle in range(3):
+        run.coarse_steps(dt0, 2)
+        o.run(dt0, 2)
+        err = rel_linf(run.blocks(), oracle_blocks(o), closed_masks(m))
+        assert err.max() <= FP64_TOL, (cycle, err)
+        o.fill()
+        otags, _ = o.tag(rule.mode, rule.comp, rule.theta_r, rule.theta_c)
+        before = run.hier.leaves()
+        run.regrid(tags=otags)
+        o.regrid(otags)
+        assert run.hier.leaves() == o.leaves()
+        changed += run.hier.leaves() != before
+    err = rel_linf(run.blocks(), oracle_blocks(o), closed_masks(m))
+    assert err.max() <= FP64_TOL, err
+    assert changed >= 1
