@@ -360,6 +360,10 @@ def swirl_runs():
         bufs = [b0, torch.zeros_like(b0)]
         reg = torch.zeros((len(leaves), 4, m, 1), dtype=torch.float64, device="cuda")
         ctx.ghost_fill(h, bufs, 0, 0, 0)
+        warm, wm = [b0.clone(), torch.zeros_like(b0)], 0
+        for k in range(2):  # untimed warm-up on a copy
+            wm = ctx.amr_coarse_step(h, warm, wm, dt, reg, t0=k * dt, global_step=global_step)
+        del warm
 
         def steps():
             mask = 0
@@ -466,6 +470,93 @@ def swirl_adaptive_runs(data):
     for mode in ("subcycled", "global"):
         out[f"eoc_{mode}"] = math.log2(out[f"3-4_{mode}"]["l1"] / out[f"3-5_{mode}"]["l1"])
     out["paper_eoc"] = {"subcycled": 2.9705, "global": 2.9703}
+    return out
+
+
+def burgers_runs():
+    """Burgers' equation (Sec. 2.2, Sec. 4.4), eq. sinsin01, unlimited.
+    Uniform levels 4, 5, 6 (256^2 to 1024^2 cells as 32^2 patches) to
+    t = 0.05, before the shock, at CFL 0.5 of |q| <= 1.1, in FP64 and FP32:
+    cell-updates/s of the general path and the L1 error against the exact
+    implicit solution.  Then the adaptive run of Sec. 4.4: base level 3
+    (8x8 patches of 16^2), levels 3-5, a patch refined where a centred
+    difference of its averages reaches 15 and coarsened below it, regridded
+    every coarse step, to t = 1 (the shock forms at t = 1/(2 pi)); reports
+    throughput, leaves and the drift of the conserved sum."""
+    import math
+    import torch
+    import afsynth
+    import paper_2205_07572_amd as af
+    from paper_2205_07572_amd.amr import TagRule, initial_hierarchy
+    data, qmax, T = afsynth.burgers_sinsin(), 1.1, 0.05
+    out = {}
+    for level in (4, 5, 6):
+        N, m = 16 << level, 32
+        n0 = N // m
+        n = math.ceil(T / (0.5 / N / qmax))
+        d0 = afsynth.dofs_periodic(data, N, N, nq=4)
+        blk = afsynth.periodic_to_blocks(d0, m)
+        ex = afsynth.dofs_periodic(afsynth.InitialData(1, lambda x, y: data.exact(x, y, T)), N, N, nq=4)["avg"][0]
+        res = {}
+        for pname, prec in (("fp64", af.FP64), ("fp32", af.FP32)):
+            prob = af.Problem(eq=af.BURGERS, prec=prec, m=m, n0x=n0, n0y=n0, lmax=0, qmax=qmax)
+            ctx = af.Context(prob)
+            leaves = afsynth.uniform_leaves(n0, n0, 0)
+            h = af.Hierarchy(ctx, leaves)
+            b0 = af.blocks_to_state(ctx, [{k: blk[k][p] for k in af.KINDS} for p in range(n0 * n0)])
+            bufs = [b0, torch.zeros_like(b0)]
+            reg = torch.zeros((len(leaves), 4, m, 1), dtype=torch.float64, device="cuda")
+            _rot_steps(ctx, h, [b0.clone(), torch.zeros_like(b0)], reg, 2, T / n)  # untimed warm-up
+            ms, mask = _event_ms(lambda: _rot_steps(ctx, h, bufs, reg, n, T / n))
+            got = af.state_to_blocks(ctx, bufs[mask & 1])
+            avg = np.zeros((N, N))
+            for p, (_, ix, iy) in enumerate(leaves):
+                avg[iy * m:(iy + 1) * m, ix * m:(ix + 1) * m] = got[p]["avg"][0, 2:2 + m, 2:2 + m]
+            l1 = float(np.abs(avg - ex).sum()) / N ** 2
+            res[pname] = {"steps": n, "ms": ms, "cell_updates_per_s": N * N * n / (ms * 1e-3), "l1": l1}
+            print(f"[bench] burgers level {level} ({N}^2) {pname}: {n} steps in {ms:.1f} ms, "
+                  f"{res[pname]['cell_updates_per_s']:.3e} cell-updates/s, L1 {l1:.4e}", file=sys.stderr,
+                  flush=True)
+            del bufs, b0
+            torch.cuda.empty_cache()
+        out[f"level{level}"] = res
+    out["eoc_4_5_fp64"] = math.log2(out["level4"]["fp64"]["l1"] / out["level5"]["fp64"]["l1"])
+    out["eoc_5_6_fp64"] = math.log2(out["level5"]["fp64"]["l1"] / out["level6"]["fp64"]["l1"])
+    m, n0, lmax, T1 = 16, 8, 2, 1.0
+    rule = TagRule(af.TAG_GRADIENT, 0, 15.0, 15.0)
+    for pname, prec in (("fp64", af.FP64), ("fp32", af.FP32)):
+        prob = af.Problem(eq=af.BURGERS, prec=prec, m=m, n0x=n0, n0y=n0, lmax=lmax, qmax=qmax)
+
+        def block_fn(l, ix, iy, prob=prob):
+            dx = prob.dx(l)
+            return afsynth.dofs_block(data, m, 2, ix * m * dx, iy * m * dx, dx, dx, 4)
+
+        run = initial_hierarchy(prob, block_fn, rule)
+        s0 = float(run.total()[0])
+        n = math.ceil(T1 / (0.5 * prob.dx(0) / qmax))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for step in range(n):
+            run.coarse_steps(T1 / n, 1)
+            if step + 1 < n:
+                run.regrid(rule)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        s1 = float(run.total()[0])
+        st = run.stats
+        hist = st.leaves_history
+        key = f"adaptive3_5_{pname}"
+        out[key] = {"coarse_steps": st.coarse_steps, "regrids": st.regrids,
+                    "cell_updates_per_s": st.cell_updates / st.step_seconds, "time_to_solution_s": wall,
+                    "leaves_mean": float(np.mean(hist)), "leaves_max": int(max(hist)),
+                    "leaves_per_level_final": np.bincount([lv for lv, _, _ in run.hier.leaves()]).tolist(),
+                    "sum_drift": abs(s1 - s0), "sum": s0}
+        print(f"[bench] burgers adaptive 3-5 {pname}: {st.coarse_steps} coarse steps, {st.regrids} regrids, "
+              f"{out[key]['cell_updates_per_s']:.3e} cell-updates/s, {wall:.2f} s to solution, leaves "
+              f"{out[key]['leaves_mean']:.0f} (max {out[key]['leaves_max']}), sum drift {abs(s1 - s0):.2e}",
+              file=sys.stderr, flush=True)
+        del run
+        torch.cuda.empty_cache()
     return out
 
 
@@ -610,6 +701,7 @@ def main():
         line["amr"] = amr_runs()
         line["rotation"] = rotation_runs()
         line["swirl"] = swirl_runs()
+        line["burgers"] = burgers_runs()
     if not args.no_cpu:
         v, el = cpu_baseline(data, args.cpu_steps, dt)
         line["cpu_baseline"] = {"value": v, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
