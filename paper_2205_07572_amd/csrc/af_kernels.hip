@@ -84,6 +84,27 @@ __device__ __forceinline__ void gather_block(T* lds, Src src) {
   }
 }
 
+// The same, with element e stored at lds[dst(e)].
+template <typename T, int NT, int NW, typename Dst, typename Src>
+__device__ __forceinline__ void gather_block_to(T* lds, Dst dst, Src src) {
+  constexpr int PER = (NW + NT - 1) / NT;
+  constexpr int CH = sizeof(T) == 4 ? 16 : 8;
+#pragma unroll
+  for (int c0 = 0; c0 < PER; c0 += CH) {
+    T v[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int e = int(threadIdx.x) + (c0 + u) * NT;
+      if (c0 + u < PER && ((c0 + u + 1) * NT <= NW || e < NW)) v[u] = src(e);
+    }
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const int e = int(threadIdx.x) + (c0 + u) * NT;
+      if (c0 + u < PER && ((c0 + u + 1) * NT <= NW || e < NW)) lds[dst(e)] = v[u];
+    }
+  }
+}
+
 template <typename T, int NCOMP, int NR, int NC, int NT2>
 struct StepLds {
   T in[4][NCOMP][NR][NC];
@@ -695,9 +716,16 @@ __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, co
 //    touches time sums and averages; nothing is held in registers across the
 //    barrier.
 //  * A cell's node pass loads all 27 source DOFs of its three node kinds
-//    before any arithmetic, and stores go through a select to a slot that is
-//    never read (LDS position (0, 0) of each array, below every region of
-//    every step), so the pass is branch free and pays the LDS latency once.
+//    before any arithmetic, so the pass pays the LDS latency once.
+//  * Every array has R spare rows.  Strips of R rows that run past a region
+//    store into positions that no later read touches: regions shrink by one
+//    cell per side and step, and a window reaches one cell past its region,
+//    so anything outside the current extended region, and the top-row
+//    x-edges and right-column y-edges in it, is never read again.  The
+//    strided passes store without selects.
+//  * The K steps are unrolled: region sizes and the buffer parity are
+//    compile-time, so every LDS address is a per-task base plus an
+//    immediate.
 //  * SS: both time levels of a node kind share one source cell (always true
 //    when the transverse Courant number is at most 1/2), one load feeds both
 //    dot products.
@@ -726,10 +754,10 @@ struct StripRows {
 template <typename T, int M, int K, int R>
 struct AdvLds {
   static constexpr int E = M + 2 * K + 1;
-  T av[E][E];         // averages; av followed by pt[0] forms the gather target
-  T pt[2][3][E][E];   // point values, [buffer][kind]
-  T ts[3][E][E];      // Simpson time sums n + 4 (n+1/2) + (n+1)
-  T pad[R][E];        // strips of the top region read up to R - 1 rows past an array
+  static constexpr int ER = E + R;  // rows of every array: E, then R spare rows for strips past a region
+  T av[ER][E];        // averages; av, pt[0][0..2] are the gather targets (stride ER * E)
+  T pt[2][3][ER][E];  // point values, [buffer][kind]
+  T ts[3][ER][E];     // Simpson time sums n + 4 (n+1/2) + (n+1)
 };
 
 template <typename T, int M, int K, int NT, bool UP, bool SS>
@@ -739,6 +767,7 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
   using L = AdvLds<T, M, K, R>;
   constexpr int E = L::E;
   constexpr int EE = E * E;
+  constexpr int AS = L::ER * E;  // stride between arrays
   __shared__ L S;
   __shared__ int32_t nb[9];
 
@@ -749,9 +778,9 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
   const size_t plane = size_t(M + 5) * A.pitch;
 
   // ---- gather: LDS position (r, c) holds local index (c - K, r - K);
-  // kind 0 goes to av, kinds 1..3 to pt[0][0..2] (contiguous after av)
+  // kind 0 goes to av, kinds 1..3 to pt[0][0..2] (stride AS after av)
   T* const g0 = &S.av[0][0];
-  gather_block<T, NT, 4 * EE>(g0, [&](int e) {
+  gather_block_to<T, NT, 4 * EE>(g0, [](int e) { return (e / EE) * AS + e % EE; }, [&](int e) {
     const int kind = e / EE, rem = e - kind * EE;
     const int rr = rem / E, x = rem - rr * E;
     const int j = rr - K, i = x - K;
@@ -765,7 +794,7 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
 
   const T inv36 = T(1) / T(36);
   const T cx = A.dtdx * A.a * inv36, cy = A.dtdy * A.b * inv36;
-#pragma unroll 1
+#pragma unroll
   for (int s = 0; s < K; ++s) {
     T* const avp = &S.av[0][0];
     const T* const po = &S.pt[s & 1][0][0][0];
@@ -797,14 +826,11 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
             const int o = b0 + (rr - 1) * E + (cc - 1);
             wa[rr][cc] = avp[o];
             w0[rr][cc] = po[o];
-            w1[rr][cc] = po[EE + o];
-            w2[rr][cc] = po[2 * EE + o];
+            w1[rr][cc] = po[AS + o];
+            w2[rr][cc] = po[2 * AS + o];
           }
 #pragma unroll
         for (int u = 0; u < R; ++u) {
-          const int jj = q * R + u;
-          const bool ok = tok && jj < EC;
-          const bool has_x = ok && jj < EC - 1, has_y = ok && ci < EC - 1;
           const int idx = b0 + u * E;
 #pragma unroll
           for (int k = 0; k < 3; ++k) {
@@ -818,10 +844,10 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
               f += W.w[k][1][e] * d[e];
             }
             const T own = k == NK_CORNER ? w0[u + 1][1] : (k == NK_XEDGE ? w1[u + 1][1] : w2[u + 1][1]);
-            const bool keep = k == NK_CORNER ? ok : (k == NK_XEDGE ? has_x : has_y);
-            const int o = keep ? idx : 0;
-            tsp[k * EE + o] = (own + T(4) * h) + f;
-            pn[k * EE + o] = f;
+            if (tok) {  // strips past the region store into rows no later read touches
+              tsp[k * AS + idx] = (own + T(4) * h) + f;
+              pn[k * AS + idx] = f;
+            }
           }
         }
       }
@@ -855,15 +881,15 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
             dd[2] = po[si + 1];
             dd[3] = po[si + E];
             dd[4] = po[si + E + 1];
-            dd[5] = po[EE + si];
-            dd[6] = po[EE + si + 1];
-            dd[7] = po[2 * EE + si];
-            dd[8] = po[2 * EE + si + E];
+            dd[5] = po[AS + si];
+            dd[6] = po[AS + si + 1];
+            dd[7] = po[2 * AS + si];
+            dd[8] = po[2 * AS + si + E];
           }
         }
         T own[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) own[k] = po[k * EE + idx];
+        for (int k = 0; k < 3; ++k) own[k] = po[k * AS + idx];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
           const T* dh = d[k];
@@ -876,8 +902,8 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
           }
           const bool keep = k == NK_CORNER ? ok : (k == NK_XEDGE ? has_x : has_y);
           const int o = keep ? idx : 0;
-          tsp[k * EE + o] = (own[k] + T(4) * h) + f;
-          pn[k * EE + o] = f;
+          tsp[k * AS + o] = (own[k] + T(4) * h) + f;
+          pn[k * AS + o] = f;
         }
       }
     }
@@ -898,18 +924,17 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
         T G[R + 1], FL[R], FR[R], Q[R];  // every load before the first store
 #pragma unroll
         for (int u = 0; u <= R; ++u)
-          G[u] = face_sum(tsp[b0 + u * E], tsp[2 * EE + b0 + u * E], tsp[b0 + u * E + 1]);
+          G[u] = face_sum(tsp[b0 + u * E], tsp[2 * AS + b0 + u * E], tsp[b0 + u * E + 1]);
 #pragma unroll
         for (int u = 0; u < R; ++u) {
           const int idx = b0 + u * E;
-          FL[u] = face_sum(tsp[idx], tsp[EE + idx], tsp[idx + E]);
-          FR[u] = face_sum(tsp[idx + 1], tsp[EE + idx + 1], tsp[idx + E + 1]);
+          FL[u] = face_sum(tsp[idx], tsp[AS + idx], tsp[idx + E]);
+          FR[u] = face_sum(tsp[idx + 1], tsp[AS + idx + 1], tsp[idx + E + 1]);
           Q[u] = avp[idx];
         }
+        if (tok) {  // rows past the region land in rows no later read touches
 #pragma unroll
-        for (int u = 0; u < R; ++u) {
-          const bool ok = tok && q * R + u < NC;
-          avp[ok ? b0 + u * E : 0] = (Q[u] - cx * (FR[u] - FL[u])) - cy * (G[u + 1] - G[u]);
+          for (int u = 0; u < R; ++u) avp[b0 + u * E] = (Q[u] - cx * (FR[u] - FL[u])) - cy * (G[u + 1] - G[u]);
         }
       }
     }
@@ -923,8 +948,8 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
     const int idx = (j + K) * E + (i + K);
     const size_t g = size_t(patch) * plane + size_t(j + kGhost) * A.pitch + (i + kGhost);
     A.out[1][g] = pf[idx];
-    if (j < M) A.out[2][g] = pf[EE + idx];
-    if (i < M) A.out[3][g] = pf[2 * EE + idx];
+    if (j < M) A.out[2][g] = pf[AS + idx];
+    if (i < M) A.out[3][g] = pf[2 * AS + idx];
     if (i < M && j < M) A.out[0][g] = g0[idx];
   }
 }
