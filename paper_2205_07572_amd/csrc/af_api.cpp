@@ -87,9 +87,8 @@ struct af_hier {
   std::vector<int> face_off;  // per coarse level offset into d_faces
   std::vector<CFFace> all_faces;
   bool on_device = false;     // tables are uploaded on first device use
-  // per level: 3x3 same-level neighbourhoods (built on first use); empty
-  // vector = not built, nbr_ok[l] = 0 if some neighbour is not a same-level leaf
-  std::vector<int32_t*> d_nbr;
+  // per level: -1 not checked, 1 the level is the complete row-major patch
+  // array (the level advance can run on it), 0 otherwise
   std::vector<int> nbr_ok;
   HierDev dev{};
   std::map<GraphKey, hipGraphExec_t> graphs;
@@ -361,7 +360,6 @@ af_status af_hier_destroy(af_hier* h) {
   (void)hipFree(h->d_side_mask);
   (void)hipFree(h->d_xy);
   (void)hipFree(h->d_faces);
-  for (int32_t* p : h->d_nbr) (void)hipFree(p);
   for (int4* p : h->d_plan) (void)hipFree(p);
   for (uint32_t* p : h->d_plan_flags) (void)hipFree(p);
   delete h;
@@ -688,35 +686,25 @@ af_status af_reduce_sum(af_ctx* ctx, const af_hier* h, const af_state* bufs, uin
 
 namespace {
 
-af_status level_neighbours(af_hier* h, int level, const int32_t** out) {
-  if (h->d_nbr.empty()) {
-    h->d_nbr.assign(h->H.lmax + 1, nullptr);
-    h->nbr_ok.assign(h->H.lmax + 1, -1);
-  }
+// A level the level advance can run on: it covers the periodic domain (every
+// patch has its eight neighbours on it), so its leaves are the complete
+// row-major nx x ny array of the level and neighbours are found by index.
+af_status level_grid(af_hier* h, int level, int* nx, int* ny) {
+  if (h->nbr_ok.empty()) h->nbr_ok.assign(h->H.lmax + 1, -1);
+  *nx = h->H.n0x << level;
+  *ny = h->H.n0y << level;
   if (h->nbr_ok[level] < 0) {
     const int first = h->H.level_count[level] ? h->H.level_first[level] : 0;
     const int count = h->H.level_count[level];
-    std::vector<int32_t> t(size_t(count) * 9);
-    int ok = 1;
+    int ok = count == *nx * *ny;
     for (int k = 0; k < count && ok; ++k) {
       const Leaf& L = h->H.leaves[first + k];
-      for (int dy = -1; dy <= 1; ++dy)
-        for (int dx = -1; dx <= 1; ++dx) {
-          const int id = h->H.find(level, L.ix + dx, L.iy + dy);
-          if (id < 0) ok = 0;
-          t[size_t(k) * 9 + (dy + 1) * 3 + (dx + 1)] = id;
-        }
+      ok = L.level == level && L.ix == k % *nx && L.iy == k / *nx;
     }
     h->nbr_ok[level] = ok;
-    if (ok && count) {
-      hipError_t err;
-      h->d_nbr[level] = dev_upload(t, &err);
-      if (err != hipSuccess) return fail(AF_ERR_DEVICE, "neighbour table upload");
-    }
   }
   if (!h->nbr_ok[level])
     return fail(AF_ERR_STATE, "af_level_advance: a patch of this level has a neighbour on another level");
-  *out = h->d_nbr[level];
   return AF_OK;
 }
 
@@ -782,8 +770,8 @@ af_status af_level_advance(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* ma
   const int count = h->H.level_count[level];
   if (count == 0 || nsteps == 0) return AF_OK;
   const int first = h->H.level_first[level];
-  const int32_t* nbr = nullptr;
-  if ((s = level_neighbours(h, level, &nbr)) != AF_OK) return s;
+  int nx, ny;
+  if ((s = level_grid(h, level, &nx, &ny)) != AF_OK) return s;
   int K, NT;
   default_advance_shape(ctx, &K, &NT);
   if (K == 0) return fail(AF_ERR_ARG, "no level-advance kernel for this (precision, equation, m)");
@@ -796,7 +784,8 @@ af_status af_level_advance(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* ma
   L.pitch = bufs[0].pitch;
   L.first = first;
   L.count = count;
-  L.nbr = nbr;
+  L.nx = nx;
+  L.ny = ny;
   L.dtdx = dt / dx;
   L.dtdy = dt / dy;
   L.a = ctx->P.a;
@@ -907,8 +896,8 @@ af_status af_autotune(af_ctx* ctx, af_hier* h, af_state* bufs, int32_t level, do
   if (best_step_us) *best_step_us = best;
   // level-advance shape (per step), if the level allows it
   double best_adv = -1.0;
-  const int32_t* nbr = nullptr;
-  if (s == AF_OK && level_neighbours(h, level, &nbr) == AF_OK) {
+  int gnx, gny;
+  if (s == AF_OK && level_grid(h, level, &gnx, &gny) == AF_OK) {
     int ks[32], nts[32];
     const int n = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, ks, nts, 32);
     double b2 = 1e300;

@@ -578,9 +578,19 @@ struct AdvanceArgs {
   const T* in[4];
   T* out[4];
   int32_t npatch, pitch, first;
-  const int32_t* nbr;  // [count][9]: 3x3 neighbourhood, (dy+1)*3 + (dx+1)
+  int32_t nx, ny;  // patches per side of the level; leaf first + iy * nx + ix is patch (ix, iy)
   T dtdx, dtdy, a, b, c;
 };
+
+// Patch index of the periodic neighbour (ox, oy) in {-1, 0, 1}^2 of patch
+// (ix, iy) on a complete level stored in row-major order.
+template <typename T>
+__device__ __forceinline__ int level_nbr(const AdvanceArgs<T>& A, int ix, int iy, int ox, int oy) {
+  int xx = ix + ox, yy = iy + oy;
+  xx = xx < 0 ? xx + A.nx : (xx >= A.nx ? xx - A.nx : xx);
+  yy = yy < 0 ? yy + A.ny : (yy >= A.ny ? yy - A.ny : yy);
+  return A.first + yy * A.nx + xx;
+}
 
 template <typename T, int M, int K, int NT>
 __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, const AcWeights<T> W) {
@@ -590,12 +600,10 @@ __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, co
   constexpr int CPT = (EMAX * EMAX + NT - 1) / NT;  // extended cells per thread (first step)
   __shared__ T st[4][NCOMP][E][E];
   __shared__ T ts[3][NCOMP][E][E];
-  __shared__ int32_t nb[9];
 
   const int pl = blockIdx.x;
   const int patch = A.first + pl;
-  if (threadIdx.x < 9) nb[threadIdx.x] = A.nbr[pl * 9 + threadIdx.x];
-  __syncthreads();
+  const int pix = pl % A.nx, piy = pl / A.nx;
   const size_t plane = size_t(M + 5) * A.pitch;
 
   // ---- gather: LDS position (r, c) holds local index (c - K, r - K)
@@ -606,7 +614,7 @@ __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, co
     const int j = rr - K, i = x - K;
     const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
     const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
-    const int src = nb[(oy + 1) * 3 + (ox + 1)];
+    const int src = level_nbr(A, pix, piy, ox, oy);
     const int li = i - ox * M, lj = j - oy * M;
     return A.in[kind][(size_t(comp) * A.npatch + src) * plane + size_t(lj + kGhost) * A.pitch + (li + kGhost)];
   });
@@ -769,27 +777,43 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
   constexpr int EE = E * E;
   constexpr int AS = L::ER * E;  // stride between arrays
   __shared__ L S;
-  __shared__ int32_t nb[9];
 
   const int pl = blockIdx.x;
   const int patch = A.first + pl;
-  if (threadIdx.x < 9) nb[threadIdx.x] = A.nbr[pl * 9 + threadIdx.x];
-  __syncthreads();
+  const int pix = pl % A.nx, piy = pl / A.nx;
   const size_t plane = size_t(M + 5) * A.pitch;
 
   // ---- gather: LDS position (r, c) holds local index (c - K, r - K);
-  // kind 0 goes to av, kinds 1..3 to pt[0][0..2] (stride AS after av)
+  // kind 0 goes to av, kinds 1..3 to pt[0][0..2] (stride AS after av).  A
+  // thread takes positions tid, tid + NT, ...; one source offset serves the
+  // four kinds, and every load is issued before the first store
   T* const g0 = &S.av[0][0];
-  gather_block_to<T, NT, 4 * EE>(g0, [](int e) { return (e / EE) * AS + e % EE; }, [&](int e) {
-    const int kind = e / EE, rem = e - kind * EE;
-    const int rr = rem / E, x = rem - rr * E;
-    const int j = rr - K, i = x - K;
-    const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
-    const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
-    const int src = nb[(oy + 1) * 3 + (ox + 1)];
-    const int li = i - ox * M, lj = j - oy * M;
-    return A.in[kind][size_t(src) * plane + size_t(lj + kGhost) * A.pitch + (li + kGhost)];
-  });
+  {
+    constexpr int NP = (EE + NT - 1) / NT;
+    T v[NP][4];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int e = int(threadIdx.x) + u * NT;
+      if (u + 1 < NP || EE % NT == 0 || e < EE) {
+        const int rr = e / E, x = e - rr * E;
+        const int j = rr - K, i = x - K;
+        const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
+        const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
+        const int src = level_nbr(A, pix, piy, ox, oy);
+        const size_t off = size_t(src) * plane + size_t(j - oy * M + kGhost) * A.pitch + (i - ox * M + kGhost);
+#pragma unroll
+        for (int kind = 0; kind < 4; ++kind) v[u][kind] = A.in[kind][off];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int e = int(threadIdx.x) + u * NT;
+      if (u + 1 < NP || EE % NT == 0 || e < EE) {
+#pragma unroll
+        for (int kind = 0; kind < 4; ++kind) g0[kind * AS + e] = v[u][kind];
+      }
+    }
+  }
   __syncthreads();
 
   const T inv36 = T(1) / T(36);
@@ -1467,7 +1491,7 @@ static AdvanceArgs<T> advance_args(const AdvanceLaunch& s) {
     A.in[k] = static_cast<const T*>(s.in[k]);
     A.out[k] = static_cast<T*>(s.out[k]);
   }
-  A.npatch = s.npatch; A.pitch = s.pitch; A.first = s.first; A.nbr = s.nbr;
+  A.npatch = s.npatch; A.pitch = s.pitch; A.first = s.first; A.nx = s.nx; A.ny = s.ny;
   A.dtdx = T(s.dtdx); A.dtdy = T(s.dtdy); A.a = T(s.a); A.b = T(s.b); A.c = T(s.c);
   return A;
 }

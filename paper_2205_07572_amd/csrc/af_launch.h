@@ -27,7 +27,7 @@ struct AdvanceLaunch {
   const void* in[4];
   void* out[4];
   int npatch, pitch, first, count;
-  const int32_t* nbr;
+  int nx, ny;  // patches per side of the (complete, row-major) level
   double dtdx, dtdy, a, b, c;
   const void* weights;
 };
