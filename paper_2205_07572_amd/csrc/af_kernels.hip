@@ -582,6 +582,15 @@ struct AdvanceArgs {
   T dtdx, dtdy, a, b, c;
 };
 
+// Workgroups are handed to the 8 XCDs round-robin (workgroup b to XCD b % 8),
+// each XCD with its own L2.  Block b takes patch pl so that XCD x runs the
+// contiguous run of patches [x n / 8, (x + 1) n / 8): a band of whole patch
+// rows, whose halo reads of each other's cells meet in one L2.
+__device__ __forceinline__ int xcd_patch(int b, int n) {
+  constexpr int kXcd = 8;
+  return (n % kXcd) ? b : (b % kXcd) * (n / kXcd) + b / kXcd;
+}
+
 // Patch index of the periodic neighbour (ox, oy) in {-1, 0, 1}^2 of patch
 // (ix, iy) on a complete level stored in row-major order.
 template <typename T>
@@ -601,7 +610,7 @@ __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, co
   __shared__ T st[4][NCOMP][E][E];
   __shared__ T ts[3][NCOMP][E][E];
 
-  const int pl = blockIdx.x;
+  const int pl = xcd_patch(int(blockIdx.x), int(gridDim.x));
   const int patch = A.first + pl;
   const int pix = pl % A.nx, piy = pl / A.nx;
   const size_t plane = size_t(M + 5) * A.pitch;
@@ -778,7 +787,7 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
   constexpr int AS = L::ER * E;  // stride between arrays
   __shared__ L S;
 
-  const int pl = blockIdx.x;
+  const int pl = xcd_patch(int(blockIdx.x), int(gridDim.x));
   const int patch = A.first + pl;
   const int pix = pl % A.nx, piy = pl / A.nx;
   const size_t plane = size_t(M + 5) * A.pitch;
