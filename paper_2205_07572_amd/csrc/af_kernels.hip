@@ -105,6 +105,17 @@ __device__ __forceinline__ void gather_block_to(T* lds, Dst dst, Src src) {
   }
 }
 
+// Workgroups are handed to the 8 XCDs round-robin (workgroup b to XCD b % 8),
+// each XCD with its own L2.  Block b takes work item xcd_patch(b, n), so
+// that XCD x runs the contiguous run of items [x n / 8, (x + 1) n / 8):
+// the tiles of one patch, and bands of neighbouring patches (leaves are
+// sorted by level and row), whose reads of each other's cells then meet in
+// one L2.
+__device__ __forceinline__ int xcd_patch(int b, int n) {
+  constexpr int kXcd = 8;
+  return (n % kXcd) ? b : (b % kXcd) * (n / kXcd) + b / kXcd;
+}
+
 template <typename T, int NCOMP, int NR, int NC, int NT2>
 struct StepLds {
   T in[4][NCOMP][NR][NC];
@@ -265,9 +276,10 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
   const int span = ihi - ilo;
   const int tiles = (span + TY - 1) / TY;
   const int rows = (span + tiles - 1) / tiles;  // balanced tile height, at most TY
-  const int pl = blockIdx.x / tiles;
+  const int w = xcd_patch(int(blockIdx.x), int(gridDim.x));
+  const int pl = w / tiles;
   const int patch = A.first + pl;
-  const int tile = blockIdx.x - pl * tiles;
+  const int tile = w - pl * tiles;
   const int jlo = ilo + tile * rows;
   const int jhi = min(jlo + rows, ihi);
   if (jlo >= jhi) return;  // block-uniform; cannot happen for the compiled (m, TY) pairs
@@ -581,15 +593,6 @@ struct AdvanceArgs {
   int32_t nx, ny;  // patches per side of the level; leaf first + iy * nx + ix is patch (ix, iy)
   T dtdx, dtdy, a, b, c;
 };
-
-// Workgroups are handed to the 8 XCDs round-robin (workgroup b to XCD b % 8),
-// each XCD with its own L2.  Block b takes patch pl so that XCD x runs the
-// contiguous run of patches [x n / 8, (x + 1) n / 8): a band of whole patch
-// rows, whose halo reads of each other's cells meet in one L2.
-__device__ __forceinline__ int xcd_patch(int b, int n) {
-  constexpr int kXcd = 8;
-  return (n % kXcd) ? b : (b % kXcd) * (n / kXcd) + b / kXcd;
-}
 
 // Patch index of the periodic neighbour (ox, oy) in {-1, 0, 1}^2 of patch
 // (ix, iy) on a complete level stored in row-major order.
@@ -1197,8 +1200,9 @@ struct FillArgs {
 
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_fill_apply(const FillArgs<T> A) {
-  const int tl = blockIdx.x / A.chunks;
-  const int chunk = blockIdx.x - tl * A.chunks;
+  const int w = xcd_patch(int(blockIdx.x), int(gridDim.x));
+  const int tl = w / A.chunks;
+  const int chunk = w - tl * A.chunks;
   const int t = A.first_target + tl;
   if (!((A.flags[t] >> A.phase) & 1u)) return;  // block-uniform
   const Bufs<T>& B = A.B;
