@@ -26,11 +26,18 @@ NCELL = (M * N0) ** 2
 T_FINAL = 1.0
 NSTEPS_T = 1280
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per launch of the level-advance kernel on this workload, from
-# rocprofv3 FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00 (scales from a plain 64 MiB
-# copy), keyed by (precision, K, threads); valid only for the kernel source
-# the counters were taken on (profiles/k_level_advance_adv_512sq.md).
-PROFILED_TRAFFIC = {("fp32", 8, 1024): 19.77e6, ("fp64", 4, 512): 29.66e6}
+# HBM bytes per launch of the level-advance kernel (k_level_advance_up) on
+# this workload, from rocprofv3 FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00 (scales
+# from a plain 64 MiB copy), keyed by (precision, K, threads); valid only for
+# the kernel source the counters were taken on
+# (profiles/k_level_advance_up_512sq.md holds the commands).
+PROFILED_TRAFFIC = {
+    ("fp32", 1, 256): 10.34e6, ("fp32", 2, 256): 10.54e6, ("fp32", 2, 512): 10.49e6, ("fp32", 4, 512): 10.85e6,
+    ("fp32", 4, 1024): 10.81e6, ("fp32", 5, 1024): 10.98e6, ("fp32", 6, 768): 11.21e6, ("fp32", 6, 1024): 11.16e6,
+    ("fp32", 7, 1024): 11.39e6, ("fp32", 8, 512): 11.69e6, ("fp32", 8, 1024): 11.57e6,
+    ("fp64", 1, 256): 19.89e6, ("fp64", 2, 512): 20.20e6, ("fp64", 3, 1024): 20.49e6, ("fp64", 4, 512): 20.86e6,
+    ("fp64", 4, 1024): 20.81e6, ("fp64", 5, 1024): 21.14e6,
+}
 
 
 def parse():
@@ -663,6 +670,7 @@ def main():
     # algorithmic bytes per launch: 8 words (read 4 DOFs, write 4 DOFs) per
     # cell-update, K steps of all 512^2 cells
     bytes32 = 8 * 4 * NCELL * K32
+    bytes64 = 8 * 8 * NCELL * res["fp64"]["K"]
     achieved = bytes32 / (k32 * 1e-3) / 1e9
     line = {
         "metric": "cell-updates/s (FP32 vs FP64) of batched AMR AF step; % HBM roofline; L∞ err",
@@ -684,7 +692,12 @@ def main():
                    "patches": N0 * N0, "patch_cells": M, "steps_per_launch": K32,
                    "threads_per_patch": res["fp32"]["NT"]},
         "fp64": {"value": ups64, "ms_per_step": ms64 / args.steps, "kernel_us": k64 * 1e3,
-                 "steps_per_launch": res["fp64"]["K"], "speedup_fp32_over_fp64": ups32 / ups64},
+                 "steps_per_launch": res["fp64"]["K"], "threads_per_patch": res["fp64"]["NT"],
+                 "speedup_fp32_over_fp64": ups32 / ups64,
+                 "roofline": {"bound": "hbm", "achieved": bytes64 / (k64 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                              "unit": "GB/s", "frac": bytes64 / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                              "traffic": PROFILED_TRAFFIC.get(("fp64", res["fp64"]["K"], res["fp64"]["NT"])),
+                              "kernel": f"k_level_advance_up<double,32,{res['fp64']['K']},{res['fp64']['NT']}>"}},
         "general_path_us_per_step": {"fp32": res["fp32"]["general_ms_per_step"] * 1e3,
                                      "fp64": res["fp64"]["general_ms_per_step"] * 1e3,
                                      "what": "af_ghost_fill + af_patch_step per step, hipGraph replay"},
@@ -694,7 +707,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": PROFILED_TRAFFIC.get(("fp32", K32, res["fp32"]["NT"])),
                      "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
-                     "kernel": f"k_level_advance_adv<float,32,{K32},{res['fp32']['NT']},upwind>",
+                     "kernel": f"k_level_advance_up<float,32,{K32},{res['fp32']['NT']}>",
                      "kernel_us": k32 * 1e3, "algorithmic_bytes_per_launch": bytes32},
     }
     if not args.no_amr:

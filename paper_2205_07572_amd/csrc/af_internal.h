@@ -56,7 +56,16 @@ template <typename T>
 struct AdvWeights {
   T w[3][2][kCellDofs];     // weights of the source cell's raw DOFs
   int32_t off[3][2][2];     // source cell offset (di, dj) from the owner cell
+  // Upwind pattern only (sources (-1,-1), (-1,0), (0,-1) for corner, x-edge,
+  // y-edge at both times): the new average of cell (0,0) as one linear
+  // combination of the 25 old DOFs of the source cells (-1..0) x (-1..0):
+  // index kUpA + (dj+1)*2 + (di+1) averages (di, dj in -1..0), kUpC +
+  // (dj+1)*3 + (di+1) corners (di, dj in -1..1), kUpX + (dj+1)*3 + (di+1)
+  // x-edges (di in -1..1, dj in -1..0), kUpY + (dj+1)*2 + (di+1) y-edges
+  // (di in -1..0, dj in -1..1).
+  T up_avg[25];
 };
+constexpr int kUpA = 0, kUpC = 4, kUpX = 13, kUpY = 19;
 
 // Acoustics: p = K.p - Dx.u - Dy.v ; u = K.u - Dx.p ; v = K.v - Dy.p
 // (eq. ERFormula: K is M_R + R d/dR M_R, Dx and Dy are R M_R of the x- and

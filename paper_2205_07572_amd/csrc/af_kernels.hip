@@ -749,15 +749,13 @@ __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, co
 //  * SS: both time levels of a node kind share one source cell (always true
 //    when the transverse Courant number is at most 1/2), one load feeds both
 //    dot products.
-//  * UP: the source cells are the upwind ones for a, b > 0 with both
-//    directional Courant numbers below 1/2 -- corner (i-1, j-1), x-edge
-//    (i-1, j), y-edge (i, j-1) -- known at compile time, so every LDS address
-//    is one base plus an immediate and the 27 loads reduce to 21 distinct
-//    ones.  UP implies SS.
+//  * The upwind pattern (a, b > 0 with both directional Courant numbers
+//    below 1/2: sources corner (i-1, j-1), x-edge (i-1, j), y-edge (i, j-1))
+//    runs in k_level_advance_up instead, one pass per step.
 //  * A wave whose 64 cells of a slot all lie outside the region skips it.
 // ---------------------------------------------------------------------------
 
-// Source-cell offset (d = 0: di, d = 1: dj) of the UP pattern for node kind k.
+// Source-cell offset (d = 0: di, d = 1: dj) of the upwind pattern for node kind k.
 __host__ __device__ constexpr int up_off(int k, int d) { return k == NK_CORNER ? -1 : (k == NK_XEDGE ? d - 1 : -d); }
 
 // Rows per strip: a thread takes R vertically adjacent cells of one column,
@@ -780,9 +778,8 @@ struct AdvLds {
   T ts[3][ER][E];     // Simpson time sums n + 4 (n+1/2) + (n+1)
 };
 
-template <typename T, int M, int K, int NT, bool UP, bool SS>
+template <typename T, int M, int K, int NT, bool SS>
 __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A, const AdvWeights<T> W) {
-  static_assert(SS || !UP, "the upwind pattern shares its source cells");
   constexpr int R = StripRows<M, K, NT>::value;
   using L = AdvLds<T, M, K, R>;
   constexpr int E = L::E;
@@ -841,106 +838,53 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
     const int base = (lo + K) * (E + 1);      // LDS index of the first extended cell
     const int nslot = (EC * EC + NT - 1) / NT;
     // ---- node values of the extended cells
-    if constexpr (UP) {
-      // strips of R rows: task t -> column t % EC, strip t / EC; the window
-      // holds rows [rb-1, rb+R] and columns [c-1, c+1] of every array (the
-      // loads that no cell uses are dropped by the compiler)
-      const int ns = (EC + R - 1) / R;
-      const int ntask = EC * ns;
+    Walk2 w(threadIdx.x, NT, EC);
 #pragma unroll 1
-      for (int t0 = 0; t0 + int(threadIdx.x & ~63u) < ntask; t0 += NT) {  // wave-uniform
-        const int t = t0 + int(threadIdx.x);
-        const bool tok = t < ntask;
-        const int q = tok ? t / EC : 0;
-        const int ci = tok ? t - q * EC : 0;
-        const int b0 = base + q * R * E + ci;
-        T wa[R + 2][3], w0[R + 2][3], w1[R + 2][3], w2[R + 2][3];
+    for (int u = 0; u < nslot; ++u, w.next()) {
+      if (u * NT + int(threadIdx.x & ~63u) >= EC * EC) break;  // wave-uniform
+      const bool ok = w.y < EC;
+      const int ii = ok ? w.x : 0, jj = ok ? w.y : 0;
+      const int idx = base + jj * E + ii;
+      const bool has_x = ok && jj < EC - 1, has_y = ok && ii < EC - 1;
+      T d[3][9], d1[3][9];
 #pragma unroll
-        for (int rr = 0; rr < R + 2; ++rr)
+      for (int k = 0; k < 3; ++k) {
 #pragma unroll
-          for (int cc = 0; cc < 3; ++cc) {
-            const int o = b0 + (rr - 1) * E + (cc - 1);
-            wa[rr][cc] = avp[o];
-            w0[rr][cc] = po[o];
-            w1[rr][cc] = po[AS + o];
-            w2[rr][cc] = po[2 * AS + o];
-          }
-#pragma unroll
-        for (int u = 0; u < R; ++u) {
-          const int idx = b0 + u * E;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const int wr = u + 1 + up_off(k, 1), wc = 1 + up_off(k, 0);  // source cell in the window
-            const T d[9] = {wa[wr][wc],     w0[wr][wc],     w0[wr][wc + 1], w0[wr + 1][wc], w0[wr + 1][wc + 1],
-                            w1[wr][wc],     w1[wr][wc + 1], w2[wr][wc],     w2[wr + 1][wc]};
-            T h = W.w[k][0][0] * d[0], f = W.w[k][1][0] * d[0];
-#pragma unroll
-            for (int e = 1; e < 9; ++e) {
-              h += W.w[k][0][e] * d[e];
-              f += W.w[k][1][e] * d[e];
-            }
-            const T own = k == NK_CORNER ? w0[u + 1][1] : (k == NK_XEDGE ? w1[u + 1][1] : w2[u + 1][1]);
-            if (tok) {  // strips past the region store into rows no later read touches
-              tsp[k * AS + idx] = (own + T(4) * h) + f;
-              pn[k * AS + idx] = f;
-            }
-          }
+        for (int t = 0; t < (SS ? 1 : 2); ++t) {
+          // source cell; the clamp only moves sources of nodes that are not
+          // kept (top-row x-edge, right-column y-edge), so that their DOFs
+          // (r + 1, c + 1) stay inside the array
+          int si = idx + W.off[k][t][1] * E + W.off[k][t][0];
+          si = min(si, EE - E - 2);
+          T* dd = t ? d1[k] : d[k];
+          dd[0] = avp[si];
+          dd[1] = po[si];
+          dd[2] = po[si + 1];
+          dd[3] = po[si + E];
+          dd[4] = po[si + E + 1];
+          dd[5] = po[AS + si];
+          dd[6] = po[AS + si + 1];
+          dd[7] = po[2 * AS + si];
+          dd[8] = po[2 * AS + si + E];
         }
       }
-    } else {
-      Walk2 w(threadIdx.x, NT, EC);
-#pragma unroll 1
-      for (int u = 0; u < nslot; ++u, w.next()) {
-        if (u * NT + int(threadIdx.x & ~63u) >= EC * EC) break;  // wave-uniform
-        const bool ok = w.y < EC;
-        const int ii = ok ? w.x : 0, jj = ok ? w.y : 0;
-        const int idx = base + jj * E + ii;
-        const bool has_x = ok && jj < EC - 1, has_y = ok && ii < EC - 1;
-        T d[3][9], d1[3][9];
+      T own[3];
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
+      for (int k = 0; k < 3; ++k) own[k] = po[k * AS + idx];
 #pragma unroll
-          for (int t = 0; t < (SS ? 1 : 2); ++t) {
-            // source cell; the clamp only moves sources of nodes that are not
-            // kept (top-row x-edge, right-column y-edge), so that their DOFs
-            // (r + 1, c + 1) stay inside the array
-            int si;
-            if constexpr (UP) {
-              si = idx + up_off(k, 1) * E + up_off(k, 0);  // in range: the top and right sources are row/column E-2
-            } else {
-              si = idx + W.off[k][t][1] * E + W.off[k][t][0];
-              si = min(si, EE - E - 2);
-            }
-            T* dd = t ? d1[k] : d[k];
-            dd[0] = avp[si];
-            dd[1] = po[si];
-            dd[2] = po[si + 1];
-            dd[3] = po[si + E];
-            dd[4] = po[si + E + 1];
-            dd[5] = po[AS + si];
-            dd[6] = po[AS + si + 1];
-            dd[7] = po[2 * AS + si];
-            dd[8] = po[2 * AS + si + E];
-          }
+      for (int k = 0; k < 3; ++k) {
+        const T* dh = d[k];
+        const T* df = SS ? d[k] : d1[k];
+        T h = W.w[k][0][0] * dh[0], f = W.w[k][1][0] * df[0];
+#pragma unroll
+        for (int e = 1; e < 9; ++e) {
+          h += W.w[k][0][e] * dh[e];
+          f += W.w[k][1][e] * df[e];
         }
-        T own[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) own[k] = po[k * AS + idx];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const T* dh = d[k];
-          const T* df = SS ? d[k] : d1[k];
-          T h = W.w[k][0][0] * dh[0], f = W.w[k][1][0] * df[0];
-#pragma unroll
-          for (int e = 1; e < 9; ++e) {
-            h += W.w[k][0][e] * dh[e];
-            f += W.w[k][1][e] * df[e];
-          }
-          const bool keep = k == NK_CORNER ? ok : (k == NK_XEDGE ? has_x : has_y);
-          const int o = keep ? idx : 0;
-          tsp[k * AS + o] = (own[k] + T(4) * h) + f;
-          pn[k * AS + o] = f;
-        }
+        const bool keep = k == NK_CORNER ? ok : (k == NK_XEDGE ? has_x : has_y);
+        const int o = keep ? idx : 0;
+        tsp[k * AS + o] = (own[k] + T(4) * h) + f;
+        pn[k * AS + o] = f;
       }
     }
     __syncthreads();
@@ -987,6 +931,158 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
     if (j < M) A.out[2][g] = pf[AS + idx];
     if (i < M) A.out[3][g] = pf[2 * AS + idx];
     if (i < M && j < M) A.out[0][g] = g0[idx];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Level advance for advection with the upwind source pattern in one pass per
+// step.  With constant velocity each node value at t + dt/2 and t + dt is a
+// fixed combination of its source cell's DOFs, so the update of eq. 2dfv
+// over the Simpson sums (eq. Simpson-2d) of a cell's eight face nodes is one
+// fixed combination of the 25 old DOFs of its source cells (-1..0)^2,
+// composed on the host (AdvWeights::up_avg).  A cell's new average and its
+// three new node values come from the same window of old DOFs.  Averages
+// and point values are double-buffered: a step reads buffer s & 1, writes
+// the other, and needs one barrier and no time sums.  Strips, spare rows and
+// the unrolled steps are those of k_level_advance_adv; the positions a step
+// leaves stale (x-edges on the top row and averages on the outer ring of its
+// extended region, anything past it) are the ones no later window uses.
+// ---------------------------------------------------------------------------
+template <typename T, int M, int K, int R>
+struct UpLds {
+  static constexpr int E = M + 2 * K + 1;
+  static constexpr int ER = E + R;  // rows of every array: E, then R spare rows
+  T q[2][4][ER][E];                 // [buffer][average, corner, x-edge, y-edge]
+};
+
+template <typename T, int M, int K, int NT>
+__global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A, const AdvWeights<T> W) {
+  constexpr int R = StripRows<M, K, NT>::value;
+  using L = UpLds<T, M, K, R>;
+  constexpr int E = L::E;
+  constexpr int EE = E * E;
+  constexpr int AS = L::ER * E;  // stride between arrays
+  __shared__ L S;
+
+  const int pl = xcd_patch(int(blockIdx.x), int(gridDim.x));
+  const int patch = A.first + pl;
+  const int pix = pl % A.nx, piy = pl / A.nx;
+  const size_t plane = size_t(M + 5) * A.pitch;
+
+  // ---- gather into buffer 0: LDS position (r, c) holds local index
+  // (c - K, r - K); one source offset serves the four kinds
+  T* const g0 = &S.q[0][0][0][0];
+  {
+    constexpr int NP = (EE + NT - 1) / NT;
+    T v[NP][4];
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int e = int(threadIdx.x) + u * NT;
+      if (u + 1 < NP || EE % NT == 0 || e < EE) {
+        const int rr = e / E, x = e - rr * E;
+        const int j = rr - K, i = x - K;
+        const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
+        const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
+        const int src = level_nbr(A, pix, piy, ox, oy);
+        const size_t off = size_t(src) * plane + size_t(j - oy * M + kGhost) * A.pitch + (i - ox * M + kGhost);
+#pragma unroll
+        for (int kind = 0; kind < 4; ++kind) v[u][kind] = A.in[kind][off];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int e = int(threadIdx.x) + u * NT;
+      if (u + 1 < NP || EE % NT == 0 || e < EE) {
+#pragma unroll
+        for (int kind = 0; kind < 4; ++kind) g0[kind * AS + e] = v[u][kind];
+      }
+    }
+  }
+  __syncthreads();
+
+#pragma unroll
+  for (int s = 0; s < K; ++s) {
+    const T* const qo = &S.q[s & 1][0][0][0];
+    T* const qn = &S.q[(s + 1) & 1][0][0][0];
+    const int lo = -(K - 1 - s);
+    const int EC = M + 2 * (K - 1 - s) + 1;  // extended cells per side
+    const int base = (lo + K) * (E + 1);      // LDS index of the first extended cell
+    const int ns = (EC + R - 1) / R;
+    const int ntask = EC * ns;
+    // strips of R rows: task t -> column t % EC, strip t / EC; the window
+    // holds rows [rb-1, rb+R] and columns [c-1, c+1] of every array
+#pragma unroll 1
+    for (int t0 = 0; t0 + int(threadIdx.x & ~63u) < ntask; t0 += NT) {  // wave-uniform
+      const int t = t0 + int(threadIdx.x);
+      const bool tok = t < ntask;
+      const int q = tok ? t / EC : 0;
+      const int ci = tok ? t - q * EC : 0;
+      const int b0 = base + q * R * E + ci;
+      T wa[R + 2][3], w0[R + 2][3], w1[R + 2][3], w2[R + 2][3];
+#pragma unroll
+      for (int rr = 0; rr < R + 2; ++rr)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          const int o = b0 + (rr - 1) * E + (cc - 1);
+          wa[rr][cc] = qo[o];
+          w0[rr][cc] = qo[AS + o];
+          w1[rr][cc] = qo[2 * AS + o];
+          w2[rr][cc] = qo[3 * AS + o];
+        }
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        // new node values at t + dt from the upwind source cells
+        T f[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const int wr = u + 1 + up_off(k, 1), wc = 1 + up_off(k, 0);
+          const T d[9] = {wa[wr][wc],     w0[wr][wc],     w0[wr][wc + 1], w0[wr + 1][wc], w0[wr + 1][wc + 1],
+                          w1[wr][wc],     w1[wr][wc + 1], w2[wr][wc],     w2[wr + 1][wc]};
+          T v = W.w[k][1][0] * d[0];
+#pragma unroll
+          for (int e = 1; e < 9; ++e) v += W.w[k][1][e] * d[e];
+          f[k] = v;
+        }
+        // new average: the 25 old DOFs of the source cells (-1..0)^2
+        T avg = T(0);
+#pragma unroll
+        for (int dj = -1; dj <= 0; ++dj)
+#pragma unroll
+          for (int di = -1; di <= 0; ++di) avg += W.up_avg[kUpA + (dj + 1) * 2 + (di + 1)] * wa[u + 1 + dj][1 + di];
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+          for (int di = -1; di <= 1; ++di) avg += W.up_avg[kUpC + (dj + 1) * 3 + (di + 1)] * w0[u + 1 + dj][1 + di];
+#pragma unroll
+        for (int dj = -1; dj <= 0; ++dj)
+#pragma unroll
+          for (int di = -1; di <= 1; ++di) avg += W.up_avg[kUpX + (dj + 1) * 3 + (di + 1)] * w1[u + 1 + dj][1 + di];
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+          for (int di = -1; di <= 0; ++di) avg += W.up_avg[kUpY + (dj + 1) * 2 + (di + 1)] * w2[u + 1 + dj][1 + di];
+        if (tok) {  // strips past the region store into rows no later read touches
+          const int idx = b0 + u * E;
+          qn[idx] = avg;
+          qn[AS + idx] = f[0];
+          qn[2 * AS + idx] = f[1];
+          qn[3 * AS + idx] = f[2];
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- write the interior averages and the closed-square nodes
+  const T* const qf = &S.q[K & 1][0][0][0];
+  for (Walk2 w(threadIdx.x, NT, M + 1); w.y < M + 1; w.next()) {
+    const int i = w.x, j = w.y;
+    const int idx = (j + K) * E + (i + K);
+    const size_t g = size_t(patch) * plane + size_t(j + kGhost) * A.pitch + (i + kGhost);
+    A.out[1][g] = qf[AS + idx];
+    if (j < M) A.out[2][g] = qf[2 * AS + idx];
+    if (i < M) A.out[3][g] = qf[3 * AS + idx];
+    if (i < M && j < M) A.out[0][g] = qf[idx];
   }
 }
 
@@ -1522,11 +1618,11 @@ static hipError_t launch_adv_t(const AdvanceLaunch& s, hipStream_t st) {
         up = up && W.off[k][t][0] == up_off(k, 0) && W.off[k][t][1] == up_off(k, 1);
       }
     if (up)
-      hipLaunchKernelGGL((k_level_advance_adv<T, M, K, NT, true, true>), grid, dim3(NT), 0, st, A, W);
+      hipLaunchKernelGGL((k_level_advance_up<T, M, K, NT>), grid, dim3(NT), 0, st, A, W);
     else if (ss)
-      hipLaunchKernelGGL((k_level_advance_adv<T, M, K, NT, false, true>), grid, dim3(NT), 0, st, A, W);
+      hipLaunchKernelGGL((k_level_advance_adv<T, M, K, NT, true>), grid, dim3(NT), 0, st, A, W);
     else
-      hipLaunchKernelGGL((k_level_advance_adv<T, M, K, NT, false, false>), grid, dim3(NT), 0, st, A, W);
+      hipLaunchKernelGGL((k_level_advance_adv<T, M, K, NT, false>), grid, dim3(NT), 0, st, A, W);
   } else {
     hipLaunchKernelGGL((k_level_advance<T, M, K, NT>), grid, dim3(NT), 0, st, A,
                        *static_cast<const AcWeights<T>*>(s.weights));
@@ -1539,9 +1635,11 @@ static hipError_t launch_adv_t(const AdvanceLaunch& s, hipStream_t st) {
 // E = m + 2K + 1.
 #define AF_ADV_SHAPES(X)                                                                                 \
   X(float, 0, 32, 1, 256) X(float, 0, 32, 2, 256) X(float, 0, 32, 2, 512) X(float, 0, 32, 4, 512)      \
-  X(float, 0, 32, 4, 1024) X(float, 0, 32, 6, 1024) X(float, 0, 32, 8, 512) X(float, 0, 32, 8, 1024)   \
+  X(float, 0, 32, 4, 1024) X(float, 0, 32, 5, 1024) X(float, 0, 32, 6, 768) X(float, 0, 32, 6, 1024)   \
+  X(float, 0, 32, 7, 1024) X(float, 0, 32, 8, 512) X(float, 0, 32, 8, 1024)                             \
   X(float, 0, 16, 1, 256) X(float, 0, 16, 2, 256) X(float, 0, 16, 4, 256) X(float, 0, 16, 8, 256)      \
-  X(double, 0, 32, 1, 256) X(double, 0, 32, 2, 512) X(double, 0, 32, 4, 512) X(double, 0, 32, 4, 1024) \
+  X(double, 0, 32, 1, 256) X(double, 0, 32, 2, 512) X(double, 0, 32, 3, 1024) X(double, 0, 32, 4, 512) \
+  X(double, 0, 32, 4, 1024) X(double, 0, 32, 5, 1024)                                                   \
   X(double, 0, 16, 1, 256) X(double, 0, 16, 2, 256) X(double, 0, 16, 4, 256)                            \
   X(float, 1, 16, 1, 256) X(float, 1, 16, 2, 256) X(float, 1, 32, 1, 512) X(float, 1, 32, 2, 512)      \
   X(double, 1, 16, 1, 256) X(double, 1, 16, 2, 256)

@@ -145,6 +145,8 @@ void adv_locate(double node, double disp, int* off, double* ref) {
 template <typename T>
 void make_adv_weights(double a_dtdx, double b_dtdy, AdvWeights<T>* W) {
   static const double node_pos[3][2] = {{-0.5, -0.5}, {-0.5, 0.0}, {0.0, -0.5}};
+  double wd[3][2][kCellDofs];
+  bool up = true;
   for (int kind = 0; kind < 3; ++kind)
     for (int t = 0; t < 2; ++t) {
       const double frac = t == 0 ? 0.5 : 1.0;
@@ -154,8 +156,45 @@ void make_adv_weights(double a_dtdx, double b_dtdy, AdvWeights<T>* W) {
       adv_locate(node_pos[kind][1], -b_dtdy * frac, &oy, &eta);
       W->off[kind][t][0] = ox;
       W->off[kind][t][1] = oy;
-      for (int d = 0; d < kCellDofs; ++d) W->w[kind][t][d] = T(poly_eval(dof_basis(d), xi, eta));
+      up = up && ox == (kind == 2 ? 0 : -1) && oy == (kind == 1 ? 0 : -1);
+      for (int d = 0; d < kCellDofs; ++d) {
+        wd[kind][t][d] = poly_eval(dof_basis(d), xi, eta);
+        W->w[kind][t][d] = T(wd[kind][t][d]);
+      }
     }
+  // Upwind pattern: compose the update of eq. 2dfv with the Simpson sums
+  // (eq. Simpson-2d) of the eight face nodes of cell (0,0), each node's
+  // half- and full-time values being its source cell's weights.
+  double acc[25] = {};
+  auto idx = [](int kind, int di, int dj) {
+    switch (kind) {
+      case 0: return kUpA + (dj + 1) * 2 + (di + 1);
+      case 1: return kUpC + (dj + 1) * 3 + (di + 1);
+      case 2: return kUpX + (dj + 1) * 3 + (di + 1);
+      default: return kUpY + (dj + 1) * 2 + (di + 1);
+    }
+  };
+  // raw DOF d of a cell: state kind and offset from the cell
+  static const int dof_kind[9] = {0, 1, 1, 1, 1, 2, 2, 3, 3};
+  static const int dof_off[9][2] = {{0, 0}, {0, 0}, {1, 0}, {0, 1}, {1, 1}, {0, 0}, {1, 0}, {0, 0}, {0, 1}};
+  // adds c * (time sum of node kind nk owned by cell (oi, oj)) to acc
+  auto add_tsum = [&](int nk, int oi, int oj, double c) {
+    acc[idx(nk + 1, oi, oj)] += c;  // the node at time n
+    const int si = oi + (nk == 2 ? 0 : -1), sj = oj + (nk == 1 ? 0 : -1);
+    for (int d = 0; d < kCellDofs; ++d)
+      acc[idx(dof_kind[d], si + dof_off[d][0], sj + dof_off[d][1])] += c * (4.0 * wd[nk][0][d] + wd[nk][1][d]);
+  };
+  const double cx = a_dtdx / 36.0, cy = b_dtdy / 36.0;
+  acc[idx(0, 0, 0)] += 1.0;
+  // -cx (FR - FL): FR over corner (1,0), x-edge (1,0), corner (1,1); FL over
+  // corner (0,0), x-edge (0,0), corner (0,1); weights 1, 4, 1
+  add_tsum(0, 1, 0, -cx); add_tsum(1, 1, 0, -4.0 * cx); add_tsum(0, 1, 1, -cx);
+  add_tsum(0, 0, 0, cx); add_tsum(1, 0, 0, 4.0 * cx); add_tsum(0, 0, 1, cx);
+  // -cy (GT - GB): GT over corner (0,1), y-edge (0,1), corner (1,1); GB over
+  // corner (0,0), y-edge (0,0), corner (1,0)
+  add_tsum(0, 0, 1, -cy); add_tsum(2, 0, 1, -4.0 * cy); add_tsum(0, 1, 1, -cy);
+  add_tsum(0, 0, 0, cy); add_tsum(2, 0, 0, 4.0 * cy); add_tsum(0, 1, 0, cy);
+  for (int e = 0; e < 25; ++e) W->up_avg[e] = up ? T(acc[e]) : T(0);
 }
 
 template <typename T>
