@@ -254,3 +254,33 @@ def test_burgers_adaptive_run_with_tag_replay():
     err = rel_linf(run.blocks(), oracle_blocks(o), closed_masks(m))
     assert err.max() <= FP64_TOL, err
     assert changed >= 1
+
+
+def test_burgers_full_size_level6():
+    """The timed configuration at full size: uniform level 6 (1024^2 as
+    32^2 patches), eq. sinsin01, general path, two steps at CFL 0.5 against
+    the oracle's periodic 1024^2 grid, every DOF compared."""
+    import torch
+    from harness import periodic_interior
+    print("[gpu-burgers] full size level 6", flush=True)
+    m, N = 32, 1024
+    n0 = N // m
+    data = afsynth.burgers_sinsin()
+    prob = _problem(af.FP64, m, n0)
+    ctx = af.Context(prob)
+    leaves = afsynth.uniform_leaves(n0, n0, 0)
+    h = af.Hierarchy(ctx, leaves)
+    d0 = afsynth.dofs_periodic(data, N, N, nq=4)
+    blk = afsynth.periodic_to_blocks(d0, m)
+    b0 = af.blocks_to_state(ctx, [{k: blk[k][p] for k in KINDS} for p in range(n0 * n0)])
+    bufs = [b0, torch.zeros_like(b0)]
+    reg = torch.zeros((len(leaves), 4, m, 1), dtype=torch.float64, device="cuda")
+    dt = 0.05 / math.ceil(0.05 / (0.5 / N / QMAX))
+    mask = 0
+    for _ in range(2):
+        mask = ctx.amr_coarse_step(h, bufs, mask, dt, reg)
+    g = periodic_interior(af.state_to_blocks(ctx, bufs[mask & 1]), leaves, m, n0)
+    ref = oracle.run_periodic(4, d0, dt, 2)
+    err = max(np.abs(g[k][0] - ref[k][0]).max() for k in KINDS) / np.abs(ref["avg"][0]).max()
+    print(f"[gpu-burgers] full size rel L-inf {err:.2e}", flush=True)
+    assert err <= FP64_TOL

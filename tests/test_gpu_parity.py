@@ -435,6 +435,46 @@ def test_full_size_config2_sampled(prec):
     assert err <= (FP64_TOL if prec == af.FP64 else 2e-6), err
 
 
+@pytest.mark.parametrize("prec", [af.FP64, af.FP32])
+def test_full_size_config2_level_advance(prec):
+    """The benchmark's timed path at full size: 16x16 patches of 32x32 cells
+    (512^2), seeded 8-mode Fourier data, the autotuner's level-advance shape
+    (as bench.py picks it), 2K + 1 steps (full launches and a tail) against
+    the oracle's single 512^2 periodic grid, every DOF compared."""
+    torch = _torch()
+    m, n0 = 32, 16
+    N = m * n0
+    prob = make_problem(0, prec, m, n0=n0, a=1.0, b=0.5)
+    ctx = af.Context(prob)
+    data = afsynth.fourier_modes(0)
+    leaves = afsynth.uniform_leaves(n0, n0, 0)
+    d0 = afsynth.dofs_periodic(data, N, N, nq=4)
+    if prec == af.FP32:
+        d0 = {k: (v.astype(np.float32).astype(np.float64) if isinstance(v, np.ndarray) else v)
+              for k, v in d0.items()}
+    blocks = afsynth.periodic_to_blocks(d0, m)
+    blocks = [{k: blocks[k][p] for k in KINDS} for p in range(n0 * n0)]
+    h = af.Hierarchy(ctx, leaves)
+    b0 = af.blocks_to_state(ctx, blocks)
+    dt = 1.0 / 1280
+    ctx.autotune(h, [b0.clone(), torch.zeros_like(b0)], 0, dt, reps=3)
+    K, NT = ctx.advance_shape
+    assert K > 0
+    nsteps = 2 * K + 1
+    print(f"[gpu-parity] full size config 2 level advance prec={prec} K={K} NT={NT} steps={nsteps}", flush=True)
+    bufs = [b0, torch.zeros_like(b0)]
+    mask = ctx.level_advance(h, bufs, 0, 0, dt, nsteps)
+    torch.cuda.synchronize()
+    got = af.state_to_blocks(ctx, bufs[mask & 1])
+    ref = oracle.run_periodic(0, d0, dt, nsteps, a=1.0, b=0.5)
+    g = periodic_interior(got, leaves, m, n0)
+    err = max(np.abs(g[k][0] - ref[k][0]).max() for k in KINDS) / np.abs(ref["avg"][0]).max()
+    print(f"[gpu-parity] full size config 2 level advance prec={prec}: rel Linf {err}", flush=True)
+    # FP32: rounding accumulates step by step; about 5 units of FP32 rounding
+    # (6e-8) per step (the 4-step general-path run measures 1.5e-7 per step)
+    assert err <= (FP64_TOL if prec == af.FP64 else 3e-7 * nsteps), err
+
+
 def test_edge_cases_and_errors():
     torch = _torch()
     prob = make_problem(0, af.FP64, 16, n0=2, a=1.0, b=0.5)

@@ -269,3 +269,35 @@ def test_rotation_adaptive_run_with_tag_replay():
     err = rel_linf(run.blocks(), oracle_blocks(o), closed_masks(m))
     assert err.max() <= FP64_TOL, err
     assert changed >= 2
+
+
+def test_rotation_full_size_level6():
+    """The timed configuration at full size: uniform level 6 (1024^2 as
+    32^2 patches) on [-1, 1]^2, general path, two steps at Courant number 0.6
+    against the oracle's periodic 1024^2 grid, every DOF compared."""
+    import math
+    import torch
+    print("[gpu-rotation] full size level 6", flush=True)
+    m, N = 32, 1024
+    n0 = N // m
+    data = afsynth.solid_body(afsynth.disc_q0(0.15, 0.02, 0.5, 0.5), OMEGA)
+    prob = _problem(af.FP64, m, n0)
+    ctx = af.Context(prob)
+    leaves = afsynth.uniform_leaves(n0, n0, 0)
+    h = af.Hierarchy(ctx, leaves)
+    d0 = afsynth.dofs_periodic(data, N, N, x0=-1.0, y0=-1.0, lx=2.0, ly=2.0, nq=4)
+    blk = afsynth.periodic_to_blocks(d0, m)
+    b0 = af.blocks_to_state(ctx, [{k: blk[k][p] for k in KINDS} for p in range(n0 * n0)])
+    bufs = [b0, torch.zeros_like(b0)]
+    reg = torch.zeros((len(leaves), 4, m, 1), dtype=torch.float64, device="cuda")
+    dt = 1.0 / math.ceil(1.0 / (0.6 * (2.0 / N) / OMEGA))
+    mask = 0
+    for _ in range(2):
+        mask = ctx.amr_coarse_step(h, bufs, mask, dt, reg)
+    got = af.state_to_blocks(ctx, bufs[mask & 1])
+    from harness import periodic_interior
+    g = periodic_interior(got, leaves, m, n0)
+    ref = oracle.run_periodic_rot(d0, dt, 2, OMEGA, x0=-1.0, y0=-1.0)
+    err = max(np.abs(g[k][0] - ref[k][0]).max() for k in KINDS) / np.abs(ref["avg"][0]).max()
+    print(f"[gpu-rotation] full size rel L-inf {err:.2e}", flush=True)
+    assert err <= FP64_TOL
