@@ -162,35 +162,74 @@ __device__ __forceinline__ void adv_eval2(const T (&s)[4][1][NR][NC], int r, int
   *f = b;
 }
 
-// Acoustic node evaluation over a fixed neighbourhood table.
-template <typename T, int NR, int NC, int NB>
-__device__ __forceinline__ void ac_eval(const T (&s)[4][3][NR][NC], int r, int c,
-                                        const NbEntry (&tab)[NB], const T (&w)[2][3][NB],
-                                        T out[2][3]) {
-  T p[NB], u[NB], v[NB];
+// Acoustic node evaluation (eq. ERFormula with the sector weights collapsed
+// on the host): the neighbourhood walked row by row.  Each table is four
+// rectangles of source offsets, one per DOF kind, listed row by row (checked
+// below), so entry e follows from (kind, row, column).  Fully unrolled, the
+// three node kinds keep 330 weights live, more than the scalar registers
+// hold, and the compiler parks them in vector lanes and reads each back
+// before its use.  Here the rows are a loop that is not unrolled: the
+// weights of a row are uniform loads issued in the iteration that uses them.
+struct NbRect {
+  int di0, di1, dj0, dj1;
+};
+constexpr NbRect kNbRects[3][4] = {
+    {{-1, 0, -1, 0}, {-1, 1, -1, 1}, {-1, 1, -1, 0}, {-1, 0, -1, 1}},  // corner
+    {{-1, 0, 0, 0}, {-1, 1, 0, 1}, {-1, 1, 0, 0}, {-1, 0, 0, 1}},      // x-edge
+    {{0, 0, -1, 0}, {0, 1, -1, 1}, {0, 1, -1, 0}, {0, 0, -1, 1}}};     // y-edge
+
+template <int NB>
+constexpr bool rects_match(int nk, const NbEntry (&tab)[NB]) {
+  int e = 0;
+  for (int kind = 0; kind < 4; ++kind) {
+    const NbRect R = kNbRects[nk][kind];
+    for (int dj = R.dj0; dj <= R.dj1; ++dj)
+      for (int di = R.di0; di <= R.di1; ++di, ++e)
+        if (e >= NB || tab[e].kind != kind || tab[e].di != di || tab[e].dj != dj) return false;
+  }
+  return e == NB;
+}
+static_assert(rects_match(0, kNbCornerTab) && rects_match(1, kNbXedgeTab) && rects_match(2, kNbYedgeTab),
+              "neighbourhood tables are four row-major rectangles");
+
+template <typename T, int NR, int NC, int NK, int NB>
+__device__ __forceinline__ void ac_eval_rows(const T (&s)[4][3][NR][NC], int r, int c, const T (&w)[2][3][NB],
+                                             T out[2][3]) {
+  T kp[2] = {T(0), T(0)}, ku[2] = {T(0), T(0)}, kv[2] = {T(0), T(0)};
+  T dxu[2] = {T(0), T(0)}, dyv[2] = {T(0), T(0)}, dxp[2] = {T(0), T(0)}, dyp[2] = {T(0), T(0)};
+  int ebase = 0;
 #pragma unroll
-  for (int e = 0; e < NB; ++e) {
-    const int k = tab[e].kind, rr = r + tab[e].dj, cc = c + tab[e].di;
-    p[e] = s[k][0][rr][cc];
-    u[e] = s[k][1][rr][cc];
-    v[e] = s[k][2][rr][cc];
+  for (int kind = 0; kind < 4; ++kind) {
+    const NbRect R = kNbRects[NK][kind];
+    const int ndi = R.di1 - R.di0 + 1;
+#pragma unroll 1
+    for (int dj = R.dj0; dj <= R.dj1; ++dj) {
+      const int e0 = ebase + (dj - R.dj0) * ndi;
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        if (q >= ndi) break;
+        const int di = R.di0 + q;
+        const T p = s[kind][0][r + dj][c + di], u = s[kind][1][r + dj][c + di], v = s[kind][2][r + dj][c + di];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const T wk = w[t][0][e0 + q], wx = w[t][1][e0 + q], wy = w[t][2][e0 + q];
+          kp[t] += wk * p;
+          ku[t] += wk * u;
+          kv[t] += wk * v;
+          dxu[t] += wx * u;
+          dyv[t] += wy * v;
+          dxp[t] += wx * p;
+          dyp[t] += wy * p;
+        }
+      }
+    }
+    ebase += ndi * (R.dj1 - R.dj0 + 1);
   }
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
-    T kp = 0, ku = 0, kv = 0, dxu = 0, dyv = 0, dxp = 0, dyp = 0;
-#pragma unroll
-    for (int e = 0; e < NB; ++e) {
-      kp += w[t][0][e] * p[e];
-      ku += w[t][0][e] * u[e];
-      kv += w[t][0][e] * v[e];
-      dxu += w[t][1][e] * u[e];
-      dyv += w[t][2][e] * v[e];
-      dxp += w[t][1][e] * p[e];
-      dyp += w[t][2][e] * p[e];
-    }
-    out[t][0] = kp - dxu - dyv;
-    out[t][1] = ku - dxp;
-    out[t][2] = kv - dyp;
+    out[t][0] = kp[t] - dxu[t] - dyv[t];
+    out[t][1] = ku[t] - dxp[t];
+    out[t][2] = kv[t] - dyp[t];
   }
 }
 
@@ -426,14 +465,14 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
       }
     } else {
       T res[2][3];
-      ac_eval<T, NR, NC, kNbCorner>(L.in, r, c, kNbCornerTab, W.corner, res);
+      ac_eval_rows<T, NR, NC, 0, kNbCorner>(L.in, r, c, W.corner, res);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
         L.tsum[NK_CORNER][q][jj][ii] = (L.in[1][q][r][c] + T(4) * res[0][q]) + res[1][q];
         if (wrow) A.out[1][(size_t(q) * A.npatch + patch) * plane + obase] = res[1][q];
       }
       if (has_x) {
-        ac_eval<T, NR, NC, kNbEdge>(L.in, r, c, kNbXedgeTab, W.xedge, res);
+        ac_eval_rows<T, NR, NC, 1, kNbEdge>(L.in, r, c, W.xedge, res);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
           L.tsum[NK_XEDGE][q][jj][ii] = (L.in[2][q][r][c] + T(4) * res[0][q]) + res[1][q];
@@ -441,7 +480,7 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
         }
       }
       if (has_y) {
-        ac_eval<T, NR, NC, kNbEdge>(L.in, r, c, kNbYedgeTab, W.yedge, res);
+        ac_eval_rows<T, NR, NC, 2, kNbEdge>(L.in, r, c, W.yedge, res);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
           L.tsum[NK_YEDGE][q][jj][ii] = (L.in[3][q][r][c] + T(4) * res[0][q]) + res[1][q];
@@ -649,14 +688,14 @@ __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, co
         const bool has_x = jj < EC - 1, has_y = ii < EC - 1;
         {
           T res[2][3];
-          ac_eval<T, E, E, kNbCorner>(st, r, c, kNbCornerTab, W.corner, res);
+          ac_eval_rows<T, E, E, 0, kNbCorner>(st, r, c, W.corner, res);
 #pragma unroll
           for (int q = 0; q < 3; ++q) {
             ts[NK_CORNER][q][r][c] = (st[1][q][r][c] + T(4) * res[0][q]) + res[1][q];
             fnew[u][NK_CORNER][q] = res[1][q];
           }
           if (has_x) {
-            ac_eval<T, E, E, kNbEdge>(st, r, c, kNbXedgeTab, W.xedge, res);
+            ac_eval_rows<T, E, E, 1, kNbEdge>(st, r, c, W.xedge, res);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
               ts[NK_XEDGE][q][r][c] = (st[2][q][r][c] + T(4) * res[0][q]) + res[1][q];
@@ -664,7 +703,7 @@ __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, co
             }
           }
           if (has_y) {
-            ac_eval<T, E, E, kNbEdge>(st, r, c, kNbYedgeTab, W.yedge, res);
+            ac_eval_rows<T, E, E, 2, kNbEdge>(st, r, c, W.yedge, res);
 #pragma unroll
             for (int q = 0; q < 3; ++q) {
               ts[NK_YEDGE][q][r][c] = (st[3][q][r][c] + T(4) * res[0][q]) + res[1][q];
