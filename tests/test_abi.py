@@ -101,3 +101,24 @@ def test_level_ranges_cover_sorted_leaves():
         assert all(lv == l for lv, _, _ in h.leaves()[f:f + c])
         total += c
     assert total == len(h) and h.finest() == 2
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """No CPU fallback: with libaf.so absent, the first call into the
+    package raises instead of computing anything."""
+    import subprocess
+    import sys
+    code = (
+        "import paper_2205_07572_amd as af, paper_2205_07572_amd._lib as L\n"
+        f"L.LIB_PATH = {str(tmp_path / 'absent.so')!r}\n"
+        "L._lib = None\n"
+        "try:\n"
+        "    af.Context(af.Problem())\n"
+        "except RuntimeError as e:\n"
+        "    print('raised:', e)\n"
+        "else:\n"
+        "    raise SystemExit('no error')\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert "raised:" in r.stdout and "is not built" in r.stdout
