@@ -410,9 +410,14 @@ const int32_t* af_hier_leaf_xy(const af_hier* h) {
 
 // ----------------------------------------------------------------- step
 
-af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t first, int32_t count,
-                        int32_t level, double dt, double t, int32_t region, double* flux_reg,
-                        const uint8_t* side_mask, const int32_t* leaf_xy, hipStream_t stream) {
+// af_patch_step with the choice of where cells outside a patch come from:
+// gnx = 0, its ghost layers; gnx > 0, the interiors of its neighbours in the
+// complete row-major gnx x gny level that starts at leaf `first` (the
+// coarse-step driver on a one-level hierarchy, which then needs no fill).
+static af_status patch_step_gather(af_ctx* ctx, const af_state* in, af_state* out, int32_t first, int32_t count,
+                                   int32_t level, double dt, double t, int32_t region, double* flux_reg,
+                                   const uint8_t* side_mask, const int32_t* leaf_xy, int32_t gnx, int32_t gny,
+                                   hipStream_t stream) {
   if (!ctx) return fail(AF_ERR_ARG, "null ctx");
   if (count < 0 || first < 0) return fail(AF_ERR_ARG, "negative patch range");
   if (region != AF_REGION_INTERIOR && region != AF_REGION_LAYER1) return fail(AF_ERR_ARG, "bad region");
@@ -462,6 +467,8 @@ af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t 
   L.reg = flux_reg;
   L.side_mask = flux_reg ? side_mask : nullptr;
   L.leaf_xy = leaf_xy;
+  L.gnx = gnx;
+  L.gny = gny;
   if (ctx->P.eq == AF_ROTATION) {
     // the rotation angle depends on dt itself, not on dt/dx: no cache
     const double th[2] = {ctx->P.omega * 0.5 * dt, ctx->P.omega * dt};
@@ -514,6 +521,13 @@ af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t 
   }
   AF_HIP(launch_patch_step(L, stream));
   return AF_OK;
+}
+
+af_status af_patch_step(af_ctx* ctx, const af_state* in, af_state* out, int32_t first, int32_t count,
+                        int32_t level, double dt, double t, int32_t region, double* flux_reg,
+                        const uint8_t* side_mask, const int32_t* leaf_xy, hipStream_t stream) {
+  return patch_step_gather(ctx, in, out, first, count, level, dt, t, region, flux_reg, side_mask, leaf_xy, 0, 0,
+                           stream);
 }
 
 // ----------------------------------------------------------------- fill etc.
@@ -934,6 +948,9 @@ struct Driver {
   uint32_t mask;
   double* reg;
   hipStream_t st;
+  // > 0: the hierarchy is one complete level (gnx x gny patches); steps read
+  // neighbours' interiors and no fill is needed
+  int gnx = 0, gny = 0;
 
   af_status step_level(int l, double t, double dt, int region) {
     int first, count;
@@ -943,8 +960,8 @@ struct Driver {
     // always "bit 0 flipped" (subcycled) or "bits 0..finest flipped" (global)
     mask ^= (1u << l);
     if (count == 0) return AF_OK;
-    return af_patch_step(ctx, &bufs[cur], &bufs[cur ^ 1], first, count, l, dt, t, region, reg,
-                         h->d_side_mask, h->d_xy, st);
+    return patch_step_gather(ctx, &bufs[cur], &bufs[cur ^ 1], first, count, l, dt, t, region, reg,
+                             h->d_side_mask, h->d_xy, gnx, gny, st);
   }
 
   af_status advance(int l, double t, double dt, bool first_of_pair, int finest) {
@@ -964,15 +981,17 @@ struct Driver {
   }
 
   af_status coarse_step(double t0, double dt0) {
-    af_status s = af_ghost_fill(ctx, h, bufs, mask, 0, 0, st);
-    if (s != AF_OK) return s;
+    if (!gnx) {
+      af_status s = af_ghost_fill(ctx, h, bufs, mask, 0, 0, st);
+      if (s != AF_OK) return s;
+    }
     return advance(0, t0, dt0, true, h->H.finest);
   }
 
   // Global time stepping: every level steps its interior from the same
   // synchronised state, then every coarse level takes the fine fluxes.
   af_status global_step(double t0, double dt) {
-    af_status s = af_ghost_fill(ctx, h, bufs, mask, 0, 0, st);
+    af_status s = gnx ? AF_OK : af_ghost_fill(ctx, h, bufs, mask, 0, 0, st);
     if (s != AF_OK) return s;
     for (int l = 0; l <= h->H.finest; ++l)
       if ((s = step_level(l, t0, dt, AF_REGION_INTERIOR)) != AF_OK) return s;
@@ -985,6 +1004,15 @@ struct Driver {
   }
 
   af_status run(int32_t flags, double t0, double dt0) {
+    // a hierarchy that is one complete level steps without a fill
+    if (h->H.finest == 0) {
+      int nx, ny;
+      if (level_grid(h, 0, &nx, &ny) == AF_OK) {
+        gnx = nx;
+        gny = ny;
+      }
+      g_err.clear();
+    }
     return (flags & AF_STEP_GLOBAL) ? global_step(t0, dt0) : coarse_step(t0, dt0);
   }
 };

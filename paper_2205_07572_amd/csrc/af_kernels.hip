@@ -37,6 +37,10 @@ struct StepArgs {
   double len_dt_y;         // dx * dt (y-faces)
   double* reg;             // [npatch][4][M][ncomp] or null
   const uint8_t* side_mask;
+  // > 0: the patches first .. first + gnx * gny - 1 are a complete periodic
+  // level in row-major order, and cells outside a patch are read from its
+  // neighbours' interiors (no ghost fill needed); 0: from its ghost layers
+  int32_t gnx, gny;
 };
 
 // Row-major walk e = start, start + stride, ... over an nx-wide grid without
@@ -302,7 +306,7 @@ __device__ __forceinline__ T rot_eval(const T (&s)[4][1][NR][NC], int r, int c, 
   return v;
 }
 
-template <typename T, int EQ, int M, int TY>
+template <typename T, int EQ, int M, int TY, bool GN>
 __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
                                                          const typename WSel<T, EQ>::type W) {
   constexpr int NCOMP = EQ == 1 ? 3 : 1;
@@ -329,13 +333,32 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
   // tile) and all M+5 columns (staged column x holds i = x - 2), so the
   // image has a compile-time shape; rows [jlo-1, jhi+1] and columns
   // [ilo-1, ihi+1] are the ones read below
-  gather_block<T, kThreads, 4 * NCOMP * NR * NC>(&L.in[0][0][0][0], [&](int e) {
-    const int kc = e / (NR * NC), rem = e - kc * (NR * NC);
-    const int rr = rem / NC, x = rem - rr * NC;
-    const int comp = kc % NCOMP, kind = kc / NCOMP;
-    const int j = min(jlo - 1 + rr, M + 2);
-    return A.in[kind][(size_t(comp) * A.npatch + patch) * plane + size_t(j + kGhost) * A.pitch + x];
-  });
+  if constexpr (GN) {  // cells outside the patch from its neighbours' interiors
+    const int gpl = patch - A.first;
+    const int pix = gpl % A.gnx, piy = gpl / A.gnx;
+    gather_block<T, kThreads, 4 * NCOMP * NR * NC>(&L.in[0][0][0][0], [&](int e) {
+      const int kc = e / (NR * NC), rem = e - kc * (NR * NC);
+      const int rr = rem / NC, x = rem - rr * NC;
+      const int comp = kc % NCOMP, kind = kc / NCOMP;
+      const int j = min(jlo - 1 + rr, M + 2), i = x - kGhost;
+      const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
+      const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
+      int xx = pix + ox, yy = piy + oy;
+      xx = xx < 0 ? xx + A.gnx : (xx >= A.gnx ? xx - A.gnx : xx);
+      yy = yy < 0 ? yy + A.gny : (yy >= A.gny ? yy - A.gny : yy);
+      const int src = A.first + yy * A.gnx + xx;
+      return A.in[kind][(size_t(comp) * A.npatch + src) * plane + size_t(j - oy * M + kGhost) * A.pitch +
+                        (i - ox * M + kGhost)];
+    });
+  } else {
+    gather_block<T, kThreads, 4 * NCOMP * NR * NC>(&L.in[0][0][0][0], [&](int e) {
+      const int kc = e / (NR * NC), rem = e - kc * (NR * NC);
+      const int rr = rem / NC, x = rem - rr * NC;
+      const int comp = kc % NCOMP, kind = kc / NCOMP;
+      const int j = min(jlo - 1 + rr, M + 2);
+      return A.in[kind][(size_t(comp) * A.npatch + patch) * plane + size_t(j + kGhost) * A.pitch + x];
+    });
+  }
   __syncthreads();
   const int coff = ilo + 2;  // staged column of cell i is i + 2 = ii + coff
   // rotation, swirl: lower-left corner of the patch's cell (0,0)
@@ -1587,12 +1610,15 @@ static hipError_t launch_step_t(const StepLaunch& s, hipStream_t st) {
   A.dtdx = T(s.dtdx); A.dtdy = T(s.dtdy);
   A.a = T(s.a); A.b = T(s.b); A.c = T(s.c);
   A.len_dt_x = s.len_dt_x; A.len_dt_y = s.len_dt_y;
-  A.reg = s.reg; A.side_mask = s.side_mask; A.leaf_xy = s.leaf_xy;
+  A.reg = s.reg; A.side_mask = s.side_mask; A.leaf_xy = s.leaf_xy; A.gnx = s.gnx; A.gny = s.gny;
   const int span = M + 2 * s.region;
   const int tiles = (span + TY - 1) / TY;
   const dim3 grid(unsigned(s.count * tiles));
-  hipLaunchKernelGGL((k_patch_step<T, EQ, M, TY>), grid, dim3(kThreads), 0, st, A,
-                     *static_cast<const typename WSel<T, EQ>::type*>(s.weights));
+  const auto& W = *static_cast<const typename WSel<T, EQ>::type*>(s.weights);
+  if (s.gnx > 0)
+    hipLaunchKernelGGL((k_patch_step<T, EQ, M, TY, true>), grid, dim3(kThreads), 0, st, A, W);
+  else
+    hipLaunchKernelGGL((k_patch_step<T, EQ, M, TY, false>), grid, dim3(kThreads), 0, st, A, W);
   return hipGetLastError();
 }
 

@@ -19,6 +19,7 @@ struct StepLaunch {
   const uint8_t* side_mask;
   const int32_t* leaf_xy;  // [npatch][2] patch (ix, iy); rotation only
   const void* weights;  // AdvWeights<T>, AcWeights<T> or RotParams<T> matching fp32/eq
+  int gnx = 0, gny = 0;  // > 0: complete level, cells outside a patch come from its neighbours
 };
 
 struct AdvanceLaunch {
