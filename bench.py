@@ -53,6 +53,8 @@ def parse():
                    help="roofline sweep: uniform grids up to 4096^2 (HBM resident); one JSON line per case")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 64 MiB device copy 20 times (HBM counter calibration)")
+    p.add_argument("--only", choices=["amr", "rotation", "swirl", "burgers"],
+                   help="only run one workload block (one JSON line with that block), e.g. for a profiler")
     return p.parse_args()
 
 
@@ -628,6 +630,10 @@ def main():
         return
     if args.sweep:
         sweep()
+        return
+    if args.only:
+        runs = {"amr": amr_runs, "rotation": rotation_runs, "swirl": swirl_runs, "burgers": burgers_runs}
+        print(json.dumps({args.only: runs[args.only]()}), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: --gpus must be 1 (multi-GPU sharding is design-only)"}))
