@@ -100,7 +100,7 @@ typedef struct {
   double c;            /* speed of sound (eq. acoustics) */
   double omega;        /* AF_ROTATION: angular velocity (pi in Sec. 4.2) */
   double xc, yc;       /* AF_ROTATION: centre of rotation */
-  double qmax;         /* AF_BURGERS: bound on |q| over the run (CFL check) */
+  double qmax;         /* AF_BURGERS: bound on |q| over the run (CFL check), > 0 */
 } af_problem;
 
 typedef struct {
@@ -255,7 +255,12 @@ af_status af_reduce_sum(af_ctx* ctx, const af_hier* h, const af_state* bufs,
  * from the neighbours' interiors (the values a same-level ghost fill would
  * copy), advances K steps in LDS and writes the interior averages and the
  * closed-square nodes to the other buffer.  Equal to nsteps x (af_ghost_fill
- * + af_patch_step) up to FMA contraction.  The level's data moves between
+ * + af_patch_step) up to rounding order: for advection with the upwind source
+ * pattern (a, b > 0, both directional Courant numbers below 1/2) each step is
+ * one pass in which a cell's new average is a fixed combination of the 25 old
+ * DOFs of its source cells, composed on the host from eq. 2dfv and eq.
+ * Simpson-2d.  AF_ADVECTION and AF_ACOUSTICS only (AF_ERR_ARG for the other
+ * equations, which step with af_patch_step).  The level's data moves between
  * bufs[0] and bufs[1] (*level_buf_mask bit `level` updated after every
  * launch); ghost layers of the result are NOT filled.
  * --------------------------------------------------------------------- */
@@ -293,6 +298,10 @@ af_status af_autotune(af_ctx* ctx, af_hier* h, af_state* bufs, int32_t level, do
  * stepping, the corollary of Sec. 4.3; dt0 must satisfy the finest level's
  * CFL): full fill, every level steps its interior, then the conservative
  * fix of every level.
+ * A hierarchy that is one complete level steps without the fill: its patch
+ * steps read the cells outside a patch from the neighbours' interiors (the
+ * values the fill would copy).  In every case the ghost layers of the result
+ * are not filled; call af_ghost_fill before reading them.
  * --------------------------------------------------------------------- */
 enum { AF_STEP_GRAPH = 1, AF_STEP_GLOBAL = 2 };
 af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* level_buf_mask,

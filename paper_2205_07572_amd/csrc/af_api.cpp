@@ -266,8 +266,8 @@ af_status af_ctx_create(const af_problem* prob, af_ctx** out) {
   if (P.n0x < 1 || P.n0y < 1 || P.lmax < 0 || P.lmax >= kMaxLevels) return fail(AF_ERR_ARG, "bad patch counts or lmax");
   if (!(P.lx > 0 && P.ly > 0)) return fail(AF_ERR_ARG, "domain extents must be positive");
   if (P.eq == AF_ACOUSTICS && !(P.c > 0)) return fail(AF_ERR_ARG, "speed of sound must be positive");
-  if (P.eq == AF_BURGERS && !(P.qmax >= 0 && std::isfinite(P.qmax)))
-    return fail(AF_ERR_ARG, "qmax must be finite and >= 0");
+  if (P.eq == AF_BURGERS && !(P.qmax > 0 && std::isfinite(P.qmax)))
+    return fail(AF_ERR_ARG, "AF_BURGERS needs a finite bound qmax > 0 on |q| (CFL check)");
   auto c = std::make_unique<af_ctx>();
   c->P = P;
   c->ncomp = P.eq == AF_ACOUSTICS ? 3 : 1;

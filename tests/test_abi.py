@@ -42,6 +42,13 @@ def test_ctx_rejects_bad_problems(field, value, status):
     assert e.value.status == status
 
 
+@pytest.mark.parametrize("qmax", [0.0, -1.0, float("inf")])
+def test_burgers_needs_a_bound_on_q(qmax):
+    with pytest.raises(af.AFError) as e:
+        af.Context(af.Problem(eq=af.BURGERS, prec=0, m=16, qmax=qmax))
+    assert e.value.status == _lib.AF_ERR_ARG
+
+
 def test_tile_heights_validated():
     ctx = af.Context(af.Problem(eq=0, prec=1, m=32))
     assert ctx.tile in (4, 8)
