@@ -1031,6 +1031,25 @@ __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A,
   const int pix = pl % A.nx, piy = pl / A.nx;
   const size_t plane = size_t(M + 5) * A.pitch;
 
+  // The 52 weights of a step (27 node, 25 average) stay in vector registers
+  // for the whole launch (FP32; 52 of the 128 registers a lane has at this
+  // occupancy).  Held as kernel arguments they overflow the scalar registers,
+  // and every reload is a scalar load whose wait also drains all outstanding
+  // LDS loads.  The empty asm statements only pin the register class.
+  T wf[3][9], wq[25];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int e = 0; e < 9; ++e) {
+      wf[k][e] = W.w[k][1][e];
+      if constexpr (sizeof(T) == 4) asm volatile("" : "+v"(wf[k][e]));
+    }
+#pragma unroll
+  for (int e = 0; e < 25; ++e) {
+    wq[e] = W.up_avg[e];
+    if constexpr (sizeof(T) == 4) asm volatile("" : "+v"(wq[e]));
+  }
+
   // ---- gather into buffer 0: LDS position (r, c) holds local index
   // (c - K, r - K); one source offset serves the four kinds
   T* const g0 = &S.q[0][0][0][0];
@@ -1100,9 +1119,9 @@ __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A,
           const int wr = u + 1 + up_off(k, 1), wc = 1 + up_off(k, 0);
           const T d[9] = {wa[wr][wc],     w0[wr][wc],     w0[wr][wc + 1], w0[wr + 1][wc], w0[wr + 1][wc + 1],
                           w1[wr][wc],     w1[wr][wc + 1], w2[wr][wc],     w2[wr + 1][wc]};
-          T v = W.w[k][1][0] * d[0];
+          T v = wf[k][0] * d[0];
 #pragma unroll
-          for (int e = 1; e < 9; ++e) v += W.w[k][1][e] * d[e];
+          for (int e = 1; e < 9; ++e) v += wf[k][e] * d[e];
           f[k] = v;
         }
         // new average: the 25 old DOFs of the source cells (-1..0)^2
@@ -1110,19 +1129,19 @@ __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A,
 #pragma unroll
         for (int dj = -1; dj <= 0; ++dj)
 #pragma unroll
-          for (int di = -1; di <= 0; ++di) avg += W.up_avg[kUpA + (dj + 1) * 2 + (di + 1)] * wa[u + 1 + dj][1 + di];
+          for (int di = -1; di <= 0; ++di) avg += wq[kUpA + (dj + 1) * 2 + (di + 1)] * wa[u + 1 + dj][1 + di];
 #pragma unroll
         for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
-          for (int di = -1; di <= 1; ++di) avg += W.up_avg[kUpC + (dj + 1) * 3 + (di + 1)] * w0[u + 1 + dj][1 + di];
+          for (int di = -1; di <= 1; ++di) avg += wq[kUpC + (dj + 1) * 3 + (di + 1)] * w0[u + 1 + dj][1 + di];
 #pragma unroll
         for (int dj = -1; dj <= 0; ++dj)
 #pragma unroll
-          for (int di = -1; di <= 1; ++di) avg += W.up_avg[kUpX + (dj + 1) * 3 + (di + 1)] * w1[u + 1 + dj][1 + di];
+          for (int di = -1; di <= 1; ++di) avg += wq[kUpX + (dj + 1) * 3 + (di + 1)] * w1[u + 1 + dj][1 + di];
 #pragma unroll
         for (int dj = -1; dj <= 1; ++dj)
 #pragma unroll
-          for (int di = -1; di <= 0; ++di) avg += W.up_avg[kUpY + (dj + 1) * 2 + (di + 1)] * w2[u + 1 + dj][1 + di];
+          for (int di = -1; di <= 0; ++di) avg += wq[kUpY + (dj + 1) * 2 + (di + 1)] * w2[u + 1 + dj][1 + di];
         if (tok) {  // strips past the region store into rows no later read touches
           const int idx = b0 + u * E;
           qn[idx] = avg;
