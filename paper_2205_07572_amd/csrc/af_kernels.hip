@@ -1004,27 +1004,79 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
 // fixed combination of the 25 old DOFs of its source cells (-1..0)^2,
 // composed on the host (AdvWeights::up_avg).  A cell's new average and its
 // three new node values come from the same window of old DOFs.  Averages
-// and point values are double-buffered: a step reads buffer s & 1, writes
-// the other, and needs one barrier and no time sums.  Strips, spare rows and
-// the unrolled steps are those of k_level_advance_adv; the positions a step
-// leaves stale (x-edges on the top row and averages on the outer ring of its
-// extended region, anything past it) are the ones no later window uses.
+// and point values are double-buffered: a step reads one buffer, writes the
+// other, and needs one barrier and no time sums.  A thread takes a strip of
+// R vertically adjacent cells of one column; strips that run past the
+// region store into spare rows that no later window reads.
+//
+// LDS layouts.  Step s reads layout s and writes layout s + 1; the layouts
+// alternate between the two buffers.  Layout s puts local cell (s - K, s - K)
+// at position 0 and has row pitch pitch(s): the gather fills layout 0, the
+// write-back reads layout K.  Step s gives each strip width(s) consecutive
+// tasks (its region width, rounded up to a multiple of gcd(R, B), where B is
+// the number of elements that cover the 32 LDS banks once) and pitch(s) is
+// the smallest pitch with R * pitch(s) = width(s) modulo B.  The address of
+// task t is then t plus a constant modulo B, across strip boundaries, so the
+// window loads of any 32 (FP32) or 16 (FP64) consecutive lanes fall in
+// distinct banks.
 // ---------------------------------------------------------------------------
 template <typename T, int M, int K, int R>
+struct UpPlan {
+  static constexpr int E0 = M + 2 * K + 1;  // side of the gathered block
+  static constexpr int B = 128 / int(sizeof(T));
+  static constexpr int gcd(int a, int b) { return b == 0 ? a : gcd(b, a % b); }
+  static constexpr int ec(int s) { return M + 2 * (K - 1 - s) + 1; }  // region side of step s
+  static constexpr int width(int s) {
+    int w = ec(s);
+    while (w % gcd(R, B) != 0) ++w;
+    return w;
+  }
+  static constexpr int pitch(int s) {
+    // layout s must hold the columns step s - 1 writes (ec(s - 1)); layout 0
+    // the gathered block, layout K the closed square of M + 1 nodes
+    int p = s == 0 ? E0 : (s == K ? M + 1 : ec(s - 1));
+    if (s == K) return p;
+    for (int i = 0; i < B && (R * p - width(s)) % B != 0; ++i) ++p;
+    return p;
+  }
+  static constexpr bool valid() {
+    for (int s = 0; s < K; ++s)
+      if ((R * pitch(s) - width(s)) % B != 0) return false;
+    return true;
+  }
+  static constexpr int max_pitch() {
+    int m = 0;
+    for (int s = 0; s <= K; ++s) m = pitch(s) > m ? pitch(s) : m;
+    return m;
+  }
+  static constexpr int ROWS = E0 + R;  // every layout: at most E0 + R - 1 rows are touched
+  static constexpr int AS = ROWS * max_pitch();
+  static_assert(valid(), "no bank-aligned pitch");
+  // the plan as plain numbers, so that a step indexes constants
+  struct Table {
+    int pitch[K + 1], width[K];
+  };
+  static constexpr Table table() {
+    Table t{};
+    for (int s = 0; s <= K; ++s) t.pitch[s] = pitch(s);
+    for (int s = 0; s < K; ++s) t.width[s] = width(s);
+    return t;
+  }
+};
+
+template <typename T, int M, int K, int R>
 struct UpLds {
-  static constexpr int E = M + 2 * K + 1;
-  static constexpr int ER = E + R;  // rows of every array: E, then R spare rows
-  T q[2][4][ER][E];                 // [buffer][average, corner, x-edge, y-edge]
+  T q[2][4][UpPlan<T, M, K, R>::AS];  // [buffer][average, corner, x-edge, y-edge]
 };
 
 template <typename T, int M, int K, int NT>
 __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A, const AdvWeights<T> W) {
   constexpr int R = StripRows<M, K, NT>::value;
-  using L = UpLds<T, M, K, R>;
-  constexpr int E = L::E;
-  constexpr int EE = E * E;
-  constexpr int AS = L::ER * E;  // stride between arrays
-  __shared__ L S;
+  using P = UpPlan<T, M, K, R>;
+  constexpr int E0 = P::E0;
+  constexpr int AS = P::AS;  // stride between arrays
+  constexpr typename P::Table kTab = P::table();
+  __shared__ UpLds<T, M, K, R> S;
 
   const int pl = xcd_patch(int(blockIdx.x), int(gridDim.x));
   const int patch = A.first + pl;
@@ -1050,17 +1102,19 @@ __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A,
     if constexpr (sizeof(T) == 4) asm volatile("" : "+v"(wq[e]));
   }
 
-  // ---- gather into buffer 0: LDS position (r, c) holds local index
-  // (c - K, r - K); one source offset serves the four kinds
-  T* const g0 = &S.q[0][0][0][0];
+  // ---- gather into layout 0: position (r, c) of the E0 x E0 block holds
+  // local index (c - K, r - K); one source offset serves the four kinds
   {
+    constexpr int EE = E0 * E0;
+    constexpr int P0 = kTab.pitch[0];
+    T* const g0 = &S.q[0][0][0];
     constexpr int NP = (EE + NT - 1) / NT;
     T v[NP][4];
 #pragma unroll
     for (int u = 0; u < NP; ++u) {
       const int e = int(threadIdx.x) + u * NT;
       if (u + 1 < NP || EE % NT == 0 || e < EE) {
-        const int rr = e / E, x = e - rr * E;
+        const int rr = e / E0, x = e - rr * E0;
         const int j = rr - K, i = x - K;
         const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
         const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
@@ -1074,8 +1128,10 @@ __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A,
     for (int u = 0; u < NP; ++u) {
       const int e = int(threadIdx.x) + u * NT;
       if (u + 1 < NP || EE % NT == 0 || e < EE) {
+        const int rr = e / E0, x = e - rr * E0;
+        const int idx = rr * P0 + x;
 #pragma unroll
-        for (int kind = 0; kind < 4; ++kind) g0[kind * AS + e] = v[u][kind];
+        for (int kind = 0; kind < 4; ++kind) g0[kind * AS + idx] = v[u][kind];
       }
     }
   }
@@ -1083,28 +1139,31 @@ __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A,
 
 #pragma unroll
   for (int s = 0; s < K; ++s) {
-    const T* const qo = &S.q[s & 1][0][0][0];
-    T* const qn = &S.q[(s + 1) & 1][0][0][0];
-    const int lo = -(K - 1 - s);
-    const int EC = M + 2 * (K - 1 - s) + 1;  // extended cells per side
-    const int base = (lo + K) * (E + 1);      // LDS index of the first extended cell
+    const T* const qo = &S.q[s & 1][0][0];
+    T* const qn = &S.q[(s + 1) & 1][0][0];
+    const int EC = M + 2 * (K - 1 - s) + 1;  // region side; the region starts at column and row 1 of layout s
+    const int WS = kTab.width[s];            // tasks per strip (columns past EC idle)
+    const int PI = kTab.pitch[s];            // pitch of the layout read
+    const int PO = kTab.pitch[s + 1];        // pitch of the layout written (origin one cell further in)
     const int ns = (EC + R - 1) / R;
-    const int ntask = EC * ns;
-    // strips of R rows: task t -> column t % EC, strip t / EC; the window
-    // holds rows [rb-1, rb+R] and columns [c-1, c+1] of every array
+    const int ntask = WS * ns;
+    // task t -> column t % WS, strip t / WS; the window holds rows
+    // [q R, q R + R + 1] and columns [c, c + 2] of every array of layout s
 #pragma unroll 1
     for (int t0 = 0; t0 + int(threadIdx.x & ~63u) < ntask; t0 += NT) {  // wave-uniform
       const int t = t0 + int(threadIdx.x);
-      const bool tok = t < ntask;
-      const int q = tok ? t / EC : 0;
-      const int ci = tok ? t - q * EC : 0;
-      const int b0 = base + q * R * E + ci;
+      const bool live = t < ntask;
+      const int q = live ? t / WS : 0;
+      const int ci = live ? t - q * WS : 0;
+      const bool tok = live && ci < EC;  // columns EC..WS-1 load in bounds and store nothing
+      const int br = q * R * PI + ci;
+      const int bw = q * R * PO + ci;
       T wa[R + 2][3], w0[R + 2][3], w1[R + 2][3], w2[R + 2][3];
 #pragma unroll
       for (int rr = 0; rr < R + 2; ++rr)
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
-          const int o = b0 + (rr - 1) * E + (cc - 1);
+          const int o = br + rr * PI + cc;
           wa[rr][cc] = qo[o];
           w0[rr][cc] = qo[AS + o];
           w1[rr][cc] = qo[2 * AS + o];
@@ -1143,7 +1202,7 @@ __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A,
 #pragma unroll
           for (int di = -1; di <= 0; ++di) avg += wq[kUpY + (dj + 1) * 2 + (di + 1)] * w2[u + 1 + dj][1 + di];
         if (tok) {  // strips past the region store into rows no later read touches
-          const int idx = b0 + u * E;
+          const int idx = bw + u * PO;
           qn[idx] = avg;
           qn[AS + idx] = f[0];
           qn[2 * AS + idx] = f[1];
@@ -1154,16 +1213,20 @@ __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A,
     __syncthreads();
   }
 
-  // ---- write the interior averages and the closed-square nodes
-  const T* const qf = &S.q[K & 1][0][0][0];
-  for (Walk2 w(threadIdx.x, NT, M + 1); w.y < M + 1; w.next()) {
-    const int i = w.x, j = w.y;
-    const int idx = (j + K) * E + (i + K);
-    const size_t g = size_t(patch) * plane + size_t(j + kGhost) * A.pitch + (i + kGhost);
-    A.out[1][g] = qf[AS + idx];
-    if (j < M) A.out[2][g] = qf[2 * AS + idx];
-    if (i < M) A.out[3][g] = qf[3 * AS + idx];
-    if (i < M && j < M) A.out[0][g] = qf[idx];
+  // ---- write the interior averages and the closed-square nodes (layout K:
+  // local cell (i, j) at row j, column i)
+  {
+    constexpr int PK = kTab.pitch[K];
+    const T* const qf = &S.q[K & 1][0][0];
+    for (Walk2 w(threadIdx.x, NT, M + 1); w.y < M + 1; w.next()) {
+      const int i = w.x, j = w.y;
+      const int idx = j * PK + i;
+      const size_t g = size_t(patch) * plane + size_t(j + kGhost) * A.pitch + (i + kGhost);
+      A.out[1][g] = qf[AS + idx];
+      if (j < M) A.out[2][g] = qf[2 * AS + idx];
+      if (i < M) A.out[3][g] = qf[3 * AS + idx];
+      if (i < M && j < M) A.out[0][g] = qf[idx];
+    }
   }
 }
 
