@@ -140,6 +140,34 @@ void adv_locate(double node, double disp, int* off, double* ref) {
   *ref = 2.0 * (s - k);
 }
 
+// Rounds the FP64 weights w[0..n) of a stencil whose weights sum to
+// `target` (1 for a value, 0 for a derivative: what a constant state
+// requires) to T, keeping the rounded sum as close to the target as T
+// allows.  Plain rounding leaves the FP32 sum off by up to a few 1e-8, and
+// that error is systematic: every step scales a constant state by the same
+// factor, so the mean drifts linearly with the step count (about 5e-5 after
+// 1280 steps).  The residual is folded into the smallest weights, whose
+// finer spacing then bounds it (an absolute change of the size of the
+// rounding of the larger weights).  For T = double the weights are rounded
+// plainly.
+template <typename T>
+void round_sum(const double* w, T* out, int n, double target) {
+  for (int e = 0; e < n; ++e) out[e] = T(w[e]);
+  if (sizeof(T) == sizeof(double)) return;
+  for (int pass = 0; pass < 3; ++pass) {
+    double sum = 0.0;  // exact: FP32 values spanning far fewer than 53 bits
+    for (int e = 0; e < n; ++e) sum += double(out[e]);
+    const double r = target - sum;
+    if (r == 0.0) return;
+    // smallest weight that the change leaves well away from zero
+    int best = -1;
+    for (int e = 0; e < n; ++e)
+      if (std::fabs(w[e]) > 1e4 * std::fabs(r) && (best < 0 || std::fabs(w[e]) < std::fabs(w[best]))) best = e;
+    if (best < 0) return;
+    out[best] = T(double(out[best]) + r);
+  }
+}
+
 }  // namespace
 
 template <typename T>
@@ -157,10 +185,8 @@ void make_adv_weights(double a_dtdx, double b_dtdy, AdvWeights<T>* W) {
       W->off[kind][t][0] = ox;
       W->off[kind][t][1] = oy;
       up = up && ox == (kind == 2 ? 0 : -1) && oy == (kind == 1 ? 0 : -1);
-      for (int d = 0; d < kCellDofs; ++d) {
-        wd[kind][t][d] = poly_eval(dof_basis(d), xi, eta);
-        W->w[kind][t][d] = T(wd[kind][t][d]);
-      }
+      for (int d = 0; d < kCellDofs; ++d) wd[kind][t][d] = poly_eval(dof_basis(d), xi, eta);
+      round_sum(wd[kind][t], W->w[kind][t], kCellDofs, 1.0);
     }
   // Upwind pattern: compose the update of eq. 2dfv with the Simpson sums
   // (eq. Simpson-2d) of the eight face nodes of cell (0,0), each node's
@@ -194,7 +220,10 @@ void make_adv_weights(double a_dtdx, double b_dtdy, AdvWeights<T>* W) {
   // corner (0,0), y-edge (0,0), corner (1,0)
   add_tsum(0, 0, 1, -cy); add_tsum(2, 0, 1, -4.0 * cy); add_tsum(0, 1, 1, -cy);
   add_tsum(0, 0, 0, cy); add_tsum(2, 0, 0, 4.0 * cy); add_tsum(0, 1, 0, cy);
-  for (int e = 0; e < 25; ++e) W->up_avg[e] = up ? T(acc[e]) : T(0);
+  if (up)
+    round_sum(acc, W->up_avg, 25, 1.0);
+  else
+    for (int e = 0; e < 25; ++e) W->up_avg[e] = T(0);
 }
 
 template <typename T>
@@ -247,12 +276,11 @@ void make_ac_weights(double c_dtdx, double c_dtdy, AcWeights<T>* W) {
           acc[2][e] += Dy;
         }
       }
-      for (int w = 0; w < 3; ++w)
-        for (int e = 0; e < nb; ++e) {
-          if (nk == 0) W->corner[t][w][e] = T(acc[w][e]);
-          else if (nk == 1) W->xedge[t][w][e] = T(acc[w][e]);
-          else W->yedge[t][w][e] = T(acc[w][e]);
-        }
+      // the spherical mean part sums to 1, the two gradient parts to 0
+      for (int w = 0; w < 3; ++w) {
+        T* dst = nk == 0 ? W->corner[t][w] : (nk == 1 ? W->xedge[t][w] : W->yedge[t][w]);
+        round_sum(acc[w], dst, nb, w == 0 ? 1.0 : 0.0);
+      }
     }
   }
 }
