@@ -1049,8 +1049,36 @@ struct UpPlan {
     for (int s = 0; s <= K; ++s) m = pitch(s) > m ? pitch(s) : m;
     return m;
   }
-  static constexpr int ROWS = E0 + R;  // every layout: at most E0 + R - 1 rows are touched
-  static constexpr int AS = ROWS * max_pitch();
+  static constexpr int strips(int s) { return (ec(s) + R - 1) / R; }
+  // words of one array of layout s that anything touches: the gather (s = 0)
+  // or step s - 1 writes, step s reads (its last strip's window reaches row
+  // strips * R + 1 and, from idle columns, column width + 1), the write-back
+  // reads the closed square (s = K)
+  static constexpr int words(int s) {
+    const int w = s == 0 ? E0 * pitch(0) : (strips(s - 1) * R - 1) * pitch(s) + ec(s - 1);
+    const int r = s == K ? M * pitch(K) + M + 1 : (strips(s) * R + 1) * pitch(s) + width(s) + 2;
+    return w > r ? w : r;
+  }
+  // array stride of each buffer: the largest of its layouts
+  static constexpr int stride(int b) {
+    int m = 0;
+    for (int s = b; s <= K; s += 2) m = words(s) > m ? words(s) : m;
+    return m;
+  }
+  // blocks of NT threads per CU that LDS of `words` words admits, at most
+  // 16 waves per CU
+  static constexpr int fit(int words, int nt) {
+    const int b = (160 * 1024) / (words * int(sizeof(T)));
+    const int w = 1024 / nt;
+    return b < 1 ? 1 : (b < w ? b : w);
+  }
+  // Two layouts of the buffers: one stride for all eight arrays (E0 + R
+  // rows of the widest pitch), or each buffer sized to the words its
+  // layouts touch.  The per-buffer sizes cost the steps some address
+  // arithmetic (about 8% at K = 8, 1024 threads), so they are used only
+  // where they let more blocks share a CU.
+  static constexpr int UNI = (E0 + R) * max_pitch();
+  static constexpr bool tight(int nt) { return fit(4 * (stride(0) + stride(1)), nt) > fit(8 * UNI, nt); }
   static_assert(valid(), "no bank-aligned pitch");
   // the plan as plain numbers, so that a step indexes constants
   struct Table {
@@ -1064,19 +1092,37 @@ struct UpPlan {
   }
 };
 
-template <typename T, int M, int K, int R>
-struct UpLds {
-  T q[2][4][UpPlan<T, M, K, R>::AS];  // [buffer][average, corner, x-edge, y-edge]
+// Buffer geometry of the upwind level advance for a block of NT threads:
+// array strides AS0 and AS1 of buffers 0 and 1 (buffer 1 starts at 4 AS0),
+// and the blocks per CU the launch bounds ask for.  On large grids a second
+// resident block overlaps one block's gather and write-back with another's
+// steps.
+template <typename T, int M, int K, int NT>
+struct UpGeom {
+  static constexpr int R = StripRows<M, K, NT>::value;
+  using P = UpPlan<T, M, K, R>;
+  static constexpr bool TIGHT = P::tight(NT);
+  static constexpr int AS0 = TIGHT ? P::stride(0) : P::UNI;
+  static constexpr int AS1 = TIGHT ? P::stride(1) : P::UNI;
+  static constexpr int WORDS = 4 * (AS0 + AS1);
+  static constexpr int OCC = P::fit(WORDS, NT);
+  static_assert(AS0 >= P::stride(0) && AS1 >= P::stride(1), "buffer smaller than a layout");
 };
 
 template <typename T, int M, int K, int NT>
-__global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A, const AdvWeights<T> W) {
+struct UpLds {
+  T q[UpGeom<T, M, K, NT>::WORDS];  // buffer 0 then 1, each: average, corner, x-edge, y-edge
+};
+
+template <typename T, int M, int K, int NT>
+__global__ __launch_bounds__(NT, (UpGeom<T, M, K, NT>::OCC)) void k_level_advance_up(const AdvanceArgs<T> A,
+                                                                                   const AdvWeights<T> W) {
   constexpr int R = StripRows<M, K, NT>::value;
   using P = UpPlan<T, M, K, R>;
   constexpr int E0 = P::E0;
-  constexpr int AS = P::AS;  // stride between arrays
+  constexpr int AS0 = UpGeom<T, M, K, NT>::AS0, AS1 = UpGeom<T, M, K, NT>::AS1;  // array strides of the buffers
   constexpr typename P::Table kTab = P::table();
-  __shared__ UpLds<T, M, K, R> S;
+  __shared__ UpLds<T, M, K, NT> S;
 
   const int pl = xcd_patch(int(blockIdx.x), int(gridDim.x));
   const int patch = A.first + pl;
@@ -1107,7 +1153,7 @@ __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A,
   {
     constexpr int EE = E0 * E0;
     constexpr int P0 = kTab.pitch[0];
-    T* const g0 = &S.q[0][0][0];
+    T* const g0 = &S.q[0];
     constexpr int NP = (EE + NT - 1) / NT;
     T v[NP][4];
 #pragma unroll
@@ -1131,7 +1177,7 @@ __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A,
         const int rr = e / E0, x = e - rr * E0;
         const int idx = rr * P0 + x;
 #pragma unroll
-        for (int kind = 0; kind < 4; ++kind) g0[kind * AS + idx] = v[u][kind];
+        for (int kind = 0; kind < 4; ++kind) g0[kind * AS0 + idx] = v[u][kind];
       }
     }
   }
@@ -1139,8 +1185,10 @@ __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A,
 
 #pragma unroll
   for (int s = 0; s < K; ++s) {
-    const T* const qo = &S.q[s & 1][0][0];
-    T* const qn = &S.q[(s + 1) & 1][0][0];
+    const T* const qo = &S.q[(s & 1) ? 4 * AS0 : 0];
+    T* const qn = &S.q[(s & 1) ? 0 : 4 * AS0];
+    const int AI = (s & 1) ? AS1 : AS0;  // array stride of the buffer read
+    const int AO = (s & 1) ? AS0 : AS1;  // and of the buffer written
     const int EC = M + 2 * (K - 1 - s) + 1;  // region side; the region starts at column and row 1 of layout s
     const int WS = kTab.width[s];            // tasks per strip (columns past EC idle)
     const int PI = kTab.pitch[s];            // pitch of the layout read
@@ -1165,9 +1213,9 @@ __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A,
         for (int cc = 0; cc < 3; ++cc) {
           const int o = br + rr * PI + cc;
           wa[rr][cc] = qo[o];
-          w0[rr][cc] = qo[AS + o];
-          w1[rr][cc] = qo[2 * AS + o];
-          w2[rr][cc] = qo[3 * AS + o];
+          w0[rr][cc] = qo[AI + o];
+          w1[rr][cc] = qo[2 * AI + o];
+          w2[rr][cc] = qo[3 * AI + o];
         }
 #pragma unroll
       for (int u = 0; u < R; ++u) {
@@ -1204,9 +1252,9 @@ __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A,
         if (tok) {  // strips past the region store into rows no later read touches
           const int idx = bw + u * PO;
           qn[idx] = avg;
-          qn[AS + idx] = f[0];
-          qn[2 * AS + idx] = f[1];
-          qn[3 * AS + idx] = f[2];
+          qn[AO + idx] = f[0];
+          qn[2 * AO + idx] = f[1];
+          qn[3 * AO + idx] = f[2];
         }
       }
     }
@@ -1217,14 +1265,15 @@ __global__ __launch_bounds__(NT) void k_level_advance_up(const AdvanceArgs<T> A,
   // local cell (i, j) at row j, column i)
   {
     constexpr int PK = kTab.pitch[K];
-    const T* const qf = &S.q[K & 1][0][0];
+    constexpr int AF = (K & 1) ? AS1 : AS0;
+    const T* const qf = &S.q[(K & 1) ? 4 * AS0 : 0];
     for (Walk2 w(threadIdx.x, NT, M + 1); w.y < M + 1; w.next()) {
       const int i = w.x, j = w.y;
       const int idx = j * PK + i;
       const size_t g = size_t(patch) * plane + size_t(j + kGhost) * A.pitch + (i + kGhost);
-      A.out[1][g] = qf[AS + idx];
-      if (j < M) A.out[2][g] = qf[2 * AS + idx];
-      if (i < M) A.out[3][g] = qf[3 * AS + idx];
+      A.out[1][g] = qf[AF + idx];
+      if (j < M) A.out[2][g] = qf[2 * AF + idx];
+      if (i < M) A.out[3][g] = qf[3 * AF + idx];
       if (i < M && j < M) A.out[0][g] = qf[idx];
     }
   }
@@ -1783,7 +1832,8 @@ static hipError_t launch_adv_t(const AdvanceLaunch& s, hipStream_t st) {
 #define AF_ADV_SHAPES(X)                                                                                 \
   X(float, 0, 32, 1, 256) X(float, 0, 32, 2, 256) X(float, 0, 32, 2, 512) X(float, 0, 32, 4, 512)      \
   X(float, 0, 32, 4, 1024) X(float, 0, 32, 5, 1024) X(float, 0, 32, 6, 768) X(float, 0, 32, 6, 1024)   \
-  X(float, 0, 32, 7, 1024) X(float, 0, 32, 8, 512) X(float, 0, 32, 8, 1024)                             \
+  X(float, 0, 32, 7, 1024) X(float, 0, 32, 8, 512) X(float, 0, 32, 8, 1024) X(float, 0, 32, 5, 512)     \
+  X(float, 0, 32, 6, 512)                                                                                \
   X(float, 0, 16, 1, 256) X(float, 0, 16, 2, 256) X(float, 0, 16, 4, 256) X(float, 0, 16, 8, 256)      \
   X(double, 0, 32, 1, 256) X(double, 0, 32, 2, 512) X(double, 0, 32, 3, 1024) X(double, 0, 32, 4, 512) \
   X(double, 0, 32, 4, 1024) X(double, 0, 32, 5, 1024)                                                   \
