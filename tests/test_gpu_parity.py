@@ -483,6 +483,48 @@ def test_full_size_config2_level_advance(prec):
     assert err <= (FP64_TOL if prec == af.FP64 else 3e-7 * nsteps), err
 
 
+@pytest.mark.parametrize("prec", [af.FP32, af.FP64])
+def test_level_advance_graph_replays_match_eager(prec):
+    """The benchmark times the level advance as a captured HIP graph.  Three
+    replays, each after eager work (a state reset and an eager run on the
+    same buffers) and a synchronisation, must each equal the eager run bit
+    for bit; the step count is not a multiple of K, so the graph also holds
+    the tail launch."""
+    torch = _torch()
+    m, n0 = 32, 4
+    prob = make_problem(0, prec, m, n0=n0, a=1.0, b=0.5)
+    ctx = af.Context(prob)
+    leaves = afsynth.uniform_leaves(n0, n0, 0)
+    h = af.Hierarchy(ctx, leaves)
+    init = af.blocks_to_state(ctx, leaf_blocks(prob, leaves, afsynth.fourier_modes(2), nq=4))
+    K, NT = ctx.advance_shape
+    nsteps = 3 * K + 1
+    dt = 0.4 * prob.dx(0)
+    bufs = [init.clone(), torch.zeros_like(init)]
+
+    def reset():
+        bufs[0].copy_(init)
+        bufs[1].zero_()
+
+    reset()
+    mask_e = ctx.level_advance(h, bufs, 0, 0, dt, nsteps)
+    torch.cuda.synchronize()
+    eager = [b.clone() for b in bufs]
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        mask_g = ctx.level_advance(h, bufs, 0, 0, dt, nsteps)
+    assert mask_g == mask_e
+    for rep in range(3):
+        reset()
+        ctx.level_advance(h, bufs, 0, 0, dt, K)  # eager work between replays
+        torch.cuda.synchronize()
+        reset()
+        graph.replay()
+        torch.cuda.synchronize()
+        for a, b in zip(bufs, eager):
+            assert torch.equal(a, b), rep
+
+
 def test_fp32_benchmark_run_stays_near_fp64():
     """The whole benchmark run (512^2, 1280 steps to T = 1) in FP32 against
     the same run in FP64 (whose level advance is pinned to the oracle above).
