@@ -1076,9 +1076,12 @@ struct UpPlan {
   // rows of the widest pitch), or each buffer sized to the words its
   // layouts touch.  The per-buffer sizes cost the steps some address
   // arithmetic (about 8% at K = 8, 1024 threads), so they are used only
-  // where they let more blocks share a CU.
+  // where they let more blocks share a CU, or where one stride would not
+  // fit in LDS at all.
   static constexpr int UNI = (E0 + R) * max_pitch();
-  static constexpr bool tight(int nt) { return fit(4 * (stride(0) + stride(1)), nt) > fit(8 * UNI, nt); }
+  static constexpr bool tight(int nt) {
+    return fit(4 * (stride(0) + stride(1)), nt) > fit(8 * UNI, nt) || 8 * UNI * int(sizeof(T)) > 160 * 1024;
+  }
   static_assert(valid(), "no bank-aligned pitch");
   // the plan as plain numbers, so that a step indexes constants
   struct Table {
@@ -1833,7 +1836,7 @@ static hipError_t launch_adv_t(const AdvanceLaunch& s, hipStream_t st) {
   X(float, 0, 32, 1, 256) X(float, 0, 32, 2, 256) X(float, 0, 32, 2, 512) X(float, 0, 32, 4, 512)      \
   X(float, 0, 32, 4, 1024) X(float, 0, 32, 5, 1024) X(float, 0, 32, 6, 768) X(float, 0, 32, 6, 1024)   \
   X(float, 0, 32, 7, 1024) X(float, 0, 32, 8, 512) X(float, 0, 32, 8, 1024) X(float, 0, 32, 5, 512)     \
-  X(float, 0, 32, 6, 512)                                                                                \
+  X(float, 0, 32, 6, 512) X(float, 0, 32, 10, 1024)                                                     \
   X(float, 0, 16, 1, 256) X(float, 0, 16, 2, 256) X(float, 0, 16, 4, 256) X(float, 0, 16, 8, 256)      \
   X(double, 0, 32, 1, 256) X(double, 0, 32, 2, 512) X(double, 0, 32, 3, 1024) X(double, 0, 32, 4, 512) \
   X(double, 0, 32, 4, 1024) X(double, 0, 32, 5, 1024)                                                   \
