@@ -54,9 +54,34 @@ def parse():
                    help="roofline sweep: uniform grids up to 4096^2 (HBM resident); one JSON line per case")
     p.add_argument("--copy-probe", action="store_true",
                    help="only run a plain 64 MiB device copy 20 times (HBM counter calibration)")
+    p.add_argument("--peak-probe", action="store_true",
+                   help="only measure the device's copy bandwidth and vector FMA rate (one JSON line)")
     p.add_argument("--only", choices=["amr", "rotation", "swirl", "burgers"],
                    help="only run one workload block (one JSON line with that block), e.g. for a profiler")
     return p.parse_args()
+
+
+def peak_probe():
+    """Copy bandwidth (device-to-device copy of 1 GiB, read + write bytes)
+    and the vector FMA rate in FP32 and FP64 (af_fma_probe), to set beside
+    the published peaks the roofline fractions use."""
+    import torch
+    import paper_2205_07572_amd as af
+    n = 1 << 28  # 1 GiB of float32
+    a = torch.empty(n, dtype=torch.float32, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    best = 1e30
+    for _ in range(10):
+        ms, _ = _event_ms(lambda: b.copy_(a))
+        best = min(best, ms)
+    copy_gbs = 2 * 4 * n / (best * 1e-3) / 1e9
+    fma = {name: max(af.fma_probe(prec) for _ in range(5)) for name, prec in (("fp32", af.FP32), ("fp64", af.FP64))}
+    print(json.dumps({"peak_probe": True, "copy_gbs": copy_gbs, "copy_frac_of_8000": copy_gbs / HBM_PEAK_GBS,
+                      "fma_tflops": fma, "published_tflops": PEAK_TFLOPS,
+                      "note": "FP32 kernels are compiled without packed FP32 instructions"}), flush=True)
 
 
 def copy_probe():
@@ -647,6 +672,9 @@ def cpu_baseline_allcore(data, nsteps, dt, nproc):
 
 def main():
     args = parse()
+    if args.peak_probe:
+        peak_probe()
+        return
     if args.copy_probe:
         copy_probe()
         return

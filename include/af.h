@@ -363,6 +363,16 @@ af_status af_cnn_tag(af_ctx* ctx, af_cnn* cnn, const af_hier* h, const af_state*
                      uint32_t level_buf_mask, const int8_t* plain, int8_t* tags, int8_t* learned,
                      hipStream_t stream);
 
+/* af_fma_probe -- measurement helper, not part of the method: nblocks
+ * blocks of 256 threads each run 8 independent multiply-add chains of
+ * 16 x iters steps in `prec` (AF_FP32 or AF_FP64), compiled like the
+ * library's kernels, and write one value per thread to out (device,
+ * [nblocks * 256] elements of that precision).  2 * 8 * 16 * iters * 256 *
+ * nblocks flops; timing it on `stream` gives the vector FMA rate the
+ * kernels can reach on this device.  AF_ERR_ARG for a bad precision, a null
+ * out or counts below 1. */
+af_status af_fma_probe(int32_t prec, void* out, int32_t nblocks, int32_t iters, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -257,6 +257,25 @@ class Hierarchy:
 # host <-> state marshalling (layout conversion only)
 # ---------------------------------------------------------------------------
 
+def fma_probe(prec, nblocks=4096, iters=256):
+    """Vector multiply-add rate of this device in TFLOP/s, measured with the
+    library's probe kernel (af_fma_probe) timed by HIP events on torch's
+    current stream."""
+    torch = _torch()
+    dt = torch.float32 if prec == FP32 else torch.float64
+    out = torch.empty(nblocks * 256, dtype=dt, device="cuda")
+    L = _lib.load()
+    check(L.af_fma_probe(int(prec), _ptr(out), int(nblocks), int(iters), _stream()))  # warm-up
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    check(L.af_fma_probe(int(prec), _ptr(out), int(nblocks), int(iters), _stream()))
+    e1.record()
+    torch.cuda.synchronize()
+    flops = 2.0 * 8 * 16 * iters * 256 * nblocks
+    return flops / (e0.elapsed_time(e1) * 1e-3) / 1e12
+
+
 def blocks_to_state(ctx: Context, blocks, npatch=None, pitch=None):
     """blocks: list over patches of dict kind -> [ncomp][m+5][m+5] arrays."""
     torch = _torch()

@@ -22,7 +22,7 @@ EXPORTS = [
     "af_patch_step", "af_ghost_fill", "af_flux_correct", "af_regrid_tag", "af_hier_regrid",
     "af_regrid_apply", "af_reduce_sum", "af_amr_coarse_step", "af_level_advance",
     "af_ctx_advance_shapes", "af_ctx_set_advance_shape", "af_autotune",
-    "af_ctx_get_advance_shape",
+    "af_ctx_get_advance_shape", "af_fma_probe",
     "af_cnn_last_error", "af_cnn_create", "af_cnn_destroy", "af_cnn_num_params", "af_cnn_set_params",
     "af_cnn_get_params", "af_cnn_set_normalization", "af_cnn_forward", "af_cnn_loss_grad",
     "af_cnn_adam_step", "af_cnn_features", "af_cnn_tag",
@@ -99,6 +99,7 @@ def load():
     L.af_ctx_set_advance_shape.argtypes = [P, i32, i32]
     L.af_autotune.argtypes = [P, P, S, i32, D, i32, P, P, P]
     L.af_ctx_get_advance_shape.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+    L.af_fma_probe.argtypes = [i32, P, i32, i32, P]
     L.af_cnn_last_error.restype = ctypes.c_char_p
     L.af_cnn_create.argtypes = [i32, ctypes.POINTER(P)]
     L.af_cnn_destroy.argtypes = [P]

@@ -312,6 +312,13 @@ af_status af_ctx_destroy(af_ctx* ctx) {
   return AF_OK;
 }
 
+af_status af_fma_probe(int32_t prec, void* out, int32_t nblocks, int32_t iters, hipStream_t stream) {
+  if (prec != AF_FP32 && prec != AF_FP64) return fail(AF_ERR_ARG, "af_fma_probe: precision must be AF_FP32 or AF_FP64");
+  if (!out || nblocks < 1 || iters < 1) return fail(AF_ERR_ARG, "af_fma_probe: need out, nblocks >= 1, iters >= 1");
+  AF_HIP(launch_fma_probe(prec == AF_FP32, out, nblocks, iters, stream));
+  return AF_OK;
+}
+
 af_status af_ctx_set_tile(af_ctx* ctx, int32_t ty) {
   if (!ctx) return fail(AF_ERR_ARG, "null ctx");
   if (!step_shape_supported(ctx->P.m, ty)) return fail(AF_ERR_ARG, "unsupported tile height for this m");

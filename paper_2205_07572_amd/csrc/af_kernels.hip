@@ -1876,6 +1876,38 @@ static Bufs<T> make_bufs(const BufLaunch& b) {
   return B;
 }
 
+// Vector FMA rate probe: every thread runs 8 independent FMA chains of
+// `iters` steps (enough chains to cover the FMA latency) and writes their sum,
+// so nothing is dead.  Compiled with the same flags as the kernels above
+// (packed FP32 off), it measures the vector rate those kernels can reach.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_fma_probe(T* out, int iters, T a, T b) {
+  T x[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = T(threadIdx.x + k);
+#pragma unroll 1
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r)
+#pragma unroll
+      for (int k = 0; k < 8; ++k) x[k] = x[k] * a + b;
+  }
+  T s = T(0);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) s += x[k];
+  out[size_t(blockIdx.x) * kThreads + threadIdx.x] = s;
+}
+
+hipError_t launch_fma_probe(bool fp32, void* out, int nblocks, int iters, hipStream_t st) {
+  if (fp32)
+    hipLaunchKernelGGL(k_fma_probe<float>, dim3(unsigned(nblocks)), dim3(kThreads), 0, st, static_cast<float*>(out),
+                       iters, 0.999999f, 1e-7f);
+  else
+    hipLaunchKernelGGL(k_fma_probe<double>, dim3(unsigned(nblocks)), dim3(kThreads), 0, st,
+                       static_cast<double*>(out), iters, 0.999999, 1e-7);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_plan(const HierDev& H, const int32_t* entries, int nentries, int m, int smin, int4* plan,
                             uint32_t* flags, hipStream_t st) {
   if (H.nleaves <= 0) return hipSuccess;

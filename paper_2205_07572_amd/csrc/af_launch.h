@@ -43,6 +43,8 @@ hipError_t launch_patch_step(const StepLaunch& s, hipStream_t st);
 hipError_t launch_level_advance(const AdvanceLaunch& s, hipStream_t st);
 // fills (K, threads) pairs available for (precision, equation, m); returns the count
 int level_advance_shapes(bool fp32, int eq, int m, int* ks, int* nts, int cap);
+// nblocks x kThreads threads, 8 chains x 16 x iters FMAs each
+hipError_t launch_fma_probe(bool fp32, void* out, int nblocks, int iters, hipStream_t st);
 bool step_shape_supported(int m, int ty);
 // resolves the fill sources of every leaf (sources of level >= smin) into
 // plan[nleaves][nentries] and flags[nleaves] (bit p: ops of phase p)

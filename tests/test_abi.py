@@ -49,6 +49,15 @@ def test_burgers_needs_a_bound_on_q(qmax):
     assert e.value.status == _lib.AF_ERR_ARG
 
 
+@pytest.mark.parametrize("prec,nblocks,iters", [(7, 1, 1), (0, 0, 1), (1, 1, 0)])
+def test_fma_probe_validates_arguments(prec, nblocks, iters):
+    """Rejected on the host before any launch (no GPU needed)."""
+    import ctypes
+    buf = ctypes.create_string_buffer(8)
+    st = _lib.load().af_fma_probe(prec, ctypes.cast(buf, ctypes.c_void_p), nblocks, iters, None)
+    assert st == _lib.AF_ERR_ARG
+
+
 def test_tile_heights_validated():
     ctx = af.Context(af.Problem(eq=0, prec=1, m=32))
     assert ctx.tile in (4, 8)

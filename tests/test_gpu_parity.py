@@ -587,6 +587,37 @@ def test_fp32_constant_state_does_not_drift(eq):
         assert err <= 2e-6, (q, err)
 
 
+@pytest.mark.parametrize("prec", [af.FP32, af.FP64])
+def test_fma_probe_computes_its_chains(prec):
+    """The FMA rate probe runs real arithmetic: thread t's output is the sum
+    over k < 8 of the recurrence x <- x a + b from x = t + k, 16 x iters
+    times, recomputed here in FP64 (FP32 within its rounding)."""
+    torch = _torch()
+    iters, nblocks = 3, 2
+    dt = torch.float32 if prec == af.FP32 else torch.float64
+    out = torch.zeros(nblocks * 256, dtype=dt, device="cuda")
+    af._lib.check(af._lib.load().af_fma_probe(int(prec), af._ptr(out), nblocks, iters, af._stream()))
+    torch.cuda.synchronize()
+    got = out.cpu().double().numpy()
+    a, b = (0.999999, 1e-7)
+    if prec == af.FP32:
+        a, b = float(np.float32(a)), float(np.float32(b))
+    t = np.arange(nblocks * 256) % 256
+    ref = np.zeros_like(got)
+    for k in range(8):
+        x = (t + k).astype(np.float64)
+        for _ in range(16 * iters):
+            x = x * a + b
+        ref += x
+    # FP32: at most one rounding (2^-24 relative) per step of the 48-step chains
+    tol = 1e-12 if prec == af.FP64 else 48 * 2.0 ** -24
+    assert np.all(np.isfinite(got))
+    assert np.max(np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)) <= tol
+    rate = af.fma_probe(prec, nblocks=512, iters=16)
+    print(f"[gpu-parity] FMA probe prec={prec}: {rate:.1f} TFLOP/s", flush=True)
+    assert rate > 1.0
+
+
 def test_edge_cases_and_errors():
     torch = _torch()
     prob = make_problem(0, af.FP64, 16, n0=2, a=1.0, b=0.5)
