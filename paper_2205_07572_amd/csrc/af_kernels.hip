@@ -88,6 +88,38 @@ __device__ __forceinline__ void gather_block(T* lds, Src src) {
   }
 }
 
+// Block gather of NPL planes of NR rows x NC contiguous columns into the LDS
+// image [plane][row][column]: plane p's row r starts at plane(p) + row(r).
+// A thread's positions within a plane are the same in every plane, so their
+// offsets are computed once; all loads are issued before the first store.
+template <typename T, int NT, int NPL, int NR, int NC, typename Plane, typename Row>
+__device__ __forceinline__ void gather_planes(T* lds, Plane plane, Row row) {
+  constexpr int PE = NR * NC;
+  constexpr int PER = (PE + NT - 1) / NT;
+  int off[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = int(threadIdx.x) + u * NT;
+    const int r = e / NC, x = e - r * NC;
+    off[u] = e < PE ? row(r) + x : 0;
+  }
+  T v[NPL][PER];
+#pragma unroll
+  for (int p = 0; p < NPL; ++p) {
+    const T* const b = plane(p);
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+      if (u + 1 < PER || PE % NT == 0 || int(threadIdx.x) + u * NT < PE) v[p][u] = b[off[u]];
+  }
+#pragma unroll
+  for (int p = 0; p < NPL; ++p)
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = int(threadIdx.x) + u * NT;
+      if (u + 1 < PER || PE % NT == 0 || e < PE) lds[p * PE + e] = v[p][u];
+    }
+}
+
 // The same, with element e stored at lds[dst(e)].
 template <typename T, int NT, int NW, typename Dst, typename Src>
 __device__ __forceinline__ void gather_block_to(T* lds, Dst dst, Src src) {
@@ -351,13 +383,12 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
                         (i - ox * M + kGhost)];
     });
   } else {
-    gather_block<T, kThreads, 4 * NCOMP * NR * NC>(&L.in[0][0][0][0], [&](int e) {
-      const int kc = e / (NR * NC), rem = e - kc * (NR * NC);
-      const int rr = rem / NC, x = rem - rr * NC;
-      const int comp = kc % NCOMP, kind = kc / NCOMP;
-      const int j = min(jlo - 1 + rr, M + 2);
-      return A.in[kind][(size_t(comp) * A.npatch + patch) * plane + size_t(j + kGhost) * A.pitch + x];
-    });
+    // the patch's own planes, (kind, component) in the image's order; rows
+    // from jlo - 1, clamped to the array for a short last tile
+    gather_planes<T, kThreads, 4 * NCOMP, NR, NC>(
+        &L.in[0][0][0][0],
+        [&](int p) { return A.in[p / NCOMP] + (size_t(p % NCOMP) * A.npatch + patch) * plane; },
+        [&](int rr) { return (min(jlo - 1 + rr, M + 2) + kGhost) * A.pitch; });
   }
   __syncthreads();
   const int coff = ilo + 2;  // staged column of cell i is i + 2 = ii + coff
