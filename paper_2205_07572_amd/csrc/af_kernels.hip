@@ -64,44 +64,20 @@ struct Walk2 {
   }
 };
 
-// Block gather into a flat LDS image: element e in [0, NW) is src(e).  Each
-// thread issues up to CH global loads before its first LDS store, so the
-// gather pays the memory latency once per CH elements rather than once per
-// element (a load-store loop waits for every load).
-template <typename T, int NT, int NW, typename Src>
-__device__ __forceinline__ void gather_block(T* lds, Src src) {
-  constexpr int PER = (NW + NT - 1) / NT;
-  constexpr int CH = sizeof(T) == 4 ? 16 : 8;
-#pragma unroll
-  for (int c0 = 0; c0 < PER; c0 += CH) {
-    T v[CH];
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int e = int(threadIdx.x) + (c0 + u) * NT;
-      if (c0 + u < PER && ((c0 + u + 1) * NT <= NW || e < NW)) v[u] = src(e);
-    }
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int e = int(threadIdx.x) + (c0 + u) * NT;
-      if (c0 + u < PER && ((c0 + u + 1) * NT <= NW || e < NW)) lds[e] = v[u];
-    }
-  }
-}
-
-// Block gather of NPL planes of NR rows x NC contiguous columns into the LDS
-// image [plane][row][column]: plane p's row r starts at plane(p) + row(r).
-// A thread's positions within a plane are the same in every plane, so their
-// offsets are computed once; all loads are issued before the first store.
-template <typename T, int NT, int NPL, int NR, int NC, typename Plane, typename Row>
-__device__ __forceinline__ void gather_planes(T* lds, Plane plane, Row row) {
+// Block gather of NPL planes of an NR x NC image into LDS [plane][row][col]:
+// position (r, x) of plane p is read from plane(p) + pos(r, x).  A thread's
+// positions are the same in every plane, so their source offsets are
+// computed once; all loads are issued before the first store.
+template <typename T, int NT, int NPL, int NR, int NC, typename Plane, typename Pos>
+__device__ __forceinline__ void gather_planes(T* lds, Plane plane, Pos pos) {
   constexpr int PE = NR * NC;
   constexpr int PER = (PE + NT - 1) / NT;
-  int off[PER];
+  size_t off[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int e = int(threadIdx.x) + u * NT;
     const int r = e / NC, x = e - r * NC;
-    off[u] = e < PE ? row(r) + x : 0;
+    off[u] = e < PE ? pos(r, x) : 0;
   }
   T v[NPL][PER];
 #pragma unroll
@@ -118,27 +94,6 @@ __device__ __forceinline__ void gather_planes(T* lds, Plane plane, Row row) {
       const int e = int(threadIdx.x) + u * NT;
       if (u + 1 < PER || PE % NT == 0 || e < PE) lds[p * PE + e] = v[p][u];
     }
-}
-
-// The same, with element e stored at lds[dst(e)].
-template <typename T, int NT, int NW, typename Dst, typename Src>
-__device__ __forceinline__ void gather_block_to(T* lds, Dst dst, Src src) {
-  constexpr int PER = (NW + NT - 1) / NT;
-  constexpr int CH = sizeof(T) == 4 ? 16 : 8;
-#pragma unroll
-  for (int c0 = 0; c0 < PER; c0 += CH) {
-    T v[CH];
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int e = int(threadIdx.x) + (c0 + u) * NT;
-      if (c0 + u < PER && ((c0 + u + 1) * NT <= NW || e < NW)) v[u] = src(e);
-    }
-#pragma unroll
-    for (int u = 0; u < CH; ++u) {
-      const int e = int(threadIdx.x) + (c0 + u) * NT;
-      if (c0 + u < PER && ((c0 + u + 1) * NT <= NW || e < NW)) lds[dst(e)] = v[u];
-    }
-  }
 }
 
 // Workgroups are handed to the 8 XCDs round-robin (workgroup b to XCD b % 8),
@@ -368,27 +323,27 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
   if constexpr (GN) {  // cells outside the patch from its neighbours' interiors
     const int gpl = patch - A.first;
     const int pix = gpl % A.gnx, piy = gpl / A.gnx;
-    gather_block<T, kThreads, 4 * NCOMP * NR * NC>(&L.in[0][0][0][0], [&](int e) {
-      const int kc = e / (NR * NC), rem = e - kc * (NR * NC);
-      const int rr = rem / NC, x = rem - rr * NC;
-      const int comp = kc % NCOMP, kind = kc / NCOMP;
-      const int j = min(jlo - 1 + rr, M + 2), i = x - kGhost;
-      const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
-      const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
-      int xx = pix + ox, yy = piy + oy;
-      xx = xx < 0 ? xx + A.gnx : (xx >= A.gnx ? xx - A.gnx : xx);
-      yy = yy < 0 ? yy + A.gny : (yy >= A.gny ? yy - A.gny : yy);
-      const int src = A.first + yy * A.gnx + xx;
-      return A.in[kind][(size_t(comp) * A.npatch + src) * plane + size_t(j - oy * M + kGhost) * A.pitch +
-                        (i - ox * M + kGhost)];
-    });
+    // the source patch and offset of a position are the same for every
+    // (kind, component) plane
+    gather_planes<T, kThreads, 4 * NCOMP, NR, NC>(
+        &L.in[0][0][0][0], [&](int p) { return A.in[p / NCOMP] + size_t(p % NCOMP) * A.npatch * plane; },
+        [&](int rr, int x) {
+          const int j = min(jlo - 1 + rr, M + 2), i = x - kGhost;
+          const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
+          const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
+          int xx = pix + ox, yy = piy + oy;
+          xx = xx < 0 ? xx + A.gnx : (xx >= A.gnx ? xx - A.gnx : xx);
+          yy = yy < 0 ? yy + A.gny : (yy >= A.gny ? yy - A.gny : yy);
+          const int src = A.first + yy * A.gnx + xx;
+          return size_t(src) * plane + size_t(j - oy * M + kGhost) * A.pitch + (i - ox * M + kGhost);
+        });
   } else {
     // the patch's own planes, (kind, component) in the image's order; rows
     // from jlo - 1, clamped to the array for a short last tile
     gather_planes<T, kThreads, 4 * NCOMP, NR, NC>(
         &L.in[0][0][0][0],
         [&](int p) { return A.in[p / NCOMP] + (size_t(p % NCOMP) * A.npatch + patch) * plane; },
-        [&](int rr) { return (min(jlo - 1 + rr, M + 2) + kGhost) * A.pitch; });
+        [&](int rr, int x) { return size_t(min(jlo - 1 + rr, M + 2) + kGhost) * A.pitch + x; });
   }
   __syncthreads();
   const int coff = ilo + 2;  // staged column of cell i is i + 2 = ii + coff
@@ -712,17 +667,16 @@ __global__ __launch_bounds__(NT) void k_level_advance(const AdvanceArgs<T> A, co
   const size_t plane = size_t(M + 5) * A.pitch;
 
   // ---- gather: LDS position (r, c) holds local index (c - K, r - K)
-  gather_block<T, NT, 4 * NCOMP * E * E>(&st[0][0][0][0], [&](int e) {
-    const int kc = e / (E * E), rem = e - kc * (E * E);
-    const int rr = rem / E, x = rem - rr * E;
-    const int comp = kc % NCOMP, kind = kc / NCOMP;
-    const int j = rr - K, i = x - K;
-    const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
-    const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
-    const int src = level_nbr(A, pix, piy, ox, oy);
-    const int li = i - ox * M, lj = j - oy * M;
-    return A.in[kind][(size_t(comp) * A.npatch + src) * plane + size_t(lj + kGhost) * A.pitch + (li + kGhost)];
-  });
+  gather_planes<T, NT, 4 * NCOMP, E, E>(
+      &st[0][0][0][0], [&](int p) { return A.in[p / NCOMP] + size_t(p % NCOMP) * A.npatch * plane; },
+      [&](int rr, int x) {
+        const int j = rr - K, i = x - K;
+        const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
+        const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
+        const int src = level_nbr(A, pix, piy, ox, oy);
+        const int li = i - ox * M, lj = j - oy * M;
+        return size_t(src) * plane + size_t(lj + kGhost) * A.pitch + (li + kGhost);
+      });
   __syncthreads();
 
   const T inv36 = T(1) / T(36);
