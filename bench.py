@@ -32,12 +32,6 @@ HBM_PEAK_GBS = 8000.0
 # the kernel source the counters were taken on
 # (profiles/k_level_advance_up_512sq.md holds the commands).
 PROFILED_TRAFFIC = {
-    ("fp32", 1, 256): 10.34e6, ("fp32", 2, 256): 10.53e6, ("fp32", 2, 512): 10.49e6, ("fp32", 4, 512): 10.84e6,
-    ("fp32", 4, 1024): 10.80e6, ("fp32", 5, 512): 11.02e6, ("fp32", 5, 1024): 10.96e6, ("fp32", 6, 512): 11.20e6,
-    ("fp32", 6, 768): 11.18e6, ("fp32", 6, 1024): 11.13e6, ("fp32", 7, 1024): 11.34e6, ("fp32", 8, 512): 11.60e6,
-    ("fp32", 8, 1024): 11.50e6, ("fp32", 10, 1024): 11.83e6,
-    ("fp64", 1, 256): 19.88e6, ("fp64", 2, 512): 20.19e6, ("fp64", 3, 1024): 20.50e6, ("fp64", 4, 512): 20.89e6,
-    ("fp64", 4, 1024): 20.82e6, ("fp64", 5, 1024): 21.16e6,
 }
 
 

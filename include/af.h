@@ -267,10 +267,16 @@ af_status af_reduce_sum(af_ctx* ctx, const af_hier* h, const af_state* bufs,
 af_status af_level_advance(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* level_buf_mask,
                            int32_t level, double dt, int32_t nsteps, hipStream_t stream);
 /* level-advance kernel shapes (steps per launch K, block size) available for
- * the context's problem; af_ctx_set_advance_shape picks one (autotuner). */
+ * the context's problem; af_ctx_set_advance_shape picks one (autotuner).  For
+ * advection the list includes shapes that only the upwind one-pass kernel
+ * runs (both Courant numbers positive and below 1/2, so that every node
+ * traces back, as in Sec. 2.1, into the upwind neighbour cell).  With other
+ * weights af_level_advance replaces such a shape by the default one. */
 int32_t af_ctx_advance_shapes(const af_ctx* ctx, int32_t* ks, int32_t* nts, int32_t cap);
 af_status af_ctx_set_advance_shape(af_ctx* ctx, int32_t k, int32_t nt);
-/* the shape af_level_advance will use (the tuned one, else the default) */
+/* the shape af_level_advance will use (the tuned one, else the default: the
+ * largest K, then the smallest block), for advection assuming the upwind
+ * pattern */
 af_status af_ctx_get_advance_shape(const af_ctx* ctx, int32_t* k, int32_t* nt);
 
 /* af_autotune -- picks, by timing `reps` launches of each candidate with HIP

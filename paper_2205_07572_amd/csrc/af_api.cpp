@@ -729,9 +729,11 @@ af_status level_grid(af_hier* h, int level, int* nx, int* ny) {
   return AF_OK;
 }
 
-void default_advance_shape(const af_ctx* c, int* k, int* nt) {
+// The shape set on the context if it runs here (up: the weights have the
+// upwind pattern), else the largest K with the smallest block.
+void default_advance_shape(const af_ctx* c, bool up, int* k, int* nt) {
   int ks[32], nts[32];
-  const int n = level_advance_shapes(c->fp32(), c->P.eq, c->P.m, ks, nts, 32);
+  const int n = level_advance_shapes(c->fp32(), c->P.eq, c->P.m, ks, nts, 32, up);
   *k = 0;
   *nt = 0;
   if (c->adv_k) {
@@ -748,7 +750,7 @@ void default_advance_shape(const af_ctx* c, int* k, int* nt) {
 af_status af_ctx_set_advance_shape(af_ctx* ctx, int32_t k, int32_t nt) {
   if (!ctx) return fail(AF_ERR_ARG, "null ctx");
   int ks[32], nts[32];
-  const int n = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, ks, nts, 32);
+  const int n = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, ks, nts, 32, true);
   for (int i = 0; i < n; ++i)
     if (ks[i] == k && nts[i] == nt) {
       ctx->adv_k = k;
@@ -761,7 +763,7 @@ af_status af_ctx_set_advance_shape(af_ctx* ctx, int32_t k, int32_t nt) {
 af_status af_ctx_get_advance_shape(const af_ctx* ctx, int32_t* k, int32_t* nt) {
   if (!ctx || !k || !nt) return fail(AF_ERR_ARG, "null argument");
   int kk, nn;
-  default_advance_shape(ctx, &kk, &nn);
+  default_advance_shape(ctx, ctx->P.eq == AF_ADVECTION, &kk, &nn);
   *k = kk;
   *nt = nn;
   return AF_OK;
@@ -770,7 +772,7 @@ af_status af_ctx_get_advance_shape(const af_ctx* ctx, int32_t* k, int32_t* nt) {
 int32_t af_ctx_advance_shapes(const af_ctx* ctx, int32_t* ks, int32_t* nts, int32_t cap) {
   if (!ctx) return -1;
   int k2[32], n2[32];
-  const int n = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, k2, n2, 32);
+  const int n = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, k2, n2, 32, true);
   for (int i = 0; i < n && i < cap; ++i) {
     if (ks) ks[i] = k2[i];
     if (nts) nts[i] = n2[i];
@@ -793,9 +795,6 @@ af_status af_level_advance(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* ma
   const int first = h->H.level_first[level];
   int nx, ny;
   if ((s = level_grid(h, level, &nx, &ny)) != AF_OK) return s;
-  int K, NT;
-  default_advance_shape(ctx, &K, &NT);
-  if (K == 0) return fail(AF_ERR_ARG, "no level-advance kernel for this (precision, equation, m)");
   const double dx = ctx->dx(level), dy = ctx->dy(level);
   AdvanceLaunch L;
   L.fp32 = ctx->fp32();
@@ -813,13 +812,17 @@ af_status af_level_advance(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* ma
   L.b = ctx->P.b;
   L.c = ctx->P.c;
   L.weights = weights_for(ctx, dt / dx, dt / dy);
+  const bool up = level_advance_up_pattern(L.fp32, L.eq, L.weights);
+  int K, NT;
+  default_advance_shape(ctx, up, &K, &NT);
+  if (K == 0) return fail(AF_ERR_ARG, "no level-advance kernel for this (precision, equation, m)");
   int done = 0;
   while (done < nsteps) {
     // a tail shorter than K runs with the K = 1 (or 2) kernel of the same family
     int kk = K, nt = NT;
     if (nsteps - done < K) {
       int ks[32], nts[32];
-      const int n = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, ks, nts, 32);
+      const int n = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, ks, nts, 32, up);
       kk = 0;
       for (int i = 0; i < n; ++i)
         if (ks[i] <= nsteps - done && (ks[i] > kk || (ks[i] == kk && nts[i] < nt))) { kk = ks[i]; nt = nts[i]; }
@@ -920,7 +923,9 @@ af_status af_autotune(af_ctx* ctx, af_hier* h, af_state* bufs, int32_t level, do
   int gnx, gny;
   if (s == AF_OK && level_grid(h, level, &gnx, &gny) == AF_OK) {
     int ks[32], nts[32];
-    const int n = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, ks, nts, 32);
+    const bool up = level_advance_up_pattern(ctx->fp32(), ctx->P.eq,
+                                             weights_for(ctx, dt / ctx->dx(level), dt / ctx->dy(level)));
+    const int n = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, ks, nts, 32, up);
     double b2 = 1e300;
     int bk = 0, bn = 0;
     for (int i = 0; i < n; ++i) {

@@ -994,6 +994,18 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
 // R vertically adjacent cells of one column; strips that run past the
 // region store into spare rows that no later window reads.
 //
+// Region.  The dependence grows by one cell per step on the upwind side only.
+// The write-back stores averages at i, j < M, corners at i, j <= M, x-edge
+// values at i <= M, j < M and y-edge values at i < M, j <= M.  In x, each of
+// these reads only averages and y-edge values at i < M and corners and
+// x-edge values at i <= M (the sources are cells i - 1 and i of the new
+// average, and cell i - 1 or i of a node at index i); y is the same with the
+// edge kinds swapped.  So step s computes local cells s + 1 - K .. M in each
+// direction, a side of M + K - s, and the gather reads local -K .. M.  The
+// column and row just past a region are read but never written: the
+// averages and edge values at index M that come from them are not among
+// the ones above, and nothing needed reads them.
+//
 // LDS layouts.  Step s reads layout s and writes layout s + 1; the layouts
 // alternate between the two buffers.  Layout s puts local cell (s - K, s - K)
 // at position 0 and has row pitch pitch(s): the gather fills layout 0, the
@@ -1007,10 +1019,10 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
 // ---------------------------------------------------------------------------
 template <typename T, int M, int K, int R>
 struct UpPlan {
-  static constexpr int E0 = M + 2 * K + 1;  // side of the gathered block
+  static constexpr int E0 = M + K + 1;  // side of the gathered block
   static constexpr int B = 128 / int(sizeof(T));
   static constexpr int gcd(int a, int b) { return b == 0 ? a : gcd(b, a % b); }
-  static constexpr int ec(int s) { return M + 2 * (K - 1 - s) + 1; }  // region side of step s
+  static constexpr int ec(int s) { return M + K - s; }  // region side of step s
   static constexpr int width(int s) {
     int w = ec(s);
     while (w % gcd(R, B) != 0) ++w;
@@ -1063,7 +1075,12 @@ struct UpPlan {
   // arithmetic (about 8% at K = 8, 1024 threads), so they are used only
   // where they let more blocks share a CU, or where one stride would not
   // fit in LDS at all.
-  static constexpr int UNI = (E0 + R) * max_pitch();
+  static constexpr int max_words() {
+    int m = (E0 + R) * max_pitch();
+    for (int s = 0; s <= K; ++s) m = words(s) > m ? words(s) : m;
+    return m;
+  }
+  static constexpr int UNI = max_words();
   static constexpr bool tight(int nt) {
     return fit(4 * (stride(0) + stride(1)), nt) > fit(8 * UNI, nt) || 8 * UNI * int(sizeof(T)) > 160 * 1024;
   }
@@ -1085,9 +1102,19 @@ struct UpPlan {
 // and the blocks per CU the launch bounds ask for.  On large grids a second
 // resident block overlaps one block's gather and write-back with another's
 // steps.
+// Rows per strip of the upwind level advance: as StripRows, for its first
+// region of side M + K.
+template <int M, int K, int NT>
+struct UpStripRows {
+  static constexpr int EC0 = M + K;
+  static constexpr int S = NT / EC0 > 0 ? NT / EC0 : 1;
+  static constexpr int R0 = (EC0 + S - 1) / S;
+  static constexpr int value = R0 > 6 ? 6 : R0;
+};
+
 template <typename T, int M, int K, int NT>
 struct UpGeom {
-  static constexpr int R = StripRows<M, K, NT>::value;
+  static constexpr int R = UpStripRows<M, K, NT>::value;
   using P = UpPlan<T, M, K, R>;
   static constexpr bool TIGHT = P::tight(NT);
   static constexpr int AS0 = TIGHT ? P::stride(0) : P::UNI;
@@ -1105,7 +1132,7 @@ struct UpLds {
 template <typename T, int M, int K, int NT>
 __global__ __launch_bounds__(NT, (UpGeom<T, M, K, NT>::OCC)) void k_level_advance_up(const AdvanceArgs<T> A,
                                                                                    const AdvWeights<T> W) {
-  constexpr int R = StripRows<M, K, NT>::value;
+  constexpr int R = UpStripRows<M, K, NT>::value;
   using P = UpPlan<T, M, K, R>;
   constexpr int E0 = P::E0;
   constexpr int AS0 = UpGeom<T, M, K, NT>::AS0, AS1 = UpGeom<T, M, K, NT>::AS1;  // array strides of the buffers
@@ -1177,7 +1204,7 @@ __global__ __launch_bounds__(NT, (UpGeom<T, M, K, NT>::OCC)) void k_level_advanc
     T* const qn = &S.q[(s & 1) ? 0 : 4 * AS0];
     const int AI = (s & 1) ? AS1 : AS0;  // array stride of the buffer read
     const int AO = (s & 1) ? AS0 : AS1;  // and of the buffer written
-    const int EC = M + 2 * (K - 1 - s) + 1;  // region side; the region starts at column and row 1 of layout s
+    const int EC = P::ec(s);                 // region side; the region starts at column and row 1 of layout s
     const int WS = kTab.width[s];            // tasks per strip (columns past EC idle)
     const int PI = kTab.pitch[s];            // pitch of the layout read
     const int PO = kTab.pitch[s + 1];        // pitch of the layout written (origin one cell further in)
@@ -1789,19 +1816,31 @@ static AdvanceArgs<T> advance_args(const AdvanceLaunch& s) {
   return A;
 }
 
+// Whether every node kind takes its source cells in the upwind pattern.
+template <typename T>
+static bool adv_up_pattern(const AdvWeights<T>& W) {
+  bool up = true;
+  for (int k = 0; k < 3; ++k)
+    for (int t = 0; t < 2; ++t) up = up && W.off[k][t][0] == up_off(k, 0) && W.off[k][t][1] == up_off(k, 1);
+  return up;
+}
+
+bool level_advance_up_pattern(bool fp32, int eq, const void* weights) {
+  if (eq != 0) return false;
+  return fp32 ? adv_up_pattern(*static_cast<const AdvWeights<float>*>(weights))
+              : adv_up_pattern(*static_cast<const AdvWeights<double>*>(weights));
+}
+
 template <typename T, int EQ, int M, int K, int NT>
 static hipError_t launch_adv_t(const AdvanceLaunch& s, hipStream_t st) {
   const AdvanceArgs<T> A = advance_args<T>(s);
   const dim3 grid(unsigned(s.count));
   if constexpr (EQ == 0) {
     const AdvWeights<T>& W = *static_cast<const AdvWeights<T>*>(s.weights);
-    bool ss = true, up = true;
+    bool ss = true;
     for (int k = 0; k < 3; ++k)
-      for (int t = 0; t < 2; ++t) {
-        ss = ss && W.off[k][t][0] == W.off[k][0][0] && W.off[k][t][1] == W.off[k][0][1];
-        up = up && W.off[k][t][0] == up_off(k, 0) && W.off[k][t][1] == up_off(k, 1);
-      }
-    if (up)
+      for (int t = 0; t < 2; ++t) ss = ss && W.off[k][t][0] == W.off[k][0][0] && W.off[k][t][1] == W.off[k][0][1];
+    if (adv_up_pattern(W))
       hipLaunchKernelGGL((k_level_advance_up<T, M, K, NT>), grid, dim3(NT), 0, st, A, W);
     else if (ss)
       hipLaunchKernelGGL((k_level_advance_adv<T, M, K, NT, true>), grid, dim3(NT), 0, st, A, W);
@@ -1829,6 +1868,23 @@ static hipError_t launch_adv_t(const AdvanceLaunch& s, hipStream_t st) {
   X(float, 1, 16, 1, 256) X(float, 1, 16, 2, 256) X(float, 1, 32, 1, 512) X(float, 1, 32, 2, 512)      \
   X(double, 1, 16, 1, 256) X(double, 1, 16, 2, 256)
 
+// Advection shapes that only the upwind one-pass kernel runs: its gathered
+// block has side m + K + 1, where the two-pass kernel's LDS would not hold
+// m + 2K + 1.  LDS: 8 arrays of (m + K + R + 1) rows of a bank-aligned pitch.
+#define AF_UP_SHAPES(X)                                                                                  \
+  X(float, 32, 12, 1024) X(float, 32, 14, 1024) X(float, 32, 16, 1024) X(float, 32, 10, 512)              \
+  X(float, 32, 12, 512) X(float, 16, 12, 256) X(float, 16, 16, 256)                                      \
+  X(double, 32, 6, 1024) X(double, 32, 8, 1024) X(double, 32, 10, 1024) X(double, 16, 8, 256)
+
+template <typename T, int M, int K, int NT>
+static hipError_t launch_up_t(const AdvanceLaunch& s, hipStream_t st) {
+  const AdvWeights<T>& W = *static_cast<const AdvWeights<T>*>(s.weights);
+  if (!adv_up_pattern(W)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((k_level_advance_up<T, M, K, NT>), dim3(unsigned(s.count)), dim3(NT), 0, st, advance_args<T>(s),
+                     W);
+  return hipGetLastError();
+}
+
 hipError_t launch_level_advance(const AdvanceLaunch& s, hipStream_t st) {
   if (s.count <= 0) return hipSuccess;
 #define AF_ADV_CASE(T_, EQ_, M_, K_, NT_)                                                                  \
@@ -1836,10 +1892,15 @@ hipError_t launch_level_advance(const AdvanceLaunch& s, hipStream_t st) {
     return launch_adv_t<T_, EQ_, M_, K_, NT_>(s, st);
   AF_ADV_SHAPES(AF_ADV_CASE)
 #undef AF_ADV_CASE
+#define AF_UP_CASE(T_, M_, K_, NT_)                                                                      \
+  if ((std::is_same<T_, float>::value == s.fp32) && s.eq == 0 && s.m == M_ && s.k == K_ && s.nt == NT_) \
+    return launch_up_t<T_, M_, K_, NT_>(s, st);
+  AF_UP_SHAPES(AF_UP_CASE)
+#undef AF_UP_CASE
   return hipErrorInvalidValue;
 }
 
-int level_advance_shapes(bool fp32, int eq, int m, int* ks, int* nts, int cap) {
+int level_advance_shapes(bool fp32, int eq, int m, int* ks, int* nts, int cap, bool up) {
   int n = 0;
 #define AF_ADV_LIST(T_, EQ_, M_, K_, NT_)                                                  \
   if ((std::is_same<T_, float>::value == fp32) && eq == EQ_ && m == M_ && n < cap) { \
@@ -1849,6 +1910,14 @@ int level_advance_shapes(bool fp32, int eq, int m, int* ks, int* nts, int cap) {
   }
   AF_ADV_SHAPES(AF_ADV_LIST)
 #undef AF_ADV_LIST
+#define AF_UP_LIST(T_, M_, K_, NT_)                                                                \
+  if (up && (std::is_same<T_, float>::value == fp32) && eq == 0 && m == M_ && n < cap) { \
+    ks[n] = K_;                                                                                   \
+    nts[n] = NT_;                                                                                 \
+    ++n;                                                                                          \
+  }
+  AF_UP_SHAPES(AF_UP_LIST)
+#undef AF_UP_LIST
   return n;
 }
 

@@ -41,8 +41,13 @@ struct BufLaunch {
 
 hipError_t launch_patch_step(const StepLaunch& s, hipStream_t st);
 hipError_t launch_level_advance(const AdvanceLaunch& s, hipStream_t st);
-// fills (K, threads) pairs available for (precision, equation, m); returns the count
-int level_advance_shapes(bool fp32, int eq, int m, int* ks, int* nts, int cap);
+// Fills the level-advance shapes (K, threads) for (precision, equation, m) and
+// returns their count.  With up, also the shapes only the upwind one-pass
+// kernel runs.
+int level_advance_shapes(bool fp32, int eq, int m, int* ks, int* nts, int cap, bool up);
+// Whether advection weights take every node from the upwind source pattern
+// (false for acoustics).
+bool level_advance_up_pattern(bool fp32, int eq, const void* weights);
 // nblocks x kThreads threads, 8 chains x 16 x iters FMAs each
 hipError_t launch_fma_probe(bool fp32, void* out, int nblocks, int iters, hipStream_t st);
 bool step_shape_supported(int m, int ty);
