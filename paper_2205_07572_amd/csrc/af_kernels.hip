@@ -1228,16 +1228,26 @@ __global__ __launch_bounds__(NT, (UpGeom<T, M, K, NT>::OCC)) void k_level_advanc
       const bool tok = live && ci < EC;  // columns EC..WS-1 load in bounds and store nothing
       const int br = q * R * PI + ci;
       const int bw = q * R * PO + ci;
+      // One base offset per array, opaque to the compiler: an array's window
+      // then lies within the 255-element offset range of paired LDS loads
+      // from that base.  Folded into one base with large constants, the
+      // loads were paired by column, with an address computed per pair.
+      int ob[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        ob[k] = int(qo - &S.q[0]) + k * AI + br;
+        asm("" : "+v"(ob[k]));
+      }
       T wa[R + 2][3], w0[R + 2][3], w1[R + 2][3], w2[R + 2][3];
 #pragma unroll
       for (int rr = 0; rr < R + 2; ++rr)
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
-          const int o = br + rr * PI + cc;
-          wa[rr][cc] = qo[o];
-          w0[rr][cc] = qo[AI + o];
-          w1[rr][cc] = qo[2 * AI + o];
-          w2[rr][cc] = qo[3 * AI + o];
+          const int o = rr * PI + cc;
+          wa[rr][cc] = S.q[ob[0] + o];
+          w0[rr][cc] = S.q[ob[1] + o];
+          w1[rr][cc] = S.q[ob[2] + o];
+          w2[rr][cc] = S.q[ob[3] + o];
         }
 #pragma unroll
       for (int u = 0; u < R; ++u) {
