@@ -1155,14 +1155,19 @@ __global__ __launch_bounds__(NT, (UpGeom<T, M, K, NT>::OCC)) void k_level_advanc
   // for the whole launch (FP32; 52 of the 128 registers a lane has at this
   // occupancy).  Held as kernel arguments they overflow the scalar registers,
   // and every reload is a scalar load whose wait also drains all outstanding
-  // LDS loads.  The empty asm statements only pin the register class.
+  // LDS loads.  FP64 blocks of 512 or more threads have room for the 18
+  // weights of the corner and x-edge stencils (36 registers); the other 34
+  // then fit in scalar registers.  Without them the compiler parked FP64
+  // weights in vector lanes, 48 lane moves per step beside 96 FMAs.  (The
+  // 256-thread FP64 shapes got slower with them.)  The empty asm statements
+  // only pin the register class.
   T wf[3][9], wq[25];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
       wf[k][e] = W.w[k][1][e];
-      if constexpr (sizeof(T) == 4) asm volatile("" : "+v"(wf[k][e]));
+      if (sizeof(T) == 4 || (k < 2 && NT >= 512)) asm volatile("" : "+v"(wf[k][e]));
     }
 #pragma unroll
   for (int e = 0; e < 25; ++e) {
