@@ -1914,7 +1914,8 @@ static hipError_t launch_adv_t(const AdvanceLaunch& s, hipStream_t st) {
   X(float, 32, 12, 1024) X(float, 32, 14, 1024) X(float, 32, 16, 1024) X(float, 32, 18, 1024)            \
   X(float, 32, 20, 1024) X(float, 32, 10, 512)                                                          \
   X(float, 32, 12, 512) X(float, 16, 12, 256) X(float, 16, 16, 256)                                      \
-  X(double, 32, 6, 1024) X(double, 32, 8, 1024) X(double, 32, 10, 1024) X(double, 16, 8, 256)
+  X(double, 32, 6, 1024) X(double, 32, 8, 1024) X(double, 32, 10, 1024) X(double, 32, 12, 1024)           \
+  X(double, 16, 8, 256)
 
 template <typename T, int M, int K, int NT>
 static hipError_t launch_up_t(const AdvanceLaunch& s, hipStream_t st) {
