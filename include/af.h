@@ -275,7 +275,8 @@ af_status af_level_advance(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* le
 int32_t af_ctx_advance_shapes(const af_ctx* ctx, int32_t* ks, int32_t* nts, int32_t cap);
 af_status af_ctx_set_advance_shape(af_ctx* ctx, int32_t k, int32_t nt);
 /* the shape af_level_advance will use (the tuned one, else the default: the
- * largest K, then the smallest block), for advection assuming the upwind
+ * largest K, then the smallest block), for advection with both velocity
+ * components positive assuming time steps small enough for the upwind
  * pattern */
 af_status af_ctx_get_advance_shape(const af_ctx* ctx, int32_t* k, int32_t* nt);
 

@@ -763,7 +763,9 @@ af_status af_ctx_set_advance_shape(af_ctx* ctx, int32_t k, int32_t nt) {
 af_status af_ctx_get_advance_shape(const af_ctx* ctx, int32_t* k, int32_t* nt) {
   if (!ctx || !k || !nt) return fail(AF_ERR_ARG, "null argument");
   int kk, nn;
-  default_advance_shape(ctx, ctx->P.eq == AF_ADVECTION, &kk, &nn);
+  // the upwind pattern needs both velocity components positive (and small
+  // enough time steps)
+  default_advance_shape(ctx, ctx->P.eq == AF_ADVECTION && ctx->P.a > 0 && ctx->P.b > 0, &kk, &nn);
   *k = kk;
   *nt = nn;
   return AF_OK;

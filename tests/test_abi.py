@@ -67,6 +67,19 @@ def test_tile_heights_validated():
         ctx.tile = 3
 
 
+def test_default_advance_shape_follows_the_velocity_signs():
+    """Advection lists the shapes that only the upwind one-pass kernel runs
+    (its source pattern needs both velocity components positive); the default
+    shape is one of them only for such a velocity."""
+    up = af.Context(af.Problem(eq=0, prec=1, m=32, a=1.0, b=0.5))
+    mixed = af.Context(af.Problem(eq=0, prec=1, m=32, a=0.8, b=-0.45))
+    assert up.advance_shapes() == mixed.advance_shapes()
+    k_up, _ = up.advance_shape
+    k_mixed, _ = mixed.advance_shape
+    assert k_up == max(k for k, _ in up.advance_shapes())
+    assert 0 < k_mixed < k_up
+
+
 @pytest.mark.parametrize("leaves,msg", [
     ([(0, 0, 0), (0, 1, 0), (0, 0, 1)], "cover"),                       # hole
     ([(0, 0, 0), (0, 1, 0), (0, 0, 1), (0, 1, 1), (1, 0, 0)], "overlap"),  # overlap
