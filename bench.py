@@ -39,7 +39,7 @@ PROFILED_TRAFFIC = {
     ("fp32", 10, 512): 11.13e6, ("fp32", 10, 1024): 11.03e6, ("fp32", 12, 512): 11.33e6,
     ("fp32", 12, 1024): 11.21e6, ("fp32", 14, 1024): 11.39e6, ("fp32", 16, 1024): 11.57e6,
     ("fp32", 18, 1024): 11.75e6, ("fp32", 20, 1024): 11.93e6,
-    ("fp64", 1, 256): 19.73e6, ("fp64", 2, 512): 19.87e6, ("fp64", 3, 1024): 20.02e6, ("fp64", 4, 512): 20.21e6,
+    ("fp64", 1, 256): 19.77e6, ("fp64", 2, 512): 19.87e6, ("fp64", 3, 1024): 20.02e6, ("fp64", 4, 512): 20.21e6,
     ("fp64", 4, 1024): 20.19e6, ("fp64", 5, 1024): 20.35e6, ("fp64", 6, 1024): 20.52e6,
     ("fp64", 8, 1024): 20.85e6, ("fp64", 10, 1024): 21.18e6, ("fp64", 12, 1024): 21.51e6,
 }

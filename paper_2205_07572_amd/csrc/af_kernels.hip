@@ -1009,7 +1009,7 @@ __global__ __launch_bounds__(NT) void k_level_advance_adv(const AdvanceArgs<T> A
 // LDS layouts.  Step s reads layout s and writes layout s + 1; the layouts
 // alternate between the two buffers.  Layout s puts local cell (s - K, s - K)
 // at position 0 and has row pitch pitch(s): the gather fills layout 0, the
-// write-back reads layout K.  In FP32 the last step instead stores its
+// write-back reads layout K.  Most shapes instead store the last step's
 // region, the closed square, to the output directly (UpGeom::DIRECT).  Step
 // s gives each strip width(s) consecutive tasks (its region width, rounded
 // up to a multiple of gcd(R, B), where B is the number of elements that
@@ -1127,10 +1127,12 @@ struct UpGeom {
   static constexpr int WORDS = 4 * (AS0 + AS1);
   static constexpr int OCC = P::fit(WORDS, NT);
   // The last step stores to the output instead of to layout K: one barrier
-  // and one LDS round trip fewer, 1-9% faster in FP32.  FP64 launches got
-  // 10-40% slower with it.  The 768-thread FP32 shape needs more registers
-  // with it (96 instead of 80) and then no longer fits two blocks per CU.
-  static constexpr bool DIRECT = sizeof(T) == 4 && NT != 768;
+  // and one LDS round trip fewer, 1-9% faster (FP64: 2-9% once 18 of its
+  // weights are held in vector registers; with the weights parked in vector
+  // lanes it had been 10-40% slower).  The 768-thread FP32 shape needs more
+  // registers with it (96 instead of 80) and then no longer fits two blocks
+  // per CU.
+  static constexpr bool DIRECT = NT != 768;
   static_assert(AS0 >= P::stride(0) && AS1 >= P::stride(1), "buffer smaller than a layout");
 };
 
