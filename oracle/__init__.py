@@ -78,6 +78,9 @@ def lib():
         L.or_hier_regrid.argtypes = [P, P]
         L.or_hier_sum.argtypes = [P, P]
         L.or_hier_balanced.argtypes = [P]
+        L.or_cnn_conv_backward.argtypes = [P, I, I, P, P, I, P, P, P]
+        L.or_cnn_head.argtypes = [I, P, P, I, P, P, P, P, P]
+        L.or_cnn_head.restype = D
         L.or_hier_balanced.restype = I
         L.or_refine_block.argtypes = [P, I, I, I, P, P, P, P]
         L.or_coarsen_block.argtypes = [P, P, P, P, P, P]
@@ -403,6 +406,45 @@ def cnn_grad(params, x, labels, bf16=False, want_acts=False):
 
 def round_bf16(v):
     return lib().or_round_bf16(float(v))
+
+
+def cnn_conv_backward(x, w, dz, bf16=False):
+    """Adjoint of one 3x3 convolution layer: x [B][cin][16][16] its input, dz
+    [B][32][16][16] the gradient with respect to its pre-activation.
+    Returns (gW [32][cin][3][3], gb [32], dx [B][cin][16][16])."""
+    xx = np.ascontiguousarray(x, dtype=np.float64)
+    ww = np.ascontiguousarray(w, dtype=np.float64)
+    dd = np.ascontiguousarray(dz, dtype=np.float64)
+    B, cin = xx.shape[0], xx.shape[1]
+    gW = np.zeros((32, cin, 3, 3))
+    gb = np.zeros(32)
+    dx = np.zeros_like(xx)
+    lib().or_cnn_conv_backward(_p(xx), B, cin, _p(ww), _p(dd), int(bf16), _p(gW), _p(gb), _p(dx))
+    return gW, gb, dx
+
+
+def cnn_head(params, a3, labels):
+    """Pooling, head and softmax cross-entropy from the last layer's
+    post-activation a3 [B][32][16][16]: (loss, logits [B][3], gWh [3][32],
+    gbh [3], da3 [B][32][16][16])."""
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    aa = np.ascontiguousarray(a3, dtype=np.float64)
+    B = aa.shape[0]
+    nin = _nin_of(p.size)
+    lab = np.ascontiguousarray(labels, dtype=np.int32)
+    logits = np.zeros((B, 3))
+    gWh = np.zeros((3, 32))
+    gbh = np.zeros(3)
+    da3 = np.zeros_like(aa)
+    loss = lib().or_cnn_head(nin, _p(p), _p(aa), B, lab.ctypes.data_as(P), _p(logits), _p(gWh), _p(gbh), _p(da3))
+    return loss, logits, gWh, gbh, da3
+
+
+def _nin_of(nparams):
+    for nin in range(1, 33):
+        if cnn_num_params(nin) == nparams:
+            return nin
+    raise ValueError("parameter count matches no input width")
 
 
 def cnn_conv(x, w, b, bf16=False):

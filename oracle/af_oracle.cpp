@@ -1744,14 +1744,8 @@ struct CnnTape {
   double pooled[kWidth], logits[kClasses], prob[kClasses];
 };
 
-void cnn_forward_one(const CnnShape& S, const double* P, const double* x, bool bf16, CnnTape& T) {
-  T.a[0].assign(x, x + size_t(S.cin[0]) * kPix);
-  for (int l = 0; l < 3; ++l) {
-    T.z[l].assign(size_t(S.cout[l]) * kPix, 0.0);
-    conv3(T.a[l].data(), S.cin[l], P + S.off_w[l], P + S.off_b[l], S.cout[l], bf16, T.z[l].data());
-    T.a[l + 1].resize(T.z[l].size());
-    for (size_t i = 0; i < T.z[l].size(); ++i) T.a[l + 1][i] = T.z[l][i] > 0.0 ? T.z[l][i] : 0.0;
-  }
+// Global mean pooling of a3, the linear head and the softmax.
+void head_forward(const CnnShape& S, const double* P, CnnTape& T) {
   for (int c = 0; c < kWidth; ++c) {
     double s = 0.0;
     for (int p = 0; p < kPix; ++p) s += T.a[3][size_t(c) * kPix + p];
@@ -1767,6 +1761,69 @@ void cnn_forward_one(const CnnShape& S, const double* P, const double* x, bool b
   double den = 0.0;
   for (int k = 0; k < kClasses; ++k) den += std::exp(T.logits[k] - mx);
   for (int k = 0; k < kClasses; ++k) T.prob[k] = std::exp(T.logits[k] - mx) / den;
+}
+
+void cnn_forward_one(const CnnShape& S, const double* P, const double* x, bool bf16, CnnTape& T) {
+  T.a[0].assign(x, x + size_t(S.cin[0]) * kPix);
+  for (int l = 0; l < 3; ++l) {
+    T.z[l].assign(size_t(S.cout[l]) * kPix, 0.0);
+    conv3(T.a[l].data(), S.cin[l], P + S.off_w[l], P + S.off_b[l], S.cout[l], bf16, T.z[l].data());
+    T.a[l + 1].resize(T.z[l].size());
+    for (size_t i = 0; i < T.z[l].size(); ++i) T.a[l + 1][i] = T.z[l][i] > 0.0 ? T.z[l][i] : 0.0;
+  }
+  head_forward(S, P, T);
+}
+
+// d(loss_b / B) through the softmax, the head and the pooling: adds the head
+// parameters' gradient to grad, writes the gradient with respect to a3 of
+// this sample ([32][16][16]) to da, returns loss_b.
+double head_backward(const CnnShape& S, const double* P, const CnnTape& T, int label, int B, double* grad,
+                     double* da) {
+  // d loss_b / d logits = prob - onehot, scaled by 1/B
+  double dlog[kClasses];
+  for (int k = 0; k < kClasses; ++k) dlog[k] = (T.prob[k] - (k == label ? 1.0 : 0.0)) / B;
+  double dpool[kWidth] = {};
+  for (int k = 0; k < kClasses; ++k) {
+    grad[S.off_bh + k] += dlog[k];
+    for (int c = 0; c < kWidth; ++c) {
+      grad[S.off_wh + size_t(k) * kWidth + c] += dlog[k] * T.pooled[c];
+      dpool[c] += dlog[k] * P[S.off_wh + size_t(k) * kWidth + c];
+    }
+  }
+  // through the pooling: every pixel of channel c gets dpool[c]/256
+  for (int c = 0; c < kWidth; ++c)
+    for (int p = 0; p < kPix; ++p) da[size_t(c) * kPix + p] = dpool[c] / kPix;
+  return -std::log(T.prob[label]);
+}
+
+// Adjoint of conv3 for one sample: with dz the gradient of the loss with
+// respect to the output (pre-activation) [cout][16][16], adds
+// d/dw = sum_p dz * in (shifted) to gW, d/db = sum_p dz to gb, and
+// d/din = sum dz * w to din.  With bf16 the products use BF16-rounded
+// operands (dz, in, w), as the forward products do.
+void conv3_backward(const double* in, int cin, const double* W, const double* dz, int cout, bool bf16, double* gW,
+                    double* gb, double* din) {
+  for (int co = 0; co < cout; ++co)
+    for (int y = 0; y < kImg; ++y)
+      for (int x = 0; x < kImg; ++x) {
+        gb[co] += dz[size_t(co) * kPix + y * kImg + x];
+        double g = dz[size_t(co) * kPix + y * kImg + x];
+        if (bf16) g = round_bf16(g);
+        for (int ci = 0; ci < cin; ++ci)
+          for (int ky = 0; ky < 3; ++ky)
+            for (int kx = 0; kx < 3; ++kx) {
+              const int yy = y + ky - 1, xx = x + kx - 1;
+              if (yy < 0 || yy >= kImg || xx < 0 || xx >= kImg) continue;
+              double a = in[size_t(ci) * kPix + yy * kImg + xx];
+              double w = W[((size_t(co) * cin + ci) * 3 + ky) * 3 + kx];
+              if (bf16) {
+                a = round_bf16(a);
+                w = round_bf16(w);
+              }
+              gW[((size_t(co) * cin + ci) * 3 + ky) * 3 + kx] += g * a;
+              din[size_t(ci) * kPix + yy * kImg + xx] += g * w;
+            }
+      }
 }
 
 }  // namespace
@@ -1803,61 +1860,60 @@ double or_cnn_grad(int nin, const double* params, const double* x, int B, const 
   for (int b = 0; b < B; ++b) {
     CnnTape T;
     cnn_forward_one(S, params, x + size_t(b) * nin * kPix, rb, T);
-    loss -= std::log(T.prob[labels[b]]);
     if (acts && b == 0)
       for (int l = 0; l < 3; ++l) {
         std::copy(T.z[l].begin(), T.z[l].end(), acts + size_t(2 * l) * kWidth * kPix);
         std::copy(T.a[l + 1].begin(), T.a[l + 1].end(), acts + size_t(2 * l + 1) * kWidth * kPix);
       }
-    // d loss_b / d logits = prob - onehot, scaled by 1/B
-    double dlog[kClasses];
-    for (int k = 0; k < kClasses; ++k) dlog[k] = (T.prob[k] - (k == labels[b] ? 1.0 : 0.0)) / B;
-    double dpool[kWidth] = {};
-    for (int k = 0; k < kClasses; ++k) {
-      grad[S.off_bh + k] += dlog[k];
-      for (int c = 0; c < kWidth; ++c) {
-        grad[S.off_wh + size_t(k) * kWidth + c] += dlog[k] * T.pooled[c];
-        dpool[c] += dlog[k] * params[S.off_wh + size_t(k) * kWidth + c];
-      }
-    }
-    // through the pooling: every pixel of channel c gets dpool[c]/256
     std::vector<double> da(size_t(kWidth) * kPix);
-    for (int c = 0; c < kWidth; ++c)
-      for (int p = 0; p < kPix; ++p) da[size_t(c) * kPix + p] = dpool[c] / kPix;
+    loss += head_backward(S, params, T, labels[b], B, grad, da.data());
     for (int l = 2; l >= 0; --l) {
-      const int cin = S.cin[l], cout = S.cout[l];
       // through the ReLU
-      std::vector<double> dz(da.size()), dzr;
+      std::vector<double> dz(da.size());
       for (size_t i = 0; i < da.size(); ++i) dz[i] = T.z[l][i] > 0.0 ? da[i] : 0.0;
-      dzr = dz;  // operand of the weight and input gradients (BF16 on request)
-      if (rb)
-        for (double& v : dzr) v = round_bf16(v);
-      const double* W = params + S.off_w[l];
-      double* gW = grad + S.off_w[l];
-      double* gb = grad + S.off_b[l];
-      std::vector<double> dain(size_t(cin) * kPix, 0.0);
-      for (int co = 0; co < cout; ++co)
-        for (int y = 0; y < kImg; ++y)
-          for (int x = 0; x < kImg; ++x) {
-            gb[co] += dz[size_t(co) * kPix + y * kImg + x];
-            const double g = dzr[size_t(co) * kPix + y * kImg + x];
-            for (int ci = 0; ci < cin; ++ci)
-              for (int ky = 0; ky < 3; ++ky)
-                for (int kx = 0; kx < 3; ++kx) {
-                  const int yy = y + ky - 1, xx = x + kx - 1;
-                  if (yy < 0 || yy >= kImg || xx < 0 || xx >= kImg) continue;
-                  double a = T.a[l][size_t(ci) * kPix + yy * kImg + xx];
-                  double w = W[((size_t(co) * cin + ci) * 3 + ky) * 3 + kx];
-                  if (rb) {
-                    a = round_bf16(a);
-                    w = round_bf16(w);
-                  }
-                  gW[((size_t(co) * cin + ci) * 3 + ky) * 3 + kx] += g * a;
-                  dain[size_t(ci) * kPix + yy * kImg + xx] += g * w;
-                }
-          }
+      std::vector<double> dain(size_t(S.cin[l]) * kPix, 0.0);
+      conv3_backward(T.a[l].data(), S.cin[l], params + S.off_w[l], dz.data(), S.cout[l], rb, grad + S.off_w[l],
+                     grad + S.off_b[l], dain.data());
       da.swap(dain);
     }
+  }
+  return loss / B;
+}
+
+// Backward of one 3x3 convolution layer (the adjoint of conv3) for a batch:
+// in [B][cin][16][16] is the layer's input, dz [B][32][16][16] the gradient
+// of the loss with respect to its pre-activation.  Adds to gW [32][cin][3][3]
+// and gb [32], writes din [B][cin][16][16] (gradient with respect to the
+// input).  With bf16 the operands of the products are rounded as in the
+// forward pass; the bias gradient sums dz itself.
+void or_cnn_conv_backward(const double* in, int B, int cin, const double* w, const double* dz, int bf16, double* gW,
+                          double* gb, double* din) {
+  for (int s = 0; s < B; ++s) {
+    std::fill(din + size_t(s) * cin * kPix, din + size_t(s + 1) * cin * kPix, 0.0);
+    conv3_backward(in + size_t(s) * cin * kPix, cin, w, dz + size_t(s) * kWidth * kPix, kWidth, bf16 != 0, gW, gb,
+                   din + size_t(s) * cin * kPix);
+  }
+}
+
+// Pooling, linear head and softmax cross-entropy of a batch from the last
+// layer's post-activation a3 [B][32][16][16]: logits [B][3], the mean loss
+// (returned), its gradient with respect to Wh [3][32] and bh [3] (added), and
+// with respect to a3 (written, [B][32][16][16]).
+double or_cnn_head(int nin, const double* params, const double* a3, int B, const int* labels, double* logits,
+                   double* gWh, double* gbh, double* da3) {
+  const CnnShape S = cnn_shape(nin);
+  std::vector<double> g(S.total, 0.0);
+  double loss = 0.0;
+  for (int b = 0; b < B; ++b) {
+    CnnTape T;
+    T.a[3].assign(a3 + size_t(b) * kWidth * kPix, a3 + size_t(b + 1) * kWidth * kPix);
+    head_forward(S, params, T);
+    for (int k = 0; k < kClasses; ++k) logits[size_t(b) * kClasses + k] = T.logits[k];
+    loss += head_backward(S, params, T, labels[b], B, g.data(), da3 + size_t(b) * kWidth * kPix);
+  }
+  for (int k = 0; k < kClasses; ++k) {
+    gbh[k] += g[S.off_bh + k];
+    for (int c = 0; c < kWidth; ++c) gWh[size_t(k) * kWidth + c] += g[S.off_wh + size_t(k) * kWidth + c];
   }
   return loss / B;
 }

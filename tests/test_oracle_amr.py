@@ -294,3 +294,40 @@ def test_tagging_gradient_of_linear_field():
             assert tags[k] == 0  # at lmax: refine is not possible
     tags2, _ = h.tag(0, 0, 10.0, 3.5)
     assert all(t == -1 for k, t in enumerate(tags2) if 0 < lv[k][1] < 3)
+
+
+def test_tagging_maxmin_linear_field_and_planted_extrema():
+    """The max - min criterion of Sec. 4.1 reads the interior averages of a
+    patch only.  On a linear field the average of a cell is its centre value,
+    so max - min over an interior patch is sx (m-1) dx + sy (m-1) dy (a term
+    dropped, a ghost layer included or a sign error fails this).  Planted
+    extrema in the interior are found; planted values in the ghost layers are
+    ignored; the thresholds follow the refine/coarsen rule."""
+    m, n0 = 8, 4
+    h = oracle.Hier(1, m, n0, n0, 2, c=1.0)
+    h.set_leaves(afsynth.uniform_leaves(n0, n0, 1))
+    sx, sy = 3.0, -1.25
+    h.init_from(afsynth.InitialData(3, lambda x, y: np.stack([sx * x + sy * y, 0 * x, 0 * x])))
+    dx = h.dx(1)
+    expect = abs(sx) * (m - 1) * dx + abs(sy) * (m - 1) * dx
+    _, vals = h.tag(1, 0, 1e300, -1.0)
+    lv = h.leaves()
+    for k, (l, ix, iy) in enumerate(lv):
+        assert abs(vals[k] - expect) < 1e-12, (k, vals[k], expect)
+    # planted extrema: interior values win, ghost values are ignored
+    k0 = 5
+    blk = h.get_block(k0)
+    rng = np.random.default_rng(3)
+    blk["avg"][0] = rng.uniform(0.0, 1.0, blk["avg"][0].shape)
+    blk["avg"][0, 2 + 3, 2 + 6] = 7.5     # interior cell (6, 3)
+    blk["avg"][0, 2 + 0, 2 + 7] = -2.25   # interior cell (7, 0)
+    blk["avg"][0, 0, 5] = 100.0           # ghost layer 2
+    blk["avg"][0, 2 + 4, 2 + m] = -50.0   # ghost layer 1 (cell i = m)
+    h.set_block(k0, blk)
+    tags, vals = h.tag(1, 0, 9.75, 9.0)
+    assert vals[k0] == 7.5 - (-2.25)
+    assert tags[k0] == 1                  # 9.75 >= theta_r and level 1 < lmax 2
+    tags, _ = h.tag(1, 0, 9.76, 9.8)
+    assert tags[k0] == -1                 # 9.75 < theta_c and level 1 > 0
+    tags, _ = h.tag(1, 0, 9.76, 9.75)
+    assert tags[k0] == 0                  # neither: the coarsen test is strict

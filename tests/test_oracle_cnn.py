@@ -80,3 +80,53 @@ def test_bf16_forward_close_to_fp64():
     l16, _ = oracle.cnn_forward(p, x, bf16=True)
     assert np.abs(l16 - l64).max() < 0.05 * max(1.0, np.abs(l64).max())
     assert np.abs(l16 - l64).max() > 0.0
+
+
+def test_conv_backward_is_the_adjoint():
+    """The per-layer backward is the adjoint of the convolution: with
+    y = conv(x, w) (no bias), <dz, y> = <dx, x> = <gW, w>, and the bias
+    gradient is the pixel sum of dz (exact identities of a bilinear map)."""
+    rng = np.random.default_rng(21)
+    B, cin = 2, 5
+    x = rng.standard_normal((B, cin, 16, 16))
+    w = rng.standard_normal((32, cin, 3, 3))
+    dz = rng.standard_normal((B, 32, 16, 16))
+    y = oracle.cnn_conv(x, w, np.zeros(32))
+    gW, gb, dx = oracle.cnn_conv_backward(x, w, dz)
+    lhs = float((dz * y).sum())
+    assert abs(lhs - float((dx * x).sum())) <= 1e-10 * abs(lhs)
+    assert abs(lhs - float((gW * w).sum())) <= 1e-10 * abs(lhs)
+    np.testing.assert_allclose(gb, dz.sum(axis=(0, 2, 3)), rtol=1e-13)
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_layerwise_backward_composes_to_the_gradient(bf16):
+    """Head and per-layer backward, chained by hand through the ReLUs, give
+    the whole-network gradient (itself pinned by finite differences above)."""
+    rng = np.random.default_rng(22)
+    nin, B = 13, 3
+    p = rng.standard_normal(oracle.cnn_num_params(nin)) * 0.3
+    x = rng.standard_normal((B, nin, 16, 16))
+    labels = np.array([2, 0, 1], np.int32)
+    loss, g = oracle.cnn_grad(p, x, labels, bf16=bf16)
+    sl, o = [], 0
+    for cin in (nin, 32, 32):
+        sl.append((o, o + 32 * cin * 9, o + 32 * cin * 9 + 32, cin))
+        o += 32 * cin * 9 + 32
+    # forward by layers
+    a, zs, ins = x, [], []
+    for (w0, w1, b1, cin) in sl:
+        ins.append(a)
+        z = oracle.cnn_conv(a, p[w0:w1].reshape(32, cin, 3, 3), p[w1:b1], bf16=bf16)
+        zs.append(z)
+        a = np.maximum(z, 0.0)
+    loss2, _, gWh, gbh, da = oracle.cnn_head(p, a, labels)
+    assert abs(loss2 - loss) <= 1e-12 * abs(loss)
+    np.testing.assert_allclose(gWh.ravel(), g[o:o + 96], rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(gbh, g[o + 96:o + 99], rtol=1e-12, atol=1e-15)
+    for l in (2, 1, 0):
+        w0, w1, b1, cin = sl[l]
+        dz = np.where(zs[l] > 0.0, da, 0.0)
+        gW, gb, da = oracle.cnn_conv_backward(ins[l], p[w0:w1].reshape(32, cin, 3, 3), dz, bf16=bf16)
+        np.testing.assert_allclose(gW.ravel(), g[w0:w1], rtol=1e-11, atol=1e-14 * np.abs(g[w0:w1]).max())
+        np.testing.assert_allclose(gb, g[w1:b1], rtol=1e-11, atol=1e-14 * np.abs(g[w1:b1]).max())
