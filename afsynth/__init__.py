@@ -180,13 +180,15 @@ WAVE_VECTORS = [(40, 0), (-40, 0), (0, 40), (0, -40), (24, 32), (-24, 32), (24, 
                 (-24, -32), (32, 24), (-32, 24), (32, -24), (-32, -24)]
 
 
-def wave_packet(seed: int, alpha=50.0):
-    """p0 = exp(-alpha |x - x0|^2) cos(k . x), |k| = 80 pi with k in 2 pi Z^2
-    (so the data is periodic), direction and x0 from the seed; u = v = 0."""
+def wave_packet(seed: int, alpha=50.0, kdiv=1):
+    """p0 = exp(-alpha |x - x0|^2) cos(k . x), |k| = 80 pi / kdiv with k in
+    2 pi Z^2 (so the data is periodic; kdiv in {1, 2, 4, 8} keeps the lattice
+    vectors integral), direction and x0 from the seed; u = v = 0."""
+    assert kdiv in (1, 2, 4, 8)
     rng = SplitMix64(0xBEEF + seed)
     x0, y0 = rng.uniform(), rng.uniform()
     kx, ky = WAVE_VECTORS[rng.randint(0, len(WAVE_VECTORS) - 1)]
-    kx, ky = 2 * np.pi * kx, 2 * np.pi * ky
+    kx, ky = 2 * np.pi * (kx // kdiv), 2 * np.pi * (ky // kdiv)
 
     def f(x, y):
         p = _periodic_gauss(x, y, x0, y0, alpha) * np.cos(kx * x + ky * y)

@@ -349,9 +349,14 @@ af_status af_cnn_forward(af_cnn* cnn, const float* x, int32_t B, float* logits, 
                          hipStream_t stream);
 /* mean cross-entropy over the batch (device float [1]) and its gradient
  * (device float [num_params], or NULL for the internal buffer used by
- * af_cnn_adam_step).  labels: device int32 [B], 0 coarsen, 1 keep, 2 refine. */
+ * af_cnn_adam_step).  labels: device int32 [B], 0 coarsen, 1 keep, 2 refine.
+ * dacts: NULL or device FP32 [3][B*256][32] receiving, for each layer, the
+ * gradient of the loss with respect to its post-ReLU output (pixel-major,
+ * channel-minor), the upstream gradient its backward pass consumes.  Every
+ * reduction (weight gradients over pixels, bias gradients, batch sums of the
+ * head) adds its terms in a fixed order, so the result is deterministic. */
 af_status af_cnn_loss_grad(af_cnn* cnn, const float* x, const int32_t* labels, int32_t B, float* loss,
-                           float* grad, hipStream_t stream);
+                           float* grad, float* dacts, hipStream_t stream);
 /* Adam (beta1 0.9, beta2 0.999, eps 1e-8) step t >= 1 with learning rate lr;
  * grad NULL = the internal gradient of the last af_cnn_loss_grad. */
 af_status af_cnn_adam_step(af_cnn* cnn, const float* grad, float lr, int32_t t, hipStream_t stream);
@@ -369,16 +374,6 @@ af_status af_cnn_features(af_ctx* ctx, af_cnn* cnn, const af_hier* h, const af_s
 af_status af_cnn_tag(af_ctx* ctx, af_cnn* cnn, const af_hier* h, const af_state* bufs,
                      uint32_t level_buf_mask, const int8_t* plain, int8_t* tags, int8_t* learned,
                      hipStream_t stream);
-
-/* af_fma_probe -- measurement helper, not part of the method: nblocks
- * blocks of 256 threads each run 8 independent multiply-add chains of
- * 16 x iters steps in `prec` (AF_FP32 or AF_FP64), compiled like the
- * library's kernels, and write one value per thread to out (device,
- * [nblocks * 256] elements of that precision).  2 * 8 * 16 * iters * 256 *
- * nblocks flops; timing it on `stream` gives the vector FMA rate the
- * kernels can reach on this device.  AF_ERR_ARG for a bad precision, a null
- * out or counts below 1. */
-af_status af_fma_probe(int32_t prec, void* out, int32_t nblocks, int32_t iters, hipStream_t stream);
 
 #ifdef __cplusplus
 }

@@ -345,12 +345,15 @@ class Tagger:
         _lib.check_cnn(_lib.load().af_cnn_forward(self.h, _ptr(x), int(B), _ptr(logits), _ptr(a), _stream()))
         return (logits, a) if acts else logits
 
-    def loss_grad(self, x, labels, grad=None):
+    def loss_grad(self, x, labels, grad=None, dacts=False):
+        """Loss (device [1]) and gradient (into grad, or the internal buffer);
+        with dacts also each layer's upstream gradient [3][B*256][32]."""
         torch = _torch()
         loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        d = torch.zeros((3, x.shape[0] * 256, 32), dtype=torch.float32, device="cuda") if dacts else None
         _lib.check_cnn(_lib.load().af_cnn_loss_grad(self.h, _ptr(x), _ptr(labels), int(x.shape[0]), _ptr(loss),
-                                                    _ptr(grad), _stream()))
-        return loss
+                                                    _ptr(grad), _ptr(d), _stream()))
+        return (loss, d) if dacts else loss
 
     def adam_step(self, lr, grad=None):
         self.t += 1

@@ -22,11 +22,15 @@ EXPORTS = [
     "af_patch_step", "af_ghost_fill", "af_flux_correct", "af_regrid_tag", "af_hier_regrid",
     "af_regrid_apply", "af_reduce_sum", "af_amr_coarse_step", "af_level_advance",
     "af_ctx_advance_shapes", "af_ctx_set_advance_shape", "af_autotune",
-    "af_ctx_get_advance_shape", "af_fma_probe",
+    "af_ctx_get_advance_shape",
     "af_cnn_last_error", "af_cnn_create", "af_cnn_destroy", "af_cnn_num_params", "af_cnn_set_params",
     "af_cnn_get_params", "af_cnn_set_normalization", "af_cnn_forward", "af_cnn_loss_grad",
     "af_cnn_adam_step", "af_cnn_features", "af_cnn_tag",
 ]
+
+# Measurement helpers the library also exports (csrc/af_probe.h); not part
+# of the method's interface.
+PROBES = ["af_fma_probe"]
 
 
 class af_problem(ctypes.Structure):
@@ -109,11 +113,11 @@ def load():
     L.af_cnn_get_params.argtypes = [P, P]
     L.af_cnn_set_normalization.argtypes = [P, P, P]
     L.af_cnn_forward.argtypes = [P, P, i32, P, P, P]
-    L.af_cnn_loss_grad.argtypes = [P, P, P, i32, P, P, P]
+    L.af_cnn_loss_grad.argtypes = [P, P, P, i32, P, P, P, P]
     L.af_cnn_adam_step.argtypes = [P, P, ctypes.c_float, i32, P]
     L.af_cnn_features.argtypes = [P, P, P, S, ctypes.c_uint32, P, P]
     L.af_cnn_tag.argtypes = [P, P, P, S, ctypes.c_uint32, P, P, P, P]
-    for name in EXPORTS:
+    for name in EXPORTS + PROBES:
         if name not in ("af_last_error", "af_hier_num_leaves", "af_ctx_get_tile", "af_hier_finest_level",
                         "af_hier_side_mask", "af_hier_leaf_xy", "af_ctx_advance_shapes", "af_cnn_last_error", "af_cnn_num_params"):
             getattr(L, name).restype = ctypes.c_int

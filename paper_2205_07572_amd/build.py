@@ -16,7 +16,7 @@ LIB = os.path.join(HERE, "libaf.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["af_kernels.hip", "af_api.cpp", "af_hier.cpp", "af_weights.cpp", "af_cnn.hip"]
-HEADERS = ["af_internal.h", "af_launch.h", "af_hier.h", "af_weights.h"]
+HEADERS = ["af_internal.h", "af_launch.h", "af_hier.h", "af_weights.h", "af_probe.h"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -35,7 +35,7 @@ def _newer(target, deps):
 def build(force: bool = True, verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     hdrs = [os.path.join(CSRC, h) for h in HEADERS] + [os.path.join(INCLUDE, "af.h")]
-    objs = []
+    objs, jobs = [], []
     for src in SOURCES:
         s = os.path.join(CSRC, src)
         o = os.path.join(BUILD, src + ".o")
@@ -45,9 +45,15 @@ def build(force: bool = True, verbose: bool = False) -> str:
             cmd = [HIPCC] + COMMON + lang + ["-c", s, "-o", o]
             if verbose:
                 print(" ".join(cmd), flush=True)
-            r = subprocess.run(cmd, capture_output=True, text=True)
-            if r.returncode != 0:
-                raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+            jobs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
+    # the translation units compile in parallel, one process each
+    failed = []
+    for src, p in jobs:
+        _, err = p.communicate()
+        if p.returncode != 0:
+            failed.append(f"hipcc failed for {src}:\n{err}")
+    if failed:
+        raise RuntimeError("\n".join(failed))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -15,6 +15,7 @@
 #include "af_hier.h"
 #include "af_internal.h"
 #include "af_launch.h"
+#include "af_probe.h"
 #include "af_weights.h"
 
 using namespace af;

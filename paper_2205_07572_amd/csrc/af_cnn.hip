@@ -13,6 +13,7 @@
 // and the Adam update are FP32 elementwise kernels.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -45,8 +46,9 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint3
 // B row j0 + l%16 at k = k0 + 8 (l/16) + e, e < 8 (the same k order for both
 // operands, so the hardware's internal k order does not matter), and the
 // accumulator holds C rows i0 + 4 (l/16) + r, r < 4, column j0 + l%16.
-// blockIdx.z splits K into chunks (multiples of 32) whose partial products
-// are added atomically.
+// blockIdx.z splits K into chunks (multiples of 32); chunk z writes its
+// partial product to part[z][i][j] and k_sum_chunks adds the chunks in
+// order, so the result does not depend on scheduling.
 // ---------------------------------------------------------------------------
 struct GemmArgs {
   const uint16_t* A;
@@ -55,7 +57,8 @@ struct GemmArgs {
   long sbj, sbk;
   float* C;
   long sci, scj;
-  int M, N, K, kchunk, atomic;
+  int M, N, K, kchunk;
+  float* part;  // [nz][M][N] when K is split, else null
 };
 
 __global__ __launch_bounds__(256) void k_gemm_bf16(const GemmArgs g) {
@@ -84,21 +87,44 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const GemmArgs g) {
   for (int r = 0; r < 4; ++r) {
     const int row = ti * 16 + 4 * (lane >> 4) + r, col = tj * 16 + (lane & 15);
     if (row < g.M && col < g.N) {
-      float* p = g.C + row * g.sci + col * g.scj;
-      if (g.atomic) atomicAdd(p, acc[r]);
-      else *p = acc[r];
+      if (g.part) g.part[(size_t(blockIdx.z) * g.M + row) * g.N + col] = acc[r];
+      else g.C[row * g.sci + col * g.scj] = acc[r];
     }
   }
 }
 
-static hipError_t gemm(const GemmArgs& g0, int ksplit, hipStream_t st) {
+// C(i, j) = sum over z = 0, 1, ... of part[z][i][j], in that order.
+__global__ void k_sum_chunks(const float* part, int nz, int M, int N, float* C, long sci, long scj) {
+  const long n = long(M) * N;
+  for (long e = blockIdx.x * long(blockDim.x) + threadIdx.x; e < n; e += long(gridDim.x) * blockDim.x) {
+    float s = part[e];
+    for (int z = 1; z < nz; ++z) s += part[size_t(z) * n + e];
+    const long i = e / N, j = e - i * N;
+    C[i * sci + j * scj] = s;
+  }
+}
+
+// Chunks a split GEMM of this K uses: about K / 4096, at most kMaxChunks.
+constexpr int kMaxChunks = 64;
+int gemm_chunks(long K, int ksplit) {
+  const long kc = ((K + ksplit - 1) / ksplit + 31) / 32 * 32;
+  return int((K + kc - 1) / kc);
+}
+
+// ws: workspace of at least nz * M * N floats when ksplit > 1.
+static hipError_t gemm(const GemmArgs& g0, int ksplit, float* ws, hipStream_t st) {
   GemmArgs g = g0;
   const int tiles = ((g.M + 15) / 16) * ((g.N + 15) / 16);
   const int kc = ((g.K + ksplit - 1) / ksplit + 31) / 32 * 32;
   g.kchunk = kc;
   const int nz = (g.K + kc - 1) / kc;
-  if (nz > 1) g.atomic = 1;
+  g.part = nz > 1 ? ws : nullptr;
   hipLaunchKernelGGL(k_gemm_bf16, dim3(unsigned((tiles + 3) / 4), 1, unsigned(nz)), dim3(256), 0, st, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || nz == 1) return e;
+  const long n = long(g.M) * g.N;
+  hipLaunchKernelGGL(k_sum_chunks, dim3(unsigned(std::min<long>((n + 255) / 256, 4096))), dim3(256), 0, st, ws, nz,
+                     g.M, g.N, g.C, g.sci, g.scj);
   return hipGetLastError();
 }
 
@@ -170,9 +196,12 @@ __global__ void k_pack_weights(const float* W, int c, int cp, uint16_t* Wm, uint
 
 // Head: pooled mean, logits, and (if labels) softmax cross-entropy, its
 // gradient w.r.t. the head parameters and the broadcast pooling gradient.
-// One block of 32 x 8 threads per 8 samples.
+// One block of 32 x 8 threads per 8 samples.  Sample b writes its terms of
+// the batch sums to hp[b][kHeadTerms] (loss, Wh [3][32], bh [3]);
+// k_head_sum adds them in sample order.
+constexpr int kHeadTerms = 1 + kClasses * kWidth + kClasses;
 __global__ void k_head(const float* a3, int B, const float* Wh, const float* bh, float* logits, const int32_t* labels,
-                       float* loss, float* gWh, float* gbh, float* dA3) {
+                       float* hp, float* dA3) {
   const int c = threadIdx.x & 31, sb = threadIdx.x >> 5;
   const int b = blockIdx.x * 8 + sb;
   __shared__ float pooled[8][kWidth], lg[8][4];
@@ -196,18 +225,33 @@ __global__ void k_head(const float* a3, int B, const float* Wh, const float* bh,
   for (int k = 0; k < kClasses; ++k) den += expf(lg[sb][k] - mx);
   float dl[kClasses];
   for (int k = 0; k < kClasses; ++k) dl[k] = (expf(lg[sb][k] - mx) / den - (k == lab ? 1.f : 0.f)) / B;
-  if (c == 0) atomicAdd(loss, -(lg[sb][lab] - mx - logf(den)) / B);
+  float* const t = hp + size_t(b) * kHeadTerms;
+  if (c == 0) t[0] = -(lg[sb][lab] - mx - logf(den)) / B;
   float dp = 0.f;
   for (int k = 0; k < kClasses; ++k) {
-    atomicAdd(&gWh[k * kWidth + c], dl[k] * pooled[sb][c]);
+    t[1 + k * kWidth + c] = dl[k] * pooled[sb][c];
     dp += dl[k] * Wh[k * kWidth + c];
   }
-  if (c < kClasses) atomicAdd(&gbh[c], dl[c]);
+  if (c < kClasses) t[1 + kClasses * kWidth + c] = dl[c];
   for (int p = 0; p < kPix; ++p) dA3[(long(b) * kPix + p) * kWidth + c] = dp * (1.0f / kPix);
 }
 
+// loss, gWh, gbh: the per-sample terms summed over b = 0, 1, ... in order.
+__global__ void k_head_sum(const float* hp, int B, float* loss, float* gWh, float* gbh) {
+  const int e = threadIdx.x;
+  if (e >= kHeadTerms) return;
+  float s = 0.f;
+  for (int b = 0; b < B; ++b) s += hp[size_t(b) * kHeadTerms + e];
+  if (e == 0) *loss = s;
+  else if (e <= kClasses * kWidth) gWh[e - 1] = s;
+  else gbh[e - 1 - kClasses * kWidth] = s;
+}
+
 // G = dA * relu'(Z): FP32 for the bias gradient, BF16 for the products.
-__global__ void k_relu_back(const float* dA, const float* z, long M, uint16_t* gb, float* gbias) {
+// Block k writes its bias partial sums to bpart[k][32] (a thread's elements
+// all belong to channel threadIdx.x % 32, since the stride is a multiple of
+// 32); k_bias_sum adds the blocks in order.
+__global__ void k_relu_back(const float* dA, const float* z, long M, uint16_t* gb, float* bpart) {
   __shared__ float part[256];
   const int c = threadIdx.x & 31;
   float s = 0.f;
@@ -221,8 +265,16 @@ __global__ void k_relu_back(const float* dA, const float* z, long M, uint16_t* g
   if (threadIdx.x < 32) {
     float t = 0.f;
     for (int w = 0; w < 8; ++w) t += part[w * 32 + c];
-    atomicAdd(&gbias[c], t);
+    bpart[size_t(blockIdx.x) * kWidth + c] = t;
   }
+}
+
+__global__ void k_bias_sum(const float* bpart, int nblocks, float* gbias) {
+  const int c = threadIdx.x;
+  if (c >= kWidth) return;
+  float s = 0.f;
+  for (int k = 0; k < nblocks; ++k) s += bpart[size_t(k) * kWidth + c];
+  gbias[c] = s;
 }
 
 // dW packed order from the GEMM layout dWm[co][tap*cp + ci].
@@ -335,6 +387,7 @@ struct af_cnn {
   float* d_dwm = nullptr;
   float* d_logits = nullptr;
   float* d_feat = nullptr;
+  float* d_part = nullptr;  // split-K, bias and head partial sums (fixed-order reductions)
   float* d_norm = nullptr;  // mean[nin], inv_std[nin]
   std::string err;
 };
@@ -352,6 +405,9 @@ af_status cfail(af_status s, const std::string& m) {
   } while (0)
 
 int grid_for(long n) { return int(std::min<long>((n + 255) / 256, 8192)); }
+// K split of the weight-gradient GEMMs (K = B * 256 pixels): chunks of about
+// 4096 pixels, at most kMaxChunks
+int wgrad_split(long M) { return int(std::min<long>(std::max<long>(1, M / 4096), kMaxChunks)); }
 
 af_status ensure_batch(af_cnn* c, int B) {
   if (B <= c->cap) return AF_OK;
@@ -366,6 +422,7 @@ af_status ensure_batch(af_cnn* c, int B) {
   (void)hipFree(c->d_g);
   (void)hipFree(c->d_logits);
   (void)hipFree(c->d_feat);
+  (void)hipFree(c->d_part);
   const long M = long(B) * kPix;
   for (int l = 0; l < 3; ++l) {
     const int cp = l == 0 ? c->cp1 : kWidth;
@@ -379,6 +436,11 @@ af_status ensure_batch(af_cnn* c, int B) {
   CNN_HIP(hipMalloc(&c->d_g, size_t(M) * kWidth * 2));
   CNN_HIP(hipMalloc(&c->d_logits, size_t(B) * kClasses * 4));
   CNN_HIP(hipMalloc(&c->d_feat, size_t(B) * c->nin * kPix * 4));
+  // partial sums: split-K chunks of the weight-gradient GEMMs, per-block
+  // bias sums, per-sample head terms
+  const size_t part = std::max({size_t(gemm_chunks(M, wgrad_split(M))) * kWidth * 9 * kWidth,
+                                size_t(grid_for(M * kWidth)) * kWidth, size_t(B) * kHeadTerms});
+  CNN_HIP(hipMalloc(&c->d_part, part * 4));
   c->cap = B;
   return AF_OK;
 }
@@ -404,8 +466,8 @@ af_status forward(af_cnn* c, const float* x, int B, hipStream_t st) {
     hipLaunchKernelGGL(k_im2col, dim3(grid_for(M * K)), dim3(256), 0, st, l == 0 ? x : nullptr,
                        l == 0 ? nullptr : c->d_ab[l - 1], B, l == 0 ? c->nin : kWidth, cp, c->d_col[l]);
     CNN_HIP(hipGetLastError());
-    GemmArgs g{c->d_col[l], K, 1, c->d_wm[l], K, 1, c->d_z[l], kWidth, 1, int(M), kWidth, K, 0, 0};
-    CNN_HIP(gemm(g, 1, st));
+    GemmArgs g{c->d_col[l], K, 1, c->d_wm[l], K, 1, c->d_z[l], kWidth, 1, int(M), kWidth, K, 0, nullptr};
+    CNN_HIP(gemm(g, 1, nullptr, st));
     hipLaunchKernelGGL(k_bias_relu, dim3(grid_for(M * kWidth)), dim3(256), 0, st, c->d_z[l],
                        c->d_params + c->off_b[l], M, c->d_ab[l], l == 2 ? c->d_a3 : nullptr);
     CNN_HIP(hipGetLastError());
@@ -478,6 +540,7 @@ af_status af_cnn_destroy(af_cnn* c) {
   (void)hipFree(c->d_dwm);
   (void)hipFree(c->d_logits);
   (void)hipFree(c->d_feat);
+  (void)hipFree(c->d_part);
   (void)hipFree(c->d_norm);
   delete c;
   return AF_OK;
@@ -512,7 +575,7 @@ af_status af_cnn_forward(af_cnn* c, const float* x, int32_t B, float* logits, fl
   af_status s = forward(c, x, B, st);
   if (s != AF_OK) return s;
   hipLaunchKernelGGL(k_head, dim3((B + 7) / 8), dim3(256), 0, st, c->d_a3, B, c->d_params + c->off_wh,
-                     c->d_params + c->off_bh, logits, nullptr, nullptr, nullptr, nullptr, nullptr);
+                     c->d_params + c->off_bh, logits, nullptr, nullptr, nullptr);
   CNN_HIP(hipGetLastError());
   if (acts) {
     // pre-activations of the three layers, FP32 [3][B*256][32] (NHWC)
@@ -524,34 +587,39 @@ af_status af_cnn_forward(af_cnn* c, const float* x, int32_t B, float* logits, fl
 }
 
 af_status af_cnn_loss_grad(af_cnn* c, const float* x, const int32_t* labels, int32_t B, float* loss, float* grad,
-                           hipStream_t st) {
+                           float* dacts, hipStream_t st) {
   if (!c || !x || !labels || !loss || B <= 0) return cfail(AF_ERR_ARG, "bad argument");
   float* G = grad ? grad : c->d_grad;
   af_status s = forward(c, x, B, st);
   if (s != AF_OK) return s;
   const long M = long(B) * kPix;
-  CNN_HIP(hipMemsetAsync(G, 0, size_t(c->nparams) * 4, st));
-  CNN_HIP(hipMemsetAsync(loss, 0, 4, st));
+  // every entry of G and loss is written below (no accumulation across calls)
   hipLaunchKernelGGL(k_head, dim3((B + 7) / 8), dim3(256), 0, st, c->d_a3, B, c->d_params + c->off_wh,
-                     c->d_params + c->off_bh, c->d_logits, labels, loss, G + c->off_wh, G + c->off_bh, c->d_dA);
+                     c->d_params + c->off_bh, c->d_logits, labels, c->d_part, c->d_dA);
+  CNN_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_head_sum, dim3(1), dim3(128), 0, st, c->d_part, B, loss, G + c->off_wh, G + c->off_bh);
   CNN_HIP(hipGetLastError());
   for (int l = 2; l >= 0; --l) {
     const int cin = l == 0 ? c->nin : kWidth, cp = l == 0 ? c->cp1 : kWidth;
     const int K = 9 * cp;
-    hipLaunchKernelGGL(k_relu_back, dim3(grid_for(M * kWidth)), dim3(256), 0, st, c->d_dA, c->d_z[l], M, c->d_g,
-                       G + c->off_b[l]);
+    if (dacts)  // the upstream gradient this layer's backward consumes
+      CNN_HIP(hipMemcpyAsync(dacts + size_t(l) * M * kWidth, c->d_dA, size_t(M) * kWidth * 4, hipMemcpyDeviceToDevice,
+                             st));
+    const int nb = grid_for(M * kWidth);
+    hipLaunchKernelGGL(k_relu_back, dim3(nb), dim3(256), 0, st, c->d_dA, c->d_z[l], M, c->d_g, c->d_part);
+    CNN_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_bias_sum, dim3(1), dim3(64), 0, st, c->d_part, nb, G + c->off_b[l]);
     CNN_HIP(hipGetLastError());
     // dWm[co][k] = sum_m G[m][co] Xcol[m][k]
-    CNN_HIP(hipMemsetAsync(c->d_dwm, 0, size_t(kWidth) * K * 4, st));
-    GemmArgs gw{c->d_g, 1, kWidth, c->d_col[l], 1, K, c->d_dwm, K, 1, kWidth, K, int(M), 0, 1};
-    CNN_HIP(gemm(gw, int(std::max<long>(1, M / 4096)), st));
+    GemmArgs gw{c->d_g, 1, kWidth, c->d_col[l], 1, K, c->d_dwm, K, 1, kWidth, K, int(M), 0, nullptr};
+    CNN_HIP(gemm(gw, wgrad_split(M), c->d_part, st));
     hipLaunchKernelGGL(k_unpack_wgrad, dim3(grid_for(kWidth * cin * 9)), dim3(256), 0, st, c->d_dwm, cin, cp,
                        G + c->off_w[l]);
     CNN_HIP(hipGetLastError());
     if (l > 0) {
       // dXcol[m][k] = sum_co G[m][co] Wm[co][k]
-      GemmArgs gx{c->d_g, kWidth, 1, c->d_wt[l], kWidth, 1, c->d_dcol, K, 1, int(M), K, kWidth, 0, 0};
-      CNN_HIP(gemm(gx, 1, st));
+      GemmArgs gx{c->d_g, kWidth, 1, c->d_wt[l], kWidth, 1, c->d_dcol, K, 1, int(M), K, kWidth, 0, nullptr};
+      CNN_HIP(gemm(gx, 1, nullptr, st));
       hipLaunchKernelGGL(k_col2im, dim3(grid_for(M * cp)), dim3(256), 0, st, c->d_dcol, B, cp, c->d_dA);
       CNN_HIP(hipGetLastError());
     }

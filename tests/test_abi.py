@@ -16,8 +16,8 @@ from paper_2205_07572_amd import _lib
 HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "af.h")
 
 
-def _declared():
-    txt = open(HEADER).read()
+def _declared(path=HEADER):
+    txt = open(path).read()
     txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
     return sorted(set(re.findall(r"\b(af_[a-z0-9_]+)\s*\(", txt)))
 
@@ -29,6 +29,18 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
     assert sorted(_lib.EXPORTS) == names
+
+
+def test_measurement_probes_stay_out_of_the_public_header():
+    """Benchmark helpers are declared in the library's internal probe header,
+    exported, and not part of include/af.h."""
+    L = _lib.load()
+    probe_h = os.path.join(os.path.dirname(HEADER), "..", "paper_2205_07572_amd", "csrc", "af_probe.h")
+    names = _declared(probe_h)
+    assert names == sorted(_lib.PROBES)
+    for n in names:
+        assert hasattr(L, n), n
+        assert n not in _declared()
 
 
 @pytest.mark.parametrize("field,value,status", [("m", 12, _lib.AF_ERR_ARG), ("eq", 5, _lib.AF_ERR_ARG),
@@ -151,3 +163,4 @@ def test_missing_library_fails_loudly(tmp_path):
     r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr
     assert "raised:" in r.stdout and "is not built" in r.stdout
+
