@@ -236,7 +236,8 @@ af_status af_hier_regrid(af_ctx* ctx, const af_hier* old, const int8_t* tags, af
  * leaves interpolate from the parent (reconstruction at fine nodes, Simpson
  * for fine averages); coarsened leaves average four children and copy fine
  * vertices.  Writes every leaf of new_h into `dst` (ghosts are not filled:
- * call af_ghost_fill(tmin=0, smin=0) after). */
+ * call af_ghost_fill(tmin=0, smin=0) after), and resolves new_h's ghost-fill
+ * plans, so that its first coarse step does not.  Synchronises the stream. */
 af_status af_regrid_apply(af_ctx* ctx, const af_hier* old, const af_state* old_bufs,
                           uint32_t old_mask, const af_hier* new_h, af_state* dst,
                           hipStream_t stream);
@@ -307,8 +308,19 @@ af_status af_autotune(af_ctx* ctx, af_hier* h, af_state* bufs, int32_t level, do
  * fix of every level.
  * A hierarchy that is one complete level steps without the fill: its patch
  * steps read the cells outside a patch from the neighbours' interiors (the
- * values the fill would copy).  In every case the ghost layers of the result
- * are not filled; call af_ghost_fill before reading them.
+ * values the fill would copy).  Otherwise, for AF_ADVECTION and AF_ACOUSTICS
+ * the subcycled step is batched by start time: with F the finest level and
+ * tau = 0 .. 2^F - 1 in finest steps, one launch steps every patch of every
+ * level that starts a step at tau, reading each ghost DOF from the source
+ * the fill of that time resolves it to (same-level copy, mean of four finer
+ * averages, coarser reconstruction) without writing the fill to memory; a
+ * launch before it makes the conservative fix of the levels that have just
+ * completed a pair of substeps and copies finer or same-level vertices onto
+ * the closed-square boundary nodes of leaves with a neighbour of another
+ * level (the part of the fill a coarser reconstruction reads).  2^F + 2^(F-1)
+ * + 1 launches per coarse step; results equal the recursion above.  In
+ * every case the ghost layers of the result are not filled; call
+ * af_ghost_fill before reading them.
  * --------------------------------------------------------------------- */
 enum { AF_STEP_GRAPH = 1, AF_STEP_GLOBAL = 2 };
 af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* level_buf_mask,

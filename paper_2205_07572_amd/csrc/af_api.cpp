@@ -42,10 +42,14 @@ struct af_ctx {
   int ncomp;
   int ty = 0;  // step tile height (rows per block)
   int adv_k = 0, adv_nt = 0;  // level-advance steps per launch and block size (0 = default)
-  // fill-set entries of one patch block (device)
+  // fill-set entries of one patch block (device); the first ninner lie
+  // within one cell of the interior (all an interior-region step reads)
   std::vector<int32_t> h_entries;
   int32_t* d_entries = nullptr;  // uploaded on first device use
-  int nentries = 0;
+  int nentries = 0, ninner = 0;
+  // indices of the entries that are nodes on the closed square [0, m]^2
+  std::vector<int32_t> h_bnd;
+  int32_t* d_bnd = nullptr;
   // coarse -> fine fill weights (device)
   FillWeights* d_fillw = nullptr;
   // reduction workspace
@@ -96,6 +100,16 @@ struct af_hier {
   // ghost-fill plans per lowest source level (built on first use)
   std::vector<int4*> d_plan;
   std::vector<uint32_t*> d_plan_flags;
+  // with the plan of source bound 0: same-level neighbours [n][9] and the
+  // directions the batched step stages by a same-level gather [n]
+  int32_t* d_nbr = nullptr;
+  uint32_t* d_gnflags = nullptr;
+  // leaves with a neighbour of another level (the only ones a coarser
+  // reconstruction can read from), in leaf order; those of level >= l are
+  // impure[impure_off[l] ..]
+  std::vector<int32_t> impure;
+  std::vector<int> impure_off;
+  int32_t* d_impure = nullptr;
 };
 
 namespace {
@@ -164,13 +178,19 @@ const void* weights_for(af_ctx* c, double dtdx, double dtdy) {
       make_adv_weights<double>(c->P.a * dtdx, c->P.b * dtdy, reinterpret_cast<AdvWeights<double>*>(buf.data()));
     }
   } else {
+    bool sym;
     if (c->fp32()) {
-      buf.resize(sizeof(AcWeights<float>));
-      make_ac_weights<float>(c->P.c * dtdx, c->P.c * dtdy, reinterpret_cast<AcWeights<float>*>(buf.data()));
+      buf.resize(sizeof(AcAllWeights<float>));
+      auto* W = reinterpret_cast<AcAllWeights<float>*>(buf.data());
+      make_ac_weights<float>(c->P.c * dtdx, c->P.c * dtdy, &W->dense);
+      sym = make_ac_orbit_weights<float>(c->P.c * dtdx, c->P.c * dtdy, &W->orbit);
     } else {
-      buf.resize(sizeof(AcWeights<double>));
-      make_ac_weights<double>(c->P.c * dtdx, c->P.c * dtdy, reinterpret_cast<AcWeights<double>*>(buf.data()));
+      buf.resize(sizeof(AcAllWeights<double>));
+      auto* W = reinterpret_cast<AcAllWeights<double>*>(buf.data());
+      make_ac_weights<double>(c->P.c * dtdx, c->P.c * dtdy, &W->dense);
+      sym = make_ac_orbit_weights<double>(c->P.c * dtdx, c->P.c * dtdy, &W->orbit);
     }
+    if (!sym) return nullptr;  // cannot happen: the sector means are mirror symmetric
   }
   auto res = c->wcache.emplace(key, std::move(buf));
   return res.first->second.data();
@@ -197,6 +217,7 @@ af_status ctx_device(af_ctx* c) {
   make_fill_weights(&fw[0]);
   c->d_fillw = dev_upload(fw, &err);
   if (err == hipSuccess) c->d_entries = dev_upload(c->h_entries, &err);
+  if (err == hipSuccess) c->d_bnd = dev_upload(c->h_bnd, &err);
   if (err != hipSuccess) return fail(AF_ERR_DEVICE, std::string("fill table upload: ") + hipGetErrorString(err));
   return AF_OK;
 }
@@ -220,6 +241,7 @@ af_status hier_device(af_hier* h) {
   if (err == hipSuccess) h->d_side_mask = dev_upload(h->H.side_mask, &err);
   if (err == hipSuccess) h->d_xy = dev_upload(xy, &err);
   if (err == hipSuccess) h->d_faces = dev_upload(h->all_faces, &err);
+  if (err == hipSuccess) h->d_impure = dev_upload(h->impure, &err);
   if (err != hipSuccess) return fail(AF_ERR_DEVICE, std::string("hierarchy upload: ") + hipGetErrorString(err));
   HierDev& D = h->dev;
   D.lut = h->d_lut;
@@ -272,32 +294,43 @@ af_status af_ctx_create(const af_problem* prob, af_ctx** out) {
   auto c = std::make_unique<af_ctx>();
   c->P = P;
   c->ncomp = P.eq == AF_ACOUSTICS ? 3 : 1;
-  // default tile heights: about 256 cells per block, smaller for FP64 acoustics (LDS)
+  // default tile heights: about 256 cells per block, smaller for FP64
+  // acoustics at m >= 32 (LDS); a whole 16^2 patch per block is the faster
+  // shape in both precisions
   const bool big = (P.eq == AF_ACOUSTICS && P.prec == AF_FP64);
   switch (P.m) {
     case 8: c->ty = 8; break;
-    case 16: c->ty = big ? 8 : 16; break;
+    case 16: c->ty = 16; break;
     case 32: c->ty = big ? 4 : 8; break;
     case 64: c->ty = big ? 2 : 4; break;
     default: c->ty = 2; break;
   }
   // fill-set entries: every block DOF except interior averages and nodes
-  // strictly inside the interior square
+  // strictly inside the interior square.  Those within one cell of the
+  // interior (cells [-1, m], nodes [-1, m+1]: what a step of the interior
+  // region reads) come first.
   std::vector<int32_t> ent;
   const int m = P.m;
-  for (int kind = 0; kind < 4; ++kind) {
-    const int ihi = (kind == 0 || kind == 3) ? m + 1 : m + 2;
-    const int jhi = (kind == 0 || kind == 2) ? m + 1 : m + 2;
-    for (int j = -2; j <= jhi; ++j)
-      for (int i = -2; i <= ihi; ++i) {
-        bool inside;
-        if (kind == 0) inside = i >= 0 && i < m && j >= 0 && j < m;
-        else if (kind == 1) inside = i >= 1 && i <= m - 1 && j >= 1 && j <= m - 1;
-        else if (kind == 2) inside = i >= 1 && i <= m - 1 && j >= 0 && j <= m - 1;
-        else inside = i >= 0 && i <= m - 1 && j >= 1 && j <= m - 1;
-        if (!inside) ent.push_back((kind << 24) | ((i + 2) << 12) | (j + 2));
-      }
-  }
+  for (int ring = 0; ring < 2; ++ring)
+    for (int kind = 0; kind < 4; ++kind) {
+      const int ihi = (kind == 0 || kind == 3) ? m + 1 : m + 2;
+      const int jhi = (kind == 0 || kind == 2) ? m + 1 : m + 2;
+      for (int j = -2; j <= jhi; ++j)
+        for (int i = -2; i <= ihi; ++i) {
+          bool inside;
+          if (kind == 0) inside = i >= 0 && i < m && j >= 0 && j < m;
+          else if (kind == 1) inside = i >= 1 && i <= m - 1 && j >= 1 && j <= m - 1;
+          else if (kind == 2) inside = i >= 1 && i <= m - 1 && j >= 0 && j <= m - 1;
+          else inside = i >= 0 && i <= m - 1 && j >= 1 && j <= m - 1;
+          if (inside) continue;
+          const bool inner = i >= -1 && i <= ihi - 1 && j >= -1 && j <= jhi - 1;
+          if (inner != (ring == 0)) continue;
+          const bool closed = kind > 0 && i >= 0 && i <= ihi - 2 && j >= 0 && j <= jhi - 2;
+          if (closed) c->h_bnd.push_back(int32_t(ent.size()));
+          ent.push_back((kind << 24) | ((i + 2) << 12) | (j + 2));
+        }
+      if (ring == 0 && kind == 3) c->ninner = int(ent.size());
+    }
   c->h_entries = std::move(ent);
   c->nentries = int(c->h_entries.size());
   *out = c.release();
@@ -307,6 +340,7 @@ af_status af_ctx_create(const af_problem* prob, af_ctx** out) {
 af_status af_ctx_destroy(af_ctx* ctx) {
   if (!ctx) return AF_OK;
   (void)hipFree(ctx->d_entries);
+  (void)hipFree(ctx->d_bnd);
   (void)hipFree(ctx->d_fillw);
   (void)hipFree(ctx->d_part);
   delete ctx;
@@ -354,6 +388,20 @@ af_status af_hier_create(af_ctx* ctx, int32_t n, const int32_t* level, const int
     h->all_faces.insert(h->all_faces.end(), h->H.faces[l].begin(), h->H.faces[l].end());
   }
   h->face_off[h->H.lmax + 1] = int(h->all_faces.size());
+  // leaves whose eight neighbours are not all leaves of their own level
+  h->impure_off.assign(h->H.lmax + 2, 0);
+  for (int k = 0; k < n; ++k) {
+    const Leaf& L = h->H.leaves[k];
+    bool pure = true;
+    for (int dy = -1; dy <= 1 && pure; ++dy)
+      for (int dx = -1; dx <= 1 && pure; ++dx)
+        if ((dx || dy) && h->H.find(L.level, L.ix + dx, L.iy + dy) < 0) pure = false;
+    if (!pure) h->impure.push_back(k);
+  }
+  for (int l = 0, e = 0; l <= h->H.lmax + 1; ++l) {
+    while (e < int(h->impure.size()) && h->H.leaves[h->impure[e]].level < l) ++e;
+    h->impure_off[l] = e;
+  }
   *out = h.release();
   return AF_OK;
 }
@@ -370,6 +418,9 @@ af_status af_hier_destroy(af_hier* h) {
   (void)hipFree(h->d_faces);
   for (int4* p : h->d_plan) (void)hipFree(p);
   for (uint32_t* p : h->d_plan_flags) (void)hipFree(p);
+  (void)hipFree(h->d_nbr);
+  (void)hipFree(h->d_gnflags);
+  (void)hipFree(h->d_impure);
   delete h;
   return AF_OK;
 }
@@ -526,6 +577,7 @@ static af_status patch_step_gather(af_ctx* ctx, const af_state* in, af_state* ou
     L.weights = ctx->fp32() ? static_cast<const void*>(&bp32) : static_cast<const void*>(&bp64);
   } else {
     L.weights = weights_for(ctx, dt / dx, dt / dy);
+    if (!L.weights) return fail(AF_ERR_STATE, "acoustic stencils lack their mirror symmetry");
   }
   AF_HIP(launch_patch_step(L, stream));
   return AF_OK;
@@ -563,7 +615,12 @@ af_status fill_plan(af_ctx* ctx, af_hier* h, int smin, hipStream_t stream) {
   }
   h->d_plan[smin] = plan;
   h->d_plan_flags[smin] = flags;
-  AF_HIP(launch_fill_plan(h->dev, ctx->d_entries, ctx->nentries, ctx->P.m, smin, plan, flags, stream));
+  if (smin == 0) {
+    AF_HIP(hipMalloc(&h->d_nbr, std::max<size_t>(1, n) * 9 * sizeof(int32_t)));
+    AF_HIP(hipMalloc(&h->d_gnflags, std::max<size_t>(1, n) * sizeof(uint32_t)));
+  }
+  AF_HIP(launch_fill_plan(h->dev, ctx->d_entries, ctx->nentries, ctx->P.m, smin, plan, flags,
+                          smin == 0 ? h->d_nbr : nullptr, smin == 0 ? h->d_gnflags : nullptr, stream));
   return AF_OK;
 }
 
@@ -683,6 +740,11 @@ af_status af_regrid_apply(af_ctx* ctx, const af_hier* old, const af_state* old_b
   if (err == hipSuccess) err = hipStreamSynchronize(stream);
   (void)hipFree(d_tr);
   if (err != hipSuccess) return fail(AF_ERR_DEVICE, std::string("transfer: ") + hipGetErrorString(err));
+  // the new hierarchy's ghost-fill plans, so that its first coarse step
+  // does not resolve them
+  af_hier* nhm = const_cast<af_hier*>(nh);
+  for (int l = 0; l <= nhm->H.finest; ++l)
+    if ((s = fill_plan(ctx, nhm, l, stream)) != AF_OK) return s;
   return AF_OK;
 }
 
@@ -815,6 +877,7 @@ af_status af_level_advance(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* ma
   L.b = ctx->P.b;
   L.c = ctx->P.c;
   L.weights = weights_for(ctx, dt / dx, dt / dy);
+  if (!L.weights) return fail(AF_ERR_STATE, "acoustic stencils lack their mirror symmetry");
   const bool up = level_advance_up_pattern(L.fp32, L.eq, L.weights);
   int K, NT;
   default_advance_shape(ctx, up, &K, &NT);
@@ -995,7 +1058,109 @@ struct Driver {
     return AF_OK;
   }
 
+  // ---- batched coarse step (constant coefficients, Sec. 3.2): one launch
+  // per substep start time for all levels that start a step then, with the
+  // ghost data staged from the fill plans; before it, one launch for the
+  // conservative fix of the levels that just completed a pair and the
+  // fill's vertex copies on coarse-fine lines.
+  af_status sync(int smin, int fix_lo, int fix_hi) {
+    const int F = h->H.finest;
+    AmrSyncLaunch S{};
+    S.fp32 = ctx->fp32();
+    S.b = make_buf(ctx, &bufs[0], &bufs[1], mask);
+    S.plevel = h->d_level;
+    S.entries = ctx->d_entries;
+    S.bnd = ctx->d_bnd;
+    S.nentries = ctx->nentries;
+    S.nbnd = int(ctx->h_bnd.size());
+    S.reg = reg;
+    S.inv_area0 = 1.0 / (ctx->dx(0) * ctx->dy(0));
+    if (smin >= 0 && smin <= F) {
+      S.canon = h->d_impure + h->impure_off[smin];
+      S.ncanon = int(h->impure.size()) - h->impure_off[smin];
+      S.plan = h->d_plan[smin];
+    }
+    if (fix_lo <= fix_hi) {
+      const int off = h->face_off[fix_lo];
+      S.faces = h->d_faces + off;
+      S.nfaces = h->face_off[fix_hi + 1] - off;
+    }
+    AF_HIP(launch_amr_sync(S, st));
+    return AF_OK;
+  }
+
+  af_status batched_step(int tau, int l0) {
+    const int F = h->H.finest;
+    // the batched step addresses a DOF array with 32-bit element offsets
+    if (double(bufs[0].npatch) * (ctx->P.m + 5) * bufs[0].pitch * ctx->ncomp >= 2147483648.0)
+      return fail(AF_ERR_LAYOUT, "af_amr_coarse_step: a DOF array of 2^31 or more elements");
+    const double dt0 = dt0_;
+    AmrStepLaunch L{};
+    L.fp32 = ctx->fp32();
+    L.eq = ctx->P.eq;
+    L.m = ctx->P.m;
+    L.ty = ctx->ty;
+    for (int b = 0; b < 2; ++b)
+      for (int k = 0; k < 4; ++k) L.p[b][k] = bufs[b].dof[k];
+    L.npatch = bufs[0].npatch;
+    L.pitch = bufs[0].pitch;
+    L.mask = mask;
+    L.lev0 = l0;
+    L.nlev = F - l0 + 1;
+    for (int k = 0; k < L.nlev; ++k) {
+      const int l = l0 + k;
+      const double dtl = dt0 / double(1 << l);
+      L.count[k] = h->H.level_count[l];
+      L.first[k] = L.count[k] ? h->H.level_first[l] : 0;
+      // the first of a pair of fine substeps also advances ghost layer 1
+      L.region[k] = (l > 0 && ((tau >> (F - l)) & 1) == 0) ? AF_REGION_LAYER1 : AF_REGION_INTERIOR;
+      L.len_dt_x[k] = ctx->dy(l) * dtl;
+      L.len_dt_y[k] = ctx->dx(l) * dtl;
+      mask ^= (1u << l);  // an empty level flips too (the mask convention of a coarse step)
+    }
+    L.dtdx = dt0 / ctx->dx(0);
+    L.dtdy = dt0 / ctx->dy(0);
+    L.a = ctx->P.a;
+    L.b = ctx->P.b;
+    L.c = ctx->P.c;
+    L.reg = reg;
+    L.side_mask = h->d_side_mask;
+    L.plan = h->d_plan[l0];
+    L.entries = ctx->d_entries;
+    L.nentries = ctx->nentries;
+    L.ninner = ctx->ninner;
+    L.fw = ctx->d_fillw;
+    L.nbr = h->d_nbr;
+    L.gnflags = h->d_gnflags;
+    L.weights = weights_for(ctx, L.dtdx, L.dtdy);
+    if (!L.weights) return fail(AF_ERR_STATE, "acoustic stencils lack their mirror symmetry");
+    AF_HIP(launch_amr_step(L, st));
+    return AF_OK;
+  }
+
+  double dt0_ = 0.0;
+
+  af_status coarse_step_batched(double dt0) {
+    const int F = h->H.finest;
+    dt0_ = dt0;
+    af_status s;
+    for (int l = 0; l <= F; ++l)
+      if ((s = fill_plan(ctx, h, l, st)) != AF_OK) return s;
+    for (int tau = 0; tau < (1 << F); ++tau) {
+      // the coarsest level that starts a step at tau
+      const int l0 = tau == 0 ? 0 : F - __builtin_ctz(unsigned(tau));
+      if (tau == 0) {
+        if ((s = sync(0, 1, 0)) != AF_OK) return s;
+      } else if (l0 < F) {
+        if ((s = sync(l0, l0, F - 1)) != AF_OK) return s;
+      }
+      if ((s = batched_step(tau, l0)) != AF_OK) return s;
+    }
+    return F > 0 ? sync(-1, 0, F - 1) : AF_OK;
+  }
+
   af_status coarse_step(double t0, double dt0) {
+    if (!gnx && (ctx->P.eq == AF_ADVECTION || ctx->P.eq == AF_ACOUSTICS)) return coarse_step_batched(dt0);
     if (!gnx) {
       af_status s = af_ghost_fill(ctx, h, bufs, mask, 0, 0, st);
       if (s != AF_OK) return s;

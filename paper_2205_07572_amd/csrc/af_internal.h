@@ -49,6 +49,103 @@ constexpr NbEntry kNbYedgeTab[kNbEdge] = {
     {2, 0, -1}, {2, 1, -1}, {2, 0, 0}, {2, 1, 0},
     {3, 0, -1}, {3, 0, 0}, {3, 0, 1}};
 
+// Mirror orbits of the acoustic neighbourhoods.  The reflections x -> -x and
+// y -> -y about a node map its neighbourhood onto itself, each DOF onto a DOF
+// of the same kind, and commute with the sector means of eq. sphe-mean (the
+// sectors of a node are mirror images).  So on an orbit of the reflections
+// the K weights are equal, the Dx weights are odd in x and even in y, and
+// the Dy weights even in x and odd in y (Dx vanishes where the offset from
+// the node is 0 in x, Dy where it is 0 in y).  A node value is then a sum
+// over orbits of K times the orbit sum plus Dx (Dy) times the orbit's
+// x-odd (y-odd) sum.
+//
+// Offsets from the node in half-cell units of DOF (kind, di, dj) of the
+// neighbourhood of node kind nk owned by cell (0,0).
+constexpr void nb_offset(int nk, int kind, int di, int dj, int* X, int* Y) {
+  // positions in half cells: x_{i-1/2} -> 2i, x_i -> 2i + 1
+  const int px = 2 * di + ((kind == 0 || kind == 3) ? 1 : 0);
+  const int py = 2 * dj + ((kind == 0 || kind == 2) ? 1 : 0);
+  const int nx = nk == 2 ? 1 : 0, ny = nk == 1 ? 1 : 0;  // the node itself
+  *X = px - nx;
+  *Y = py - ny;
+}
+
+struct OrbitMember {
+  int8_t kind, di, dj;
+};
+struct NbOrbit {
+  int8_t n;           // 1, 2 or 4 members
+  int8_t hasx, hasy;  // the members' offsets from the node are nonzero in x / in y
+  // members in the order (+x, +y), (-x, +y), (+x, -y), (-x, -y), those with
+  // a zero offset component left out
+  OrbitMember m[4];
+};
+constexpr int kMaxOrbits = 9;
+struct OrbitTable {
+  int n;
+  NbOrbit o[kMaxOrbits];
+};
+
+constexpr NbEntry nb_entry(int nk, int e) {
+  return nk == 0 ? kNbCornerTab[e] : (nk == 1 ? kNbXedgeTab[e] : kNbYedgeTab[e]);
+}
+constexpr int nb_size(int nk) { return nk == 0 ? kNbCorner : kNbEdge; }
+constexpr int iabs_c(int v) { return v < 0 ? -v : v; }
+
+constexpr OrbitTable make_orbits(int nk) {
+  OrbitTable T{};
+  bool used[kNbCorner] = {};
+  for (int e = 0; e < nb_size(nk); ++e) {
+    if (used[e]) continue;
+    const NbEntry E = nb_entry(nk, e);
+    int X = 0, Y = 0;
+    nb_offset(nk, E.kind, E.di, E.dj, &X, &Y);
+    const int ax = iabs_c(X), ay = iabs_c(Y);
+    NbOrbit O{};
+    O.hasx = ax != 0;
+    O.hasy = ay != 0;
+    for (int sy = 1; sy >= -1; sy -= 2) {
+      if (ay == 0 && sy < 0) continue;
+      for (int sx = 1; sx >= -1; sx -= 2) {
+        if (ax == 0 && sx < 0) continue;
+        for (int f = 0; f < nb_size(nk); ++f) {
+          const NbEntry G = nb_entry(nk, f);
+          int gx = 0, gy = 0;
+          nb_offset(nk, G.kind, G.di, G.dj, &gx, &gy);
+          if (G.kind == E.kind && gx == sx * ax && gy == sy * ay) {
+            used[f] = true;
+            O.m[O.n++] = OrbitMember{G.kind, G.di, G.dj};
+          }
+        }
+      }
+    }
+    T.o[T.n++] = O;
+  }
+  return T;
+}
+constexpr OrbitTable kOrbitTab[3] = {make_orbits(0), make_orbits(1), make_orbits(2)};
+constexpr bool orbits_complete() {
+  for (int nk = 0; nk < 3; ++nk) {
+    int cnt = 0;
+    for (int o = 0; o < kOrbitTab[nk].n; ++o) {
+      const NbOrbit& O = kOrbitTab[nk].o[o];
+      if (O.n != (O.hasx ? 2 : 1) * (O.hasy ? 2 : 1)) return false;
+      cnt += O.n;
+    }
+    if (cnt != nb_size(nk)) return false;
+  }
+  return kOrbitTab[0].n == 9 && kOrbitTab[1].n == 6 && kOrbitTab[2].n == 6;
+}
+static_assert(orbits_complete(), "every neighbourhood entry lies in exactly one mirror orbit");
+
+// Acoustic stencils in orbit form: [node kind][orbit][c][K, Dx, Dy] with
+// c = 0 the value at t + dt and c = 1 the Simpson time sum without its term
+// at t, 4 q(t + dt/2) + q(t + dt).
+template <typename T>
+struct AcOrbitWeights {
+  T w[3][kMaxOrbits][2][3];
+};
+
 // Stencil weights of one level's step (same on every level under 2:1
 // subcycling, since dt/dx is fixed).  Index [kind][tau] with tau 0 = dt/2,
 // 1 = dt.
@@ -75,6 +172,14 @@ struct AcWeights {
   T corner[2][3][kNbCorner];  // [tau][K,Dx,Dy][entry]
   T xedge[2][3][kNbEdge];
   T yedge[2][3][kNbEdge];
+};
+
+// Both forms of one step's acoustic stencils: the dense tables (level
+// advance) and the orbit form (patch steps).
+template <typename T>
+struct AcAllWeights {
+  AcWeights<T> dense;
+  AcOrbitWeights<T> orbit;
 };
 
 // Device tables of a hierarchy.

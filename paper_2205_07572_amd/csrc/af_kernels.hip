@@ -224,12 +224,71 @@ __device__ __forceinline__ void ac_eval_rows(const T (&s)[4][3][NR][NC], int r, 
   }
 }
 
+// Acoustic node evaluation in mirror-orbit form (af_internal.h): each node
+// kind sums its neighbourhood orbit by orbit, reading an orbit's members
+// from LDS just before use.  For an orbit of four members (+x,+y), (-x,+y),
+// (+x,-y), (-x,-y) the sum, the x-odd sum and the y-odd sum take 7 additions
+// from the pair sums and differences; K multiplies the sum of every
+// component, Dx the x-odd sums of u (into p) and p (into u), Dy the y-odd
+// sums of v (into p) and p (into v).
+// v1: the node's value at t + dt; vs: 4 q(t + dt/2) + q(t + dt).
+template <typename T, int NK, int NR, int NC>
+__device__ __forceinline__ void ac_node(const T (&s)[4][3][NR][NC], int r, int c,
+                                        const T (&w)[kMaxOrbits][2][3], T v1[3], T vs[3]) {
+  T acc[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+#pragma unroll
+  for (int o = 0; o < kOrbitTab[NK].n; ++o) {
+    const NbOrbit& O = kOrbitTab[NK].o[o];
+    T S[3], Dx[3] = {T(0), T(0), T(0)}, Dy[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const T m0 = s[O.m[0].kind][q][r + O.m[0].dj][c + O.m[0].di];
+      if (O.n == 1) {
+        S[q] = m0;
+      } else if (O.n == 2) {
+        const T m1 = s[O.m[1].kind][q][r + O.m[1].dj][c + O.m[1].di];
+        S[q] = m0 + m1;
+        if (O.hasx && q != 2) Dx[q] = m0 - m1;
+        if (O.hasy && q != 1) Dy[q] = m0 - m1;
+      } else {
+        const T m1 = s[O.m[1].kind][q][r + O.m[1].dj][c + O.m[1].di];
+        const T m2 = s[O.m[2].kind][q][r + O.m[2].dj][c + O.m[2].di];
+        const T m3 = s[O.m[3].kind][q][r + O.m[3].dj][c + O.m[3].di];
+        const T hi = m0 + m1, lo = m2 + m3;
+        S[q] = hi + lo;
+        if (q != 1) Dy[q] = hi - lo;
+        if (q != 2) Dx[q] = (m0 - m1) + (m2 - m3);
+      }
+    }
+#pragma unroll
+    for (int cc = 0; cc < 2; ++cc) {
+      const T wk = w[o][cc][0], wx = w[o][cc][1], wy = w[o][cc][2];
+      acc[cc][0] += wk * S[0];
+      acc[cc][1] += wk * S[1];
+      acc[cc][2] += wk * S[2];
+      if (O.hasx) {
+        acc[cc][0] -= wx * Dx[1];
+        acc[cc][1] -= wx * Dx[0];
+      }
+      if (O.hasy) {
+        acc[cc][0] -= wy * Dy[2];
+        acc[cc][2] -= wy * Dy[0];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    v1[q] = acc[0][q];
+    vs[q] = acc[1][q];
+  }
+}
+
 template <typename T, int EQ>
 struct WSel;
 template <typename T>
 struct WSel<T, 0> { using type = AdvWeights<T>; };
 template <typename T>
-struct WSel<T, 1> { using type = AcWeights<T>; };
+struct WSel<T, 1> { using type = AcOrbitWeights<T>; };
 template <typename T>
 struct WSel<T, 2> { using type = RotParams<T>; };
 template <typename T>
@@ -293,66 +352,34 @@ __device__ __forceinline__ T rot_eval(const T (&s)[4][1][NR][NC], int r, int c, 
   return v;
 }
 
-template <typename T, int EQ, int M, int TY, bool GN>
-__global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
-                                                         const typename WSel<T, EQ>::type W) {
+// The compute part of a patch step on a staged block (shared by the one-level
+// kernel k_patch_step and the multi-level kernel k_amr_step): point values of
+// the extended cells [ilo, ihi] x [jlo, jhi] at t + dt/2 and t + dt, their
+// Simpson time sums in LDS, then fluxes and the conservative update of cells
+// [ilo, ihi) x [jlo, jhi), flux registers of the patch's boundary faces.
+template <typename T>
+struct StepIO {
+  T* out[4];               // the output state (patch planes at patch, component stride npatch planes)
+  int32_t npatch, pitch, patch, region;
+  T dtdx, dtdy, a, b, c;
+  double len_dt_x, len_dt_y;  // dy * dt, dx * dt of the patch's level
+  double* reg;             // FP64 registers [npatch][4][M][NCOMP]; null: nothing recorded
+  uint32_t smask;          // sides whose faces are recorded
+};
+
+template <typename T, int EQ, int M, int TY, typename L_t>
+__device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const typename WSel<T, EQ>::type& W,
+                                             int jlo, int jhi, T px0, T py0) {
   constexpr int NCOMP = EQ == 1 ? 3 : 1;
   constexpr int NR = TY + 3;
   constexpr int NC = M + 5;
-  __shared__ StepLds<T, NCOMP, NR, NC, EQ == 3 ? 3 : 1> L;
-
+  const int patch = A.patch;
   const int region = A.region;
   const int ilo = -region, ihi = M + region;
   const int span = ihi - ilo;
-  const int tiles = (span + TY - 1) / TY;
-  const int rows = (span + tiles - 1) / tiles;  // balanced tile height, at most TY
-  const int w = xcd_patch(int(blockIdx.x), int(gridDim.x));
-  const int pl = w / tiles;
-  const int patch = A.first + pl;
-  const int tile = w - pl * tiles;
-  const int jlo = ilo + tile * rows;
-  const int jhi = min(jlo + rows, ihi);
-  if (jlo >= jhi) return;  // block-uniform; cannot happen for the compiled (m, TY) pairs
   const int nrow = jhi - jlo;
   const size_t plane = size_t(M + 5) * A.pitch;
-
-  // ---- stage NR rows from j = jlo-1 (clamped to the array for a short last
-  // tile) and all M+5 columns (staged column x holds i = x - 2), so the
-  // image has a compile-time shape; rows [jlo-1, jhi+1] and columns
-  // [ilo-1, ihi+1] are the ones read below
-  if constexpr (GN) {  // cells outside the patch from its neighbours' interiors
-    const int gpl = patch - A.first;
-    const int pix = gpl % A.gnx, piy = gpl / A.gnx;
-    // the source patch and offset of a position are the same for every
-    // (kind, component) plane
-    gather_planes<T, kThreads, 4 * NCOMP, NR, NC>(
-        &L.in[0][0][0][0], [&](int p) { return A.in[p / NCOMP] + size_t(p % NCOMP) * A.npatch * plane; },
-        [&](int rr, int x) {
-          const int j = min(jlo - 1 + rr, M + 2), i = x - kGhost;
-          const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
-          const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
-          int xx = pix + ox, yy = piy + oy;
-          xx = xx < 0 ? xx + A.gnx : (xx >= A.gnx ? xx - A.gnx : xx);
-          yy = yy < 0 ? yy + A.gny : (yy >= A.gny ? yy - A.gny : yy);
-          const int src = A.first + yy * A.gnx + xx;
-          return size_t(src) * plane + size_t(j - oy * M + kGhost) * A.pitch + (i - ox * M + kGhost);
-        });
-  } else {
-    // the patch's own planes, (kind, component) in the image's order; rows
-    // from jlo - 1, clamped to the array for a short last tile
-    gather_planes<T, kThreads, 4 * NCOMP, NR, NC>(
-        &L.in[0][0][0][0],
-        [&](int p) { return A.in[p / NCOMP] + (size_t(p % NCOMP) * A.npatch + patch) * plane; },
-        [&](int rr, int x) { return size_t(min(jlo - 1 + rr, M + 2) + kGhost) * A.pitch + x; });
-  }
-  __syncthreads();
   const int coff = ilo + 2;  // staged column of cell i is i + 2 = ii + coff
-  // rotation, swirl: lower-left corner of the patch's cell (0,0)
-  T px0 = T(0), py0 = T(0);
-  if constexpr (EQ == 2 || EQ == 3) {
-    px0 = W.x0 + T(A.leaf_xy[2 * patch] * M) * W.dx;
-    py0 = W.y0 + T(A.leaf_xy[2 * patch + 1] * M) * W.dy;
-  }
 
   // ---- point values of the extended cells [ilo, ihi] x [jlo, jhi]
   const int EC = span + 1, ER = nrow + 1;
@@ -473,27 +500,29 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
         if (wrow) A.out[kind + 1][size_t(patch) * plane + obase] = val[1];
       }
     } else {
-      T res[2][3];
-      ac_eval_rows<T, NR, NC, 0, kNbCorner>(L.in, r, c, W.corner, res);
+      // acoustics (eq. ERFormula): the three nodes of the cell from its
+      // neighbourhood in registers, orbit by orbit
+      T v1[3], vs[3];
+      ac_node<T, 0, NR, NC>(L.in, r, c, W.w[0], v1, vs);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        L.tsum[NK_CORNER][q][jj][ii] = (L.in[1][q][r][c] + T(4) * res[0][q]) + res[1][q];
-        if (wrow) A.out[1][(size_t(q) * A.npatch + patch) * plane + obase] = res[1][q];
+        L.tsum[NK_CORNER][q][jj][ii] = L.in[1][q][r][c] + vs[q];
+        if (wrow) A.out[1][(size_t(q) * A.npatch + patch) * plane + obase] = v1[q];
       }
       if (has_x) {
-        ac_eval_rows<T, NR, NC, 1, kNbEdge>(L.in, r, c, W.xedge, res);
+        ac_node<T, 1, NR, NC>(L.in, r, c, W.w[1], v1, vs);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          L.tsum[NK_XEDGE][q][jj][ii] = (L.in[2][q][r][c] + T(4) * res[0][q]) + res[1][q];
-          A.out[2][(size_t(q) * A.npatch + patch) * plane + obase] = res[1][q];
+          L.tsum[NK_XEDGE][q][jj][ii] = L.in[2][q][r][c] + vs[q];
+          A.out[2][(size_t(q) * A.npatch + patch) * plane + obase] = v1[q];
         }
       }
       if (has_y) {
-        ac_eval_rows<T, NR, NC, 2, kNbEdge>(L.in, r, c, W.yedge, res);
+        ac_node<T, 2, NR, NC>(L.in, r, c, W.w[2], v1, vs);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          L.tsum[NK_YEDGE][q][jj][ii] = (L.in[3][q][r][c] + T(4) * res[0][q]) + res[1][q];
-          if (wrow) A.out[3][(size_t(q) * A.npatch + patch) * plane + obase] = res[1][q];
+          L.tsum[NK_YEDGE][q][jj][ii] = L.in[3][q][r][c] + vs[q];
+          if (wrow) A.out[3][(size_t(q) * A.npatch + patch) * plane + obase] = v1[q];
         }
       }
     }
@@ -501,7 +530,7 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
   __syncthreads();
 
   // ---- fluxes and conservative update (eq. 2dfv) of cells [ilo,ihi) x [jlo,jhi)
-  const uint8_t smask = (A.reg && A.side_mask) ? A.side_mask[patch] : uint8_t(0);
+  const uint32_t smask = A.reg ? A.smask : 0u;
   const T inv36 = T(1) / T(36);
   for (Walk2 w(threadIdx.x, kThreads, span); w.y < nrow; w.next()) {
     const int ii = w.x, jj = w.y;
@@ -615,6 +644,85 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
       }
     }
   }
+}
+
+
+template <typename T, int EQ, int M, int TY, bool GN>
+__global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
+                                                         const typename WSel<T, EQ>::type W) {
+  constexpr int NCOMP = EQ == 1 ? 3 : 1;
+  constexpr int NR = TY + 3;
+  constexpr int NC = M + 5;
+  __shared__ StepLds<T, NCOMP, NR, NC, EQ == 3 ? 3 : 1> L;
+
+  const int region = A.region;
+  const int ilo = -region, ihi = M + region;
+  const int span = ihi - ilo;
+  const int tiles = (span + TY - 1) / TY;
+  const int rows = (span + tiles - 1) / tiles;  // balanced tile height, at most TY
+  const int w = xcd_patch(int(blockIdx.x), int(gridDim.x));
+  const int pl = w / tiles;
+  const int patch = A.first + pl;
+  const int tile = w - pl * tiles;
+  const int jlo = ilo + tile * rows;
+  const int jhi = min(jlo + rows, ihi);
+  if (jlo >= jhi) return;  // block-uniform; cannot happen for the compiled (m, TY) pairs
+  const int nrow = jhi - jlo;
+  const size_t plane = size_t(M + 5) * A.pitch;
+
+  // ---- stage NR rows from j = jlo-1 (clamped to the array for a short last
+  // tile) and all M+5 columns (staged column x holds i = x - 2), so the
+  // image has a compile-time shape; rows [jlo-1, jhi+1] and columns
+  // [ilo-1, ihi+1] are the ones read below
+  if constexpr (GN) {  // cells outside the patch from its neighbours' interiors
+    const int gpl = patch - A.first;
+    const int pix = gpl % A.gnx, piy = gpl / A.gnx;
+    // the source patch and offset of a position are the same for every
+    // (kind, component) plane
+    gather_planes<T, kThreads, 4 * NCOMP, NR, NC>(
+        &L.in[0][0][0][0], [&](int p) { return A.in[p / NCOMP] + size_t(p % NCOMP) * A.npatch * plane; },
+        [&](int rr, int x) {
+          const int j = min(jlo - 1 + rr, M + 2), i = x - kGhost;
+          const int oy = j < 0 ? -1 : (j >= M ? 1 : 0);
+          const int ox = i < 0 ? -1 : (i >= M ? 1 : 0);
+          int xx = pix + ox, yy = piy + oy;
+          xx = xx < 0 ? xx + A.gnx : (xx >= A.gnx ? xx - A.gnx : xx);
+          yy = yy < 0 ? yy + A.gny : (yy >= A.gny ? yy - A.gny : yy);
+          const int src = A.first + yy * A.gnx + xx;
+          return size_t(src) * plane + size_t(j - oy * M + kGhost) * A.pitch + (i - ox * M + kGhost);
+        });
+  } else {
+    // the patch's own planes, (kind, component) in the image's order; rows
+    // from jlo - 1, clamped to the array for a short last tile
+    gather_planes<T, kThreads, 4 * NCOMP, NR, NC>(
+        &L.in[0][0][0][0],
+        [&](int p) { return A.in[p / NCOMP] + (size_t(p % NCOMP) * A.npatch + patch) * plane; },
+        [&](int rr, int x) { return size_t(min(jlo - 1 + rr, M + 2) + kGhost) * A.pitch + x; });
+  }
+  __syncthreads();
+  // rotation, swirl: lower-left corner of the patch's cell (0,0)
+  T px0 = T(0), py0 = T(0);
+  if constexpr (EQ == 2 || EQ == 3) {
+    px0 = W.x0 + T(A.leaf_xy[2 * patch] * M) * W.dx;
+    py0 = W.y0 + T(A.leaf_xy[2 * patch + 1] * M) * W.dy;
+  }
+  StepIO<T> io;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) io.out[k] = A.out[k];
+  io.npatch = A.npatch;
+  io.pitch = A.pitch;
+  io.patch = patch;
+  io.region = region;
+  io.dtdx = A.dtdx;
+  io.dtdy = A.dtdy;
+  io.a = A.a;
+  io.b = A.b;
+  io.c = A.c;
+  io.len_dt_x = A.len_dt_x;
+  io.len_dt_y = A.len_dt_y;
+  io.reg = A.side_mask ? A.reg : nullptr;
+  io.smask = (A.reg && A.side_mask) ? A.side_mask[patch] : 0u;
+  step_compute<T, EQ, M, TY>(L, io, W, jlo, jhi, px0, py0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1513,11 +1621,38 @@ __device__ int4 fill_resolve(const HierDev& H, int m, int smin, int t, int32_t c
   return make_int4(src, fill_info(FO_EVAL, 0, lt - 1, px + 5 * py, 1), ci, cj);
 }
 
+// Direction d = (oy + 1) * 3 + (ox + 1) of block position (i, j) of a patch
+// (ox = -1, 0, 1 for i < 0, 0 <= i < m, i >= m; oy likewise): the patch
+// whose interior holds it on a complete level.
+__device__ __forceinline__ int gather_dir(int i, int j, int m) {
+  const int ox = i < 0 ? -1 : (i >= m ? 1 : 0), oy = j < 0 ? -1 : (j >= m ? 1 : 0);
+  return (oy + 1) * 3 + (ox + 1);
+}
+
 // One block per leaf: the plan row of the leaf and a flag word (bit p: the
-// leaf has ops of phase p).
+// leaf has ops of phase p).  With nbr (the plan of smin = 0), also the
+// leaf's same-level neighbours nbr[t][d] (-1 where the direction holds no
+// leaf of its level; d = 4 is the leaf) and gnflags[t] bit d: every fill-set
+// DOF in direction d resolves to the copy a same-level gather would read
+// (the neighbour's own DOF at the shifted position; for d = 4, the leaf's
+// own value).  Such ops resolve the same way for every source bound up to
+// the leaf's level, since same-level and finer sources are then admissible.
 __global__ __launch_bounds__(kThreads) void k_fill_plan(const HierDev H, const int32_t* entries, int nentries, int m,
-                                                        int smin, int4* plan, uint32_t* flags) {
+                                                        int smin, int4* plan, uint32_t* flags, int32_t* nbr,
+                                                        uint32_t* gnflags) {
   const int t = blockIdx.x;
+  const int lt = H.plevel[t];
+  __shared__ int32_t nb[9];
+  __shared__ uint32_t gn;
+  if (nbr) {
+    if (threadIdx.x < 9) {
+      const int d = threadIdx.x, ox = d % 3 - 1, oy = d / 3 - 1;
+      nb[d] = d == 4 ? t : lut_find(H, lt, (long long)H.pix[t] + ox, (long long)H.piy[t] + oy);
+      nbr[size_t(t) * 9 + d] = nb[d];
+    }
+    if (threadIdx.x == 0) gn = 0x1ffu;
+    __syncthreads();
+  }
   int has0 = 0, has1 = 0;
   for (int e = threadIdx.x; e < nentries; e += kThreads) {
     const int4 op = fill_resolve(H, m, smin, t, entries[e]);
@@ -1526,10 +1661,27 @@ __global__ __launch_bounds__(kThreads) void k_fill_plan(const HierDev H, const i
       if ((op.y >> 16) & 1) has1 = 1;
       else has0 = 1;
     }
+    if (nbr) {
+      const int32_t code = entries[e];
+      const int kind = code >> 24, i = ((code >> 12) & 0xfff) - kGhost, j = (code & 0xfff) - kGhost;
+      const int d = gather_dir(i, j, m), ox = d % 3 - 1, oy = d / 3 - 1;
+      bool ok;
+      if (d == 4) {
+        ok = op.x < 0;
+      } else {
+        const int fo = op.y & 3, skind = (op.y >> 2) & 3, ls = (op.y >> 4) & 15;
+        ok = nb[d] >= 0 && op.x == nb[d] && fo == FO_COPY && skind == kind && ls == lt && op.z == i - ox * m &&
+             op.w == j - oy * m;
+      }
+      if (!ok) atomicAnd(&gn, ~(1u << d));
+    }
   }
   has0 = __syncthreads_or(has0);
   has1 = __syncthreads_or(has1);
-  if (threadIdx.x == 0) flags[t] = uint32_t(has0) | (uint32_t(has1) << 1);
+  if (threadIdx.x == 0) {
+    flags[t] = uint32_t(has0) | (uint32_t(has1) << 1);
+    if (nbr) gnflags[t] = gn;
+  }
 }
 
 template <typename T>
@@ -1595,6 +1747,296 @@ __global__ __launch_bounds__(kThreads) void k_fill_apply(const FillArgs<T> A) {
       }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// Batched subcycled coarse step (Sec. 3.2) for the constant-coefficient
+// equations: one launch per substep start time steps every patch of every
+// level that starts a step then.
+//
+// With the finest level F and time points tau = 0 .. 2^F - 1 in units of the
+// finest step, level l starts a step at tau when 2^(F-l) divides tau; the
+// coarsest such level is l0(tau).  The recursion of Sec. 3.2 fills levels >=
+// l0 from sources of level >= l0 just before those steps, and the steps read
+// only their own patch and its halo, so all of them can share a launch.  The
+// halo is not filled in HBM: k_amr_step stages every fill-set DOF straight
+// from the source the fill plan of that time point names (same-level copy,
+// mean of four finer averages, coarser reconstruction), the values a fill
+// would have written.  A coarser reconstruction reads the source leaf's
+// closed-square nodes, whose copies on coarse-fine lines the fill makes equal
+// to the finer leaf's vertices first (the second fill phase); k_amr_sync does
+// that copy, together with the conservative fix of the levels that just
+// completed a pair of fine substeps, before the launch.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+struct AmrStepArgs {
+  T* p[2][4];                      // the two state buffers
+  int32_t npatch, pitch;
+  uint32_t mask;                   // level l's data before the step: p[(mask >> l) & 1]
+  int32_t nlev, lev0;              // levels lev0 .. lev0 + nlev - 1 step
+  int32_t first[kMaxLevels];       // first leaf of each of those levels
+  int32_t bstart[kMaxLevels + 1];  // first block of each level; bstart[nlev] = blocks
+  int32_t region[kMaxLevels], tiles[kMaxLevels], rows[kMaxLevels];
+  double len_dt_x[kMaxLevels], len_dt_y[kMaxLevels];
+  T dtdx, dtdy, a, b, c;
+  double* reg;                     // FP64 flux registers
+  const uint8_t* side_mask;
+  const int4* plan;                // fill plan of this time point, [nleaves][nentries]
+  const int32_t* entries;          // fill-set entries; the first ninner lie within one cell of the interior
+  int32_t nentries, ninner;
+  const FillWeights* fw;
+  const int32_t* nbr;              // [nleaves][9] same-level neighbours (k_fill_plan)
+  const uint32_t* gnflags;         // [nleaves] directions staged by the same-level gather
+};
+
+// Interior DOFs of a patch that no fill writes (af_ctx_create's fill set is
+// the complement): averages of cells [0,m)^2 and nodes strictly inside.
+__device__ __forceinline__ bool own_dof(int kind, int i, int j, int m) {
+  switch (kind) {
+    case 0: return i >= 0 && i < m && j >= 0 && j < m;
+    case 1: return i >= 1 && i <= m - 1 && j >= 1 && j <= m - 1;
+    case 2: return i >= 1 && i <= m - 1 && j >= 0 && j <= m - 1;
+    default: return i >= 0 && i <= m - 1 && j >= 1 && j <= m - 1;
+  }
+}
+
+// Value of fill-set DOF (kind, i, j) of leaf t as the fill plan resolves it
+// (op), component q; own = the leaf's own buffer (for "no source: keep").
+template <typename T>
+__device__ __forceinline__ T planned_value(T* const (&p)[2][4], uint32_t mask, int npatch, int pitch, int m,
+                                           const FillWeights* fw, const int4& op, const T* own, int q) {
+  const size_t plane = size_t(m + 5) * pitch;
+  if (op.x < 0) return own[size_t(q) * npatch * plane];
+  const int fo = op.y & 3, skind = (op.y >> 2) & 3, ls = (op.y >> 4) & 15, pos = (op.y >> 8) & 255;
+  T* const* sb = p[(mask >> ls) & 1u];
+  const size_t o = (size_t(q) * npatch + op.x) * plane + size_t(op.w + kGhost) * pitch + (op.z + kGhost);
+  if (fo == FO_COPY) return sb[skind][o];
+  if (fo == FO_MEAN4) {
+    const T* v = sb[0] + o;
+    return T(0.25 * ((double(v[0]) + double(v[1])) + (double(v[pitch]) + double(v[pitch + 1]))));
+  }
+  const double* w = fw->w[pos];
+  const T* av = sb[0] + o;
+  const T* co = sb[1] + o;
+  const T* xe = sb[2] + o;
+  const T* ye = sb[3] + o;
+  double v = w[0] * double(av[0]);
+  v += w[1] * double(co[0]);
+  v += w[2] * double(co[1]);
+  v += w[3] * double(co[pitch]);
+  v += w[4] * double(co[pitch + 1]);
+  v += w[5] * double(xe[0]);
+  v += w[6] * double(xe[1]);
+  v += w[7] * double(ye[0]);
+  v += w[8] * double(ye[pitch]);
+  return T(v);
+}
+
+template <typename T, int EQ, int M, int TY>
+__global__ __launch_bounds__(kThreads) void k_amr_step(const AmrStepArgs<T> A, const typename WSel<T, EQ>::type W) {
+  static_assert(EQ == 0 || EQ == 1, "constant-coefficient equations only");
+  constexpr int NCOMP = EQ == 1 ? 3 : 1;
+  constexpr int NR = TY + 3;
+  constexpr int NC = M + 5;
+  __shared__ StepLds<T, NCOMP, NR, NC, 1> L;
+
+  // ---- block -> (level, patch, tile)
+  const int b = xcd_patch(int(blockIdx.x), int(gridDim.x));
+  int k = 0;
+  while (k + 1 < A.nlev && b >= A.bstart[k + 1]) ++k;
+  const int lvl = A.lev0 + k;
+  const int local = b - A.bstart[k];
+  const int tiles = A.tiles[k], rows = A.rows[k], region = A.region[k];
+  const int pl = local / tiles;
+  const int tile = local - pl * tiles;
+  const int patch = A.first[k] + pl;
+  const int ilo = -region, ihi = M + region;
+  const int jlo = ilo + tile * rows;
+  const int jhi = min(jlo + rows, ihi);
+  if (jlo >= jhi) return;  // block-uniform; cannot happen for the compiled (m, TY) pairs
+  const int cur = (A.mask >> lvl) & 1;
+  const size_t plane = size_t(M + 5) * A.pitch;
+  const T* const* in = A.p[cur];
+
+  // ---- stage rows jlo-1 .. jlo-1+NR-1 (those up to m+2) of the patch
+  // block.  Pass A: the DOFs no fill writes from the patch itself, and the
+  // fill-set DOFs of every direction whose planned sources are the same-level
+  // gather's (gnflags) from the neighbour's interior; all loads of a thread
+  // are issued before its stores.  Pass B: the other fill-set DOFs from the
+  // plan.  An interior-region step reads only cells [-1, m] and nodes
+  // [-1, m+1], so both passes skip the outer ring then.
+  const uint32_t gn = A.gnflags[patch];
+  const int32_t* const nbrow = A.nbr + size_t(patch) * 9;
+  const int lo = region == 0 ? -1 : -2, hi = M + 2 - (region == 0 ? 1 : 0);
+  {
+    constexpr int PE = NR * NC;
+    constexpr int PER = (PE + kThreads - 1) / kThreads;
+    // element offsets fit in 32 bits (checked on the host): the loads take a
+    // uniform plane base and a 32-bit per-lane offset
+    const uint32_t plane32 = uint32_t(M + 5) * uint32_t(A.pitch);
+    const uint32_t cstride = uint32_t(A.npatch) * plane32;
+    uint32_t off[PER][4];
+    uint32_t use = 0;  // bit 4u + kind: position u, kind loaded
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = int(threadIdx.x) + u * kThreads;
+      const int rr = e / NC, x = e - rr * NC;
+      const int j = jlo - 1 + rr, i = x - kGhost;
+      const bool valid = e < PE && j <= hi && j >= lo && i >= lo && i <= hi;
+      const int d = gather_dir(i, j, M), ox = d % 3 - 1, oy = d / 3 - 1;
+      const bool gd = valid && ((gn >> d) & 1u);
+      const int src = gd && d != 4 ? nbrow[d] : patch;
+      const uint32_t o_own = uint32_t(patch) * plane32 + uint32_t(j + kGhost) * uint32_t(A.pitch) + uint32_t(x);
+      const uint32_t o_src = uint32_t(src) * plane32 + uint32_t(j - oy * M + kGhost) * uint32_t(A.pitch) +
+                             uint32_t(i - ox * M + kGhost);
+#pragma unroll
+      for (int kind = 0; kind < 4; ++kind) {
+        const bool own = valid && own_dof(kind, i, j, M);
+        off[u][kind] = own ? o_own : o_src;
+        if (own || gd) use |= 1u << (4 * u + kind);
+      }
+    }
+    T v[PER][4][NCOMP];
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+#pragma unroll
+      for (int kind = 0; kind < 4; ++kind)
+        if ((use >> (4 * u + kind)) & 1u)
+#pragma unroll
+          for (int q = 0; q < NCOMP; ++q) v[u][kind][q] = in[kind][off[u][kind] + uint32_t(q) * cstride];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = int(threadIdx.x) + u * kThreads;
+      const int rr = e / NC, x = e - rr * NC;
+#pragma unroll
+      for (int kind = 0; kind < 4; ++kind)
+        if ((use >> (4 * u + kind)) & 1u)
+#pragma unroll
+          for (int q = 0; q < NCOMP; ++q) L.in[kind][q][rr][x] = v[u][kind][q];
+    }
+  }
+  if (gn != 0x1ffu) {
+    const int nent = region == 0 ? A.ninner : A.nentries;
+    const int4* const prow = A.plan + size_t(patch) * A.nentries;
+    for (int e = threadIdx.x; e < nent; e += kThreads) {
+      const int32_t code = A.entries[e];
+      const int kind = code >> 24, i = ((code >> 12) & 0xfff) - kGhost, j = (code & 0xfff) - kGhost;
+      const int rr = j - (jlo - 1);
+      if (rr < 0 || rr >= NR || ((gn >> gather_dir(i, j, M)) & 1u)) continue;
+      const int4 op = prow[e];
+      const T* own = in[kind] + size_t(patch) * plane + size_t(j + kGhost) * A.pitch + (i + kGhost);
+#pragma unroll
+      for (int q = 0; q < NCOMP; ++q)
+        L.in[kind][q][rr][i + kGhost] = planned_value<T>(A.p, A.mask, A.npatch, A.pitch, M, A.fw, op, own, q);
+    }
+  }
+  __syncthreads();
+
+  StepIO<T> io;
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) io.out[kk] = A.p[cur ^ 1][kk];
+  io.npatch = A.npatch;
+  io.pitch = A.pitch;
+  io.patch = patch;
+  io.region = region;
+  io.dtdx = A.dtdx;
+  io.dtdy = A.dtdy;
+  io.a = A.a;
+  io.b = A.b;
+  io.c = A.c;
+  io.len_dt_x = A.len_dt_x[k];
+  io.len_dt_y = A.len_dt_y[k];
+  io.reg = (A.reg && A.side_mask) ? A.reg : nullptr;
+  io.smask = io.reg ? A.side_mask[patch] : 0u;
+  step_compute<T, EQ, M, TY>(L, io, W, jlo, jhi, T(0), T(0));
+}
+
+// Before the launch of a time point: the conservative fix (Sec. 3.2) of the
+// coarse cells next to finer leaves, for the faces [0, nfaces) (the levels
+// that just completed a pair of fine substeps), and the fill's copies of
+// finer or same-level vertices onto the closed-square boundary nodes of the
+// leaves canon[0 .. ncanon) (those with a neighbour of another level: a
+// coarser reconstruction in the next launch may read their nodes).  The two
+// touch disjoint DOFs: the fix only cell averages, the copies only nodes,
+// read from leaves that own them (never a copy target).  Blocks [0, ncanon)
+// copy, one per leaf; the rest fix.
+template <typename T>
+struct AmrSyncArgs {
+  Bufs<T> B;
+  const int32_t* plevel;
+  const int32_t* canon;
+  int32_t ncanon;
+  const int4* plan;
+  const int32_t* entries;
+  const int32_t* bnd;       // indices of the fill-set entries that are closed-square boundary nodes
+  int32_t nentries, nbnd;
+  const CFFace* faces;
+  int32_t nfaces;
+  double* reg;
+  double inv_area0;         // 1 / (dx_0 dy_0); level l: times 4^l
+};
+
+template <typename T>
+__device__ void reflux_face_group(const Bufs<T>& B, const CFFace* faces, int nfaces, int f, double* reg,
+                                  const int32_t* plevel, double inv_area0) {
+  const int m = B.m, nc = B.ncomp;
+  auto cell_of = [&](const CFFace& F, int* ci, int* cj) {
+    *ci = F.side == 0 ? 0 : (F.side == 1 ? m - 1 : F.k);
+    *cj = F.side == 2 ? 0 : (F.side == 3 ? m - 1 : F.k);
+  };
+  int ci, cj;
+  cell_of(faces[f], &ci, &cj);
+  if (f > 0) {
+    int pi, pj;
+    cell_of(faces[f - 1], &pi, &pj);
+    if (faces[f - 1].coarse == faces[f].coarse && pi == ci && pj == cj) return;
+  }
+  const int level = plevel[faces[f].coarse];
+  const double inv_area = inv_area0 * double(1LL << (2 * level));
+  T* av = buf_of(B, level, 0);
+  for (int g = f; g < nfaces; ++g) {
+    const CFFace F = faces[g];
+    int gi, gj;
+    cell_of(F, &gi, &gj);
+    if (F.coarse != faces[f].coarse || gi != ci || gj != cj) break;
+    const double sgn = (F.side == 1 || F.side == 3) ? 1.0 : -1.0;
+    const int opp = F.side ^ 1;
+    double* Rc = reg + (size_t(F.coarse) * 4 + F.side) * m * nc + size_t(F.k) * nc;
+    double* Rf = reg + (size_t(F.fine) * 4 + opp) * m * nc + size_t(F.fk) * nc;
+    for (int q = 0; q < nc; ++q) {
+      const double rf = Rf[q] + Rf[nc + q];
+      const size_t idx = at(B, q, F.coarse, ci, cj);
+      av[idx] = T(double(av[idx]) + sgn * (Rc[q] - rf) * inv_area);
+      Rc[q] = 0.0;
+      Rf[q] = 0.0;
+      Rf[nc + q] = 0.0;
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_amr_sync(const AmrSyncArgs<T> A) {
+  const Bufs<T>& B = A.B;
+  if (int(blockIdx.x) < A.ncanon) {
+    const int t = A.canon[blockIdx.x];
+    const int lt = A.plevel[t];
+    const size_t cstride = size_t(B.npatch) * (B.m + 5) * B.pitch;
+    for (int e = threadIdx.x; e < A.nbnd; e += kThreads) {
+      const int ent = A.bnd[e];
+      const int4 op = A.plan[size_t(t) * A.nentries + ent];
+      if (op.x < 0) continue;  // the leaf owns this node
+      const int32_t code = A.entries[ent];
+      const int kind = code >> 24, i = ((code >> 12) & 0xfff) - kGhost, j = (code & 0xfff) - kGhost;
+      const int skind = (op.y >> 2) & 3, ls = (op.y >> 4) & 15;
+      T* const dst = buf_of(B, lt, kind) + at(B, 0, t, i, j);
+      const T* const src = buf_of(B, ls, skind) + at(B, 0, op.x, op.z, op.w);
+      for (int q = 0; q < B.ncomp; ++q) dst[q * cstride] = src[q * cstride];
+    }
+    return;
+  }
+  const int f = (int(blockIdx.x) - A.ncanon) * kThreads + int(threadIdx.x);
+  if (f < A.nfaces) reflux_face_group(B, A.faces, A.nfaces, f, A.reg, A.plevel, A.inv_area0);
 }
 
 template <typename T>
@@ -1786,6 +2228,16 @@ __global__ __launch_bounds__(kThreads) void k_sum_final(const double* part, int 
 // Launchers
 // ---------------------------------------------------------------------------
 
+// The weights a patch step of equation EQ takes from the host's table
+// (acoustics: the orbit form of AcAllWeights).
+template <typename T, int EQ>
+static const typename WSel<T, EQ>::type& step_weights(const void* p) {
+  if constexpr (EQ == 1)
+    return static_cast<const AcAllWeights<T>*>(p)->orbit;
+  else
+    return *static_cast<const typename WSel<T, EQ>::type*>(p);
+}
+
 template <typename T, int EQ, int M, int TY>
 static hipError_t launch_step_t(const StepLaunch& s, hipStream_t st) {
   StepArgs<T> A;
@@ -1801,7 +2253,7 @@ static hipError_t launch_step_t(const StepLaunch& s, hipStream_t st) {
   const int span = M + 2 * s.region;
   const int tiles = (span + TY - 1) / TY;
   const dim3 grid(unsigned(s.count * tiles));
-  const auto& W = *static_cast<const typename WSel<T, EQ>::type*>(s.weights);
+  const auto& W = step_weights<T, EQ>(s.weights);
   if (s.gnx > 0)
     hipLaunchKernelGGL((k_patch_step<T, EQ, M, TY, true>), grid, dim3(kThreads), 0, st, A, W);
   else
@@ -1832,6 +2284,97 @@ hipError_t launch_patch_step(const StepLaunch& s, hipStream_t st) {
     case 4: return s.fp32 ? launch_step_m<float, 4>(s, st) : launch_step_m<double, 4>(s, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <typename T, int EQ, int M, int TY>
+static hipError_t launch_amr_t(const AmrStepLaunch& s, hipStream_t st) {
+  AmrStepArgs<T> A;
+  for (int b = 0; b < 2; ++b)
+    for (int k = 0; k < 4; ++k) A.p[b][k] = static_cast<T*>(s.p[b][k]);
+  A.npatch = s.npatch;
+  A.pitch = s.pitch;
+  A.mask = s.mask;
+  A.nlev = s.nlev;
+  A.lev0 = s.lev0;
+  int blocks = 0;
+  for (int k = 0; k < s.nlev; ++k) {
+    const int span = M + 2 * s.region[k];
+    const int tiles = (span + TY - 1) / TY;
+    A.first[k] = s.first[k];
+    A.region[k] = s.region[k];
+    A.tiles[k] = tiles;
+    A.rows[k] = (span + tiles - 1) / tiles;
+    A.len_dt_x[k] = s.len_dt_x[k];
+    A.len_dt_y[k] = s.len_dt_y[k];
+    A.bstart[k] = blocks;
+    blocks += s.count[k] * tiles;
+  }
+  A.bstart[s.nlev] = blocks;
+  if (blocks == 0) return hipSuccess;
+  A.dtdx = T(s.dtdx); A.dtdy = T(s.dtdy);
+  A.a = T(s.a); A.b = T(s.b); A.c = T(s.c);
+  A.reg = s.reg;
+  A.side_mask = s.side_mask;
+  A.plan = s.plan;
+  A.entries = s.entries;
+  A.nentries = s.nentries;
+  A.ninner = s.ninner;
+  A.fw = s.fw;
+  A.nbr = s.nbr;
+  A.gnflags = s.gnflags;
+  const auto& W = step_weights<T, EQ>(s.weights);
+  hipLaunchKernelGGL((k_amr_step<T, EQ, M, TY>), dim3(unsigned(blocks)), dim3(kThreads), 0, st, A, W);
+  return hipGetLastError();
+}
+
+template <typename T, int EQ>
+static hipError_t launch_amr_m(const AmrStepLaunch& s, hipStream_t st) {
+  switch (s.m) {
+    case 8: return launch_amr_t<T, EQ, 8, 8>(s, st);
+    case 16: return s.ty == 8 ? launch_amr_t<T, EQ, 16, 8>(s, st) : launch_amr_t<T, EQ, 16, 16>(s, st);
+    case 32: return s.ty == 4 ? launch_amr_t<T, EQ, 32, 4>(s, st) : launch_amr_t<T, EQ, 32, 8>(s, st);
+    case 64: return s.ty == 2 ? launch_amr_t<T, EQ, 64, 2>(s, st) : launch_amr_t<T, EQ, 64, 4>(s, st);
+    case 128: return launch_amr_t<T, EQ, 128, 2>(s, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_amr_step(const AmrStepLaunch& s, hipStream_t st) {
+  if (s.nlev <= 0) return hipSuccess;
+  switch (s.eq) {
+    case 0: return s.fp32 ? launch_amr_m<float, 0>(s, st) : launch_amr_m<double, 0>(s, st);
+    case 1: return s.fp32 ? launch_amr_m<float, 1>(s, st) : launch_amr_m<double, 1>(s, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+static Bufs<T> make_bufs(const BufLaunch& b);
+
+template <typename T>
+static hipError_t launch_sync_t(const AmrSyncLaunch& s, hipStream_t st) {
+  AmrSyncArgs<T> A;
+  A.B = make_bufs<T>(s.b);
+  A.plevel = s.plevel;
+  A.canon = s.canon;
+  A.ncanon = s.ncanon;
+  A.plan = s.plan;
+  A.entries = s.entries;
+  A.bnd = s.bnd;
+  A.nentries = s.nentries;
+  A.nbnd = s.nbnd;
+  A.faces = s.faces;
+  A.nfaces = s.nfaces;
+  A.reg = s.reg;
+  A.inv_area0 = s.inv_area0;
+  const int blocks = s.ncanon + (s.nfaces + kThreads - 1) / kThreads;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_amr_sync<T>, dim3(unsigned(blocks)), dim3(kThreads), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_amr_sync(const AmrSyncLaunch& s, hipStream_t st) {
+  return s.fp32 ? launch_sync_t<float>(s, st) : launch_sync_t<double>(s, st);
 }
 
 bool step_shape_supported(int m, int ty) {
@@ -1889,7 +2432,7 @@ static hipError_t launch_adv_t(const AdvanceLaunch& s, hipStream_t st) {
       hipLaunchKernelGGL((k_level_advance_adv<T, M, K, NT, false>), grid, dim3(NT), 0, st, A, W);
   } else {
     hipLaunchKernelGGL((k_level_advance<T, M, K, NT>), grid, dim3(NT), 0, st, A,
-                       *static_cast<const AcWeights<T>*>(s.weights));
+                       static_cast<const AcAllWeights<T>*>(s.weights)->dense);
   }
   return hipGetLastError();
 }
@@ -2006,10 +2549,10 @@ hipError_t launch_fma_probe(bool fp32, void* out, int nblocks, int iters, hipStr
 }
 
 hipError_t launch_fill_plan(const HierDev& H, const int32_t* entries, int nentries, int m, int smin, int4* plan,
-                            uint32_t* flags, hipStream_t st) {
+                            uint32_t* flags, int32_t* nbr, uint32_t* gnflags, hipStream_t st) {
   if (H.nleaves <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_plan, dim3(unsigned(H.nleaves)), dim3(kThreads), 0, st, H, entries, nentries, m, smin, plan,
-                     flags);
+                     flags, nbr, gnflags);
   return hipGetLastError();
 }
 

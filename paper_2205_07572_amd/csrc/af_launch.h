@@ -39,6 +39,50 @@ struct BufLaunch {
   uint32_t mask;
 };
 
+// One time point of the batched subcycled coarse step (constant-coefficient
+// equations): levels lev0 .. lev0 + nlev - 1 step together; level lev0 + k
+// holds leaves [first[k], first[k] + count[k]) and steps `region[k]`.
+struct AmrStepLaunch {
+  bool fp32;
+  int eq, m, ty;
+  void* p[2][4];
+  int npatch, pitch;
+  uint32_t mask;
+  int nlev, lev0;
+  int first[kMaxLevels], count[kMaxLevels], region[kMaxLevels];
+  double len_dt_x[kMaxLevels], len_dt_y[kMaxLevels];
+  double dtdx, dtdy, a, b, c;
+  double* reg;
+  const uint8_t* side_mask;
+  const int4* plan;
+  const int32_t* entries;
+  int nentries, ninner;
+  const FillWeights* fw;
+  const int32_t* nbr;
+  const uint32_t* gnflags;
+  const void* weights;  // AdvWeights<T> or AcAllWeights<T>
+};
+hipError_t launch_amr_step(const AmrStepLaunch& s, hipStream_t st);
+
+// Conservative fix of faces [0, nfaces) and the fill's vertex copies onto
+// the closed-square boundary nodes of the leaves canon[0 .. ncanon).
+struct AmrSyncLaunch {
+  bool fp32;
+  BufLaunch b;
+  const int32_t* plevel;
+  const int32_t* canon;
+  int ncanon;
+  const int4* plan;
+  const int32_t* entries;
+  const int32_t* bnd;
+  int nentries, nbnd;
+  const CFFace* faces;
+  int nfaces;
+  double* reg;
+  double inv_area0;
+};
+hipError_t launch_amr_sync(const AmrSyncLaunch& s, hipStream_t st);
+
 hipError_t launch_patch_step(const StepLaunch& s, hipStream_t st);
 hipError_t launch_level_advance(const AdvanceLaunch& s, hipStream_t st);
 // Fills the level-advance shapes (K, threads) for (precision, equation, m) and
@@ -52,9 +96,11 @@ bool level_advance_up_pattern(bool fp32, int eq, const void* weights);
 hipError_t launch_fma_probe(bool fp32, void* out, int nblocks, int iters, hipStream_t st);
 bool step_shape_supported(int m, int ty);
 // resolves the fill sources of every leaf (sources of level >= smin) into
-// plan[nleaves][nentries] and flags[nleaves] (bit p: ops of phase p)
+// plan[nleaves][nentries] and flags[nleaves] (bit p: ops of phase p); with
+// nbr and gnflags non-null also the same-level neighbours [nleaves][9] and
+// the directions a same-level gather stages (bit d)
 hipError_t launch_fill_plan(const HierDev& H, const int32_t* entries, int nentries, int m, int smin, int4* plan,
-                            uint32_t* flags, hipStream_t st);
+                            uint32_t* flags, int32_t* nbr, uint32_t* gnflags, hipStream_t st);
 // applies the phase-`phase` ops of leaves [first_target, first_target + ntargets)
 hipError_t launch_fill_apply(bool fp32, const BufLaunch& b, const HierDev& H, const int32_t* entries, int nentries,
                              const int4* plan, const uint32_t* flags, const FillWeights* W, int first_target,

@@ -13,6 +13,7 @@
 //   * acoustics (eq. ERFormula, eq. sphe-mean): the spherical mean of each
 //     cell polynomial over the disc sectors lying in that cell, integrated
 //     in closed form monomial by monomial.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -226,8 +227,11 @@ void make_adv_weights(double a_dtdx, double b_dtdy, AdvWeights<T>* W) {
     for (int e = 0; e < 25; ++e) W->up_avg[e] = T(0);
 }
 
-template <typename T>
-void make_ac_weights(double c_dtdx, double c_dtdy, AcWeights<T>* W) {
+namespace {
+
+// FP64 acoustic stencils D[tau][node kind][K, Dx, Dy][entry] (entries of the
+// node kind's neighbourhood table), tau 0 = dt/2, 1 = dt.
+void ac_dense(double c_dtdx, double c_dtdy, double D[2][3][3][kNbCorner]) {
   // node kind -> sectors: (quadrant mask, cell offset, node position in the
   // cell's reference coordinates)
   struct Sector { int qmask, di, dj; double xi, eta; };
@@ -247,7 +251,9 @@ void make_ac_weights(double c_dtdx, double c_dtdy, AcWeights<T>* W) {
       const int nsec = nk == 0 ? 4 : 2;
       const NbEntry* tab = nk == 0 ? kNbCornerTab : (nk == 1 ? kNbXedgeTab : kNbYedgeTab);
       const int nb = nk == 0 ? kNbCorner : kNbEdge;
-      double acc[3][kNbCorner] = {};
+      double (*acc)[kNbCorner] = D[t][nk];
+      for (int w = 0; w < 3; ++w)
+        for (int e = 0; e < kNbCorner; ++e) acc[w][e] = 0.0;
       for (int s = 0; s < nsec; ++s) {
         const Sector& S = secs[s];
         for (int d = 0; d < kCellDofs; ++d) {
@@ -276,13 +282,132 @@ void make_ac_weights(double c_dtdx, double c_dtdy, AcWeights<T>* W) {
           acc[2][e] += Dy;
         }
       }
+    }
+  }
+}
+
+// round_sum for weights that enter a sum with multiplicities mult (the
+// orbit sizes 1, 2, 4: exact scalings): the rounded sum of mult * w is kept
+// as close to `target` as T allows.
+// Each pass moves the one weight (of those well above the residual, so that
+// the change is relatively tiny) whose rounded move leaves the smallest
+// residual.
+template <typename T>
+void round_sum_mult(const double* w, const int* mult, T* out, int n, double target) {
+  for (int e = 0; e < n; ++e) out[e] = T(w[e]);
+  if (sizeof(T) == sizeof(double)) return;
+  auto residual = [&]() {
+    double sum = 0.0;  // exact: FP32 values times 1, 2 or 4
+    for (int e = 0; e < n; ++e) sum += double(mult[e]) * double(out[e]);
+    return target - sum;
+  };
+  for (int pass = 0; pass < 8; ++pass) {
+    const double r = residual();
+    if (r == 0.0) return;
+    int best = -1;
+    T best_val = T(0);
+    double best_r = std::fabs(r);
+    for (int e = 0; e < n; ++e) {
+      if (!(std::fabs(w[e]) > 1e4 * std::fabs(r))) continue;
+      const T keep = out[e];
+      const T cand = T(double(keep) + r / double(mult[e]));
+      out[e] = cand;
+      const double nr = std::fabs(residual());
+      out[e] = keep;
+      if (nr < best_r) {
+        best_r = nr;
+        best = e;
+        best_val = cand;
+      }
+    }
+    if (best < 0) return;
+    out[best] = best_val;
+  }
+}
+
+int entry_index(int nk, const OrbitMember& mb) {
+  for (int e = 0; e < nb_size(nk); ++e) {
+    const NbEntry E = nb_entry(nk, e);
+    if (E.kind == mb.kind && E.di == mb.di && E.dj == mb.dj) return e;
+  }
+  return -1;
+}
+
+}  // namespace
+
+template <typename T>
+void make_ac_weights(double c_dtdx, double c_dtdy, AcWeights<T>* W) {
+  double D[2][3][3][kNbCorner];
+  ac_dense(c_dtdx, c_dtdy, D);
+  for (int t = 0; t < 2; ++t)
+    for (int nk = 0; nk < 3; ++nk) {
+      const int nb = nk == 0 ? kNbCorner : kNbEdge;
       // the spherical mean part sums to 1, the two gradient parts to 0
       for (int w = 0; w < 3; ++w) {
         T* dst = nk == 0 ? W->corner[t][w] : (nk == 1 ? W->xedge[t][w] : W->yedge[t][w]);
-        round_sum(acc[w], dst, nb, w == 0 ? 1.0 : 0.0);
+        round_sum(D[t][nk][w], dst, nb, w == 0 ? 1.0 : 0.0);
       }
     }
+}
+
+template <typename T>
+bool make_ac_orbit_weights(double c_dtdx, double c_dtdy, AcOrbitWeights<T>* W) {
+  double D[2][3][3][kNbCorner];
+  ac_dense(c_dtdx, c_dtdy, D);
+  double scale = 0.0;
+  for (int t = 0; t < 2; ++t)
+    for (int nk = 0; nk < 3; ++nk)
+      for (int w = 0; w < 3; ++w)
+        for (int e = 0; e < nb_size(nk); ++e) scale = std::max(scale, std::fabs(D[t][nk][w][e]));
+  const double tol = 1e-12 * scale;
+  bool ok = true;
+  std::memset(W, 0, sizeof(*W));
+  for (int nk = 0; nk < 3; ++nk) {
+    const OrbitTable& OT = kOrbitTab[nk];
+    // orbit weights per tau, then the two combinations
+    double ow[2][kMaxOrbits][3] = {};
+    for (int t = 0; t < 2; ++t)
+      for (int o = 0; o < OT.n; ++o) {
+        const NbOrbit& O = OT.o[o];
+        for (int w = 0; w < 3; ++w) {
+          double sum = 0.0;
+          double val[4];
+          for (int mb = 0; mb < O.n; ++mb) {
+            int X = 0, Y = 0;
+            nb_offset(nk, O.m[mb].kind, O.m[mb].di, O.m[mb].dj, &X, &Y);
+            const double sg = w == 0 ? 1.0 : (w == 1 ? (X > 0 ? 1.0 : (X < 0 ? -1.0 : 0.0))
+                                                     : (Y > 0 ? 1.0 : (Y < 0 ? -1.0 : 0.0)));
+            const double d = D[t][nk][w][entry_index(nk, O.m[mb])];
+            // a part odd in a direction with zero offset vanishes
+            if (sg == 0.0 && std::fabs(d) > tol) ok = false;
+            val[mb] = sg * d;
+            sum += val[mb];
+          }
+          const bool present = w == 0 || (w == 1 && O.hasx) || (w == 2 && O.hasy);
+          const double v = present ? sum / O.n : 0.0;
+          for (int mb = 0; mb < O.n; ++mb)
+            if (present && std::fabs(val[mb] - v) > tol) ok = false;
+          ow[t][o][w] = v;
+        }
+      }
+    // c = 0: value at t + dt; c = 1: 4 q(t + dt/2) + q(t + dt)
+    for (int w = 0; w < 3; ++w)
+      for (int c = 0; c < 2; ++c) {
+        double src[kMaxOrbits];
+        int mult[kMaxOrbits];
+        for (int o = 0; o < OT.n; ++o) {
+          src[o] = c == 0 ? ow[1][o][w] : 4.0 * ow[0][o][w] + ow[1][o][w];
+          mult[o] = OT.o[o].n;
+        }
+        T out[kMaxOrbits];
+        if (w == 0)
+          round_sum_mult(src, mult, out, OT.n, c == 0 ? 1.0 : 5.0);
+        else
+          for (int o = 0; o < OT.n; ++o) out[o] = T(src[o]);
+        for (int o = 0; o < OT.n; ++o) W->w[nk][o][c][w] = out[o];
+      }
   }
+  return ok;
 }
 
 void make_fill_weights(FillWeights* W) {
@@ -307,5 +432,7 @@ template void make_adv_weights<float>(double, double, AdvWeights<float>*);
 template void make_adv_weights<double>(double, double, AdvWeights<double>*);
 template void make_ac_weights<float>(double, double, AcWeights<float>*);
 template void make_ac_weights<double>(double, double, AcWeights<double>*);
+template bool make_ac_orbit_weights<float>(double, double, AcOrbitWeights<float>*);
+template bool make_ac_orbit_weights<double>(double, double, AcOrbitWeights<double>*);
 
 }  // namespace af
