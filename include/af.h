@@ -248,6 +248,21 @@ af_status af_regrid_apply(af_ctx* ctx, const af_hier* old, const af_state* old_b
 af_status af_reduce_sum(af_ctx* ctx, const af_hier* h, const af_state* bufs,
                         uint32_t level_buf_mask, double* out, hipStream_t stream);
 
+/* af_reduce_sum_noalloc -- af_reduce_sum for callers that cannot allocate
+ * device memory (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  Same result, bit for bit, from the same kernels; the
+ * per-leaf partial sums live in a statically allocated device array of
+ * 196608 doubles (1.5 MiB, nleaves * ncomp <= 196608, else AF_ERR_ARG), one
+ * per GPU, held until the process ends.  Calls no hipMalloc, hipFree or
+ * allocating library routine.  The hierarchy's device tables must already
+ * exist (any earlier launching call with it, or af_hier_leaf_xy, uploads
+ * them), else AF_ERR_STATE.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (concurrent streams or threads) race; calls
+ * ordered on one stream do not (every partial sum is written before it is
+ * read, so nothing needs clearing between calls). */
+af_status af_reduce_sum_noalloc(af_ctx* ctx, const af_hier* h, const af_state* bufs,
+                                uint32_t level_buf_mask, double* out, hipStream_t stream);
+
 /* ---------------------------------------------------------------------
  * af_level_advance -- nsteps AF steps (Sec. 2) of all leaves of `level`, for
  * a level whose every leaf has same-level leaves as its eight neighbours

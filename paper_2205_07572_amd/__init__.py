@@ -168,6 +168,12 @@ class Context:
     def reduce_sum(self, hier, bufs, mask, out):
         check(_lib.load().af_reduce_sum(self.h, hier.h, self._pair(bufs), int(mask), _ptr(out), _stream()))
 
+    def reduce_sum_noalloc(self, hier, bufs, mask, out):
+        """af_reduce_sum_noalloc: the same sums with the library's static
+        scratch (no device allocation; the hierarchy must be on the device)."""
+        check(_lib.load().af_reduce_sum_noalloc(self.h, hier.h, self._pair(bufs), int(mask), _ptr(out),
+                                                _stream()))
+
     def level_advance(self, hier, bufs, mask, level, dt, nsteps):
         mk = ctypes.c_uint32(mask)
         check(_lib.load().af_level_advance(self.h, hier.h, self._pair(bufs), ctypes.byref(mk), int(level),

@@ -766,6 +766,28 @@ af_status af_reduce_sum(af_ctx* ctx, const af_hier* h, const af_state* bufs, uin
   return AF_OK;
 }
 
+af_status af_reduce_sum_noalloc(af_ctx* ctx, const af_hier* h, const af_state* bufs, uint32_t mask, double* out,
+                                hipStream_t stream) {
+  if (!ctx || !h || !out) return fail(AF_ERR_ARG, "null argument");
+  af_status s = check_pair(ctx, h, bufs, "af_reduce_sum_noalloc");
+  if (s != AF_OK) return s;
+  const size_t need = h->H.leaves.size() * size_t(ctx->ncomp);
+  if (need > kScratchSums)
+    return fail(AF_ERR_ARG, "af_reduce_sum_noalloc: nleaves * ncomp = " + std::to_string(need) +
+                                " exceeds the static scratch of " + std::to_string(kScratchSums) + " partial sums");
+  // the hierarchy's tables must already be on the device: uploading them
+  // would allocate
+  if (!h->on_device)
+    return fail(AF_ERR_STATE,
+                "af_reduce_sum_noalloc: the hierarchy's device tables are not uploaded yet (any launching call with "
+                "it, or af_hier_leaf_xy, uploads them)");
+  double* part = nullptr;
+  AF_HIP(scratch_sums(&part));
+  AF_HIP(launch_sum(ctx->fp32(), make_buf(ctx, &bufs[0], &bufs[1], mask), h->dev, ctx->dx(0) * ctx->dy(0), part, out,
+                    stream));
+  return AF_OK;
+}
+
 // ----------------------------------------------------------------- level advance
 
 namespace {

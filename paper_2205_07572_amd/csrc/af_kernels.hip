@@ -5,6 +5,7 @@
 // [m+5][pitch] (see include/af.h).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <type_traits>
 
 #include "af_internal.h"
@@ -2222,6 +2223,36 @@ __global__ __launch_bounds__(kThreads) void k_sum_final(const double* part, int 
     if (threadIdx.x == 0) out[q] = red[0];
     __syncthreads();
   }
+}
+
+// ---------------------------------------------------------------------------
+// Statically allocated scratch of the allocation-free reduction
+// (af_reduce_sum_noalloc): the per-leaf partial sums, kScratchSums doubles.
+// Each device holds its own copy until the process ends; its device address
+// is looked up once per device (hipGetSymbolAddress) and used from then on.
+// Host code never passes the array's name to a kernel: on the host it is a
+// stand-in, not a device address.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kScratchSums];
+
+hipError_t scratch_sums(double** ptr) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static double* addr[kMaxDevices] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    addr[dev] = static_cast<double*>(p);
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 // ---------------------------------------------------------------------------

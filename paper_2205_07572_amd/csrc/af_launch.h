@@ -111,6 +111,12 @@ hipError_t launch_tag(bool fp32, const BufLaunch& b, const HierDev& H, int mode,
                       double inv2dy0, double tr, double tc, int8_t* tags, double* values, hipStream_t st);
 hipError_t launch_transfer(bool fp32, const BufLaunch& old_b, const HierDev& HO, const BufLaunch& new_b,
                            const Transfer* tr, int nnew, hipStream_t st);
+// Capacity (doubles) of the statically allocated partial-sum scratch of
+// af_reduce_sum_noalloc: nleaves * ncomp partial sums.
+constexpr size_t kScratchSums = size_t(3) * 65536;
+// The calling thread's current device's address of that scratch (looked up
+// on the first call per device).
+hipError_t scratch_sums(double** ptr);
 hipError_t launch_sum(bool fp32, const BufLaunch& b, const HierDev& H, double area0, double* part, double* out,
                       hipStream_t st);
 

@@ -164,3 +164,32 @@ def test_missing_library_fails_loudly(tmp_path):
     assert r.returncode == 0, r.stderr
     assert "raised:" in r.stdout and "is not built" in r.stdout
 
+
+def _fake_pair(ctx, npatch):
+    """Two states with aligned non-null pointers: enough for the host-side
+    validation, which rejects the calls below before anything is launched."""
+    import ctypes
+    pair = (_lib.af_state * 2)()
+    for k in range(2):
+        for q in range(4):
+            pair[k].dof[q] = ctypes.c_void_p(4096 * (1 + 4 * k + q))
+        pair[k].npatch = npatch
+        pair[k].pitch = ctx.prob.m + 5
+    return pair
+
+
+def test_noalloc_sum_rejects_too_many_leaves_and_undeployed_hierarchies():
+    """af_reduce_sum_noalloc: more partial sums than its static scratch holds
+    is AF_ERR_ARG; a hierarchy whose tables are not on the device yet is
+    AF_ERR_STATE (uploading them would allocate)."""
+    import ctypes
+    L = _lib.load()
+    out = ctypes.c_void_p(4096)
+    big = af.Context(af.Problem(eq=1, prec=1, m=8, n0x=257, n0y=256, lmax=0))   # 65792 leaves x 3 > 196608
+    hb = af.Hierarchy(big, afsynth.uniform_leaves(257, 256, 0))
+    st = L.af_reduce_sum_noalloc(big.h, hb.h, _fake_pair(big, len(hb)), 0, out, None)
+    assert st == _lib.AF_ERR_ARG and b"exceeds the static scratch" in L.af_last_error()
+    ok = af.Context(af.Problem(eq=1, prec=1, m=8, n0x=256, n0y=256, lmax=0))    # exactly 196608: admitted
+    ho = af.Hierarchy(ok, afsynth.uniform_leaves(256, 256, 0))
+    st = L.af_reduce_sum_noalloc(ok.h, ho.h, _fake_pair(ok, len(ho)), 0, out, None)
+    assert st == _lib.AF_ERR_STATE and b"not uploaded" in L.af_last_error()
