@@ -1,12 +1,24 @@
-"""Benchmark: batched Active Flux patch step on one MI355X.
+"""Benchmark: the batched adaptive Active Flux step on one MI355X.
 
-Workload (the metric's configuration): 2D linear advection, a=1, b=0.5, on
-the periodic unit square as one level of 16x16 patches of 32x32 cells
-(512^2 cells, two ghost layers), seeded 8-mode Fourier initial data, T=1
-(1280 steps at CFL 0.4).  One "step" is one pass of the whole path: ghost
-fill between patches plus the patch step of every patch, replayed as a
-hipGraph.  FP32 is the headline (FP32 state and arithmetic, FP64 sums); the
-FP64 path is timed beside it.
+Headline workload (config 4): 2D acoustics (p, u, v), c = 1, on the periodic
+unit square; a high-frequency wave packet p0 = exp(-50 |x - x0|^2) cos(k.x),
+|k| = 80 pi, u = v = 0 (seed 0); 16x16-cell patches with two ghost layers on
+8x8 level-0 patches and 4 levels (ratio 2, subcycling, conservative fix);
+gradient tagging of p (refine at 8, coarsen below 2), FP32 state and
+arithmetic with FP64 flux registers.  One "step" is one coarse step of the
+whole hierarchy: 2^3 batched launches (one per substep start time) plus the
+launches of the conservative fix.  The timed hierarchy is the run's state at
+t = T/2 = 0.25 (the initial hierarchy advanced with a regrid every 4 coarse
+steps), frozen during the warm-up and the timed steps; cell-updates/s counts
+interior leaf cells advanced by their level's step.  FP64 is timed beside
+it.  The oracle (single-threaded FP64 C++) runs the first coarse step of the
+same workload in a separate process while the GPU is timed; its rate is the
+CPU baseline and its result the reference of the FP32 and FP64 L-infinity
+errors.
+
+Secondary blocks: config 2 (uniform 512^2 advection, level advance), the full
+adaptive runs of configs 3 and 4 to T with regrids (time to solution), and
+the rotation, swirl and Burgers runs.
 
 Prints one JSON line.  --gpus N with N > 1 is not supported (single GPU).
 """
@@ -45,13 +57,45 @@ PROFILED_TRAFFIC = {
 }
 
 
+# Config-4 step kernel (k_amr_step, acoustics FP32): algorithmic HBM bytes per
+# interior cell-update (read and write the 4 DOF kinds of 3 components) and
+# the operations of the orbit-form evaluation (af_kernels.hip): 416 node
+# operations (186 additions, 230 multiply-adds) = 646 flops, time sums and
+# update about 60 more.
+C4_BYTES_PER_UPDATE = {"fp32": 96, "fp64": 192}
+C4_FLOPS_PER_UPDATE = 706
+C4_T, C4_EVERY, C4_M, C4_N0, C4_LMAX, C4_THETA = 0.5, 4, 16, 8, 3, (8.0, 2.0)
+
+
+# HBM bytes per launch of the config-4 step kernel in the timed region (the
+# last batched launches of `bench.py --c4-profile`), from rocprofv3
+# FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00 KiB (the factors a plain 64 MiB
+# device copy gives), valid for the kernel source whose hash is recorded
+# (profiles/k_amr_step_config4.md holds the commands).
+C4_TRAFFIC = {"source_sha256_16": "e2116d3d1ce442b3", "fp32": 124578851, "fp64": 221828094}
+
+
+def _kernel_source_hash():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2205_07572_amd", "csrc", "af_kernels.hip")
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def c4_traffic(name):
+    """Measured HBM bytes per step launch, or None if the kernel source
+    changed since the counters were taken."""
+    if C4_TRAFFIC["source_sha256_16"] != _kernel_source_hash():
+        return None
+    return C4_TRAFFIC.get(name)
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=NSTEPS_T)
-    p.add_argument("--warmup", type=int, default=20)
+    p.add_argument("--steps", type=int, default=20, help="timed coarse steps of config 4")
+    p.add_argument("--warmup", type=int, default=5)
+    p.add_argument("--c2-steps", type=int, default=NSTEPS_T, help="steps of the config-2 block (T = 1 at 1280)")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    p.add_argument("--cpu-steps", type=int, default=144)
     p.add_argument("--general-steps", type=int, default=128)
     p.add_argument("--no-amr", action="store_true", help="skip the adaptive acoustics runs")
     p.add_argument("--sweep", action="store_true",
@@ -60,6 +104,8 @@ def parse():
                    help="only run a plain 64 MiB device copy 20 times (HBM counter calibration)")
     p.add_argument("--peak-probe", action="store_true",
                    help="only measure the device's copy bandwidth and vector FMA rate (one JSON line)")
+    p.add_argument("--c4-profile", choices=["fp32", "fp64"],
+                   help="only the config-4 timed step in that precision (for a profiler run)")
     p.add_argument("--only", choices=["amr", "rotation", "swirl", "burgers"],
                    help="only run one workload block (one JSON line with that block), e.g. for a profiler")
     return p.parse_args()
@@ -627,51 +673,181 @@ def _rot_steps(ctx, h, bufs, reg, n, dt):
     return mask
 
 
-def cpu_baseline(data, nsteps, dt):
-    """The FP64 oracle, single-threaded, on `nsteps` steps of the benchmark
-    grid."""
+class HipEvents:
+    """Raw HIP events (timing enabled) through the HIP runtime torch has
+    loaded, for the library's timed coarse step."""
+
+    def __init__(self, n):
+        import ctypes
+        self.ct = ctypes
+        self.hip = ctypes.CDLL("libamdhip64.so.7")
+        self.hip.hipEventCreate.argtypes = [ctypes.POINTER(ctypes.c_void_p)]
+        self.hip.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.hip.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.ev = []
+        for _ in range(n):
+            e = ctypes.c_void_p()
+            assert self.hip.hipEventCreate(ctypes.byref(e)) == 0
+            self.ev.append(e.value)
+
+    def handles(self, first, count):
+        return self.ev[first:first + count]
+
+    def ms(self, a, b):
+        t = self.ct.c_float()
+        assert self.hip.hipEventElapsedTime(self.ct.byref(t), self.ev[a], self.ev[b]) == 0
+        return float(t.value)
+
+    def __del__(self):
+        for e in getattr(self, "ev", []):
+            self.hip.hipEventDestroy(e)
+
+
+def c4_problem(prec):
+    import paper_2205_07572_amd as af
+    return af.Problem(eq=af.ACOUSTICS, prec=prec, m=C4_M, n0x=C4_N0, n0y=C4_N0, lmax=C4_LMAX, c=1.0)
+
+
+def c4_initial(prec):
+    """The config-4 run's initial hierarchy (exact data, lmax passes of
+    gradient tagging and refinement) and its coarse time step."""
+    import math
     import afsynth
-    import oracle
-    d0 = afsynth.dofs_periodic(data, M * N0, M * N0, nq=4)
-    t0 = time.perf_counter()
-    oracle.run_periodic(0, d0, dt, nsteps, a=1.0, b=0.5)
-    el = time.perf_counter() - t0
-    return NCELL * nsteps / el, el
+    import paper_2205_07572_amd as af
+    from paper_2205_07572_amd.amr import TagRule, initial_hierarchy
+    prob = c4_problem(prec)
+    data = afsynth.wave_packet(0)
+
+    def block_fn(l, ix, iy):
+        dx = prob.dx(l)
+        return afsynth.dofs_block(data, C4_M, 2, ix * C4_M * dx, iy * C4_M * dx, dx, dx, 4)
+
+    rule = TagRule(af.TAG_GRADIENT, 0, *C4_THETA)
+    run = initial_hierarchy(prob, block_fn, rule)
+    n = math.ceil(C4_T / (0.4 * prob.dx(0)))
+    return run, rule, C4_T / n, n
 
 
-_ORACLE_CHILD = """
-import sys, time
+def c4_headline(prec, steps, warmup):
+    """The timed config-4 step: the run advanced to t = T/2 with a regrid
+    every 4 coarse steps, then `warmup` and `steps` coarse steps on that
+    hierarchy.  The timed steps record HIP events around every batched step
+    launch on the stream it runs on (the dominant kernel's launch times)."""
+    import torch
+    import paper_2205_07572_amd as af
+    run, rule, dt0, n = c4_initial(prec)
+    half = n // 2
+    step = 0
+    while step < half:
+        k = min(C4_EVERY, half - step)
+        run.coarse_steps(dt0, k)
+        step += k
+        if step < half:
+            run.regrid(rule)
+    leaves = run.hier.leaves()
+    per_step = run.cell_updates_per_coarse_step()
+    ctx, h = run.ctx, run.hier
+    for _ in range(warmup):
+        run.mask = ctx.amr_coarse_step(h, run.bufs, run.mask, dt0, run.reg, t0=run.time)
+        run.time += dt0
+    nmax = 1 << C4_LMAX  # batched step launches per coarse step
+    ev = HipEvents(2 * nmax * steps)
+    cells = []
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record()
+    for k in range(steps):
+        run.mask, nl, c = ctx.amr_coarse_step_timed(h, run.bufs, run.mask, dt0, run.reg,
+                                                    ev.handles(2 * nmax * k, 2 * nmax), t0=run.time)
+        run.time += dt0
+        cells.append((nl, c))
+    e1.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ms = e0.elapsed_time(e1)
+    launch_ms, launch_cells = [], []
+    for k, (nl, c) in enumerate(cells):
+        for j in range(nl):
+            launch_ms.append(ev.ms(2 * nmax * k + 2 * j, 2 * nmax * k + 2 * j + 1))
+            launch_cells.append(float(c[j]))
+    counts = np.bincount([l for l, _, _ in leaves], minlength=C4_LMAX + 1).tolist()
+    return dict(ms=ms, wall_s=t_wall, per_step=per_step, leaves=len(leaves), per_level=counts,
+                launch_ms=np.array(launch_ms), launch_cells=np.array(launch_cells), dt0=dt0, t_start=half * dt0)
+
+
+_C4_ORACLE_CHILD = """
+import sys, time, json
 import numpy as np
 sys.path.insert(0, sys.argv[1])
 import oracle
 z = np.load(sys.argv[2])
-d0 = {k: (z[k].item() if z[k].ndim == 0 else z[k]) for k in z.files}
+leaves = [tuple(int(v) for v in l) for l in z["leaves"]]
+o = oracle.Hier(1, int(z["m"]), int(z["n0"]), int(z["n0"]), int(z["lmax"]), c=1.0)
+o.set_leaves(leaves)
+for k in range(len(leaves)):
+    o.set_block(k, {kind: z[kind][k] for kind in oracle.KINDS})
 t0 = time.perf_counter()
-oracle.run_periodic(0, d0, float(sys.argv[3]), int(sys.argv[4]), a=1.0, b=0.5)
-print(time.perf_counter() - t0)
+o.coarse_step(float(z["dt0"]))
+el = time.perf_counter() - t0
+if len(sys.argv) > 4 and sys.argv[4] == "time-only":
+    np.savez(sys.argv[3], seconds=el)
+else:
+    out = {kind: np.stack([o.get_block(k)[kind] for k in range(len(leaves))]) for kind in oracle.KINDS}
+    np.savez(sys.argv[3], seconds=el, **out)
 """
 
 
-def cpu_baseline_allcore(data, nsteps, dt, nproc):
-    """All-core oracle throughput: nproc independent single-threaded oracle
-    processes (fresh interpreters that never touch the GPU), each stepping
-    its own copy of the benchmark grid; aggregate cell-updates/s over the
-    wall time of the slowest."""
+def c4_oracle_start(tmp):
+    """Starts the oracle on the first coarse step of config 4 (FP64, one
+    thread, a fresh interpreter that never touches the GPU) from the GPU's
+    FP64 initial hierarchy; returns what c4_oracle_finish needs."""
     import subprocess
-    import tempfile
-    import afsynth
-    d0 = afsynth.dofs_periodic(data, M * N0, M * N0, nq=4)
-    with tempfile.TemporaryDirectory() as tmp:
-        path = os.path.join(tmp, "d0.npz")
-        np.savez(path, **{k: np.asarray(v) for k, v in d0.items()})
-        t0 = time.perf_counter()
-        procs = [subprocess.Popen([sys.executable, "-c", _ORACLE_CHILD, ROOT, path, repr(dt), str(nsteps)],
-                                  stdout=subprocess.PIPE, text=True) for _ in range(nproc)]
-        outs = [p.communicate()[0] for p in procs]
-        wall = time.perf_counter() - t0
-        if any(p.returncode != 0 for p in procs):
-            raise RuntimeError("oracle child failed")
-    return nproc * NCELL * nsteps / wall, wall, [float(o.strip()) for o in outs]
+    import paper_2205_07572_amd as af
+    run, _, dt0, _ = c4_initial(af.FP64)
+    leaves = run.hier.leaves()
+    blocks = run.blocks()
+    path = os.path.join(tmp, "c4_init.npz")
+    np.savez(path, leaves=np.array(leaves, np.int32), m=C4_M, n0=C4_N0, lmax=C4_LMAX, dt0=dt0,
+             **{k: np.stack([b[k] for b in blocks]) for k in ("avg", "corner", "xedge", "yedge")})
+    out = os.path.join(tmp, "c4_oracle.npz")
+    proc = subprocess.Popen([sys.executable, "-c", _C4_ORACLE_CHILD, ROOT, path, out])
+    cu = run.cell_updates_per_coarse_step()
+    del run
+    return dict(proc=proc, out=out, leaves=leaves, blocks=blocks, dt0=dt0, cell_updates=cu)
+
+
+def c4_gpu_first_step(job, prec):
+    """The same first coarse step on the GPU (from the same FP64 blocks,
+    rounded to FP32 for the FP32 path)."""
+    import paper_2205_07572_amd as af
+    from paper_2205_07572_amd.amr import AMRRun
+    by_leaf = {lf: b for lf, b in zip(job["leaves"], job["blocks"])}
+    run = AMRRun(c4_problem(prec), job["leaves"], lambda l, ix, iy: by_leaf[(l, ix, iy)])
+    run.coarse_steps(job["dt0"], 1)
+    return run.blocks()
+
+
+def c4_oracle_finish(job, gpu):
+    """Waits for the oracle; L-infinity of each GPU result against it over
+    the interior averages and closed-square nodes of every leaf, relative to
+    the state's largest value."""
+    if job["proc"].wait() != 0:
+        raise RuntimeError("oracle child failed")
+    z = np.load(job["out"])
+    m = C4_M
+    sl = {"avg": (slice(2, 2 + m), slice(2, 2 + m)), "corner": (slice(2, 3 + m), slice(2, 3 + m)),
+          "xedge": (slice(2, 2 + m), slice(2, 3 + m)), "yedge": (slice(2, 3 + m), slice(2, 2 + m))}
+    scale = max(float(np.abs(z[k][(slice(None), slice(None)) + sl[k]]).max()) for k in sl)
+    errs = {}
+    for name, blocks in gpu.items():
+        e_avg = max(float(np.abs(b["avg"][(slice(None),) + sl["avg"]] - z["avg"][i][(slice(None),) + sl["avg"]]).max())
+                    for i, b in enumerate(blocks))
+        e_pt = max(float(np.abs(b[k][(slice(None),) + sl[k]] - z[k][i][(slice(None),) + sl[k]]).max())
+                   for i, b in enumerate(blocks) for k in ("corner", "xedge", "yedge"))
+        errs[name] = {"averages": e_avg / scale, "point_values": e_pt / scale}
+    return float(z["seconds"]), errs
 
 
 def main():
@@ -685,53 +861,68 @@ def main():
     if args.sweep:
         sweep()
         return
+    if args.gpus != 1:
+        print(json.dumps({"error": "single-GPU build: --gpus must be 1 (multi-GPU sharding is design-only)"}))
+        sys.exit(2)
+    if args.c4_profile:
+        import paper_2205_07572_amd as af
+        r = c4_headline(af.FP32 if args.c4_profile == "fp32" else af.FP64, args.steps, args.warmup)
+        print(json.dumps({"c4_profile": args.c4_profile, "steps": args.steps, "launches": len(r["launch_ms"]),
+                          "launch_us_avg": 1e3 * float(np.mean(r["launch_ms"])),
+                          "launch_cells_avg": float(np.mean(r["launch_cells"])),
+                          "kernel_source_sha256_16": _kernel_source_hash()}), flush=True)
+        return
     if args.only:
         runs = {"amr": amr_runs, "rotation": rotation_runs, "swirl": swirl_runs, "burgers": burgers_runs}
         print(json.dumps({args.only: runs[args.only]()}), flush=True)
         return
-    if args.gpus != 1:
-        print(json.dumps({"error": "single-GPU build: --gpus must be 1 (multi-GPU sharding is design-only)"}))
-        sys.exit(2)
+    import tempfile
     import torch
     import afsynth
     import paper_2205_07572_amd as af
     assert torch.cuda.is_available(), "bench needs a GPU"
-    data = afsynth.fourier_modes(0)
-    dt = T_FINAL / NSTEPS_T
-    res = {}
+    tmp = tempfile.TemporaryDirectory()
+    job = None if args.no_cpu else c4_oracle_start(tmp.name)
+
+    # ---- headline: config 4, FP32 and FP64
+    c4 = {}
     for name, prec in (("fp32", af.FP32), ("fp64", af.FP64)):
-        r = time_path(prec, data, args.steps, args.warmup, dt, args.general_steps)
-        res[name] = r
-        print(f"[bench] {name}: {args.steps} steps in {r['ms']:.3f} ms; level-advance launch (K={r['K']}, "
-              f"{r['NT']} threads) {r['k_ms'] * 1e3:.2f} us; tuned patch step {r['step_us']:.2f} us (tile "
-              f"{r['tile']}); general path {r['general_ms_per_step'] * 1e3:.2f} us/step",
-              file=sys.stderr, flush=True)
-    # accuracy: FP32 vs FP64 (FP64 is parity-tested against the oracle) and
-    # both against the exact solution when the run reaches T = 1
-    def interior(blocks):
-        return np.stack([np.stack([b[k][0, 2:2 + M, 2:2 + M] for k in af.KINDS]) for b in blocks])
-    a32, a64 = interior(res["fp32"]["out"]), interior(res["fp64"]["out"])
-    linf_32_64 = float(np.abs(a32 - a64).max() / np.abs(a64).max())
-    err_exact = None
-    if args.steps == NSTEPS_T:
-        t = args.steps * dt
-        ex = []
-        for (l, ix, iy) in afsynth.uniform_leaves(N0, N0, 0):
-            dx = 1.0 / (M * N0)
-            b = afsynth.dofs_block(afsynth.InitialData(1, lambda x, y: data.exact(x, y, t)), M, 2, ix * M * dx,
-                                   iy * M * dx, dx, dx, 4)
-            ex.append(b)
-        ae = interior(ex)
-        err_exact = {"fp32": float(np.abs(a32 - ae).max()), "fp64": float(np.abs(a64 - ae).max())}
-    ms32, k32, K32 = res["fp32"]["ms"], res["fp32"]["k_ms"], res["fp32"]["K"]
-    ms64, k64 = res["fp64"]["ms"], res["fp64"]["k_ms"]
-    ups32 = NCELL * args.steps / (ms32 * 1e-3)
-    ups64 = NCELL * args.steps / (ms64 * 1e-3)
-    # algorithmic bytes per launch: 8 words (read 4 DOFs, write 4 DOFs) per
-    # cell-update, K steps of all 512^2 cells
-    bytes32 = 8 * 4 * NCELL * K32
-    bytes64 = 8 * 8 * NCELL * res["fp64"]["K"]
-    achieved = bytes32 / (k32 * 1e-3) / 1e9
+        r = c4_headline(prec, args.steps, args.warmup)
+        c4[name] = r
+        us = np.sum(r["launch_ms"]) * 1e3
+        print(f"[bench] config4 {name}: {r['leaves']} leaves {r['per_level']}, {args.steps} coarse steps in "
+              f"{r['ms']:.3f} ms ({1e3 * r['ms'] / args.steps:.1f} us each), "
+              f"{r['per_step'] * args.steps / (r['ms'] * 1e-3):.3e} cell-updates/s; batched step launches "
+              f"{len(r['launch_ms'])}, {us / len(r['launch_ms']):.2f} us average", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+    r32, r64 = c4["fp32"], c4["fp64"]
+    ups32 = r32["per_step"] * args.steps / (r32["ms"] * 1e-3)
+    ups64 = r64["per_step"] * args.steps / (r64["ms"] * 1e-3)
+
+    def roofline(r, name):
+        bytes_ = C4_BYTES_PER_UPDATE[name] * float(np.sum(r["launch_cells"]))
+        secs = float(np.sum(r["launch_ms"])) * 1e-3
+        achieved = bytes_ / secs / 1e9
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": c4_traffic(name),
+                "kernel": f"k_amr_step<{'float' if name == 'fp32' else 'double'},1,16,16>",
+                "launches": int(len(r["launch_ms"])),
+                "kernel_us_avg": 1e3 * float(np.mean(r["launch_ms"])),
+                "algorithmic_bytes_per_launch_avg": bytes_ / len(r["launch_ms"]),
+                "bytes_per_cell_update": C4_BYTES_PER_UPDATE[name],
+                "alu_tflops": C4_FLOPS_PER_UPDATE * float(np.sum(r["launch_cells"])) / secs / 1e12,
+                "alu_frac_of_78.6": C4_FLOPS_PER_UPDATE * float(np.sum(r["launch_cells"])) / secs / 1e12 / 78.6,
+                "what": "dominant kernel: batched step launches of the timed coarse steps, HIP events around "
+                        "each on its stream; algorithmic bytes = bytes per cell-update x interior leaf "
+                        "cell-updates of the launch"}
+
+    def step_roofline(r, name, ups):
+        achieved = C4_BYTES_PER_UPDATE[name] * ups / 1e9
+        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS,
+                "what": "whole coarse step (all launches and the gaps between them): bytes per cell-update x "
+                        "cell-updates / ms_per_step"}
+
     line = {
         "metric": "cell-updates/s (FP32 vs FP64) of batched AMR AF step; % HBM roofline; L∞ err",
         "value": ups32,
@@ -739,71 +930,141 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms32 / args.steps,
+        "ms_per_step": r32["ms"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "advection a=1 b=0.5, periodic unit square, one level of 16x16 patches of "
-                               "32x32 cells (512^2), 2 ghost layers, seeded 8-mode Fourier data, T=1 "
-                               "(1280 steps, CFL 0.4); step = same-level ghost exchange + patch step, "
-                               "K steps per launch (af_level_advance, autotuned), launches replayed as one "
-                               "HIP graph",
-                   "patches": N0 * N0, "patch_cells": M, "steps_per_launch": K32,
-                   "threads_per_patch": res["fp32"]["NT"]},
-        "eager_ms_per_step": {"fp32": res["fp32"]["eager_ms"] / args.steps,
-                              "fp64": res["fp64"]["eager_ms"] / args.steps,
-                              "what": "the same launches issued one by one from the library, not replayed"},
-        "fp64": {"value": ups64, "ms_per_step": ms64 / args.steps, "kernel_us": k64 * 1e3,
-                 "kernel_us_separate_run": res["fp64"]["k_sep"] * 1e3,
-                 "steps_per_launch": res["fp64"]["K"], "threads_per_patch": res["fp64"]["NT"],
-                 "speedup_fp32_over_fp64": ups32 / ups64,
-                 "roofline": {"bound": "hbm", "achieved": bytes64 / (k64 * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                              "unit": "GB/s", "frac": bytes64 / (k64 * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                              "traffic": PROFILED_TRAFFIC.get(("fp64", res["fp64"]["K"], res["fp64"]["NT"])),
-                              "kernel": f"k_level_advance_up<double,32,{res['fp64']['K']},{res['fp64']['NT']}>"}},
-        "general_path_us_per_step": {"fp32": res["fp32"]["general_ms_per_step"] * 1e3,
-                                     "fp64": res["fp64"]["general_ms_per_step"] * 1e3,
-                                     "what": "af_ghost_fill + af_patch_step per step, hipGraph replay"},
-        "linf_fp32_vs_fp64_rel": linf_32_64,
-        "linf_vs_exact_T1": err_exact,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": PROFILED_TRAFFIC.get(("fp32", K32, res["fp32"]["NT"])),
-                     "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
-                     "kernel": f"k_level_advance_up<float,32,{K32},{res['fp32']['NT']}>",
-                     "kernel_us": k32 * 1e3, "kernel_us_separate_run": res["fp32"]["k_sep"] * 1e3,
-                     "algorithmic_bytes_per_launch": bytes32},
-        # the same launch against the vector ALU: the method's flops per
-        # cell-update (two time levels of three node stencils, time and face
-        # sums, update) over the FP32 peak without packed instructions (256
-        # CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s), the
-        # ceiling of this build
-        "roofline_alu": {"bound": "alu", "achieved": FLOPS_PER_UPDATE[0] * NCELL * K32 / (k32 * 1e-3) / 1e12,
-                         "peak": 78.6, "unit": "TFLOP/s",
-                         "frac": FLOPS_PER_UPDATE[0] * NCELL * K32 / (k32 * 1e-3) / 1e12 / 78.6,
-                         "flops_per_cell_update": FLOPS_PER_UPDATE[0]},
+        "config": {"workload": "config 4: acoustics c=1 on the periodic unit square, wave packet "
+                               "exp(-50|x-x0|^2) cos(k.x), |k|=80 pi, seed 0; 16x16-cell patches, 8x8 level-0 "
+                               "patches, 4 levels (subcycling, conservative fix), gradient tags refine 8 / "
+                               "coarsen 2; step = one coarse step of the hierarchy reached at t=T/2=0.25 "
+                               "(regrid every 4 coarse steps), FP32 bulk, FP64 flux registers",
+                   "leaves": r32["leaves"], "leaves_per_level": r32["per_level"],
+                   "cell_updates_per_step": r32["per_step"], "t_start": r32["t_start"], "dt0": r32["dt0"]},
+        "roofline": roofline(r32, "fp32"),
+        "roofline_step": step_roofline(r32, "fp32", ups32),
+        "fp64": {"value": ups64, "ms_per_step": r64["ms"] / args.steps, "leaves": r64["leaves"],
+                 "cell_updates_per_step": r64["per_step"], "speedup_fp32_over_fp64": ups32 / ups64,
+                 "roofline": roofline(r64, "fp64"), "roofline_step": step_roofline(r64, "fp64", ups64)},
     }
+    del c4
+
+    # ---- the oracle's first coarse step: CPU baseline and L-infinity errors
+    if job is not None:
+        gpu = {"fp32": c4_gpu_first_step(job, af.FP32), "fp64": c4_gpu_first_step(job, af.FP64)}
+        secs, errs = c4_oracle_finish(job, gpu)
+        line["linf_vs_oracle"] = dict(errs, what="first coarse step of config 4 from the initial hierarchy "
+                                                 f"({len(job['leaves'])} leaves), relative to the state's largest "
+                                                 "value; the FP32 run starts from the same data rounded to FP32")
+        line["cpu_baseline"] = {"value": job["cell_updates"] / secs, "unit": "cell-updates/s", "cores": 1,
+                                "kind": "oracle", "cpu": _cpu_model(),
+                                "sample": f"the first coarse step of config 4 ({len(job['leaves'])} leaves, "
+                                          f"{job['cell_updates']} cell-updates, {secs:.1f} s), single-threaded "
+                                          "FP64 oracle in its own process, run while the GPU was timed"}
+        print(f"[bench] oracle: config-4 first coarse step {secs:.1f} s, "
+              f"{job['cell_updates'] / secs:.3e} cell-updates/s; L-inf vs oracle {errs}", file=sys.stderr,
+              flush=True)
+        del gpu
+
+    # ---- config 2: uniform advection through the level advance
+    data = afsynth.fourier_modes(0)
+    dt = T_FINAL / NSTEPS_T
+    res = {}
+    for name, prec in (("fp32", af.FP32), ("fp64", af.FP64)):
+        r = time_path(prec, data, args.c2_steps, 20, dt, args.general_steps)
+        res[name] = r
+        print(f"[bench] config2 {name}: {args.c2_steps} steps in {r['ms']:.3f} ms; level-advance launch "
+              f"(K={r['K']}, {r['NT']} threads) {r['k_ms'] * 1e3:.2f} us", file=sys.stderr, flush=True)
+    line["config2"] = config2_block(res, args.c2_steps, dt)
+    del res
+
     if not args.no_amr:
-        line["amr"] = amr_runs()
+        line["amr_runs"] = amr_runs()
         line["rotation"] = rotation_runs()
         line["swirl"] = swirl_runs()
         line["burgers"] = burgers_runs()
-    if not args.no_cpu:
-        v, el = cpu_baseline(data, args.cpu_steps, dt)
-        line["cpu_baseline"] = {"value": v, "unit": "cell-updates/s", "cores": 1, "kind": "oracle",
-                                "sample": f"{args.cpu_steps} of the 1280 steps on the 512^2 grid "
-                                          f"(single-threaded FP64 oracle, {el:.1f} s)"}
+    if job is not None:
+        # all host cores: independent oracle processes, each the same first
+        # coarse step, after the GPU work (so that they do not compete with
+        # its launches)
         nproc = min(16, len(os.sched_getaffinity(0)))
-        va, wa, each = cpu_baseline_allcore(data, args.cpu_steps // 3, dt, nproc)
-        line["cpu_baseline_allcore"] = {"value": va, "unit": "cell-updates/s", "cores": nproc, "kind": "oracle",
-                                        "sample": f"{nproc} independent oracle processes, {args.cpu_steps // 3} "
-                                                  f"steps of the 512^2 grid each, {wa:.1f} s wall "
-                                                  f"(slowest process {max(each):.1f} s)"}
-        print(f"[bench] oracle: {v:.3e} cell-updates/s on 1 core, {va:.3e} on {nproc} cores", file=sys.stderr,
-              flush=True)
+        wall, each = c4_oracle_allcore(job, tmp.name, nproc)
+        line["cpu_baseline_allcore"] = {"value": nproc * job["cell_updates"] / wall, "unit": "cell-updates/s",
+                                        "cores": nproc, "kind": "oracle", "cpu": _cpu_model(),
+                                        "sample": f"{nproc} independent oracle processes, each the first coarse "
+                                                  f"step of config 4, {wall:.1f} s wall (slowest {max(each):.1f} s)"}
+        print(f"[bench] oracle on {nproc} cores: {nproc * job['cell_updates'] / wall:.3e} cell-updates/s",
+              file=sys.stderr, flush=True)
+    tmp.cleanup()
     print(json.dumps(line), flush=True)
+
+
+def c4_oracle_allcore(job, tmp, nproc):
+    import subprocess
+    path = os.path.join(tmp, "c4_init.npz")
+    outs = [os.path.join(tmp, f"c4_oracle_{k}.npz") for k in range(nproc)]
+    t0 = time.perf_counter()
+    procs = [subprocess.Popen([sys.executable, "-c", _C4_ORACLE_CHILD, ROOT, path, o, "time-only"]) for o in outs]
+    if any(p.wait() != 0 for p in procs):
+        raise RuntimeError("oracle child failed")
+    wall = time.perf_counter() - t0
+    return wall, [float(np.load(o)["seconds"]) for o in outs]
+
+
+def _cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def config2_block(res, steps, dt):
+    """Config 2 (512^2 uniform advection, af_level_advance with K steps per
+    launch, replayed as a HIP graph): throughput, the roofline of the timed
+    region itself (algorithmic bytes per step over ms per step) and of its
+    launches, and the measured HBM traffic of a launch."""
+    import afsynth
+    import paper_2205_07572_amd as af
+    out = {"workload": "advection a=1 b=0.5, periodic unit square, 16x16 patches of 32x32 cells (512^2), "
+                       "seeded 8-mode Fourier data, CFL 0.4, T=1 in 1280 steps"}
+
+    def interior(blocks):
+        return np.stack([np.stack([b[k][0, 2:2 + M, 2:2 + M] for k in af.KINDS]) for b in blocks])
+
+    a32, a64 = interior(res["fp32"]["out"]), interior(res["fp64"]["out"])
+    out["linf_fp32_vs_fp64_rel"] = float(np.abs(a32 - a64).max() / np.abs(a64).max())
+    for name, wb in (("fp32", 4), ("fp64", 8)):
+        r = res[name]
+        ms_step = r["ms"] / steps
+        bytes_step = 8 * wb * NCELL
+        traffic = PROFILED_TRAFFIC.get((name, r["K"], r["NT"]))
+        out[name] = {"cell_updates_per_s": NCELL / (ms_step * 1e-3), "ms_per_step": ms_step,
+                     "steps_per_launch": r["K"], "threads_per_patch": r["NT"], "kernel_us": r["k_ms"] * 1e3,
+                     "roofline_step": {"bound": "hbm", "achieved": bytes_step / (ms_step * 1e-3) / 1e9,
+                                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                       "frac": bytes_step / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                       "what": "algorithmic bytes (8 words per cell-update) / ms per step, "
+                                               "graph replay of the whole run"},
+                     "traffic_per_launch": traffic,
+                     "traffic_frac": (traffic / (r["k_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS) if traffic else None,
+                     "eager_ms_per_step": r["eager_ms"] / steps,
+                     "general_path_us_per_step": r["general_ms_per_step"] * 1e3}
+    out["speedup_fp32_over_fp64"] = out["fp32"]["cell_updates_per_s"] / out["fp64"]["cell_updates_per_s"]
+    if steps == NSTEPS_T:
+        t = steps * dt
+        ex = []
+        for (l, ix, iy) in afsynth.uniform_leaves(N0, N0, 0):
+            dx = 1.0 / (M * N0)
+            ex.append(afsynth.dofs_block(afsynth.InitialData(1, lambda x, y: afsynth.fourier_modes(0).exact(x, y, t)),
+                                         M, 2, ix * M * dx, iy * M * dx, dx, dx, 4))
+        ae = interior(ex)
+        out["linf_vs_exact_T1"] = {"fp32": float(np.abs(a32 - ae).max()), "fp64": float(np.abs(a64 - ae).max())}
+    return out
 
 
 if __name__ == "__main__":

@@ -198,6 +198,22 @@ class Context:
         return mk.value
 
 
+    def amr_coarse_step_timed(self, hier, bufs, mask, dt0, flux_reg, events, t0=0.0):
+        """af_amr_coarse_step_timed (a measurement helper): the subcycled
+        coarse step with HIP event pairs recorded around its batched step
+        launches.  events: raw hipEvent_t handles, two per launch.  Returns
+        (mask, launches timed, cell-updates of each)."""
+        n = len(events) // 2
+        arr = (ctypes.c_void_p * max(1, 2 * n))(*events)
+        cells = np.zeros(max(1, n))
+        nl = ctypes.c_int32()
+        mk = ctypes.c_uint32(mask)
+        check(_lib.load().af_amr_coarse_step_timed(self.h, hier.h, self._pair(bufs), ctypes.byref(mk), float(t0),
+                                                   float(dt0), _ptr(flux_reg), _stream(), arr, int(n),
+                                                   ctypes.byref(nl), cells.ctypes.data_as(ctypes.c_void_p)))
+        return mk.value, nl.value, cells[:nl.value].copy()
+
+
 class Hierarchy:
     def __init__(self, ctx: Context, leaves=None, _handle=None):
         self.ctx = ctx

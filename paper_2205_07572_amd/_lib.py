@@ -30,7 +30,7 @@ EXPORTS = [
 
 # Measurement helpers the library also exports (csrc/af_probe.h); not part
 # of the method's interface.
-PROBES = ["af_fma_probe"]
+PROBES = ["af_fma_probe", "af_amr_coarse_step_timed"]
 
 
 class af_problem(ctypes.Structure):
@@ -105,6 +105,8 @@ def load():
     L.af_autotune.argtypes = [P, P, S, i32, D, i32, P, P, P]
     L.af_ctx_get_advance_shape.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
     L.af_fma_probe.argtypes = [i32, P, i32, i32, P]
+    L.af_amr_coarse_step_timed.argtypes = [P, P, S, ctypes.POINTER(ctypes.c_uint32), D, D, P, P, P, i32,
+                                           ctypes.POINTER(i32), P]
     L.af_cnn_last_error.restype = ctypes.c_char_p
     L.af_cnn_create.argtypes = [i32, ctypes.POINTER(P)]
     L.af_cnn_destroy.argtypes = [P]

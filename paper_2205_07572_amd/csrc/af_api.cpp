@@ -1156,9 +1156,26 @@ struct Driver {
     L.gnflags = h->d_gnflags;
     L.weights = weights_for(ctx, L.dtdx, L.dtdy);
     if (!L.weights) return fail(AF_ERR_STATE, "acoustic stencils lack their mirror symmetry");
+    const bool timed = ev && nev < max_ev;
+    if (timed) AF_HIP(hipEventRecord(ev[2 * nev], st));
     AF_HIP(launch_amr_step(L, st));
+    if (timed) {
+      AF_HIP(hipEventRecord(ev[2 * nev + 1], st));
+      if (ev_cells) {
+        double cells = 0.0;
+        for (int k = 0; k < L.nlev; ++k) cells += double(L.count[k]) * ctx->P.m * ctx->P.m;
+        ev_cells[nev] = cells;
+      }
+      ++nev;
+    }
     return AF_OK;
   }
+
+  // measurement (af_amr_coarse_step_timed): event pairs around the step
+  // launches of the batched path
+  hipEvent_t* ev = nullptr;
+  double* ev_cells = nullptr;
+  int max_ev = 0, nev = 0;
 
   double dt0_ = 0.0;
 
@@ -1282,6 +1299,26 @@ af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* 
   // take an even number of steps; global, every level up to the finest flips
   *mask ^= global ? ((2u << h->H.finest) - 1u) : 1u;
   return AF_OK;
+}
+
+af_status af_amr_coarse_step_timed(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* mask, double t0, double dt0,
+                                   double* flux_reg, hipStream_t stream, void** events, int32_t max_launches,
+                                   int32_t* nlaunch, double* cell_updates) {
+  if (!ctx || !h || !mask || !flux_reg || !events || !nlaunch || max_launches < 0)
+    return fail(AF_ERR_ARG, "null argument");
+  af_status s = check_pair(ctx, h, bufs, "af_amr_coarse_step_timed");
+  if (s != AF_OK) return s;
+  if (!std::isfinite(t0)) return fail(AF_ERR_ARG, "t0 must be finite");
+  if ((s = check_cfl(ctx, 0, dt0)) != AF_OK) return s;
+  if ((s = ctx_device(ctx)) != AF_OK || (s = hier_device(h)) != AF_OK) return s;
+  Driver D{ctx, h, bufs, *mask, flux_reg, stream};
+  D.ev = reinterpret_cast<hipEvent_t*>(events);
+  D.ev_cells = cell_updates;
+  D.max_ev = max_launches;
+  s = D.run(0, t0, dt0);
+  *nlaunch = D.nev;
+  if (s == AF_OK) *mask = D.mask;
+  return s;
 }
 
 }  // extern "C"

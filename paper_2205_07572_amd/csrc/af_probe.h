@@ -23,6 +23,19 @@ extern "C" {
  * out or counts below 1; nothing is launched then. */
 af_status af_fma_probe(int32_t prec, void* out, int32_t nblocks, int32_t iters, hipStream_t stream);
 
+/* af_amr_coarse_step_timed -- af_amr_coarse_step (subcycled, eager) that
+ * also records a pair of HIP events on `stream` around each launch of the
+ * batched step kernel: events[2k] before and events[2k + 1] after the k-th,
+ * for the first max_launches launches (events: caller-created hipEvent_t,
+ * 2 * max_launches of them, created with timing enabled).  *nlaunch receives
+ * the number of launches timed; cell_updates (host, max_launches entries, or
+ * NULL) the interior leaf cell-updates of each.  Hierarchies stepped by the
+ * one-level path or the per-level path (variable coefficients) record
+ * nothing. */
+af_status af_amr_coarse_step_timed(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* level_buf_mask, double t0,
+                                   double dt0, double* flux_reg, hipStream_t stream, void** events,
+                                   int32_t max_launches, int32_t* nlaunch, double* cell_updates);
+
 #ifdef __cplusplus
 }
 #endif
