@@ -123,6 +123,16 @@ af_status af_ctx_destroy(af_ctx* ctx);
  * autotuner picks it; results do not depend on it. */
 af_status af_ctx_set_tile(af_ctx* ctx, int32_t ty);
 int32_t af_ctx_get_tile(const af_ctx* ctx);
+/* Fused pairs of finest-level substeps in the batched coarse step of
+ * af_amr_coarse_step (on = 1, the default; off = 0): with m = 8 or 16 and a
+ * finest level F >= 2, one block takes both substeps of a pair of level F
+ * (Sec. 3.2) from one staging of its halo, the first (layer-1 region) into
+ * on-chip memory, the second from there, and the launches of the odd time
+ * points go away.  Results are bit-identical with it off; only which of the
+ * two buffers holds level F in the middle of a coarse step differs.
+ * AF_ERR_ARG for a null ctx or on not 0 or 1. */
+af_status af_ctx_set_fused_pairs(af_ctx* ctx, int32_t on);
+int32_t af_ctx_get_fused_pairs(const af_ctx* ctx); /* -1 for a null ctx */
 
 /* ---------------------------------------------------------------------
  * Hierarchy (Sec. 3): a leaf set of the quadtree.  Leaf k is patch k of
@@ -333,7 +343,8 @@ af_status af_autotune(af_ctx* ctx, af_hier* h, af_state* bufs, int32_t level, do
  * completed a pair of substeps and copies finer or same-level vertices onto
  * the closed-square boundary nodes of leaves with a neighbour of another
  * level (the part of the fill a coarser reconstruction reads).  2^F + 2^(F-1)
- * + 1 launches per coarse step; results equal the recursion above.  In
+ * + 1 launches per coarse step, 2^(F-1) + 2^(F-1) + 1 with fused pairs (see
+ * af_ctx_set_fused_pairs); results equal the recursion above.  In
  * every case the ghost layers of the result are not filled; call
  * af_ghost_fill before reading them.
  * --------------------------------------------------------------------- */

@@ -94,6 +94,16 @@ class Context:
     def tile(self, ty):
         check(_lib.load().af_ctx_set_tile(self.h, int(ty)))
 
+    @property
+    def fused_pairs(self):
+        """af_ctx_get_fused_pairs: the batched coarse step fuses each pair of
+        finest-level substeps into one launch (bit-identical results)."""
+        return bool(_lib.load().af_ctx_get_fused_pairs(self.h))
+
+    @fused_pairs.setter
+    def fused_pairs(self, on):
+        check(_lib.load().af_ctx_set_fused_pairs(self.h, int(bool(on))))
+
     def advance_shapes(self):
         """(K, threads) pairs of the level-advance kernel for this problem."""
         L = _lib.load()

@@ -16,6 +16,7 @@ STATUS_NAMES = {0: "AF_OK", -1: "AF_ERR_ARG", -2: "AF_ERR_CFL", -3: "AF_ERR_LAYO
 # Every symbol include/af.h declares.
 EXPORTS = [
     "af_last_error", "af_ctx_create", "af_ctx_destroy", "af_ctx_set_tile", "af_ctx_get_tile",
+    "af_ctx_set_fused_pairs", "af_ctx_get_fused_pairs",
     "af_hier_create", "af_hier_destroy", "af_hier_num_leaves", "af_hier_get_leaves",
     "af_hier_level_range", "af_hier_finest_level", "af_hier_side_relations", "af_hier_side_mask",
     "af_hier_leaf_xy",
@@ -76,6 +77,9 @@ def load():
     L.af_ctx_set_tile.argtypes = [P, i32]
     L.af_ctx_get_tile.argtypes = [P]
     L.af_ctx_get_tile.restype = i32
+    L.af_ctx_set_fused_pairs.argtypes = [P, i32]
+    L.af_ctx_get_fused_pairs.argtypes = [P]
+    L.af_ctx_get_fused_pairs.restype = i32
     L.af_hier_create.argtypes = [P, i32, P, P, P, ctypes.POINTER(P)]
     L.af_hier_destroy.argtypes = [P]
     L.af_hier_num_leaves.argtypes = [P]
@@ -121,7 +125,8 @@ def load():
     L.af_cnn_features.argtypes = [P, P, P, S, ctypes.c_uint32, P, P]
     L.af_cnn_tag.argtypes = [P, P, P, S, ctypes.c_uint32, P, P, P, P]
     for name in EXPORTS + PROBES:
-        if name not in ("af_last_error", "af_hier_num_leaves", "af_ctx_get_tile", "af_hier_finest_level",
+        if name not in ("af_last_error", "af_hier_num_leaves", "af_ctx_get_tile", "af_ctx_get_fused_pairs",
+                        "af_hier_finest_level",
                         "af_hier_side_mask", "af_hier_leaf_xy", "af_ctx_advance_shapes", "af_cnn_last_error", "af_cnn_num_params"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L

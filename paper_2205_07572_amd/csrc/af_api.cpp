@@ -41,6 +41,7 @@ struct af_ctx {
   af_problem P;
   int ncomp;
   int ty = 0;  // step tile height (rows per block)
+  bool fused_pairs = true;  // batched coarse step: fused pairs of finest-level substeps
   int adv_k = 0, adv_nt = 0;  // level-advance steps per launch and block size (0 = default)
   // fill-set entries of one patch block (device); the first ninner lie
   // within one cell of the interior (all an interior-region step reads)
@@ -362,6 +363,15 @@ af_status af_ctx_set_tile(af_ctx* ctx, int32_t ty) {
 }
 
 int32_t af_ctx_get_tile(const af_ctx* ctx) { return ctx ? ctx->ty : -1; }
+
+af_status af_ctx_set_fused_pairs(af_ctx* ctx, int32_t on) {
+  if (!ctx) return fail(AF_ERR_ARG, "null ctx");
+  if (on != 0 && on != 1) return fail(AF_ERR_ARG, "af_ctx_set_fused_pairs: on must be 0 or 1");
+  ctx->fused_pairs = on == 1;
+  return AF_OK;
+}
+
+int32_t af_ctx_get_fused_pairs(const af_ctx* ctx) { return ctx ? int32_t(ctx->fused_pairs) : -1; }
 
 // ----------------------------------------------------------------- hierarchy
 
@@ -1156,6 +1166,7 @@ struct Driver {
     L.gnflags = h->d_gnflags;
     L.weights = weights_for(ctx, L.dtdx, L.dtdy);
     if (!L.weights) return fail(AF_ERR_STATE, "acoustic stencils lack their mirror symmetry");
+    L.pair = pair_;  // level F (the last here, region layer 1 at even tau) takes its pair
     const bool timed = ev && nev < max_ev;
     if (timed) AF_HIP(hipEventRecord(ev[2 * nev], st));
     AF_HIP(launch_amr_step(L, st));
@@ -1163,7 +1174,8 @@ struct Driver {
       AF_HIP(hipEventRecord(ev[2 * nev + 1], st));
       if (ev_cells) {
         double cells = 0.0;
-        for (int k = 0; k < L.nlev; ++k) cells += double(L.count[k]) * ctx->P.m * ctx->P.m;
+        for (int k = 0; k < L.nlev; ++k)
+          cells += double(L.count[k]) * ctx->P.m * ctx->P.m * (L.pair && k == L.nlev - 1 ? 2 : 1);
         ev_cells[nev] = cells;
       }
       ++nev;
@@ -1178,6 +1190,7 @@ struct Driver {
   int max_ev = 0, nev = 0;
 
   double dt0_ = 0.0;
+  bool pair_ = false;
 
   af_status coarse_step_batched(double dt0) {
     const int F = h->H.finest;
@@ -1185,7 +1198,11 @@ struct Driver {
     af_status s;
     for (int l = 0; l <= F; ++l)
       if ((s = fill_plan(ctx, h, l, st)) != AF_OK) return s;
-    for (int tau = 0; tau < (1 << F); ++tau) {
+    // fused pairs: the launch of each even time point also takes the finest
+    // level's second substep, so the odd time points (where only level F
+    // starts a step) need no launch
+    pair_ = ctx->fused_pairs && F >= 2 && amr_pair_supported(ctx->P.m);
+    for (int tau = 0; tau < (1 << F); tau += pair_ ? 2 : 1) {
       // the coarsest level that starts a step at tau
       const int l0 = tau == 0 ? 0 : F - __builtin_ctz(unsigned(tau));
       if (tau == 0) {

@@ -99,20 +99,57 @@ __device__ __forceinline__ void gather_planes(T* lds, Plane plane, Pos pos) {
 
 // Workgroups are handed to the 8 XCDs round-robin (workgroup b to XCD b % 8),
 // each XCD with its own L2.  Block b takes work item xcd_patch(b, n), so
-// that XCD x runs the contiguous run of items [x n / 8, (x + 1) n / 8):
-// the tiles of one patch, and bands of neighbouring patches (leaves are
-// sorted by level and row), whose reads of each other's cells then meet in
-// one L2.
+// that each XCD runs one contiguous run of items: with n = 8 q + r, XCD x
+// gets the q + (x < r) items from x q + min(x, r) on.  Those are the tiles of
+// one patch and bands of neighbouring patches (leaves are sorted by level
+// and row), whose reads of each other's cells then meet in one L2.  The map
+// is a bijection of [0, n) for every n.
 __device__ __forceinline__ int xcd_patch(int b, int n) {
   constexpr int kXcd = 8;
-  return (n % kXcd) ? b : (b % kXcd) * (n / kXcd) + b / kXcd;
+  const int x = b % kXcd, q = n / kXcd, r = n - q * kXcd;
+  return x * q + min(x, r) + b / kXcd;
 }
 
-template <typename T, int NCOMP, int NR, int NC, int NT2>
-struct StepLds {
+// LDS of a patch step: the staged DOFs, then the nodes' time sums.
+// kLdsAlias: the update reads only the averages and the sums, so the sums
+// overwrite the staged node values once every node is evaluated; the block
+// then holds 4 NCOMP NR NC values, not 7 NCOMP NR NC, and more blocks fit on
+// a CU.  kLdsPair: separate sums; the first of a fused pair of substeps puts
+// its new node values and averages back in place of the staged ones, where
+// the second substep reads them.  kLdsSwirl: separate sums, and the swirl's
+// values at t+dt (tsum2); its update also reads the nodes at t.
+enum StepLdsKind { kLdsAlias, kLdsPair, kLdsSwirl };
+
+template <typename T, int NCOMP, int NR, int NC, int KIND>
+struct StepLds;
+
+template <typename T, int NCOMP, int NR, int NC>
+struct StepLds<T, NCOMP, NR, NC, kLdsAlias> {
+  using TS = T[3][NCOMP][NR - 2][NC - 2];
+  static constexpr bool kSeparate = false;
   T in[4][NCOMP][NR][NC];
-  T tsum[3][NCOMP][NR - 2][NC - 2];   // time sums; for the swirl the values at t+dt/2
-  T tsum2[NT2][NCOMP][NR - 2][NC - 2];  // swirl: the values at t+dt
+  __device__ __forceinline__ TS& tsum() { return *reinterpret_cast<TS*>(&in[1][0][0][0]); }
+  __device__ __forceinline__ TS& tsum2() { return tsum(); }  // unused without the swirl
+};
+
+template <typename T, int NCOMP, int NR, int NC>
+struct StepLds<T, NCOMP, NR, NC, kLdsPair> {
+  using TS = T[3][NCOMP][NR - 2][NC - 2];
+  static constexpr bool kSeparate = true;
+  T in[4][NCOMP][NR][NC];
+  TS ts;
+  __device__ __forceinline__ TS& tsum() { return ts; }
+  __device__ __forceinline__ TS& tsum2() { return ts; }  // unused without the swirl
+};
+
+template <typename T, int NCOMP, int NR, int NC>
+struct StepLds<T, NCOMP, NR, NC, kLdsSwirl> {
+  using TS = T[3][NCOMP][NR - 2][NC - 2];
+  static constexpr bool kSeparate = true;
+  T in[4][NCOMP][NR][NC];
+  TS ts, ts2;
+  __device__ __forceinline__ TS& tsum() { return ts; }
+  __device__ __forceinline__ TS& tsum2() { return ts2; }
 };
 
 // Simpson space-time sum of one face from the time sums of its three nodes
@@ -368,9 +405,14 @@ struct StepIO {
   uint32_t smask;          // sides whose faces are recorded
 };
 
-template <typename T, int EQ, int M, int TY, typename L_t>
+// TO_LDS: the first substep of a fused pair (no HBM output): new node values
+// and averages replace the staged ones in L.in.  rofs: staged row of cell row
+// j is j - jlo + 1 + rofs (the pair's second substep reads the first's rows).
+template <typename T, int EQ, int M, int TY, bool TO_LDS = false, typename L_t>
 __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const typename WSel<T, EQ>::type& W,
-                                             int jlo, int jhi, T px0, T py0) {
+                                             int jlo, int jhi, T px0, T py0, int rofs = 0) {
+  static_assert(!TO_LDS || (L_t::kSeparate && (EQ == 0 || EQ == 1)),
+                "a fused pair needs separate time sums and a constant-coefficient equation");
   constexpr int NCOMP = EQ == 1 ? 3 : 1;
   constexpr int NR = TY + 3;
   constexpr int NC = M + 5;
@@ -391,10 +433,27 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
     for (int kind = 0; kind < 3; ++kind)
       shared_src = shared_src && W.off[kind][0][0] == W.off[kind][1][0] && W.off[kind][0][1] == W.off[kind][1][1];
   }
-  for (Walk2 w(threadIdx.x, kThreads, EC); w.y < ER; w.next()) {
+  // the extended cells of a thread: at most MAXIT (region <= 1, nrow <= TY);
+  // their time sums wait in registers until every node is evaluated
+  constexpr int MAXIT = ((M + 3) * (TY + 1) + kThreads - 1) / kThreads;
+  T tsv[MAXIT][3][NCOMP];
+  T nv[TO_LDS ? MAXIT : 1][3][NCOMP];  // TO_LDS: the new node values, stored after the barrier
+  // a new node value: to HBM (if `keep`, the rows and columns this tile
+  // owns), or held for LDS
+  auto emit = [&](int it, int kind, int q, bool keep, size_t o, T v) {
+    if constexpr (TO_LDS) {
+      nv[it][kind][q] = v;
+    } else {
+      if (keep) A.out[kind + 1][o] = v;
+    }
+  };
+  Walk2 w(threadIdx.x, kThreads, EC);
+#pragma unroll
+  for (int it = 0; it < MAXIT; ++it, w.next()) {
+    if (w.y >= ER) break;
     const int ii = w.x, jj = w.y;
     const int i = ilo + ii, j = jlo + jj;
-    const int r = jj + 1, c = ii + coff;  // staged position of cell (i,j)
+    const int r = jj + 1 + rofs, c = ii + coff;  // staged position of cell (i,j)
     const bool wrow = (jj < nrow) || last_tile;
     const bool has_x = jj < nrow;      // xedge (i,j) belongs to rows [jlo, jhi)
     const bool has_y = ii < span;      // yedge (i,j) belongs to cols [ilo, ihi)
@@ -412,8 +471,8 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
           f = adv_eval<T, NR, NC>(L.in, r + W.off[kind][1][1], c + W.off[kind][1][0], W.w[kind][1]);
         }
         const T cur = L.in[kind + 1][0][r][c];
-        L.tsum[kind][0][jj][ii] = (cur + T(4) * h) + f;
-        if (wrow) A.out[kind + 1][size_t(patch) * plane + obase] = f;
+        tsv[it][kind][0] = (cur + T(4) * h) + f;
+        emit(it, kind, 0, wrow, size_t(patch) * plane + obase, f);
       }
     } else if constexpr (EQ == 2 || EQ == 3) {
       // solid-body rotation (Sec. 4.2): the foot is the node turned back by
@@ -455,10 +514,10 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
         }
         if constexpr (EQ == 2) {
           const T cur = L.in[kind + 1][0][r][c];
-          L.tsum[kind][0][jj][ii] = (cur + T(4) * val[0]) + val[1];
+          tsv[it][kind][0] = (cur + T(4) * val[0]) + val[1];
         } else {
-          L.tsum[kind][0][jj][ii] = val[0];
-          L.tsum2[kind][0][jj][ii] = val[1];
+          tsv[it][kind][0] = val[0];
+          L.tsum2()[kind][0][jj][ii] = val[1];
         }
         if (wrow) A.out[kind + 1][size_t(patch) * plane + obase] = val[1];
       }
@@ -497,33 +556,89 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
           val[t] = Q;
         }
         const T cur = L.in[kind + 1][0][r][c];
-        L.tsum[kind][0][jj][ii] = (T(0.5) * cur * cur + T(2) * val[0] * val[0]) + T(0.5) * val[1] * val[1];
+        tsv[it][kind][0] = (T(0.5) * cur * cur + T(2) * val[0] * val[0]) + T(0.5) * val[1] * val[1];
         if (wrow) A.out[kind + 1][size_t(patch) * plane + obase] = val[1];
       }
-    } else {
-      // acoustics (eq. ERFormula): the three nodes of the cell from its
+    } else if constexpr (EQ == 1 && sizeof(T) == 8 && !TO_LDS) {
+      // acoustics (eq. ERFormula), FP64: the three nodes of the cell from its
       // neighbourhood in registers, orbit by orbit
       T v1[3], vs[3];
       ac_node<T, 0, NR, NC>(L.in, r, c, W.w[0], v1, vs);
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
-        L.tsum[NK_CORNER][q][jj][ii] = L.in[1][q][r][c] + vs[q];
-        if (wrow) A.out[1][(size_t(q) * A.npatch + patch) * plane + obase] = v1[q];
+        tsv[it][NK_CORNER][q] = L.in[1][q][r][c] + vs[q];
+        emit(it, NK_CORNER, q, wrow, (size_t(q) * A.npatch + patch) * plane + obase, v1[q]);
       }
       if (has_x) {
         ac_node<T, 1, NR, NC>(L.in, r, c, W.w[1], v1, vs);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          L.tsum[NK_XEDGE][q][jj][ii] = L.in[2][q][r][c] + vs[q];
-          A.out[2][(size_t(q) * A.npatch + patch) * plane + obase] = v1[q];
+          tsv[it][NK_XEDGE][q] = L.in[2][q][r][c] + vs[q];
+          emit(it, NK_XEDGE, q, true, (size_t(q) * A.npatch + patch) * plane + obase, v1[q]);
         }
       }
       if (has_y) {
         ac_node<T, 2, NR, NC>(L.in, r, c, W.w[2], v1, vs);
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
-          L.tsum[NK_YEDGE][q][jj][ii] = L.in[3][q][r][c] + vs[q];
-          if (wrow) A.out[3][(size_t(q) * A.npatch + patch) * plane + obase] = v1[q];
+          tsv[it][NK_YEDGE][q] = L.in[3][q][r][c] + vs[q];
+          emit(it, NK_YEDGE, q, wrow, (size_t(q) * A.npatch + patch) * plane + obase, v1[q]);
+        }
+      }
+    }
+  }
+  if constexpr (EQ == 1 && (sizeof(T) == 4 || TO_LDS)) {
+    // acoustics (eq. ERFormula), FP32: one node kind at a time over the
+    // thread's cells, each node from its neighbourhood orbit by orbit.  The
+    // kind's orbit weights stay in scalar registers for the whole pass and
+    // the kernel needs 91 VGPRs, not 126 (5 waves per SIMD, not 4).  In FP64
+    // the kernel holds 2 waves per SIMD either way, and the three nodes of a
+    // cell together give each wave more independent work (the first substep
+    // of a fused pair goes kind by kind in FP64 too: it also holds the new
+    // node values).
+    auto kind_pass = [&](auto kc) {
+      constexpr int K = decltype(kc)::value;
+      Walk2 v(threadIdx.x, kThreads, EC);
+#pragma unroll
+      for (int it = 0; it < MAXIT; ++it, v.next()) {
+        if (v.y >= ER) break;
+        const int ii = v.x, jj = v.y;
+        if (K == NK_XEDGE && jj >= nrow) continue;  // x-edges of rows [jlo, jhi)
+        if (K == NK_YEDGE && ii >= span) continue;  // y-edges of cols [ilo, ihi)
+        const int r = jj + 1 + rofs, c = ii + coff;
+        const size_t obase = size_t(jlo + jj + kGhost) * A.pitch + (ilo + ii + kGhost);
+        const bool wst = K == NK_XEDGE || jj < nrow || last_tile;
+        T v1[3], vs[3];
+        ac_node<T, K, NR, NC>(L.in, r, c, W.w[K], v1, vs);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          tsv[it][K][q] = L.in[K + 1][q][r][c] + vs[q];
+          emit(it, K, q, wst, (size_t(q) * A.npatch + patch) * plane + obase, v1[q]);
+        }
+      }
+    };
+    kind_pass(std::integral_constant<int, NK_CORNER>());
+    kind_pass(std::integral_constant<int, NK_XEDGE>());
+    kind_pass(std::integral_constant<int, NK_YEDGE>());
+  }
+  __syncthreads();
+  auto& ts = L.tsum();
+  {
+    Walk2 v(threadIdx.x, kThreads, EC);
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it, v.next()) {
+      if (v.y >= ER) break;
+      const int ii = v.x, jj = v.y;
+      const int r = jj + 1 + rofs, c = ii + coff;
+#pragma unroll
+      for (int q = 0; q < NCOMP; ++q) {
+        ts[NK_CORNER][q][jj][ii] = tsv[it][NK_CORNER][q];
+        if (jj < nrow) ts[NK_XEDGE][q][jj][ii] = tsv[it][NK_XEDGE][q];
+        if (ii < span) ts[NK_YEDGE][q][jj][ii] = tsv[it][NK_YEDGE][q];
+        if constexpr (TO_LDS) {
+          L.in[1][q][r][c] = nv[it][NK_CORNER][q];
+          if (jj < nrow) L.in[2][q][r][c] = nv[it][NK_XEDGE][q];
+          if (ii < span) L.in[3][q][r][c] = nv[it][NK_YEDGE][q];
         }
       }
     }
@@ -540,12 +655,12 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
     T FL[NCOMP], FR[NCOMP], GB[NCOMP], GT[NCOMP];
 #pragma unroll
     for (int q = 0; q < NCOMP; ++q) {
-      FL[q] = face_sum(L.tsum[NK_CORNER][q][jj][ii], L.tsum[NK_XEDGE][q][jj][ii], L.tsum[NK_CORNER][q][jj + 1][ii]);
-      FR[q] = face_sum(L.tsum[NK_CORNER][q][jj][ii + 1], L.tsum[NK_XEDGE][q][jj][ii + 1],
-                       L.tsum[NK_CORNER][q][jj + 1][ii + 1]);
-      GB[q] = face_sum(L.tsum[NK_CORNER][q][jj][ii], L.tsum[NK_YEDGE][q][jj][ii], L.tsum[NK_CORNER][q][jj][ii + 1]);
-      GT[q] = face_sum(L.tsum[NK_CORNER][q][jj + 1][ii], L.tsum[NK_YEDGE][q][jj + 1][ii],
-                       L.tsum[NK_CORNER][q][jj + 1][ii + 1]);
+      FL[q] = face_sum(ts[NK_CORNER][q][jj][ii], ts[NK_XEDGE][q][jj][ii], ts[NK_CORNER][q][jj + 1][ii]);
+      FR[q] = face_sum(ts[NK_CORNER][q][jj][ii + 1], ts[NK_XEDGE][q][jj][ii + 1],
+                       ts[NK_CORNER][q][jj + 1][ii + 1]);
+      GB[q] = face_sum(ts[NK_CORNER][q][jj][ii], ts[NK_YEDGE][q][jj][ii], ts[NK_CORNER][q][jj][ii + 1]);
+      GT[q] = face_sum(ts[NK_CORNER][q][jj + 1][ii], ts[NK_YEDGE][q][jj + 1][ii],
+                       ts[NK_CORNER][q][jj + 1][ii + 1]);
     }
     // physical fluxes of the Simpson sums: advection f = a q, g = b q;
     // acoustics f = c (u, p, 0), g = c (v, 0, p)  (Sec. 2.3)
@@ -556,10 +671,10 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
     } else if constexpr (EQ == 3) {
       // swirl (eq. swirlF, swirlG): the face-midpoint velocity at t, t+dt/2,
       // t+dt times the Simpson sum of the three nodes at that time
-      const int rr = jj + 1, cc = ii + coff;  // staged position of cell (i, j)
+      const int rr = jj + 1 + rofs, cc = ii + coff;  // staged position of cell (i, j)
       const auto& Q0 = L.in;
-      const auto& Qh = L.tsum;
-      const auto& Qf = L.tsum2;
+      const auto& Qh = ts;
+      const auto& Qf = L.tsum2();
       const T xl = px0 + T(i) * W.dx, xr = px0 + T(i + 1) * W.dx, xm = px0 + (T(i) + T(0.5)) * W.dx;
       const T yb = py0 + T(j) * W.dy, yt = py0 + T(j + 1) * W.dy, ym = py0 + (T(j) + T(0.5)) * W.dy;
       // the spatial factors of the face-midpoint velocities, then one
@@ -611,7 +726,6 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
       const T b0 = W.omega * (px0 + T(i) * W.dx - W.xc);
       const T b1 = W.omega * (px0 + (T(i) + T(0.5)) * W.dx - W.xc);
       const T b2 = W.omega * (px0 + T(i + 1) * W.dx - W.xc);
-      const auto& ts = L.tsum;
       fL[0] = (a0 * ts[NK_CORNER][0][jj][ii] + T(4) * a1 * ts[NK_XEDGE][0][jj][ii] + a2 * ts[NK_CORNER][0][jj + 1][ii]) * inv36;
       fR[0] = (a0 * ts[NK_CORNER][0][jj][ii + 1] + T(4) * a1 * ts[NK_XEDGE][0][jj][ii + 1] +
                a2 * ts[NK_CORNER][0][jj + 1][ii + 1]) * inv36;
@@ -626,9 +740,13 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
     }
 #pragma unroll
     for (int q = 0; q < NCOMP; ++q) {
-      const T Q = L.in[0][q][jj + 1][ii + coff];
+      const T Q = L.in[0][q][jj + 1 + rofs][ii + coff];
       const T Qn = Q - A.dtdx * (fR[q] - fL[q]) - A.dtdy * (gT[q] - gB[q]);
-      A.out[0][(size_t(q) * A.npatch + patch) * plane + obase] = Qn;
+      if constexpr (TO_LDS) {
+        L.in[0][q][jj + 1 + rofs][ii + coff] = Qn;  // read only by this thread
+      } else {
+        A.out[0][(size_t(q) * A.npatch + patch) * plane + obase] = Qn;
+      }
     }
     if (smask) {
       // boundary faces of the interior block -> FP64 registers (Sec. 3.2)
@@ -654,7 +772,7 @@ __global__ __launch_bounds__(kThreads) void k_patch_step(const StepArgs<T> A,
   constexpr int NCOMP = EQ == 1 ? 3 : 1;
   constexpr int NR = TY + 3;
   constexpr int NC = M + 5;
-  __shared__ StepLds<T, NCOMP, NR, NC, EQ == 3 ? 3 : 1> L;
+  __shared__ StepLds<T, NCOMP, NR, NC, EQ == 3 ? kLdsSwirl : kLdsAlias> L;
 
   const int region = A.region;
   const int ilo = -region, ihi = M + region;
@@ -1777,7 +1895,8 @@ struct AmrStepArgs {
   uint32_t mask;                   // level l's data before the step: p[(mask >> l) & 1]
   int32_t nlev, lev0;              // levels lev0 .. lev0 + nlev - 1 step
   int32_t first[kMaxLevels];       // first leaf of each of those levels
-  int32_t bstart[kMaxLevels + 1];  // first block of each level; bstart[nlev] = blocks
+  int32_t bstart[kMaxLevels + 1];  // first block of each level (multiples of 8); bstart[nlev] = blocks
+  int32_t items[kMaxLevels];       // (patch, tile) items of each level, <= its block range
   int32_t region[kMaxLevels], tiles[kMaxLevels], rows[kMaxLevels];
   double len_dt_x[kMaxLevels], len_dt_y[kMaxLevels];
   T dtdx, dtdy, a, b, c;
@@ -1789,6 +1908,7 @@ struct AmrStepArgs {
   const FillWeights* fw;
   const int32_t* nbr;              // [nleaves][9] same-level neighbours (k_fill_plan)
   const uint32_t* gnflags;         // [nleaves] directions staged by the same-level gather
+  int32_t pair;                    // the last level takes both substeps of its pair
 };
 
 // Interior DOFs of a patch that no fill writes (af_ctx_create's fill set is
@@ -1834,20 +1954,25 @@ __device__ __forceinline__ T planned_value(T* const (&p)[2][4], uint32_t mask, i
   return T(v);
 }
 
-template <typename T, int EQ, int M, int TY>
+template <typename T, int EQ, int M, int TY, bool PAIR>
 __global__ __launch_bounds__(kThreads) void k_amr_step(const AmrStepArgs<T> A, const typename WSel<T, EQ>::type W) {
   static_assert(EQ == 0 || EQ == 1, "constant-coefficient equations only");
+  static_assert(!PAIR || TY >= M + 2, "a fused pair steps the whole layer-1 region in one block");
   constexpr int NCOMP = EQ == 1 ? 3 : 1;
   constexpr int NR = TY + 3;
   constexpr int NC = M + 5;
-  __shared__ StepLds<T, NCOMP, NR, NC, 1> L;
+  __shared__ StepLds<T, NCOMP, NR, NC, PAIR ? kLdsPair : kLdsAlias> L;
 
-  // ---- block -> (level, patch, tile)
-  const int b = xcd_patch(int(blockIdx.x), int(gridDim.x));
+  // ---- block -> (level, patch, tile).  Each level's block range is a
+  // multiple of 8 long, so every XCD takes an equal share of every level (the
+  // coarse levels' blocks, which fill most of their halo from the plan, are
+  // the slow ones), and within a level a contiguous run of its leaves.
+  const int b = int(blockIdx.x);
   int k = 0;
   while (k + 1 < A.nlev && b >= A.bstart[k + 1]) ++k;
   const int lvl = A.lev0 + k;
-  const int local = b - A.bstart[k];
+  const int local = xcd_patch(b - A.bstart[k], A.bstart[k + 1] - A.bstart[k]);
+  if (local >= A.items[k]) return;  // padding of the level's range (block-uniform)
   const int tiles = A.tiles[k], rows = A.rows[k], region = A.region[k];
   const int pl = local / tiles;
   const int tile = local - pl * tiles;
@@ -1950,7 +2075,25 @@ __global__ __launch_bounds__(kThreads) void k_amr_step(const AmrStepArgs<T> A, c
   io.len_dt_y = A.len_dt_y[k];
   io.reg = (A.reg && A.side_mask) ? A.reg : nullptr;
   io.smask = io.reg ? A.side_mask[patch] : 0u;
-  step_compute<T, EQ, M, TY>(L, io, W, jlo, jhi, T(0), T(0));
+  bool pair = false;
+  if constexpr (PAIR) pair = A.pair && k == A.nlev - 1;
+  if (pair) {
+    // the finest level's pair of substeps (Sec. 3.2).  The first advances the
+    // layer-1 region (cells [-1, m], nodes [-1, m+1]) into LDS; the second
+    // steps the interior from exactly those values.  They are what a fill
+    // would stage at the odd time point: the fill there has no coarser
+    // sources, so coarse-fine ghosts keep the layer-1 values, and a
+    // same-level neighbour's interior is the same arithmetic on the same
+    // data.
+    if constexpr (PAIR) {
+      step_compute<T, EQ, M, TY, true>(L, io, W, jlo, jhi, T(0), T(0));
+      __syncthreads();
+      io.region = 0;  // interior
+      step_compute<T, EQ, M, TY>(L, io, W, 0, M, T(0), T(0), -jlo);
+    }
+  } else {
+    step_compute<T, EQ, M, TY>(L, io, W, jlo, jhi, T(0), T(0));
+  }
 }
 
 // Before the launch of a time point: the conservative fix (Sec. 3.2) of the
@@ -2317,7 +2460,7 @@ hipError_t launch_patch_step(const StepLaunch& s, hipStream_t st) {
   }
 }
 
-template <typename T, int EQ, int M, int TY>
+template <typename T, int EQ, int M, int TY, bool PAIR = false>
 static hipError_t launch_amr_t(const AmrStepLaunch& s, hipStream_t st) {
   AmrStepArgs<T> A;
   for (int b = 0; b < 2; ++b)
@@ -2338,7 +2481,8 @@ static hipError_t launch_amr_t(const AmrStepLaunch& s, hipStream_t st) {
     A.len_dt_x[k] = s.len_dt_x[k];
     A.len_dt_y[k] = s.len_dt_y[k];
     A.bstart[k] = blocks;
-    blocks += s.count[k] * tiles;
+    A.items[k] = s.count[k] * tiles;
+    blocks += (A.items[k] + 7) / 8 * 8;
   }
   A.bstart[s.nlev] = blocks;
   if (blocks == 0) return hipSuccess;
@@ -2353,13 +2497,21 @@ static hipError_t launch_amr_t(const AmrStepLaunch& s, hipStream_t st) {
   A.fw = s.fw;
   A.nbr = s.nbr;
   A.gnflags = s.gnflags;
+  A.pair = PAIR && s.pair;
   const auto& W = step_weights<T, EQ>(s.weights);
-  hipLaunchKernelGGL((k_amr_step<T, EQ, M, TY>), dim3(unsigned(blocks)), dim3(kThreads), 0, st, A, W);
+  hipLaunchKernelGGL((k_amr_step<T, EQ, M, TY, PAIR>), dim3(unsigned(blocks)), dim3(kThreads), 0, st, A, W);
   return hipGetLastError();
 }
 
 template <typename T, int EQ>
 static hipError_t launch_amr_m(const AmrStepLaunch& s, hipStream_t st) {
+  if (s.pair) {
+    switch (s.m) {
+      case 8: return launch_amr_t<T, EQ, 8, 10, true>(s, st);
+      case 16: return launch_amr_t<T, EQ, 16, 18, true>(s, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (s.m) {
     case 8: return launch_amr_t<T, EQ, 8, 8>(s, st);
     case 16: return s.ty == 8 ? launch_amr_t<T, EQ, 16, 8>(s, st) : launch_amr_t<T, EQ, 16, 16>(s, st);

@@ -61,7 +61,12 @@ struct AmrStepLaunch {
   const int32_t* nbr;
   const uint32_t* gnflags;
   const void* weights;  // AdvWeights<T> or AcAllWeights<T>
+  // the last level (the finest, region layer 1) takes both substeps of its
+  // pair in one block (m = 8 or 16; whole-patch tiles)
+  bool pair;
 };
+// m for which a fused pair of finest-level substeps is compiled
+inline bool amr_pair_supported(int m) { return m == 8 || m == 16; }
 hipError_t launch_amr_step(const AmrStepLaunch& s, hipStream_t st);
 
 // Conservative fix of faces [0, nfaces) and the fill's vertex copies onto
