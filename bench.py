@@ -38,6 +38,11 @@ NCELL = (M * N0) ** 2
 T_FINAL = 1.0
 NSTEPS_T = 1280
 HBM_PEAK_GBS = 8000.0
+# Vector ALU peak of these kernels: 256 CUs x 64 fused multiply-adds per clock
+# (FP32 or FP64) x 2 flops x 2.4 GHz = 78.6 TFLOP/s.  The FP32 figure of
+# 157.3 TFLOP/s counts packed FP32 instructions, which this build does not
+# emit.
+VALU_PEAK_TFLOPS = 78.6
 # HBM bytes per launch of the level-advance kernel (k_level_advance_up) on
 # this workload, from rocprofv3 FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00 (scales
 # from a plain 64 MiB copy), keyed by (precision, K, threads); valid only for
@@ -57,12 +62,13 @@ PROFILED_TRAFFIC = {
 }
 
 
-# Config-4 step kernel (k_amr_step, acoustics FP32): algorithmic HBM bytes per
-# interior cell-update (read and write the 4 DOF kinds of 3 components) and
-# the operations of the orbit-form evaluation (af_kernels.hip): 416 node
-# operations (186 additions, 230 multiply-adds) = 646 flops, time sums and
-# update about 60 more.
-C4_BYTES_PER_UPDATE = {"fp32": 96, "fp64": 192}
+# Config-4 step kernel (k_amr_step, acoustics): algorithmic HBM bytes per leaf
+# cell a launch steps (read and write the 4 DOF kinds of 3 components once;
+# a fused pair of finest-level substeps makes two cell-updates of them) and
+# the operations per cell-update of the orbit-form evaluation
+# (af_kernels.hip): 416 node operations (186 additions, 230 multiply-adds) =
+# 646 flops, time sums and update about 60 more.
+C4_BYTES_PER_CELL = {"fp32": 96, "fp64": 192}
 C4_FLOPS_PER_UPDATE = 706
 C4_T, C4_EVERY, C4_M, C4_N0, C4_LMAX, C4_THETA = 0.5, 4, 16, 8, 3, (8.0, 2.0)
 
@@ -72,7 +78,7 @@ C4_T, C4_EVERY, C4_M, C4_N0, C4_LMAX, C4_THETA = 0.5, 4, 16, 8, 3, (8.0, 2.0)
 # FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00 KiB (the factors a plain 64 MiB
 # device copy gives), valid for the kernel source whose hash is recorded
 # (profiles/k_amr_step_config4.md holds the commands).
-C4_TRAFFIC = {"source_sha256_16": "e2116d3d1ce442b3", "fp32": 124578851, "fp64": 221828094}
+C4_TRAFFIC = {"source_sha256_16": "b969717add23735c", "fp32": 77729562, "fp64": 150985363}
 
 
 def _kernel_source_hash():
@@ -773,8 +779,22 @@ def c4_headline(prec, steps, warmup):
             launch_ms.append(ev.ms(2 * nmax * k + 2 * j, 2 * nmax * k + 2 * j + 1))
             launch_cells.append(float(c[j]))
     counts = np.bincount([l for l, _, _ in leaves], minlength=C4_LMAX + 1).tolist()
+    # leaf cells each launch reads and writes once: the levels that start a
+    # step at its time point tau; with fused pairs (finest level F >= 2,
+    # m = 16) the launches are the even tau and level F takes two substeps
+    F = max(l for l, _, _ in leaves)
+    fused = ctx.fused_pairs and F >= 2 and C4_M in (8, 16)
+    leaf_cells = []
+    for k, (nl, _) in enumerate(cells):
+        for j in range(nl):
+            tau = 2 * j if fused else j
+            l0 = 0 if tau == 0 else F - ((tau & -tau).bit_length() - 1)
+            leaf_cells.append(float(C4_M * C4_M * sum(counts[l0:F + 1])))
+            upd = leaf_cells[-1] + (C4_M * C4_M * counts[F] if fused else 0)
+            assert upd == launch_cells[len(leaf_cells) - 1], (upd, launch_cells[len(leaf_cells) - 1])
     return dict(ms=ms, wall_s=t_wall, per_step=per_step, leaves=len(leaves), per_level=counts,
-                launch_ms=np.array(launch_ms), launch_cells=np.array(launch_cells), dt0=dt0, t_start=half * dt0)
+                launch_ms=np.array(launch_ms), launch_cells=np.array(launch_cells),
+                launch_leaf_cells=np.array(leaf_cells), fused_pairs=fused, dt0=dt0, t_start=half * dt0)
 
 
 _C4_ORACLE_CHILD = """
@@ -900,28 +920,45 @@ def main():
     ups64 = r64["per_step"] * args.steps / (r64["ms"] * 1e-3)
 
     def roofline(r, name):
-        bytes_ = C4_BYTES_PER_UPDATE[name] * float(np.sum(r["launch_cells"]))
+        """The dominant kernel against the roof its arithmetic intensity
+        meets: HBM bytes = the leaf DOFs a launch reads and writes once,
+        flops = the orbit-form operations of every cell-update it makes."""
+        bytes_ = C4_BYTES_PER_CELL[name] * float(np.sum(r["launch_leaf_cells"]))
+        flops = C4_FLOPS_PER_UPDATE * float(np.sum(r["launch_cells"]))
         secs = float(np.sum(r["launch_ms"])) * 1e-3
-        achieved = bytes_ / secs / 1e9
-        return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": c4_traffic(name),
-                "kernel": f"k_amr_step<{'float' if name == 'fp32' else 'double'},1,16,16>",
-                "launches": int(len(r["launch_ms"])),
-                "kernel_us_avg": 1e3 * float(np.mean(r["launch_ms"])),
-                "algorithmic_bytes_per_launch_avg": bytes_ / len(r["launch_ms"]),
-                "bytes_per_cell_update": C4_BYTES_PER_UPDATE[name],
-                "alu_tflops": C4_FLOPS_PER_UPDATE * float(np.sum(r["launch_cells"])) / secs / 1e12,
-                "alu_frac_of_78.6": C4_FLOPS_PER_UPDATE * float(np.sum(r["launch_cells"])) / secs / 1e12 / 78.6,
-                "what": "dominant kernel: batched step launches of the timed coarse steps, HIP events around "
-                        "each on its stream; algorithmic bytes = bytes per cell-update x interior leaf "
-                        "cell-updates of the launch"}
+        gbs, tfl = bytes_ / secs / 1e9, flops / secs / 1e12
+        intensity = flops / bytes_
+        alu_bound = intensity * HBM_PEAK_GBS * 1e-3 > VALU_PEAK_TFLOPS
+        hbm = {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbs / HBM_PEAK_GBS}
+        alu = {"bound": "alu", "achieved": tfl, "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+               "frac": tfl / VALU_PEAK_TFLOPS}
+        out = dict(alu if alu_bound else hbm)
+        out.update({"traffic": c4_traffic(name),
+                    "kernel": f"k_amr_step<{'float' if name == 'fp32' else 'double'},1,16,18,pair>",
+                    "launches": int(len(r["launch_ms"])),
+                    "kernel_us_avg": 1e3 * float(np.mean(r["launch_ms"])),
+                    "algorithmic_bytes_per_launch_avg": bytes_ / len(r["launch_ms"]),
+                    "algorithmic_flops_per_launch_avg": flops / len(r["launch_ms"]),
+                    "flops_per_byte": intensity,
+                    "other_roof": alu if not alu_bound else hbm,
+                    "fused_pairs": r["fused_pairs"],
+                    "what": "dominant kernel: the batched step launches of the timed coarse steps, HIP events "
+                            "around each on its stream; bytes = bytes per leaf cell (each DOF read and written "
+                            "once) x leaf cells of the levels stepping at the launch's time point; flops = "
+                            "operations per cell-update x cell-updates (the finest level's fused pair counts "
+                            "twice); bound = the lower roof at that intensity (FP32 vector peak without packed "
+                            "FP32 instructions)"})
+        return out
 
     def step_roofline(r, name, ups):
-        achieved = C4_BYTES_PER_UPDATE[name] * ups / 1e9
+        bytes_step = C4_BYTES_PER_CELL[name] * float(np.sum(r["launch_leaf_cells"])) / args.steps
+        achieved = bytes_step / (r["ms"] / args.steps * 1e-3) / 1e9
         return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
-                "what": "whole coarse step (all launches and the gaps between them): bytes per cell-update x "
-                        "cell-updates / ms_per_step"}
+                "alu_tflops": C4_FLOPS_PER_UPDATE * ups / 1e12,
+                "alu_frac": C4_FLOPS_PER_UPDATE * ups / 1e12 / VALU_PEAK_TFLOPS,
+                "what": "whole coarse step (all launches and the gaps between them): leaf bytes of the step "
+                        "launches / ms_per_step, and operations x cell-updates / ms_per_step"}
 
     line = {
         "metric": "cell-updates/s (FP32 vs FP64) of batched AMR AF step; % HBM roofline; L∞ err",
