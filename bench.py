@@ -6,8 +6,9 @@ unit square; a high-frequency wave packet p0 = exp(-50 |x - x0|^2) cos(k.x),
 8x8 level-0 patches and 4 levels (ratio 2, subcycling, conservative fix);
 gradient tagging of p (refine at 8, coarsen below 2), FP32 state and
 arithmetic with FP64 flux registers.  One "step" is one coarse step of the
-whole hierarchy: 2^3 batched launches (one per substep start time) plus the
-launches of the conservative fix.  The timed hierarchy is the run's state at
+whole hierarchy: one batched launch per even substep start time (4 for 4
+levels; each also takes the finest level's second substep) plus the
+launches of the conservative fix and vertex copies.  The timed hierarchy is the run's state at
 t = T/2 = 0.25 (the initial hierarchy advanced with a regrid every 4 coarse
 steps), frozen during the warm-up and the timed steps; cell-updates/s counts
 interior leaf cells advanced by their level's step.  FP64 is timed beside
