@@ -111,6 +111,13 @@ def parse():
                    help="only run a plain 64 MiB device copy 20 times (HBM counter calibration)")
     p.add_argument("--peak-probe", action="store_true",
                    help="only measure the device's copy bandwidth and vector FMA rate (one JSON line)")
+    p.add_argument("--config5", action="store_true",
+                   help="the learned-tagger workload instead of the benchmark line: train on config-3 runs, "
+                        "evaluate held-out seeds against plain tagging and a uniform fine run (minutes)")
+    p.add_argument("--c5-train-seeds", type=int, default=200)
+    p.add_argument("--c5-eval-seeds", type=int, default=20)
+    p.add_argument("--c5-ref-n", type=int, default=4096)
+    p.add_argument("--c5-steps", type=int, default=2000)
     p.add_argument("--c4-profile", choices=["fp32", "fp64"],
                    help="only the config-4 timed step in that precision (for a profiler run)")
     p.add_argument("--only", choices=["amr", "rotation", "swirl", "burgers"],
@@ -885,6 +892,13 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "single-GPU build: --gpus must be 1 (multi-GPU sharding is design-only)"}))
         sys.exit(2)
+    if args.config5:
+        from paper_2205_07572_amd import tagger_train as tt
+        log = lambda s: print("[config5]", s, file=sys.stderr, flush=True)  # noqa: E731
+        r = tt.config5(train_seeds=range(args.c5_train_seeds), eval_seeds=range(200, 200 + args.c5_eval_seeds),
+                       steps=args.c5_steps, ref_n=args.c5_ref_n or None, log=log)
+        print(json.dumps({"config5": r}), flush=True)
+        return
     if args.c4_profile:
         import paper_2205_07572_amd as af
         r = c4_headline(af.FP32 if args.c4_profile == "fp32" else af.FP64, args.steps, args.warmup)

@@ -299,6 +299,11 @@ af_status af_level_advance(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* le
  * traces back, as in Sec. 2.1, into the upwind neighbour cell).  With other
  * weights af_level_advance replaces such a shape by the default one. */
 int32_t af_ctx_advance_shapes(const af_ctx* ctx, int32_t* ks, int32_t* nts, int32_t cap);
+/* the shapes of that list that only the upwind one-pass kernel runs (the
+ * ones af_level_advance replaces by the default shape for other weights);
+ * same conventions: returns their count (-1 for a null ctx), writes at most
+ * cap of them to the optional arrays */
+int32_t af_ctx_advance_shapes_upwind(const af_ctx* ctx, int32_t* ks, int32_t* nts, int32_t cap);
 af_status af_ctx_set_advance_shape(af_ctx* ctx, int32_t k, int32_t nt);
 /* the shape af_level_advance will use (the tuned one, else the default: the
  * largest K, then the smallest block), for advection with both velocity

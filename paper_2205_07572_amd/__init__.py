@@ -113,6 +113,17 @@ class Context:
         L.af_ctx_advance_shapes(self.h, ks.ctypes.data_as(ctypes.c_void_p), nts.ctypes.data_as(ctypes.c_void_p), n)
         return [(int(k), int(t)) for k, t in zip(ks[:n], nts[:n])]
 
+    def advance_shapes_upwind(self):
+        """The (K, threads) pairs of advance_shapes() that only the upwind
+        one-pass kernel runs (others fall back to the default shape)."""
+        L = _lib.load()
+        n = L.af_ctx_advance_shapes_upwind(self.h, None, None, 0)
+        ks = np.zeros(max(n, 1), np.int32)
+        nts = np.zeros(max(n, 1), np.int32)
+        L.af_ctx_advance_shapes_upwind(self.h, ks.ctypes.data_as(ctypes.c_void_p),
+                                       nts.ctypes.data_as(ctypes.c_void_p), n)
+        return [(int(k), int(t)) for k, t in zip(ks[:n], nts[:n])]
+
     def set_advance_shape(self, k, nt):
         check(_lib.load().af_ctx_set_advance_shape(self.h, int(k), int(nt)))
 

@@ -22,7 +22,7 @@ EXPORTS = [
     "af_hier_leaf_xy",
     "af_patch_step", "af_ghost_fill", "af_flux_correct", "af_regrid_tag", "af_hier_regrid",
     "af_regrid_apply", "af_reduce_sum", "af_reduce_sum_noalloc", "af_amr_coarse_step", "af_level_advance",
-    "af_ctx_advance_shapes", "af_ctx_set_advance_shape", "af_autotune",
+    "af_ctx_advance_shapes", "af_ctx_advance_shapes_upwind", "af_ctx_set_advance_shape", "af_autotune",
     "af_ctx_get_advance_shape",
     "af_cnn_last_error", "af_cnn_create", "af_cnn_destroy", "af_cnn_num_params", "af_cnn_set_params",
     "af_cnn_get_params", "af_cnn_set_normalization", "af_cnn_forward", "af_cnn_loss_grad",
@@ -105,6 +105,8 @@ def load():
     L.af_level_advance.argtypes = [P, P, S, ctypes.POINTER(ctypes.c_uint32), i32, D, i32, P]
     L.af_ctx_advance_shapes.argtypes = [P, P, P, i32]
     L.af_ctx_advance_shapes.restype = i32
+    L.af_ctx_advance_shapes_upwind.argtypes = [P, P, P, i32]
+    L.af_ctx_advance_shapes_upwind.restype = i32
     L.af_ctx_set_advance_shape.argtypes = [P, i32, i32]
     L.af_autotune.argtypes = [P, P, S, i32, D, i32, P, P, P]
     L.af_ctx_get_advance_shape.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -127,7 +129,8 @@ def load():
     for name in EXPORTS + PROBES:
         if name not in ("af_last_error", "af_hier_num_leaves", "af_ctx_get_tile", "af_ctx_get_fused_pairs",
                         "af_hier_finest_level",
-                        "af_hier_side_mask", "af_hier_leaf_xy", "af_ctx_advance_shapes", "af_cnn_last_error", "af_cnn_num_params"):
+                        "af_hier_side_mask", "af_hier_leaf_xy", "af_ctx_advance_shapes", "af_ctx_advance_shapes_upwind", "af_cnn_last_error",
+                        "af_cnn_num_params"):
             getattr(L, name).restype = ctypes.c_int
     _lib = L
     return L

@@ -877,6 +877,19 @@ int32_t af_ctx_advance_shapes(const af_ctx* ctx, int32_t* ks, int32_t* nts, int3
   return n;
 }
 
+int32_t af_ctx_advance_shapes_upwind(const af_ctx* ctx, int32_t* ks, int32_t* nts, int32_t cap) {
+  if (!ctx) return -1;
+  int k2[32], n2[32];
+  // the list with the upwind-only shapes holds the two-pass shapes first
+  const int two = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, k2, n2, 32, false);
+  const int all = level_advance_shapes(ctx->fp32(), ctx->P.eq, ctx->P.m, k2, n2, 32, true);
+  for (int i = two; i < all && i - two < cap; ++i) {
+    if (ks) ks[i - two] = k2[i];
+    if (nts) nts[i - two] = n2[i];
+  }
+  return all - two;
+}
+
 af_status af_level_advance(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* mask, int32_t level, double dt,
                            int32_t nsteps, hipStream_t stream) {
   if (!ctx || !h || !mask) return fail(AF_ERR_ARG, "null argument");

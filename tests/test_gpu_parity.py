@@ -166,10 +166,46 @@ def _shape_cases():
     for eq, prec, m in [(0, af.FP32, 32), (0, af.FP64, 32), (0, af.FP32, 16), (0, af.FP64, 16),
                         (1, af.FP32, 16), (1, af.FP64, 16), (1, af.FP32, 32)]:
         ctx = af.Context(make_problem(eq, prec, m, n0=4))
+        up_only = set(ctx.advance_shapes_upwind())
         for k, nt in ctx.advance_shapes():
-            for vel in (VELOCITY if eq == 0 else ["-"]):
+            # the upwind-only shapes run only with the upwind velocity (other
+            # weights fall back to the default shape: test_upwind_shape_fallback)
+            vels = ["-"] if eq != 0 else (["upwind"] if (k, nt) in up_only else list(VELOCITY))
+            for vel in vels:
                 cases.append((eq, prec, m, k, nt, vel))
     return cases
+
+
+@pytest.mark.parametrize("prec", [af.FP32, af.FP64], ids=["fp32", "fp64"])
+def test_upwind_shape_fallback(prec):
+    """An upwind-only shape with weights of another pattern: af_level_advance
+    launches the default shape instead, so the result equals the default
+    shape's bit for bit."""
+    torch = _torch()
+    m, n0 = 32, 4
+    prob = make_problem(0, prec, m, n0=n0, a=VELOCITY["mixed"][0], b=VELOCITY["mixed"][1])
+    ctx = af.Context(prob)
+    up_only = ctx.advance_shapes_upwind()
+    assert up_only, "no upwind-only shape compiled for this case"
+    assert set(up_only) <= set(ctx.advance_shapes())
+    data = afsynth.fourier_modes(6)
+    N = n0 * m
+    d0 = afsynth.dofs_periodic(data, N, N, nq=4)
+    blk = afsynth.periodic_to_blocks(d0, m)
+    blocks = [{kk: blk[kk][p] for kk in KINDS} for p in range(n0 * n0)]
+    dt = VELOCITY["mixed"][2] / (N * max(abs(prob.a), abs(prob.b)))
+    out = []
+    for shape in (up_only[-1], None):
+        c = af.Context(prob)
+        if shape is not None:
+            c.set_advance_shape(*shape)
+        h = af.Hierarchy(c, afsynth.uniform_leaves(n0, n0, 0))
+        b0 = af.blocks_to_state(c, blocks)
+        bufs = [b0, torch.zeros_like(b0)]
+        mask = c.level_advance(h, bufs, 0, 0, dt, 7)
+        torch.cuda.synchronize()
+        out.append(bufs[mask & 1].cpu())
+    assert torch.equal(out[0], out[1])
 
 
 @pytest.mark.parametrize("eq,prec,m,k,nt,vel", _shape_cases())
