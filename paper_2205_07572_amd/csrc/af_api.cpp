@@ -58,6 +58,9 @@ struct af_ctx {
   int part_cap = 0;
   // weights cache keyed by (dt/dx, dt/dy)
   std::map<std::pair<double, double>, std::vector<unsigned char>> wcache;
+  // device copies of the acoustic orbit weights (the batched step reads them
+  // through a pointer), keyed like wcache
+  std::map<std::pair<double, double>, void*> wdev;
 
   double dx(int l) const { return P.lx / double(P.n0x * P.m) / double(1 << l); }
   double dy(int l) const { return P.ly / double(P.n0y * P.m) / double(1 << l); }
@@ -195,6 +198,27 @@ const void* weights_for(af_ctx* c, double dtdx, double dtdy) {
   }
   auto res = c->wcache.emplace(key, std::move(buf));
   return res.first->second.data();
+}
+
+// The acoustic orbit weights of weights_for on the device (made on first use
+// of a key, outside any graph capture); null on a device error.
+const void* weights_dev_for(af_ctx* c, double dtdx, double dtdy) {
+  auto key = std::make_pair(dtdx, dtdy);
+  auto it = c->wdev.find(key);
+  if (it != c->wdev.end()) return it->second;
+  const void* host = weights_for(c, dtdx, dtdy);
+  if (!host || c->P.eq != AF_ACOUSTICS) return nullptr;
+  const void* src = c->fp32() ? static_cast<const void*>(&static_cast<const AcAllWeights<float>*>(host)->orbit)
+                              : static_cast<const void*>(&static_cast<const AcAllWeights<double>*>(host)->orbit);
+  const size_t bytes = c->fp32() ? sizeof(AcOrbitWeights<float>) : sizeof(AcOrbitWeights<double>);
+  void* d = nullptr;
+  if (hipMalloc(&d, bytes) != hipSuccess) return nullptr;
+  if (hipMemcpy(d, src, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+    (void)hipFree(d);
+    return nullptr;
+  }
+  c->wdev.emplace(key, d);
+  return d;
 }
 
 BufLaunch make_buf(const af_ctx* c, const af_state* b0, const af_state* b1, uint32_t mask) {
@@ -344,6 +368,7 @@ af_status af_ctx_destroy(af_ctx* ctx) {
   (void)hipFree(ctx->d_bnd);
   (void)hipFree(ctx->d_fillw);
   (void)hipFree(ctx->d_part);
+  for (auto& w : ctx->wdev) (void)hipFree(w.second);
   delete ctx;
   return AF_OK;
 }
@@ -1179,6 +1204,8 @@ struct Driver {
     L.gnflags = h->d_gnflags;
     L.weights = weights_for(ctx, L.dtdx, L.dtdy);
     if (!L.weights) return fail(AF_ERR_STATE, "acoustic stencils lack their mirror symmetry");
+    if (ctx->P.eq == AF_ACOUSTICS && !(L.weights_dev = weights_dev_for(ctx, L.dtdx, L.dtdy)))
+      return fail(AF_ERR_DEVICE, "acoustic weight upload failed");
     L.pair = pair_;  // level F (the last here, region layer 1 at even tau) takes its pair
     const bool timed = ev && nev < max_ev;
     if (timed) AF_HIP(hipEventRecord(ev[2 * nev], st));
@@ -1302,6 +1329,8 @@ af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* 
     for (int l = 0; l <= h->H.finest; ++l) {
       const double dtl = global ? dt0 : dt0 / (1 << l);
       if (ctx->P.eq == AF_ADVECTION || ctx->P.eq == AF_ACOUSTICS) weights_for(ctx, dtl / ctx->dx(l), dtl / ctx->dy(l));
+      if (ctx->P.eq == AF_ACOUSTICS && !global && !weights_dev_for(ctx, dtl / ctx->dx(l), dtl / ctx->dy(l)))
+        return fail(AF_ERR_DEVICE, "acoustic weight upload failed");
       if ((s = fill_plan(ctx, h, l, stream)) != AF_OK) return s;
     }
     hipStream_t cs;

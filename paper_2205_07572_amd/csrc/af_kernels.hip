@@ -590,8 +590,9 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
   if constexpr (EQ == 1 && (sizeof(T) == 4 || TO_LDS)) {
     // acoustics (eq. ERFormula), FP32: one node kind at a time over the
     // thread's cells, each node from its neighbourhood orbit by orbit.  The
-    // kind's orbit weights stay in scalar registers for the whole pass and
-    // the kernel needs 91 VGPRs, not 126 (5 waves per SIMD, not 4).  In FP64
+    // kind's orbit weights (42 for a corner, 26 for an edge) fit in scalar
+    // registers for the whole pass and the kernel needs about 90 VGPRs, not
+    // 126 (5 waves per SIMD, not 4).  In FP64
     // the kernel holds 2 waves per SIMD either way, and the three nodes of a
     // cell together give each wave more independent work (the first substep
     // of a fused pair goes kind by kind in FP64 too: it also holds the new
@@ -1954,8 +1955,25 @@ __device__ __forceinline__ T planned_value(T* const (&p)[2][4], uint32_t mask, i
   return T(v);
 }
 
+// The stencil weights a batched step reads: acoustics through wdev, the
+// advection weights (the kernel argument) as they are.  As a kernel argument
+// the acoustic table is loaded into scalar registers at entry, more than
+// there are, and the compiler parked the rest in vector lanes (a quarter of
+// the node phase's vector instructions were lane reads).  Through a
+// read-only pointer argument each node kind's weights are scalar loads where
+// the kind is evaluated.
+template <typename T, int EQ>
+__device__ __forceinline__ const typename WSel<T, EQ>::type& amr_weights(const AcOrbitWeights<T>* wdev,
+                                                                        const typename WSel<T, EQ>::type& W) {
+  if constexpr (EQ == 1)
+    return *wdev;
+  else
+    return W;
+}
+
 template <typename T, int EQ, int M, int TY, bool PAIR>
-__global__ __launch_bounds__(kThreads) void k_amr_step(const AmrStepArgs<T> A, const typename WSel<T, EQ>::type W) {
+__global__ __launch_bounds__(kThreads) void k_amr_step(const AmrStepArgs<T> A, const typename WSel<T, EQ>::type W,
+                                                       const AcOrbitWeights<T>* __restrict__ wdev) {
   static_assert(EQ == 0 || EQ == 1, "constant-coefficient equations only");
   static_assert(!PAIR || TY >= M + 2, "a fused pair steps the whole layer-1 region in one block");
   constexpr int NCOMP = EQ == 1 ? 3 : 1;
@@ -2086,13 +2104,13 @@ __global__ __launch_bounds__(kThreads) void k_amr_step(const AmrStepArgs<T> A, c
     // same-level neighbour's interior is the same arithmetic on the same
     // data.
     if constexpr (PAIR) {
-      step_compute<T, EQ, M, TY, true>(L, io, W, jlo, jhi, T(0), T(0));
+      step_compute<T, EQ, M, TY, true>(L, io, amr_weights<T, EQ>(wdev, W), jlo, jhi, T(0), T(0));
       __syncthreads();
       io.region = 0;  // interior
-      step_compute<T, EQ, M, TY>(L, io, W, 0, M, T(0), T(0), -jlo);
+      step_compute<T, EQ, M, TY>(L, io, amr_weights<T, EQ>(wdev, W), 0, M, T(0), T(0), -jlo);
     }
   } else {
-    step_compute<T, EQ, M, TY>(L, io, W, jlo, jhi, T(0), T(0));
+    step_compute<T, EQ, M, TY>(L, io, amr_weights<T, EQ>(wdev, W), jlo, jhi, T(0), T(0));
   }
 }
 
@@ -2498,8 +2516,9 @@ static hipError_t launch_amr_t(const AmrStepLaunch& s, hipStream_t st) {
   A.nbr = s.nbr;
   A.gnflags = s.gnflags;
   A.pair = PAIR && s.pair;
+  const auto* wdev = static_cast<const AcOrbitWeights<T>*>(s.weights_dev);
   const auto& W = step_weights<T, EQ>(s.weights);
-  hipLaunchKernelGGL((k_amr_step<T, EQ, M, TY, PAIR>), dim3(unsigned(blocks)), dim3(kThreads), 0, st, A, W);
+  hipLaunchKernelGGL((k_amr_step<T, EQ, M, TY, PAIR>), dim3(unsigned(blocks)), dim3(kThreads), 0, st, A, W, wdev);
   return hipGetLastError();
 }
 

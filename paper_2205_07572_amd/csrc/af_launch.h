@@ -61,6 +61,7 @@ struct AmrStepLaunch {
   const int32_t* nbr;
   const uint32_t* gnflags;
   const void* weights;  // AdvWeights<T> or AcAllWeights<T>
+  const void* weights_dev;  // acoustics: AcOrbitWeights<T> on the device
   // the last level (the finest, region layer 1) takes both substeps of its
   // pair in one block (m = 8 or 16; whole-patch tiles)
   bool pair;
