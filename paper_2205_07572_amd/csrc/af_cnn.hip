@@ -49,6 +49,13 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(uint3
 // blockIdx.z splits K into chunks (multiples of 32); chunk z writes its
 // partial product to part[z][i][j] and k_sum_chunks adds the chunks in
 // order, so the result does not depend on scheduling.
+// A lane's 8 values of one operand are one 16-byte load where they are
+// contiguous and aligned (unit k stride, row stride a multiple of 8, K a
+// multiple of 8, so that a group of 8 lies wholly inside or outside
+// [0, K)); else 8 element loads.  With X set, A is the im2col matrix of the
+// BF16 NHWC images X (cp channels, cp a multiple of 8), read in place: the
+// 8 values of a lane are 8 channels of one pixel of one tap, zero outside
+// the image.
 // ---------------------------------------------------------------------------
 struct GemmArgs {
   const uint16_t* A;
@@ -59,6 +66,9 @@ struct GemmArgs {
   long sci, scj;
   int M, N, K, kchunk;
   float* part;  // [nz][M][N] when K is split, else null
+  const uint16_t* X = nullptr;  // implicit im2col source (then A is unused)
+  int cp = 0;
+  int avec = 0, bvec = 0;       // set by gemm(): 16-byte loads for A, B
 };
 
 __global__ __launch_bounds__(256) void k_gemm_bf16(const GemmArgs g) {
@@ -71,14 +81,36 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(const GemmArgs g) {
   const int kb = blockIdx.z * g.kchunk;
   const int ke = min(g.K, kb + g.kchunk);
   f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const u16x8 zero8 = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int k0 = kb; k0 < ke; k0 += 32) {
     u16x8 a, b;
+    const int ks = k0 + 8 * (lane >> 4);  // this lane's first k
+    if (g.X) {
+      a = zero8;
+      if (ks < ke && i < g.M) {
+        const int tap = ks / g.cp, ci = ks - tap * g.cp;
+        const int bi = i / kPix, p = i - bi * kPix;
+        const int y = p / kImg + tap / 3 - 1, x = p % kImg + tap % 3 - 1;
+        if (y >= 0 && y < kImg && x >= 0 && x < kImg)
+          a = *reinterpret_cast<const u16x8*>(g.X + (long(bi) * kPix + y * kImg + x) * g.cp + ci);
+      }
+    } else if (g.avec) {
+      a = (ks < ke && i < g.M) ? *reinterpret_cast<const u16x8*>(g.A + i * g.sai + ks) : zero8;
+    } else {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int k = k0 + 8 * (lane >> 4) + e;
-      const bool kin = k < ke;
-      a[e] = (kin && i < g.M) ? g.A[i * g.sai + k * g.sak] : uint16_t(0);
-      b[e] = (kin && j < g.N) ? g.B[j * g.sbj + k * g.sbk] : uint16_t(0);
+      for (int e = 0; e < 8; ++e) {
+        const int k = ks + e;
+        a[e] = (k < ke && i < g.M) ? g.A[i * g.sai + k * g.sak] : uint16_t(0);
+      }
+    }
+    if (g.bvec) {
+      b = (ks < ke && j < g.N) ? *reinterpret_cast<const u16x8*>(g.B + j * g.sbj + ks) : zero8;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int k = ks + e;
+        b[e] = (k < ke && j < g.N) ? g.B[j * g.sbj + k * g.sbk] : uint16_t(0);
+      }
     }
     acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
                                                   acc, 0, 0, 0);
@@ -114,6 +146,10 @@ int gemm_chunks(long K, int ksplit) {
 // ws: workspace of at least nz * M * N floats when ksplit > 1.
 static hipError_t gemm(const GemmArgs& g0, int ksplit, float* ws, hipStream_t st) {
   GemmArgs g = g0;
+  auto al16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+  g.avec = !g.X && g.sak == 1 && g.sai % 8 == 0 && g.K % 8 == 0 && al16(g.A);
+  g.bvec = g.sbk == 1 && g.sbj % 8 == 0 && g.K % 8 == 0 && al16(g.B);
+  if (g.X && (g.cp % 8 != 0 || g.K != 9 * g.cp || !al16(g.X))) return hipErrorInvalidValue;
   const int tiles = ((g.M + 15) / 16) * ((g.N + 15) / 16);
   const int kc = ((g.K + ksplit - 1) / ksplit + 31) / 32 * 32;
   g.kchunk = kc;
@@ -148,6 +184,17 @@ __global__ void k_im2col(const float* xf, const uint16_t* xb, int B, int c, int 
       else v = xb[(long(b) * kPix + y * kImg + x) * cp + ci];
     }
     col[e] = v;
+  }
+}
+
+// X(b, c, y, x) FP32 NCHW -> BF16 NHWC with cp >= c channels (zero-padded)
+__global__ void k_to_nhwc(const float* xf, int B, int c, int cp, uint16_t* xb) {
+  const long total = long(B) * kPix * cp;
+  for (long e = blockIdx.x * long(blockDim.x) + threadIdx.x; e < total; e += long(gridDim.x) * blockDim.x) {
+    const int ci = int(e % cp);
+    const long bp = e / cp;
+    const int b = int(bp / kPix), p = int(bp - long(b) * kPix);
+    xb[e] = ci < c ? f2bf(xf[(long(b) * c + ci) * kPix + p]) : uint16_t(0);
   }
 }
 
@@ -455,18 +502,33 @@ af_status pack_weights(af_cnn* c, hipStream_t st) {
   return AF_OK;
 }
 
-af_status forward(af_cnn* c, const float* x, int B, hipStream_t st) {
+// With cols (training), each layer's im2col matrix is written to d_col[l]
+// (the weight gradient reads it); without (inference), the input is
+// converted once to BF16 NHWC and every layer's GEMM reads its im2col
+// matrix in place from the NHWC images.  Both give the same products in the
+// same k order, bit for bit.
+af_status forward(af_cnn* c, const float* x, int B, hipStream_t st, bool cols = true) {
   af_status s = ensure_batch(c, B);
   if (s != AF_OK) return s;
   if ((s = pack_weights(c, st)) != AF_OK) return s;
   const long M = long(B) * kPix;
+  if (!cols) {
+    // layer-0 input as BF16 NHWC with cp1 channels (d_col[0] holds 9x that)
+    hipLaunchKernelGGL(k_to_nhwc, dim3(grid_for(M * c->cp1)), dim3(256), 0, st, x, B, c->nin, c->cp1, c->d_col[0]);
+    CNN_HIP(hipGetLastError());
+  }
   for (int l = 0; l < 3; ++l) {
     const int cp = l == 0 ? c->cp1 : kWidth;
     const int K = 9 * cp;
-    hipLaunchKernelGGL(k_im2col, dim3(grid_for(M * K)), dim3(256), 0, st, l == 0 ? x : nullptr,
-                       l == 0 ? nullptr : c->d_ab[l - 1], B, l == 0 ? c->nin : kWidth, cp, c->d_col[l]);
-    CNN_HIP(hipGetLastError());
     GemmArgs g{c->d_col[l], K, 1, c->d_wm[l], K, 1, c->d_z[l], kWidth, 1, int(M), kWidth, K, 0, nullptr};
+    if (cols) {
+      hipLaunchKernelGGL(k_im2col, dim3(grid_for(M * K)), dim3(256), 0, st, l == 0 ? x : nullptr,
+                         l == 0 ? nullptr : c->d_ab[l - 1], B, l == 0 ? c->nin : kWidth, cp, c->d_col[l]);
+      CNN_HIP(hipGetLastError());
+    } else {
+      g.X = l == 0 ? c->d_col[0] : c->d_ab[l - 1];
+      g.cp = cp;
+    }
     CNN_HIP(gemm(g, 1, nullptr, st));
     hipLaunchKernelGGL(k_bias_relu, dim3(grid_for(M * kWidth)), dim3(256), 0, st, c->d_z[l],
                        c->d_params + c->off_b[l], M, c->d_ab[l], l == 2 ? c->d_a3 : nullptr);
@@ -572,7 +634,7 @@ af_status af_cnn_set_normalization(af_cnn* c, const float* mean, const float* in
 
 af_status af_cnn_forward(af_cnn* c, const float* x, int32_t B, float* logits, float* acts, hipStream_t st) {
   if (!c || !x || !logits || B <= 0) return cfail(AF_ERR_ARG, "bad argument");
-  af_status s = forward(c, x, B, st);
+  af_status s = forward(c, x, B, st, false);
   if (s != AF_OK) return s;
   hipLaunchKernelGGL(k_head, dim3((B + 7) / 8), dim3(256), 0, st, c->d_a3, B, c->d_params + c->off_wh,
                      c->d_params + c->off_bh, logits, nullptr, nullptr, nullptr);
