@@ -104,6 +104,7 @@ struct af_hier {
   // ghost-fill plans per lowest source level (built on first use)
   std::vector<int4*> d_plan;
   std::vector<uint32_t*> d_plan_flags;
+  std::vector<int4*> d_canon_ops;  // per source bound: the vertex copies of k_amr_sync
   // with the plan of source bound 0: same-level neighbours [n][9] and the
   // directions the batched step stages by a same-level gather [n]
   int32_t* d_nbr = nullptr;
@@ -453,6 +454,7 @@ af_status af_hier_destroy(af_hier* h) {
   (void)hipFree(h->d_faces);
   for (int4* p : h->d_plan) (void)hipFree(p);
   for (uint32_t* p : h->d_plan_flags) (void)hipFree(p);
+  for (int4* p : h->d_canon_ops) (void)hipFree(p);
   (void)hipFree(h->d_nbr);
   (void)hipFree(h->d_gnflags);
   (void)hipFree(h->d_impure);
@@ -636,6 +638,7 @@ af_status fill_plan(af_ctx* ctx, af_hier* h, int smin, hipStream_t stream) {
   if (int(h->d_plan.size()) <= h->H.lmax) {
     h->d_plan.resize(h->H.lmax + 1, nullptr);
     h->d_plan_flags.resize(h->H.lmax + 1, nullptr);
+    h->d_canon_ops.resize(h->H.lmax + 1, nullptr);
   }
   if (h->d_plan[smin]) return AF_OK;
   af_status s;
@@ -656,6 +659,16 @@ af_status fill_plan(af_ctx* ctx, af_hier* h, int smin, hipStream_t stream) {
   }
   AF_HIP(launch_fill_plan(h->dev, ctx->d_entries, ctx->nentries, ctx->P.m, smin, plan, flags,
                           smin == 0 ? h->d_nbr : nullptr, smin == 0 ? h->d_gnflags : nullptr, stream));
+  // the batched step's vertex copies for this bound, resolved from the plan
+  const int ncanon = int(h->impure.size()) - h->impure_off[smin];
+  const int nbnd = int(ctx->h_bnd.size());
+  if (ncanon > 0 && nbnd > 0) {
+    int4* ops = nullptr;
+    AF_HIP(hipMalloc(&ops, size_t(ncanon) * nbnd * sizeof(int4)));
+    h->d_canon_ops[smin] = ops;
+    AF_HIP(launch_canon_ops(plan, ctx->d_entries, ctx->nentries, ctx->d_bnd, nbnd, h->d_impure + h->impure_off[smin],
+                            ncanon, h->d_level, ops, stream));
+  }
   return AF_OK;
 }
 
@@ -1139,16 +1152,11 @@ struct Driver {
     S.fp32 = ctx->fp32();
     S.b = make_buf(ctx, &bufs[0], &bufs[1], mask);
     S.plevel = h->d_level;
-    S.entries = ctx->d_entries;
-    S.bnd = ctx->d_bnd;
-    S.nentries = ctx->nentries;
-    S.nbnd = int(ctx->h_bnd.size());
     S.reg = reg;
     S.inv_area0 = 1.0 / (ctx->dx(0) * ctx->dy(0));
-    if (smin >= 0 && smin <= F) {
-      S.canon = h->d_impure + h->impure_off[smin];
-      S.ncanon = int(h->impure.size()) - h->impure_off[smin];
-      S.plan = h->d_plan[smin];
+    if (smin >= 0 && smin <= F && h->d_canon_ops[smin]) {
+      S.cops = h->d_canon_ops[smin];
+      S.ncops = (int(h->impure.size()) - h->impure_off[smin]) * int(ctx->h_bnd.size());
     }
     if (fix_lo <= fix_hi) {
       const int off = h->face_off[fix_lo];

@@ -2127,12 +2127,8 @@ template <typename T>
 struct AmrSyncArgs {
   Bufs<T> B;
   const int32_t* plevel;
-  const int32_t* canon;
-  int32_t ncanon;
-  const int4* plan;
-  const int32_t* entries;
-  const int32_t* bnd;       // indices of the fill-set entries that are closed-square boundary nodes
-  int32_t nentries, nbnd;
+  const int4* cops;         // the vertex copies (k_canon_ops), ncops of them
+  int32_t ncops;
   const CFFace* faces;
   int32_t nfaces;
   double* reg;
@@ -2180,25 +2176,51 @@ __device__ void reflux_face_group(const Bufs<T>& B, const CFFace* faces, int nfa
 template <typename T>
 __global__ __launch_bounds__(kThreads) void k_amr_sync(const AmrSyncArgs<T> A) {
   const Bufs<T>& B = A.B;
-  if (int(blockIdx.x) < A.ncanon) {
-    const int t = A.canon[blockIdx.x];
-    const int lt = A.plevel[t];
+  const int cblocks = (A.ncops + kThreads - 1) / kThreads;
+  if (int(blockIdx.x) < cblocks) {
+    const int e = int(blockIdx.x) * kThreads + int(threadIdx.x);
+    if (e >= A.ncops) return;
+    const int4 op = A.cops[e];
+    if (op.x < 0) return;  // the leaf owns this node
+    const int di = (op.z & 0xff) - kGhost, dj = ((op.z >> 8) & 0xff) - kGhost;
+    const int kind = (op.z >> 16) & 3, lt = (op.z >> 20) & 15, skind = (op.z >> 24) & 3, ls = (op.z >> 28) & 15;
+    const int si = (op.w & 0xffff) - kGhost, sj = (op.w >> 16) - kGhost;
     const size_t cstride = size_t(B.npatch) * (B.m + 5) * B.pitch;
-    for (int e = threadIdx.x; e < A.nbnd; e += kThreads) {
-      const int ent = A.bnd[e];
-      const int4 op = A.plan[size_t(t) * A.nentries + ent];
-      if (op.x < 0) continue;  // the leaf owns this node
-      const int32_t code = A.entries[ent];
-      const int kind = code >> 24, i = ((code >> 12) & 0xfff) - kGhost, j = (code & 0xfff) - kGhost;
-      const int skind = (op.y >> 2) & 3, ls = (op.y >> 4) & 15;
-      T* const dst = buf_of(B, lt, kind) + at(B, 0, t, i, j);
-      const T* const src = buf_of(B, ls, skind) + at(B, 0, op.x, op.z, op.w);
-      for (int q = 0; q < B.ncomp; ++q) dst[q * cstride] = src[q * cstride];
-    }
+    T* const dst = buf_of(B, lt, kind) + at(B, 0, op.x, di, dj);
+    const T* const src = buf_of(B, ls, skind) + at(B, 0, op.y, si, sj);
+    for (int q = 0; q < B.ncomp; ++q) dst[q * cstride] = src[q * cstride];
     return;
   }
-  const int f = (int(blockIdx.x) - A.ncanon) * kThreads + int(threadIdx.x);
+  const int f = (int(blockIdx.x) - cblocks) * kThreads + int(threadIdx.x);
   if (f < A.nfaces) reflux_face_group(B, A.faces, A.nfaces, f, A.reg, A.plevel, A.inv_area0);
+}
+
+// The fill's vertex copies onto the closed-square boundary nodes of the
+// leaves canon[0 .. ncanon), resolved once per hierarchy and source bound
+// from the fill plan into ops[k * nbnd + b] (boundary entry b of leaf
+// canon[k]): x = target leaf (-1: the leaf owns the node), y = source leaf,
+// z = target column | row << 8 (both + kGhost) | kind << 16 | target level
+// << 20 | source kind << 24 | source level << 28, w = source column |
+// row << 16 (both + kGhost).  k_amr_sync then copies with one op load and
+// one source load per node.
+__global__ void k_canon_ops(const int4* plan, const int32_t* entries, int nentries, const int32_t* bnd, int nbnd,
+                            const int32_t* canon, int ncanon, const int32_t* plevel, int4* ops) {
+  const long n = long(ncanon) * nbnd;
+  for (long e = blockIdx.x * long(blockDim.x) + threadIdx.x; e < n; e += long(gridDim.x) * blockDim.x) {
+    const int k = int(e / nbnd), b = int(e - long(k) * nbnd);
+    const int t = canon[k];
+    const int ent = bnd[b];
+    const int4 op = plan[size_t(t) * nentries + ent];
+    int4 r = make_int4(-1, 0, 0, 0);
+    if (op.x >= 0) {
+      const int32_t code = entries[ent];
+      const int kind = code >> 24, i = (code >> 12) & 0xfff, j = code & 0xfff;  // + kGhost
+      const int skind = (op.y >> 2) & 3, ls = (op.y >> 4) & 15;
+      r = make_int4(t, op.x, i | (j << 8) | (kind << 16) | (plevel[t] << 20) | (skind << 24) | (ls << 28),
+                    (op.z + kGhost) | ((op.w + kGhost) << 16));
+    }
+    ops[e] = r;
+  }
 }
 
 template <typename T>
@@ -2558,18 +2580,13 @@ static hipError_t launch_sync_t(const AmrSyncLaunch& s, hipStream_t st) {
   AmrSyncArgs<T> A;
   A.B = make_bufs<T>(s.b);
   A.plevel = s.plevel;
-  A.canon = s.canon;
-  A.ncanon = s.ncanon;
-  A.plan = s.plan;
-  A.entries = s.entries;
-  A.bnd = s.bnd;
-  A.nentries = s.nentries;
-  A.nbnd = s.nbnd;
+  A.cops = s.cops;
+  A.ncops = s.ncops;
   A.faces = s.faces;
   A.nfaces = s.nfaces;
   A.reg = s.reg;
   A.inv_area0 = s.inv_area0;
-  const int blocks = s.ncanon + (s.nfaces + kThreads - 1) / kThreads;
+  const int blocks = (s.ncops + kThreads - 1) / kThreads + (s.nfaces + kThreads - 1) / kThreads;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(k_amr_sync<T>, dim3(unsigned(blocks)), dim3(kThreads), 0, st, A);
   return hipGetLastError();
@@ -2577,6 +2594,15 @@ static hipError_t launch_sync_t(const AmrSyncLaunch& s, hipStream_t st) {
 
 hipError_t launch_amr_sync(const AmrSyncLaunch& s, hipStream_t st) {
   return s.fp32 ? launch_sync_t<float>(s, st) : launch_sync_t<double>(s, st);
+}
+
+hipError_t launch_canon_ops(const int4* plan, const int32_t* entries, int nentries, const int32_t* bnd, int nbnd,
+                            const int32_t* canon, int ncanon, const int32_t* plevel, int4* ops, hipStream_t st) {
+  const long n = long(ncanon) * nbnd;
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_canon_ops, dim3(unsigned(std::min<long>((n + kThreads - 1) / kThreads, 4096))),
+                     dim3(kThreads), 0, st, plan, entries, nentries, bnd, nbnd, canon, ncanon, plevel, ops);
+  return hipGetLastError();
 }
 
 bool step_shape_supported(int m, int ty) {

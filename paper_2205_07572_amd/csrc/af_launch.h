@@ -76,18 +76,18 @@ struct AmrSyncLaunch {
   bool fp32;
   BufLaunch b;
   const int32_t* plevel;
-  const int32_t* canon;
-  int ncanon;
-  const int4* plan;
-  const int32_t* entries;
-  const int32_t* bnd;
-  int nentries, nbnd;
+  const int4* cops;  // vertex copies (launch_canon_ops)
+  int ncops;
   const CFFace* faces;
   int nfaces;
   double* reg;
   double inv_area0;
 };
 hipError_t launch_amr_sync(const AmrSyncLaunch& s, hipStream_t st);
+// Resolves the vertex copies of the leaves canon[0 .. ncanon) (boundary
+// entries bnd of the fill set) from the fill plan into ncanon * nbnd ops.
+hipError_t launch_canon_ops(const int4* plan, const int32_t* entries, int nentries, const int32_t* bnd, int nbnd,
+                            const int32_t* canon, int ncanon, const int32_t* plevel, int4* ops, hipStream_t st);
 
 hipError_t launch_patch_step(const StepLaunch& s, hipStream_t st);
 hipError_t launch_level_advance(const AdvanceLaunch& s, hipStream_t st);
