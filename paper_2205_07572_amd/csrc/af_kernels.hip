@@ -1887,6 +1887,10 @@ __global__ __launch_bounds__(kThreads) void k_fill_apply(const FillArgs<T> A) {
 // to the finer leaf's vertices first (the second fill phase); k_amr_sync does
 // that copy, together with the conservative fix of the levels that just
 // completed a pair of fine substeps, before the launch.
+//
+// With fused pairs the launches are those of the even time points, and the
+// finest level's block there also takes the odd time point's substep (see
+// the pair branch of k_amr_step).
 // ---------------------------------------------------------------------------
 
 template <typename T>
