@@ -114,10 +114,13 @@ __device__ __forceinline__ int xcd_patch(int b, int n) {
 // kLdsAlias: the update reads only the averages and the sums, so the sums
 // overwrite the staged node values once every node is evaluated; the block
 // then holds 4 NCOMP NR NC values, not 7 NCOMP NR NC, and more blocks fit on
-// a CU.  kLdsPair: separate sums; the first of a fused pair of substeps puts
-// its new node values and averages back in place of the staged ones, where
-// the second substep reads them.  kLdsSwirl: separate sums, and the swirl's
-// values at t+dt (tsum2); its update also reads the nodes at t.
+// a CU.  The first of a fused pair of substeps uses it too in FP32: its new
+// node values wait in registers until the update is done and then replace
+// the sums.  kLdsPair: separate sums, for the FP64 fused pair, whose
+// registers, not its LDS, already limit it to 2 blocks per CU: its new node
+// values go in place of the staged ones with the sums, one barrier earlier.
+// kLdsSwirl: separate sums, and the swirl's values at t+dt (tsum2); its
+// update also reads the nodes at t.
 enum StepLdsKind { kLdsAlias, kLdsPair, kLdsSwirl };
 
 template <typename T, int NCOMP, int NR, int NC, int KIND>
@@ -125,7 +128,7 @@ struct StepLds;
 
 template <typename T, int NCOMP, int NR, int NC>
 struct StepLds<T, NCOMP, NR, NC, kLdsAlias> {
-  using TS = T[3][NCOMP][NR - 2][NC - 2];
+  using TS = T[3][NCOMP][NR - 2][NC];
   static constexpr bool kSeparate = false;
   T in[4][NCOMP][NR][NC];
   __device__ __forceinline__ TS& tsum() { return *reinterpret_cast<TS*>(&in[1][0][0][0]); }
@@ -134,7 +137,7 @@ struct StepLds<T, NCOMP, NR, NC, kLdsAlias> {
 
 template <typename T, int NCOMP, int NR, int NC>
 struct StepLds<T, NCOMP, NR, NC, kLdsPair> {
-  using TS = T[3][NCOMP][NR - 2][NC - 2];
+  using TS = T[3][NCOMP][NR - 2][NC];
   static constexpr bool kSeparate = true;
   T in[4][NCOMP][NR][NC];
   TS ts;
@@ -144,7 +147,7 @@ struct StepLds<T, NCOMP, NR, NC, kLdsPair> {
 
 template <typename T, int NCOMP, int NR, int NC>
 struct StepLds<T, NCOMP, NR, NC, kLdsSwirl> {
-  using TS = T[3][NCOMP][NR - 2][NC - 2];
+  using TS = T[3][NCOMP][NR - 2][NC];
   static constexpr bool kSeparate = true;
   T in[4][NCOMP][NR][NC];
   TS ts, ts2;
@@ -406,13 +409,15 @@ struct StepIO {
 };
 
 // TO_LDS: the first substep of a fused pair (no HBM output): new node values
-// and averages replace the staged ones in L.in.  rofs: staged row of cell row
-// j is j - jlo + 1 + rofs (the pair's second substep reads the first's rows).
+// and averages replace the staged ones in L.in.  With the sums aliased onto
+// the staged nodes the node values go in after the update, which reads the
+// sums from where they will be stored; with separate sums, beside them.
+// rofs: staged row of cell row j is j - jlo + 1 + rofs (the pair's second
+// substep reads the first's rows).
 template <typename T, int EQ, int M, int TY, bool TO_LDS = false, typename L_t>
 __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const typename WSel<T, EQ>::type& W,
                                              int jlo, int jhi, T px0, T py0, int rofs = 0) {
-  static_assert(!TO_LDS || (L_t::kSeparate && (EQ == 0 || EQ == 1)),
-                "a fused pair needs separate time sums and a constant-coefficient equation");
+  static_assert(!TO_LDS || EQ == 0 || EQ == 1, "a fused pair needs a constant-coefficient equation");
   constexpr int NCOMP = EQ == 1 ? 3 : 1;
   constexpr int NR = TY + 3;
   constexpr int NC = M + 5;
@@ -434,8 +439,15 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
       shared_src = shared_src && W.off[kind][0][0] == W.off[kind][1][0] && W.off[kind][0][1] == W.off[kind][1][1];
   }
   // the extended cells of a thread: at most MAXIT (region <= 1, nrow <= TY);
-  // their time sums wait in registers until every node is evaluated
-  constexpr int MAXIT = ((M + 3) * (TY + 1) + kThreads - 1) / kThreads;
+  // their time sums wait in registers until every node is evaluated.  The
+  // FP32 acoustic node pass walks rows of the LDS pitch NC (the columns past
+  // EC idle): the 64 lanes of a wave then read 64 consecutive LDS words at
+  // every stencil point, free of bank conflicts (rows of EC on a pitch of NC
+  // wrap onto the banks of the wave's first lanes).  The time sums are
+  // stored on the same pitch.
+  constexpr bool kWide = EQ == 1 && sizeof(T) == 4;
+  const int WN = kWide ? NC : EC;
+  constexpr int MAXIT = ((kWide ? M + 5 : M + 3) * (TY + 1) + kThreads - 1) / kThreads;
   T tsv[MAXIT][3][NCOMP];
   T nv[TO_LDS ? MAXIT : 1][3][NCOMP];  // TO_LDS: the new node values, stored after the barrier
   // a new node value: to HBM (if `keep`, the rows and columns this tile
@@ -447,10 +459,11 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
       if (keep) A.out[kind + 1][o] = v;
     }
   };
-  Walk2 w(threadIdx.x, kThreads, EC);
+  Walk2 w(threadIdx.x, kThreads, WN);
 #pragma unroll
   for (int it = 0; it < MAXIT; ++it, w.next()) {
     if (w.y >= ER) break;
+    if (kWide && w.x >= EC) continue;
     const int ii = w.x, jj = w.y;
     const int i = ilo + ii, j = jlo + jj;
     const int r = jj + 1 + rofs, c = ii + coff;  // staged position of cell (i,j)
@@ -599,10 +612,11 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
     // node values).
     auto kind_pass = [&](auto kc) {
       constexpr int K = decltype(kc)::value;
-      Walk2 v(threadIdx.x, kThreads, EC);
+      Walk2 v(threadIdx.x, kThreads, WN);
 #pragma unroll
       for (int it = 0; it < MAXIT; ++it, v.next()) {
         if (v.y >= ER) break;
+        if (kWide && v.x >= EC) continue;
         const int ii = v.x, jj = v.y;
         if (K == NK_XEDGE && jj >= nrow) continue;  // x-edges of rows [jlo, jhi)
         if (K == NK_YEDGE && ii >= span) continue;  // y-edges of cols [ilo, ihi)
@@ -625,18 +639,19 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
   __syncthreads();
   auto& ts = L.tsum();
   {
-    Walk2 v(threadIdx.x, kThreads, EC);
+    Walk2 v(threadIdx.x, kThreads, WN);
 #pragma unroll
     for (int it = 0; it < MAXIT; ++it, v.next()) {
       if (v.y >= ER) break;
+      if (kWide && v.x >= EC) continue;
       const int ii = v.x, jj = v.y;
-      const int r = jj + 1 + rofs, c = ii + coff;
 #pragma unroll
       for (int q = 0; q < NCOMP; ++q) {
         ts[NK_CORNER][q][jj][ii] = tsv[it][NK_CORNER][q];
         if (jj < nrow) ts[NK_XEDGE][q][jj][ii] = tsv[it][NK_XEDGE][q];
         if (ii < span) ts[NK_YEDGE][q][jj][ii] = tsv[it][NK_YEDGE][q];
-        if constexpr (TO_LDS) {
+        if constexpr (TO_LDS && L_t::kSeparate) {
+          const int r = jj + 1 + rofs, c = ii + coff;
           L.in[1][q][r][c] = nv[it][NK_CORNER][q];
           if (jj < nrow) L.in[2][q][r][c] = nv[it][NK_XEDGE][q];
           if (ii < span) L.in[3][q][r][c] = nv[it][NK_YEDGE][q];
@@ -761,6 +776,24 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
           if (j == 0 && (smask & 4)) R[(2 * M + i) * NCOMP + q] += double(gB[q]) * A.len_dt_y;
           if (j == M - 1 && (smask & 8)) R[(3 * M + i) * NCOMP + q] += double(gT[q]) * A.len_dt_y;
         }
+      }
+    }
+  }
+  if constexpr (TO_LDS && !L_t::kSeparate) {
+    // the new node values of the extended cells, over the time sums
+    __syncthreads();
+    Walk2 v(threadIdx.x, kThreads, WN);
+#pragma unroll
+    for (int it = 0; it < MAXIT; ++it, v.next()) {
+      if (v.y >= ER) break;
+      if (kWide && v.x >= EC) continue;
+      const int ii = v.x, jj = v.y;
+      const int r = jj + 1 + rofs, c = ii + coff;
+#pragma unroll
+      for (int q = 0; q < NCOMP; ++q) {
+        L.in[1][q][r][c] = nv[it][NK_CORNER][q];
+        if (jj < nrow) L.in[2][q][r][c] = nv[it][NK_XEDGE][q];
+        if (ii < span) L.in[3][q][r][c] = nv[it][NK_YEDGE][q];
       }
     }
   }
@@ -1983,7 +2016,7 @@ __global__ __launch_bounds__(kThreads) void k_amr_step(const AmrStepArgs<T> A, c
   constexpr int NCOMP = EQ == 1 ? 3 : 1;
   constexpr int NR = TY + 3;
   constexpr int NC = M + 5;
-  __shared__ StepLds<T, NCOMP, NR, NC, PAIR ? kLdsPair : kLdsAlias> L;
+  __shared__ StepLds<T, NCOMP, NR, NC, PAIR && sizeof(T) == 8 ? kLdsPair : kLdsAlias> L;
 
   // ---- block -> (level, patch, tile).  Each level's block range is a
   // multiple of 8 long, so every XCD takes an equal share of every level (the
