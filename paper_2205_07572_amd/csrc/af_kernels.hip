@@ -440,12 +440,12 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
   }
   // the extended cells of a thread: at most MAXIT (region <= 1, nrow <= TY);
   // their time sums wait in registers until every node is evaluated.  The
-  // FP32 acoustic node pass walks rows of the LDS pitch NC (the columns past
-  // EC idle): the 64 lanes of a wave then read 64 consecutive LDS words at
+  // acoustic node pass walks rows of the LDS pitch NC (the columns past EC
+  // idle): the 64 lanes of a wave then read 64 consecutive LDS values at
   // every stencil point, free of bank conflicts (rows of EC on a pitch of NC
   // wrap onto the banks of the wave's first lanes).  The time sums are
   // stored on the same pitch.
-  constexpr bool kWide = EQ == 1 && sizeof(T) == 4;
+  constexpr bool kWide = EQ == 1;
   const int WN = kWide ? NC : EC;
   constexpr int MAXIT = ((kWide ? M + 5 : M + 3) * (TY + 1) + kThreads - 1) / kThreads;
   T tsv[MAXIT][3][NCOMP];
