@@ -114,14 +114,11 @@ __device__ __forceinline__ int xcd_patch(int b, int n) {
 // kLdsAlias: the update reads only the averages and the sums, so the sums
 // overwrite the staged node values once every node is evaluated; the block
 // then holds 4 NCOMP NR NC values, not 7 NCOMP NR NC, and more blocks fit on
-// a CU.  The first of a fused pair of substeps uses it too in FP32: its new
-// node values wait in registers until the update is done and then replace
-// the sums.  kLdsPair: separate sums, for the FP64 fused pair, whose
-// registers, not its LDS, already limit it to 2 blocks per CU: its new node
-// values go in place of the staged ones with the sums, one barrier earlier.
-// kLdsSwirl: separate sums, and the swirl's values at t+dt (tsum2); its
-// update also reads the nodes at t.
-enum StepLdsKind { kLdsAlias, kLdsPair, kLdsSwirl };
+// a CU.  The first of a fused pair of substeps uses it too: its new node
+// values wait in registers until the update is done and then replace the
+// sums.  kLdsSwirl: separate sums, and the swirl's values at t+dt (tsum2);
+// its update also reads the nodes at t.
+enum StepLdsKind { kLdsAlias, kLdsSwirl };
 
 template <typename T, int NCOMP, int NR, int NC, int KIND>
 struct StepLds;
@@ -133,16 +130,6 @@ struct StepLds<T, NCOMP, NR, NC, kLdsAlias> {
   T in[4][NCOMP][NR][NC];
   __device__ __forceinline__ TS& tsum() { return *reinterpret_cast<TS*>(&in[1][0][0][0]); }
   __device__ __forceinline__ TS& tsum2() { return tsum(); }  // unused without the swirl
-};
-
-template <typename T, int NCOMP, int NR, int NC>
-struct StepLds<T, NCOMP, NR, NC, kLdsPair> {
-  using TS = T[3][NCOMP][NR - 2][NC];
-  static constexpr bool kSeparate = true;
-  T in[4][NCOMP][NR][NC];
-  TS ts;
-  __device__ __forceinline__ TS& tsum() { return ts; }
-  __device__ __forceinline__ TS& tsum2() { return ts; }  // unused without the swirl
 };
 
 template <typename T, int NCOMP, int NR, int NC>
@@ -273,50 +260,64 @@ __device__ __forceinline__ void ac_eval_rows(const T (&s)[4][3][NR][NC], int r, 
 // component, Dx the x-odd sums of u (into p) and p (into u), Dy the y-odd
 // sums of v (into p) and p (into v).
 // v1: the node's value at t + dt; vs: 4 q(t + dt/2) + q(t + dt).
+// Orbit o of node kind NK added to acc: the orbit sum S and odd parts Dx,
+// Dy of the neighbourhood values, times the orbit's weights.
+template <typename T, int NK, int NR, int NC>
+__device__ __forceinline__ void ac_orbit(const T (&s)[4][3][NR][NC], int r, int c,
+                                         const T (&w)[kMaxOrbits][2][3], int o, T (&acc)[2][3]) {
+  const NbOrbit& O = kOrbitTab[NK].o[o];
+  T S[3], Dx[3] = {T(0), T(0), T(0)}, Dy[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    const T m0 = s[O.m[0].kind][q][r + O.m[0].dj][c + O.m[0].di];
+    if (O.n == 1) {
+      S[q] = m0;
+    } else if (O.n == 2) {
+      const T m1 = s[O.m[1].kind][q][r + O.m[1].dj][c + O.m[1].di];
+      S[q] = m0 + m1;
+      if (O.hasx && q != 2) Dx[q] = m0 - m1;
+      if (O.hasy && q != 1) Dy[q] = m0 - m1;
+    } else {
+      const T m1 = s[O.m[1].kind][q][r + O.m[1].dj][c + O.m[1].di];
+      const T m2 = s[O.m[2].kind][q][r + O.m[2].dj][c + O.m[2].di];
+      const T m3 = s[O.m[3].kind][q][r + O.m[3].dj][c + O.m[3].di];
+      const T hi = m0 + m1, lo = m2 + m3;
+      S[q] = hi + lo;
+      if (q != 1) Dy[q] = hi - lo;
+      if (q != 2) Dx[q] = (m0 - m1) + (m2 - m3);
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < 2; ++cc) {
+    const T wk = w[o][cc][0], wx = w[o][cc][1], wy = w[o][cc][2];
+    acc[cc][0] += wk * S[0];
+    acc[cc][1] += wk * S[1];
+    acc[cc][2] += wk * S[2];
+    if (O.hasx) {
+      acc[cc][0] -= wx * Dx[1];
+      acc[cc][1] -= wx * Dx[0];
+    }
+    if (O.hasy) {
+      acc[cc][0] -= wy * Dy[2];
+      acc[cc][2] -= wy * Dy[0];
+    }
+  }
+}
+
+// Orbits [O0, O1) of node kind NK added to acc.
+template <typename T, int NK, int NR, int NC, int O0, int O1>
+__device__ __forceinline__ void ac_orbit_range(const T (&s)[4][3][NR][NC], int r, int c,
+                                               const T (&w)[kMaxOrbits][2][3], T (&acc)[2][3]) {
+#pragma unroll
+  for (int o = O0; o < O1; ++o) ac_orbit<T, NK, NR, NC>(s, r, c, w, o, acc);
+}
+
 template <typename T, int NK, int NR, int NC>
 __device__ __forceinline__ void ac_node(const T (&s)[4][3][NR][NC], int r, int c,
                                         const T (&w)[kMaxOrbits][2][3], T v1[3], T vs[3]) {
   T acc[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
 #pragma unroll
-  for (int o = 0; o < kOrbitTab[NK].n; ++o) {
-    const NbOrbit& O = kOrbitTab[NK].o[o];
-    T S[3], Dx[3] = {T(0), T(0), T(0)}, Dy[3] = {T(0), T(0), T(0)};
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      const T m0 = s[O.m[0].kind][q][r + O.m[0].dj][c + O.m[0].di];
-      if (O.n == 1) {
-        S[q] = m0;
-      } else if (O.n == 2) {
-        const T m1 = s[O.m[1].kind][q][r + O.m[1].dj][c + O.m[1].di];
-        S[q] = m0 + m1;
-        if (O.hasx && q != 2) Dx[q] = m0 - m1;
-        if (O.hasy && q != 1) Dy[q] = m0 - m1;
-      } else {
-        const T m1 = s[O.m[1].kind][q][r + O.m[1].dj][c + O.m[1].di];
-        const T m2 = s[O.m[2].kind][q][r + O.m[2].dj][c + O.m[2].di];
-        const T m3 = s[O.m[3].kind][q][r + O.m[3].dj][c + O.m[3].di];
-        const T hi = m0 + m1, lo = m2 + m3;
-        S[q] = hi + lo;
-        if (q != 1) Dy[q] = hi - lo;
-        if (q != 2) Dx[q] = (m0 - m1) + (m2 - m3);
-      }
-    }
-#pragma unroll
-    for (int cc = 0; cc < 2; ++cc) {
-      const T wk = w[o][cc][0], wx = w[o][cc][1], wy = w[o][cc][2];
-      acc[cc][0] += wk * S[0];
-      acc[cc][1] += wk * S[1];
-      acc[cc][2] += wk * S[2];
-      if (O.hasx) {
-        acc[cc][0] -= wx * Dx[1];
-        acc[cc][1] -= wx * Dx[0];
-      }
-      if (O.hasy) {
-        acc[cc][0] -= wy * Dy[2];
-        acc[cc][2] -= wy * Dy[0];
-      }
-    }
-  }
+  for (int o = 0; o < kOrbitTab[NK].n; ++o) ac_orbit<T, NK, NR, NC>(s, r, c, w, o, acc);
 #pragma unroll
   for (int q = 0; q < 3; ++q) {
     v1[q] = acc[0][q];
@@ -409,15 +410,16 @@ struct StepIO {
 };
 
 // TO_LDS: the first substep of a fused pair (no HBM output): new node values
-// and averages replace the staged ones in L.in.  With the sums aliased onto
-// the staged nodes the node values go in after the update, which reads the
-// sums from where they will be stored; with separate sums, beside them.
-// rofs: staged row of cell row j is j - jlo + 1 + rofs (the pair's second
-// substep reads the first's rows).
+// and averages replace the staged ones in L.in.  The time sums are aliased
+// onto the staged nodes, so the node values go in after the update, which
+// reads the sums from where they will be stored.  rofs: staged row of cell
+// row j is j - jlo + 1 + rofs (the pair's second substep reads the first's
+// rows).
 template <typename T, int EQ, int M, int TY, bool TO_LDS = false, typename L_t>
 __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const typename WSel<T, EQ>::type& W,
                                              int jlo, int jhi, T px0, T py0, int rofs = 0) {
-  static_assert(!TO_LDS || EQ == 0 || EQ == 1, "a fused pair needs a constant-coefficient equation");
+  static_assert(!TO_LDS || ((EQ == 0 || EQ == 1) && !L_t::kSeparate),
+                "a fused pair needs a constant-coefficient equation and the aliased LDS layout");
   constexpr int NCOMP = EQ == 1 ? 3 : 1;
   constexpr int NR = TY + 3;
   constexpr int NC = M + 5;
@@ -572,44 +574,17 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
         tsv[it][kind][0] = (T(0.5) * cur * cur + T(2) * val[0] * val[0]) + T(0.5) * val[1] * val[1];
         if (wrow) A.out[kind + 1][size_t(patch) * plane + obase] = val[1];
       }
-    } else if constexpr (EQ == 1 && sizeof(T) == 8 && !TO_LDS) {
-      // acoustics (eq. ERFormula), FP64: the three nodes of the cell from its
-      // neighbourhood in registers, orbit by orbit
-      T v1[3], vs[3];
-      ac_node<T, 0, NR, NC>(L.in, r, c, W.w[0], v1, vs);
-#pragma unroll
-      for (int q = 0; q < 3; ++q) {
-        tsv[it][NK_CORNER][q] = L.in[1][q][r][c] + vs[q];
-        emit(it, NK_CORNER, q, wrow, (size_t(q) * A.npatch + patch) * plane + obase, v1[q]);
-      }
-      if (has_x) {
-        ac_node<T, 1, NR, NC>(L.in, r, c, W.w[1], v1, vs);
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          tsv[it][NK_XEDGE][q] = L.in[2][q][r][c] + vs[q];
-          emit(it, NK_XEDGE, q, true, (size_t(q) * A.npatch + patch) * plane + obase, v1[q]);
-        }
-      }
-      if (has_y) {
-        ac_node<T, 2, NR, NC>(L.in, r, c, W.w[2], v1, vs);
-#pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          tsv[it][NK_YEDGE][q] = L.in[3][q][r][c] + vs[q];
-          emit(it, NK_YEDGE, q, wrow, (size_t(q) * A.npatch + patch) * plane + obase, v1[q]);
-        }
-      }
     }
   }
-  if constexpr (EQ == 1 && (sizeof(T) == 4 || TO_LDS)) {
-    // acoustics (eq. ERFormula), FP32: one node kind at a time over the
-    // thread's cells, each node from its neighbourhood orbit by orbit.  The
-    // kind's orbit weights (42 for a corner, 26 for an edge) fit in scalar
-    // registers for the whole pass and the kernel needs about 90 VGPRs, not
-    // 126 (5 waves per SIMD, not 4).  In FP64
-    // the kernel holds 2 waves per SIMD either way, and the three nodes of a
-    // cell together give each wave more independent work (the first substep
-    // of a fused pair goes kind by kind in FP64 too: it also holds the new
-    // node values).
+  if constexpr (EQ == 1) {
+    // acoustics (eq. ERFormula): one node kind at a time over the thread's
+    // cells, each node from its neighbourhood orbit by orbit.  The kind's
+    // orbit weights (42 for a corner, 26 for an edge) fit in scalar
+    // registers for the whole pass and the FP32 kernel needs about 90 VGPRs,
+    // not 126 (5 waves per SIMD, not 4).  An FP64 weight takes two scalar
+    // registers, so FP64 sums a node's orbits in two ranges, each with its
+    // own weight loads: the kernel then fits 168 VGPRs (3 waves per SIMD,
+    // not 2).
     auto kind_pass = [&](auto kc) {
       constexpr int K = decltype(kc)::value;
       Walk2 v(threadIdx.x, kThreads, WN);
@@ -624,7 +599,19 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
         const size_t obase = size_t(jlo + jj + kGhost) * A.pitch + (ilo + ii + kGhost);
         const bool wst = K == NK_XEDGE || jj < nrow || last_tile;
         T v1[3], vs[3];
-        ac_node<T, K, NR, NC>(L.in, r, c, W.w[K], v1, vs);
+        if constexpr (sizeof(T) == 8) {
+          constexpr int H = K == NK_CORNER ? 5 : 3;
+          T acc[2][3] = {{T(0), T(0), T(0)}, {T(0), T(0), T(0)}};
+          ac_orbit_range<T, K, NR, NC, 0, H>(L.in, r, c, W.w[K], acc);
+          ac_orbit_range<T, K, NR, NC, H, kOrbitTab[K].n>(L.in, r, c, W.w[K], acc);
+#pragma unroll
+          for (int q = 0; q < 3; ++q) {
+            v1[q] = acc[0][q];
+            vs[q] = acc[1][q];
+          }
+        } else {
+          ac_node<T, K, NR, NC>(L.in, r, c, W.w[K], v1, vs);
+        }
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
           tsv[it][K][q] = L.in[K + 1][q][r][c] + vs[q];
@@ -650,12 +637,6 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
         ts[NK_CORNER][q][jj][ii] = tsv[it][NK_CORNER][q];
         if (jj < nrow) ts[NK_XEDGE][q][jj][ii] = tsv[it][NK_XEDGE][q];
         if (ii < span) ts[NK_YEDGE][q][jj][ii] = tsv[it][NK_YEDGE][q];
-        if constexpr (TO_LDS && L_t::kSeparate) {
-          const int r = jj + 1 + rofs, c = ii + coff;
-          L.in[1][q][r][c] = nv[it][NK_CORNER][q];
-          if (jj < nrow) L.in[2][q][r][c] = nv[it][NK_XEDGE][q];
-          if (ii < span) L.in[3][q][r][c] = nv[it][NK_YEDGE][q];
-        }
       }
     }
   }
@@ -779,7 +760,7 @@ __device__ __forceinline__ void step_compute(L_t& L, const StepIO<T>& A, const t
       }
     }
   }
-  if constexpr (TO_LDS && !L_t::kSeparate) {
+  if constexpr (TO_LDS) {
     // the new node values of the extended cells, over the time sums
     __syncthreads();
     Walk2 v(threadIdx.x, kThreads, WN);
@@ -2016,7 +1997,7 @@ __global__ __launch_bounds__(kThreads) void k_amr_step(const AmrStepArgs<T> A, c
   constexpr int NCOMP = EQ == 1 ? 3 : 1;
   constexpr int NR = TY + 3;
   constexpr int NC = M + 5;
-  __shared__ StepLds<T, NCOMP, NR, NC, PAIR && sizeof(T) == 8 ? kLdsPair : kLdsAlias> L;
+  __shared__ StepLds<T, NCOMP, NR, NC, kLdsAlias> L;
 
   // ---- block -> (level, patch, tile).  Each level's block range is a
   // multiple of 8 long, so every XCD takes an equal share of every level (the
