@@ -1914,7 +1914,7 @@ struct AmrStepArgs {
   uint32_t mask;                   // level l's data before the step: p[(mask >> l) & 1]
   int32_t nlev, lev0;              // levels lev0 .. lev0 + nlev - 1 step
   int32_t first[kMaxLevels];       // first leaf of each of those levels
-  int32_t bstart[kMaxLevels + 1];  // first block of each level (multiples of 8); bstart[nlev] = blocks
+  int32_t bstart[kMaxLevels + 1];  // first block of range kk, level nlev - 1 - kk (multiples of 8); bstart[nlev] = blocks
   int32_t items[kMaxLevels];       // (patch, tile) items of each level, <= its block range
   int32_t region[kMaxLevels], tiles[kMaxLevels], rows[kMaxLevels];
   double len_dt_x[kMaxLevels], len_dt_y[kMaxLevels];
@@ -2002,12 +2002,16 @@ __global__ __launch_bounds__(kThreads) void k_amr_step(const AmrStepArgs<T> A, c
   // ---- block -> (level, patch, tile).  Each level's block range is a
   // multiple of 8 long, so every XCD takes an equal share of every level (the
   // coarse levels' blocks, which fill most of their halo from the plan, are
-  // the slow ones), and within a level a contiguous run of its leaves.
+  // slow ones), and within a level a contiguous run of its leaves.  The
+  // ranges run from the finest level (range kk = 0) to the coarsest: the
+  // finest level's blocks, which carry both substeps of a fused pair, are
+  // dispatched first, and the shorter ones fill the end of the launch.
   const int b = int(blockIdx.x);
-  int k = 0;
-  while (k + 1 < A.nlev && b >= A.bstart[k + 1]) ++k;
+  int kk = 0;
+  while (kk + 1 < A.nlev && b >= A.bstart[kk + 1]) ++kk;
+  const int k = A.nlev - 1 - kk;
   const int lvl = A.lev0 + k;
-  const int local = xcd_patch(b - A.bstart[k], A.bstart[k + 1] - A.bstart[k]);
+  const int local = xcd_patch(b - A.bstart[kk], A.bstart[kk + 1] - A.bstart[kk]);
   if (local >= A.items[k]) return;  // padding of the level's range (block-uniform)
   const int tiles = A.tiles[k], rows = A.rows[k], region = A.region[k];
   const int pl = local / tiles;
@@ -2538,9 +2542,11 @@ static hipError_t launch_amr_t(const AmrStepLaunch& s, hipStream_t st) {
     A.rows[k] = (span + tiles - 1) / tiles;
     A.len_dt_x[k] = s.len_dt_x[k];
     A.len_dt_y[k] = s.len_dt_y[k];
-    A.bstart[k] = blocks;
     A.items[k] = s.count[k] * tiles;
-    blocks += (A.items[k] + 7) / 8 * 8;
+  }
+  for (int kk = 0; kk < s.nlev; ++kk) {
+    A.bstart[kk] = blocks;
+    blocks += (A.items[s.nlev - 1 - kk] + 7) / 8 * 8;
   }
   A.bstart[s.nlev] = blocks;
   if (blocks == 0) return hipSuccess;
