@@ -79,7 +79,7 @@ C4_T, C4_EVERY, C4_M, C4_N0, C4_LMAX, C4_THETA = 0.5, 4, 16, 8, 3, (8.0, 2.0)
 # FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00 KiB (the factors a plain 64 MiB
 # device copy gives), valid for the kernel source whose hash is recorded
 # (profiles/k_amr_step_config4.md holds the commands).
-C4_TRAFFIC = {"source_sha256_16": "d7e169b1868867a1", "fp32": 77703645, "fp64": 150418192}
+C4_TRAFFIC = {"source_sha256_16": "50aba14026eab9fa", "fp32": 76885481, "fp64": 147248083}
 
 
 def _kernel_source_hash(text=None):
