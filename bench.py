@@ -41,8 +41,8 @@ NSTEPS_T = 1280
 HBM_PEAK_GBS = 8000.0
 # Vector ALU peak of these kernels: 256 CUs x 64 fused multiply-adds per clock
 # (FP32 or FP64) x 2 flops x 2.4 GHz = 78.6 TFLOP/s.  The FP32 figure of
-# 157.3 TFLOP/s counts packed FP32 instructions, which this build does not
-# emit.
+# 157.3 TFLOP/s counts packed FP32 instructions, which the library's kernels
+# are compiled without.
 VALU_PEAK_TFLOPS = 78.6
 # HBM bytes per launch of the level-advance kernel (k_level_advance_up) on
 # this workload, from rocprofv3 FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00 (scales
@@ -264,8 +264,8 @@ def time_path(prec, data, steps, warmup, dt, general_steps):
 
 
 # FP32 / FP64 vector peaks (MI355X published figures, TFLOP/s); packed FP32
-# instructions are disabled in this build, so FP32 kernels can reach at most
-# half of the FP32 figure.
+# instructions are disabled for every kernel of the library, so FP32 kernels
+# can reach at most half of the FP32 figure.
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
 # algorithmic flops per cell-update of the collapsed stencils: advection 6
 # node values x 9 FMA + 3 time sums (2 ops) + 4 face sums (2 ops) + update
