@@ -7,10 +7,7 @@
 // tables (leaf id or -1), so every query is O(levels).
 #include <algorithm>
 #include <cstdio>
-#include <map>
-#include <set>
 #include <string>
-#include <tuple>
 #include <vector>
 
 #include "af_hier.h"
@@ -154,85 +151,99 @@ std::string Hier::build(const std::vector<Leaf>& in) {
 // Regrid (Sec. 3): refine tagged leaves, close under 2:1 corner balance,
 // coarsen qualifying families, sort by (level, iy, ix).
 std::vector<Leaf> Hier::regrid(const int8_t* tags) const {
-  using Key = std::tuple<int, int, int>;  // (level, iy, ix) -- sort order
-  std::map<Key, int> old_tag;
-  for (size_t k = 0; k < leaves.size(); ++k) old_tag[Key(leaves[k].level, leaves[k].iy, leaves[k].ix)] = tags[k];
-  std::set<Key> cur;
+  // the candidate leaf set as dense per-level flags, indexed like the lookup
+  // table; scanning them level by level, row by row gives the (level, iy, ix)
+  // order of the result
+  const size_t total = lut.size();
+  auto at = [&](int l, long long px, long long py) {
+    const long long nx = npx(l), ny = npy(l);
+    return size_t(lut_off[l] + wrapi(py, ny) * nx + wrapi(px, nx));
+  };
+  std::vector<uint8_t> cur(total, 0), was(total, 0);
+  std::vector<int8_t> old_tag(total, 0);
   for (size_t k = 0; k < leaves.size(); ++k) {
     const Leaf& L = leaves[k];
+    const size_t e = at(L.level, L.ix, L.iy);
+    was[e] = 1;
+    old_tag[e] = tags[k];
     if (tags[k] == 1 && L.level < lmax) {
-      for (int q = 0; q < 4; ++q) cur.insert(Key(L.level + 1, 2 * L.iy + (q >> 1), 2 * L.ix + (q & 1)));
+      for (int q = 0; q < 4; ++q) cur[at(L.level + 1, 2 * L.ix + (q & 1), 2 * L.iy + (q >> 1))] = 1;
     } else {
-      cur.insert(Key(L.level, L.iy, L.ix));
+      cur[e] = 1;
     }
   }
-  auto covering = [&](const std::set<Key>& S, int l, long long px, long long py, int* lev) -> bool {
-    for (int k = l; k >= 0; --k) {
-      const long long nx = npx(k), ny = npy(k);
-      const long long qx = wrapi(px >> (l - k), nx), qy = wrapi(py >> (l - k), ny);
-      if (S.count(Key(k, int(qy), int(qx)))) {
+  // leaf of the set covering position (l, px, py), itself or an ancestor
+  auto covering = [&](int l, long long px, long long py, int* lev) -> bool {
+    for (int k = l; k >= 0; --k)
+      if (cur[at(k, px >> (l - k), py >> (l - k))]) {
         *lev = k;
         return true;
       }
-    }
     return false;
   };
+  // every leaf of the set, in (level, iy, ix) order
+  auto for_each = [&](auto&& f) {
+    for (int l = 0; l <= lmax; ++l)
+      for (int iy = 0; iy < npy(l); ++iy)
+        for (int ix = 0; ix < npx(l); ++ix)
+          if (cur[size_t(lut_off[l] + (long long)iy * npx(l) + ix)]) f(l, ix, iy);
+  };
   // balance closure: a leaf two levels coarser than a touching leaf splits
+  std::vector<uint8_t> mark(total, 0);
+  std::vector<Leaf> split;
   for (;;) {
-    std::set<Key> split;
-    for (const Key& F : cur) {
-      const int l = std::get<0>(F);
-      const int iy = std::get<1>(F), ix = std::get<2>(F);
+    split.clear();
+    for_each([&](int l, int ix, int iy) {
       for (int dy = -1; dy <= 1; ++dy)
         for (int dx = -1; dx <= 1; ++dx) {
           if (!dx && !dy) continue;
           const long long px = wrapi(ix + dx, npx(l)), py = wrapi(iy + dy, npy(l));
           int lev;
-          if (covering(cur, l, px, py, &lev) && lev <= l - 2)
-            split.insert(Key(lev, int(py >> (l - lev)), int(px >> (l - lev))));
+          if (covering(l, px, py, &lev) && lev <= l - 2) {
+            const Leaf S{lev, int(px >> (l - lev)), int(py >> (l - lev))};
+            uint8_t& m = mark[at(S.level, S.ix, S.iy)];
+            if (!m) {
+              m = 1;
+              split.push_back(S);
+            }
+          }
         }
-    }
+    });
     if (split.empty()) break;
-    for (const Key& S : split) {
-      cur.erase(S);
-      const int l = std::get<0>(S), iy = std::get<1>(S), ix = std::get<2>(S);
-      for (int q = 0; q < 4; ++q) cur.insert(Key(l + 1, 2 * iy + (q >> 1), 2 * ix + (q & 1)));
+    for (const Leaf& S : split) {
+      const size_t e = at(S.level, S.ix, S.iy);
+      mark[e] = 0;
+      cur[e] = 0;
+      for (int q = 0; q < 4; ++q) cur[at(S.level + 1, 2 * S.ix + (q & 1), 2 * S.iy + (q >> 1))] = 1;
     }
   }
   // families: all four siblings are leaves tagged -1, and no sibling has a
   // subdivided level-l neighbour position outside the family
-  std::vector<Key> parents;
-  std::set<Key> dropped;
-  for (const Key& K : cur) {
-    const int l = std::get<0>(K), iy = std::get<1>(K), ix = std::get<2>(K);
-    if (l == 0 || (ix & 1) || (iy & 1)) continue;
+  std::vector<Leaf> parents;
+  for_each([&](int l, int ix, int iy) {
+    if (l == 0 || (ix & 1) || (iy & 1)) return;
     bool ok = true;
     for (int q = 0; q < 4 && ok; ++q) {
-      const Key S(l, iy + (q >> 1), ix + (q & 1));
-      auto it = old_tag.find(S);
-      if (!cur.count(S) || it == old_tag.end() || it->second != -1) ok = false;
+      const size_t e = at(l, ix + (q & 1), iy + (q >> 1));
+      if (!cur[e] || !was[e] || old_tag[e] != -1) ok = false;
     }
     for (int q = 0; q < 4 && ok; ++q) {
       const int sx = ix + (q & 1), sy = iy + (q >> 1);
       for (int dy = -1; dy <= 1 && ok; ++dy)
         for (int dx = -1; dx <= 1 && ok; ++dx) {
           if (!dx && !dy) continue;
-          const long long px = wrapi(sx + dx, npx(l)), py = wrapi(sy + dy, npy(l));
           int lev;
-          if (!covering(cur, l, px, py, &lev)) ok = false;  // subdivided: finer leaves touch the parent
+          if (!covering(l, wrapi(sx + dx, npx(l)), wrapi(sy + dy, npy(l)), &lev)) ok = false;  // finer leaves touch the parent
         }
     }
-    if (!ok) continue;
-    for (int q = 0; q < 4; ++q) dropped.insert(Key(l, iy + (q >> 1), ix + (q & 1)));
-    parents.push_back(Key(l - 1, iy >> 1, ix >> 1));
+    if (ok) parents.push_back({l - 1, ix >> 1, iy >> 1});
+  });
+  for (const Leaf& P : parents) {
+    for (int q = 0; q < 4; ++q) cur[at(P.level + 1, 2 * P.ix + (q & 1), 2 * P.iy + (q >> 1))] = 0;
+    cur[at(P.level, P.ix, P.iy)] = 1;
   }
-  std::set<Key> fin;
-  for (const Key& K : cur)
-    if (!dropped.count(K)) fin.insert(K);
-  for (const Key& P : parents) fin.insert(P);
   std::vector<Leaf> out;
-  out.reserve(fin.size());
-  for (const Key& K : fin) out.push_back({std::get<0>(K), std::get<2>(K), std::get<1>(K)});
+  for_each([&](int l, int ix, int iy) { out.push_back({l, ix, iy}); });
   return out;
 }
 

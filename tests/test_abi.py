@@ -114,13 +114,13 @@ def test_hierarchy_rejects_unbalanced():
     assert e.value.status == _lib.AF_ERR_BALANCE
 
 
-@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("seed", range(10))
 def test_regrid_and_side_relations_match_oracle(seed):
     rng = np.random.default_rng(seed)
-    n0 = 2 + seed % 2
-    ctx = af.Context(af.Problem(eq=1, prec=0, m=8, n0x=n0, n0y=n0, lmax=4))
-    o = oracle.Hier(1, 8, n0, n0, 4)
-    leaves = afsynth.uniform_leaves(n0, n0, 1)
+    n0x, n0y = 2 + seed % 2, 2 + (seed // 2) % 3
+    ctx = af.Context(af.Problem(eq=1, prec=0, m=8, n0x=n0x, n0y=n0y, lmax=4))
+    o = oracle.Hier(1, 8, n0x, n0y, 4)
+    leaves = afsynth.uniform_leaves(n0x, n0y, 1)
     o.set_leaves(leaves)
     h = af.Hierarchy(ctx, leaves)
     for _ in range(6):
