@@ -37,8 +37,41 @@ af_status fail(af_status s, const std::string& msg) {
 
 }  // namespace
 
+// Device memory for the tables of a context's hierarchies.  A regrid builds
+// a new hierarchy of about the size of the old one every few coarse steps;
+// its tables reuse the old one's blocks instead of a hipMalloc per table and
+// a hipFree per table, which drains the device.  Blocks come in power-of-two
+// capacities.  Shared by the context and its hierarchies and freed with the
+// last of them.
+struct DevPool {
+  std::multimap<size_t, void*> idle;  // capacity -> block not in use
+  std::map<void*, size_t> cap;        // every block -> capacity
+  ~DevPool() {
+    for (auto& b : cap) (void)hipFree(b.first);
+  }
+  hipError_t get(void** p, size_t bytes) {
+    size_t c = 256;
+    while (c < bytes) c <<= 1;
+    auto it = idle.find(c);
+    if (it != idle.end()) {
+      *p = it->second;
+      idle.erase(it);
+      return hipSuccess;
+    }
+    const hipError_t e = hipMalloc(p, c);
+    if (e == hipSuccess) cap[*p] = c;
+    return e;
+  }
+  // back to the pool; the caller has made sure no queued work reads it
+  void put(void* p) {
+    auto it = p ? cap.find(p) : cap.end();
+    if (it != cap.end()) idle.emplace(it->second, p);
+  }
+};
+
 struct af_ctx {
   af_problem P;
+  std::shared_ptr<DevPool> pool = std::make_shared<DevPool>();
   int ncomp;
   int ty = 0;  // step tile height (rows per block)
   bool fused_pairs = true;  // batched coarse step: fused pairs of finest-level substeps
@@ -85,6 +118,7 @@ struct GraphKey {
 
 struct af_hier {
   af_ctx* ctx = nullptr;
+  std::shared_ptr<DevPool> pool;  // the context's (the tables below come from it)
   Hier H;
   int32_t* d_lut = nullptr;
   int32_t* d_level = nullptr;
@@ -127,6 +161,16 @@ T* dev_upload(const std::vector<T>& v, hipError_t* err) {
   if (*err != hipSuccess) return nullptr;
   if (!v.empty()) *err = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
   return p;
+}
+
+// dev_upload into a block of the pool
+template <typename T>
+T* pool_upload(DevPool& pool, const std::vector<T>& v, hipError_t* err) {
+  void* p = nullptr;
+  *err = pool.get(&p, std::max<size_t>(1, v.size()) * sizeof(T));
+  if (*err != hipSuccess) return nullptr;
+  if (!v.empty()) *err = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  return static_cast<T*>(p);
 }
 
 af_status check_state(const af_ctx* c, const af_state* s, int need_patches, const char* what) {
@@ -260,14 +304,15 @@ af_status hier_device(af_hier* h) {
     xy[2 * k + 1] = vy[k];
   }
   hipError_t err;
-  h->d_lut = dev_upload(h->H.lut, &err);
-  if (err == hipSuccess) h->d_level = dev_upload(lv, &err);
-  if (err == hipSuccess) h->d_ix = dev_upload(vx, &err);
-  if (err == hipSuccess) h->d_iy = dev_upload(vy, &err);
-  if (err == hipSuccess) h->d_side_mask = dev_upload(h->H.side_mask, &err);
-  if (err == hipSuccess) h->d_xy = dev_upload(xy, &err);
-  if (err == hipSuccess) h->d_faces = dev_upload(h->all_faces, &err);
-  if (err == hipSuccess) h->d_impure = dev_upload(h->impure, &err);
+  DevPool& pool = *h->pool;
+  h->d_lut = pool_upload(pool, h->H.lut, &err);
+  if (err == hipSuccess) h->d_level = pool_upload(pool, lv, &err);
+  if (err == hipSuccess) h->d_ix = pool_upload(pool, vx, &err);
+  if (err == hipSuccess) h->d_iy = pool_upload(pool, vy, &err);
+  if (err == hipSuccess) h->d_side_mask = pool_upload(pool, h->H.side_mask, &err);
+  if (err == hipSuccess) h->d_xy = pool_upload(pool, xy, &err);
+  if (err == hipSuccess) h->d_faces = pool_upload(pool, h->all_faces, &err);
+  if (err == hipSuccess) h->d_impure = pool_upload(pool, h->impure, &err);
   if (err != hipSuccess) return fail(AF_ERR_DEVICE, std::string("hierarchy upload: ") + hipGetErrorString(err));
   HierDev& D = h->dev;
   D.lut = h->d_lut;
@@ -406,6 +451,7 @@ af_status af_hier_create(af_ctx* ctx, int32_t n, const int32_t* level, const int
   if (!ctx || !out || n <= 0 || !level || !ix || !iy) return fail(AF_ERR_ARG, "bad hierarchy arguments");
   auto h = std::make_unique<af_hier>();
   h->ctx = ctx;
+  h->pool = ctx->pool;
   h->H.m = ctx->P.m;
   h->H.n0x = ctx->P.n0x;
   h->H.n0y = ctx->P.n0y;
@@ -445,19 +491,17 @@ af_status af_hier_create(af_ctx* ctx, int32_t n, const int32_t* level, const int
 af_status af_hier_destroy(af_hier* h) {
   if (!h) return AF_OK;
   for (auto& g : h->graphs) (void)hipGraphExecDestroy(g.second);
-  (void)hipFree(h->d_lut);
-  (void)hipFree(h->d_level);
-  (void)hipFree(h->d_ix);
-  (void)hipFree(h->d_iy);
-  (void)hipFree(h->d_side_mask);
-  (void)hipFree(h->d_xy);
-  (void)hipFree(h->d_faces);
-  for (int4* p : h->d_plan) (void)hipFree(p);
-  for (uint32_t* p : h->d_plan_flags) (void)hipFree(p);
-  for (int4* p : h->d_canon_ops) (void)hipFree(p);
-  (void)hipFree(h->d_nbr);
-  (void)hipFree(h->d_gnflags);
-  (void)hipFree(h->d_impure);
+  // the tables go back to the pool once no queued work can read them
+  if (h->on_device) (void)hipDeviceSynchronize();
+  DevPool& pool = *h->pool;
+  for (void* p : {static_cast<void*>(h->d_lut), static_cast<void*>(h->d_level), static_cast<void*>(h->d_ix),
+                  static_cast<void*>(h->d_iy), static_cast<void*>(h->d_side_mask), static_cast<void*>(h->d_xy),
+                  static_cast<void*>(h->d_faces), static_cast<void*>(h->d_nbr), static_cast<void*>(h->d_gnflags),
+                  static_cast<void*>(h->d_impure)})
+    pool.put(p);
+  for (int4* p : h->d_plan) pool.put(p);
+  for (uint32_t* p : h->d_plan_flags) pool.put(p);
+  for (int4* p : h->d_canon_ops) pool.put(p);
   delete h;
   return AF_OK;
 }
@@ -646,16 +690,17 @@ af_status fill_plan(af_ctx* ctx, af_hier* h, int smin, hipStream_t stream) {
   const size_t n = h->H.leaves.size();
   int4* plan = nullptr;
   uint32_t* flags = nullptr;
-  AF_HIP(hipMalloc(&plan, std::max<size_t>(1, n * size_t(ctx->nentries)) * sizeof(int4)));
-  if (hipMalloc(&flags, std::max<size_t>(1, n) * sizeof(uint32_t)) != hipSuccess) {
-    (void)hipFree(plan);
+  DevPool& pool = *h->pool;
+  AF_HIP(pool.get(reinterpret_cast<void**>(&plan), std::max<size_t>(1, n * size_t(ctx->nentries)) * sizeof(int4)));
+  if (pool.get(reinterpret_cast<void**>(&flags), std::max<size_t>(1, n) * sizeof(uint32_t)) != hipSuccess) {
+    pool.put(plan);
     return fail(AF_ERR_DEVICE, "fill plan allocation");
   }
   h->d_plan[smin] = plan;
   h->d_plan_flags[smin] = flags;
   if (smin == 0) {
-    AF_HIP(hipMalloc(&h->d_nbr, std::max<size_t>(1, n) * 9 * sizeof(int32_t)));
-    AF_HIP(hipMalloc(&h->d_gnflags, std::max<size_t>(1, n) * sizeof(uint32_t)));
+    AF_HIP(pool.get(reinterpret_cast<void**>(&h->d_nbr), std::max<size_t>(1, n) * 9 * sizeof(int32_t)));
+    AF_HIP(pool.get(reinterpret_cast<void**>(&h->d_gnflags), std::max<size_t>(1, n) * sizeof(uint32_t)));
   }
   AF_HIP(launch_fill_plan(h->dev, ctx->d_entries, ctx->nentries, ctx->P.m, smin, plan, flags,
                           smin == 0 ? h->d_nbr : nullptr, smin == 0 ? h->d_gnflags : nullptr, stream));
@@ -664,7 +709,7 @@ af_status fill_plan(af_ctx* ctx, af_hier* h, int smin, hipStream_t stream) {
   const int nbnd = int(ctx->h_bnd.size());
   if (ncanon > 0 && nbnd > 0) {
     int4* ops = nullptr;
-    AF_HIP(hipMalloc(&ops, size_t(ncanon) * nbnd * sizeof(int4)));
+    AF_HIP(pool.get(reinterpret_cast<void**>(&ops), size_t(ncanon) * nbnd * sizeof(int4)));
     h->d_canon_ops[smin] = ops;
     AF_HIP(launch_canon_ops(plan, ctx->d_entries, ctx->nentries, ctx->d_bnd, nbnd, h->d_impure + h->impure_off[smin],
                             ncanon, h->d_level, ops, stream));
@@ -779,14 +824,14 @@ af_status af_regrid_apply(af_ctx* ctx, const af_hier* old, const af_state* old_b
   }
   if ((s = hier_device(const_cast<af_hier*>(old))) != AF_OK) return s;
   hipError_t err;
-  Transfer* d_tr = dev_upload(tr, &err);
+  Transfer* d_tr = pool_upload(*ctx->pool, tr, &err);
   if (err != hipSuccess) return fail(AF_ERR_DEVICE, "transfer table upload");
   HierDev HO = old->dev;
   BufLaunch ob = make_buf(ctx, &old_bufs[0], &old_bufs[1], old_mask);
   BufLaunch nb = make_buf(ctx, dst, dst, 0);
   err = launch_transfer(ctx->fp32(), ob, HO, nb, d_tr, int(tr.size()), stream);
   if (err == hipSuccess) err = hipStreamSynchronize(stream);
-  (void)hipFree(d_tr);
+  if (err == hipSuccess) ctx->pool->put(d_tr);  // after a failure the block stays out of the pool
   if (err != hipSuccess) return fail(AF_ERR_DEVICE, std::string("transfer: ") + hipGetErrorString(err));
   // the new hierarchy's ghost-fill plans, so that its first coarse step
   // does not resolve them
