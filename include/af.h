@@ -358,6 +358,21 @@ af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* 
                              double t0, double dt0, double* flux_reg, int32_t flags,
                              hipStream_t stream);
 
+/* ---------------------------------------------------------------------
+ * af_amr_coarse_steps -- nsteps > 0 coarse steps of dt0 from t0 (step k
+ * from t0 + k dt0), each as af_amr_coarse_step with the same flags
+ * (AF_STEP_GLOBAL allowed, AF_STEP_GRAPH not), in one call: the state
+ * between two of them is not returned, so on the batched path the last
+ * launch of a step (the conservative fix of levels 0..F-1, cell averages
+ * only) joins the first launch of the next (vertex copies, nodes only), one
+ * launch fewer per step.  The result is bit for bit that of nsteps calls of
+ * af_amr_coarse_step.  Arguments and errors as for af_amr_coarse_step, and
+ * AF_ERR_ARG for nsteps <= 0 or other flags.
+ * --------------------------------------------------------------------- */
+af_status af_amr_coarse_steps(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* level_buf_mask,
+                              double t0, double dt0, int32_t nsteps, double* flux_reg, int32_t flags,
+                              hipStream_t stream);
+
 /* device uint8 [nleaves]: bit s set when side s borders another level */
 const uint8_t* af_hier_side_mask(const af_hier* h);
 /* Device int32 [nleaves][2] of the leaves' (ix, iy), the leaf_xy argument of

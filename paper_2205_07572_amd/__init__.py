@@ -218,6 +218,16 @@ class Context:
                                              float(dt0), _ptr(flux_reg), int(flags), _stream()))
         return mk.value
 
+    def amr_coarse_steps(self, hier, bufs, mask, dt0, nsteps, flux_reg, t0=0.0, global_step=False):
+        """nsteps coarse steps dt0 from time t0 in one call (af_amr_coarse_steps):
+        the result of nsteps amr_coarse_step calls, with one launch fewer per
+        step on the batched path."""
+        mk = ctypes.c_uint32(mask)
+        flags = STEP_GLOBAL if global_step else 0
+        check(_lib.load().af_amr_coarse_steps(self.h, hier.h, self._pair(bufs), ctypes.byref(mk), float(t0),
+                                              float(dt0), int(nsteps), _ptr(flux_reg), int(flags), _stream()))
+        return mk.value
+
 
     def amr_coarse_step_timed(self, hier, bufs, mask, dt0, flux_reg, events, t0=0.0):
         """af_amr_coarse_step_timed (a measurement helper): the subcycled

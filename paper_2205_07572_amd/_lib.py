@@ -21,7 +21,8 @@ EXPORTS = [
     "af_hier_level_range", "af_hier_finest_level", "af_hier_side_relations", "af_hier_side_mask",
     "af_hier_leaf_xy",
     "af_patch_step", "af_ghost_fill", "af_flux_correct", "af_regrid_tag", "af_hier_regrid",
-    "af_regrid_apply", "af_reduce_sum", "af_reduce_sum_noalloc", "af_amr_coarse_step", "af_level_advance",
+    "af_regrid_apply", "af_reduce_sum", "af_reduce_sum_noalloc", "af_amr_coarse_step", "af_amr_coarse_steps",
+    "af_level_advance",
     "af_ctx_advance_shapes", "af_ctx_advance_shapes_upwind", "af_ctx_set_advance_shape", "af_autotune",
     "af_ctx_get_advance_shape",
     "af_cnn_last_error", "af_cnn_create", "af_cnn_destroy", "af_cnn_num_params", "af_cnn_set_params",
@@ -102,6 +103,7 @@ def load():
     L.af_reduce_sum.argtypes = [P, P, S, ctypes.c_uint32, P, P]
     L.af_reduce_sum_noalloc.argtypes = [P, P, S, ctypes.c_uint32, P, P]
     L.af_amr_coarse_step.argtypes = [P, P, S, ctypes.POINTER(ctypes.c_uint32), D, D, P, i32, P]
+    L.af_amr_coarse_steps.argtypes = [P, P, S, ctypes.POINTER(ctypes.c_uint32), D, D, i32, P, i32, P]
     L.af_level_advance.argtypes = [P, P, S, ctypes.POINTER(ctypes.c_uint32), i32, D, i32, P]
     L.af_ctx_advance_shapes.argtypes = [P, P, P, i32]
     L.af_ctx_advance_shapes.restype = i32

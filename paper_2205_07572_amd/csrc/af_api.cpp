@@ -1284,6 +1284,11 @@ struct Driver {
 
   double dt0_ = 0.0;
   bool pair_ = false;
+  // several coarse steps in one call (af_amr_coarse_steps): the last launch
+  // of a step, the fix of levels 0..F-1, joins the first launch of the next
+  // (vertex copies only), which touches nodes only
+  bool defer_fix = false;    // leave this step's final fix to the next step
+  bool pending_fix = false;  // the previous step's final fix is still to make
 
   af_status coarse_step_batched(double dt0) {
     const int F = h->H.finest;
@@ -1299,11 +1304,16 @@ struct Driver {
       // the coarsest level that starts a step at tau
       const int l0 = tau == 0 ? 0 : F - __builtin_ctz(unsigned(tau));
       if (tau == 0) {
-        if ((s = sync(0, 1, 0)) != AF_OK) return s;
+        if ((s = pending_fix ? sync(0, 0, F - 1) : sync(0, 1, 0)) != AF_OK) return s;
+        pending_fix = false;
       } else if (l0 < F) {
         if ((s = sync(l0, l0, F - 1)) != AF_OK) return s;
       }
       if ((s = batched_step(tau, l0)) != AF_OK) return s;
+    }
+    if (F > 0 && defer_fix) {
+      pending_fix = true;
+      return AF_OK;
     }
     return F > 0 ? sync(-1, 0, F - 1) : AF_OK;
   }
@@ -1410,6 +1420,28 @@ af_status af_amr_coarse_step(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* 
   // the mask after a coarse step: subcycled, level 0 flips and finer levels
   // take an even number of steps; global, every level up to the finest flips
   *mask ^= global ? ((2u << h->H.finest) - 1u) : 1u;
+  return AF_OK;
+}
+
+af_status af_amr_coarse_steps(af_ctx* ctx, af_hier* h, af_state* bufs, uint32_t* mask, double t0, double dt0,
+                              int32_t nsteps, double* flux_reg, int32_t flags, hipStream_t stream) {
+  if (!ctx || !h || !mask || !flux_reg) return fail(AF_ERR_ARG, "null argument");
+  if (nsteps <= 0) return fail(AF_ERR_ARG, "af_amr_coarse_steps: nsteps must be positive");
+  if (flags & ~AF_STEP_GLOBAL) return fail(AF_ERR_ARG, "af_amr_coarse_steps: flags other than AF_STEP_GLOBAL");
+  af_status s = check_pair(ctx, h, bufs, "af_amr_coarse_steps");
+  if (s != AF_OK) return s;
+  if (!std::isfinite(t0)) return fail(AF_ERR_ARG, "t0 must be finite");
+  const bool global = flags & AF_STEP_GLOBAL;
+  s = check_cfl(ctx, global ? h->H.finest : 0, dt0);
+  if (s != AF_OK) return s;
+  if ((s = ctx_device(ctx)) != AF_OK || (s = hier_device(h)) != AF_OK) return s;
+  Driver D{ctx, h, bufs, *mask, flux_reg, stream};
+  for (int32_t k = 0; k < nsteps; ++k) {
+    D.defer_fix = k + 1 < nsteps;  // used by the batched path only
+    s = D.run(flags, t0 + double(k) * dt0, dt0);
+    if (s != AF_OK) return s;
+  }
+  *mask = D.mask;
   return AF_OK;
 }
 

@@ -193,3 +193,16 @@ def test_noalloc_sum_rejects_too_many_leaves_and_undeployed_hierarchies():
     ho = af.Hierarchy(ok, afsynth.uniform_leaves(256, 256, 0))
     st = L.af_reduce_sum_noalloc(ok.h, ho.h, _fake_pair(ok, len(ho)), 0, out, None)
     assert st == _lib.AF_ERR_STATE and b"not uploaded" in L.af_last_error()
+
+
+@pytest.mark.parametrize("nsteps,flags", [(0, 0), (-3, 0), (2, 1), (2, 4)])
+def test_coarse_steps_validates_count_and_flags(nsteps, flags):
+    """af_amr_coarse_steps rejects a non-positive step count and any flag but
+    AF_STEP_GLOBAL (graph replay included) before it touches the device."""
+    import ctypes
+    ctx = af.Context(af.Problem(eq=1, prec=0, m=8, n0x=2, n0y=2, lmax=1))
+    h = af.Hierarchy(ctx, afsynth.uniform_leaves(2, 2, 0))
+    mk = ctypes.c_uint32(0)
+    st = _lib.load().af_amr_coarse_steps(ctx.h, h.h, None, ctypes.byref(mk), 0.0, 1e-3, nsteps,
+                                         ctypes.c_void_p(16), flags, None)
+    assert st == _lib.AF_ERR_ARG
